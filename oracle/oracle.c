@@ -1,0 +1,977 @@
+/*
+ * oracle.c -- plain, slow, single-threaded FP64 CPU oracle for one Runge-Kutta
+ * substep of the finite-volume GRMHD update on a list of blocks.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may link, load or call
+ * this library: only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg use it. It shares no source, header, table or helper with the
+ * HIP library; the two meet only in the data contract (structure-of-arrays
+ * [9][padded cells], blocks stored one after another, x fastest).
+ *
+ * What it computes. The paper (Section 2, "Code overview") names the method's
+ * ingredients: GRMHD in a covariant coordinate system, a high-resolution
+ * shock-capturing finite-volume scheme, second-order time stepping, second- or
+ * third-order (PPM) reconstruction, and a Newton-Raphson conserved-to-primitive
+ * inversion with backups, on blocks of cells with ghost layers (Section 4.3 names
+ * the same-level ghost fill, Section 5.1 the ghost-cell exchange). It prints no
+ * equation, so every formula below is the standard 3+1 ("Valencia") form of
+ * ideal GRMHD that the code family uses; each function says which reading it
+ * implements. Build: gcc -O2 -ffp-contract=off, no fast-math.
+ *
+ * Parity pins: every function here is checked in tests/ against something other
+ * than itself (closed forms, invariants, brute force, covariant re-derivations).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NV 9
+enum { IRHO = 0, IU1 = 1, IP = 4, IB1 = 5, IPSI = 8 };
+enum { ID = 0, IS1 = 1, ITAU = 4 };
+
+/* ---------------------------------------------------------------------------------
+ * Parameters (the oracle's own definition; same meaning as the library's struct).
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+    int ndim, nghost, metric;          /* metric: 0 Minkowski Cartesian, 1 Kerr-Schild (ln r, theta, phi) */
+    double spin, gamma_ad;
+    double x_lo[3], x_hi[3];
+    int ncell0[3];
+    int bc[3][2];                      /* 0 periodic, 1 outflow */
+    int recon, flux;                   /* recon: 0 MC, 1 PPM; flux: 0 HLL, 1 TVDLF */
+    double cfl, rho_floor, p_floor, w_max, glm_alpha, c2p_tol;
+    int c2p_maxit;
+} orc_params;
+
+typedef struct { int level, size[3], origin[3]; } orc_block;
+
+typedef struct {
+    double dt_next, dt, ch, kappa;
+    double lam[3];
+    double dt_fixed;                   /* > 0: every step uses this dt */
+    int have_dt;
+    int64_t c2p_fail, floor_hits;
+    int max_iter;
+} orc_state;
+
+/* ---------------------------------------------------------------------------------
+ * Spacetime metric (reading: stationary Kerr-Schild in spherical coordinates with
+ * x1 = ln r, x2 = theta, x3 = phi, M = 1; or flat Cartesian). Section 2 allows any
+ * covariant coordinate system; the metric is analytic and evaluated pointwise.
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+    double alpha, beta[3], g[3][3], gi[3][3], sqrtg;
+    double da[3];          /* d_j alpha */
+    double db[3][3];       /* db[j][i] = d_j beta^i */
+    double dg[3][3][3];    /* dg[j][i][k] = d_j gamma_ik */
+} ometric;
+
+static void metric_at(const orc_params *p, double x1, double x2, ometric *m)
+{
+    memset(m, 0, sizeof *m);
+    if (p->metric == 0) {
+        m->alpha = 1.0;
+        m->sqrtg = 1.0;
+        for (int i = 0; i < 3; i++) { m->g[i][i] = 1.0; m->gi[i][i] = 1.0; }
+        return;
+    }
+    const double a = p->spin;
+    const double r = exp(x1), st = sin(x2), ct = cos(x2);
+    const double sig = r * r + a * a * ct * ct;
+    const double z = 2.0 * r / sig;
+    const double opz = 1.0 + z;
+
+    m->alpha = 1.0 / sqrt(opz);
+    m->beta[0] = z / (r * opz);
+    m->g[0][0] = r * r * opz;
+    m->g[0][2] = m->g[2][0] = -a * r * st * st * opz;
+    m->g[1][1] = sig;
+    m->g[2][2] = st * st * (sig + a * a * st * st * opz);
+    m->sqrtg = r * sig * st * sqrt(opz);
+    const double det13 = m->g[0][0] * m->g[2][2] - m->g[0][2] * m->g[0][2];
+    m->gi[0][0] = m->g[2][2] / det13;
+    m->gi[2][2] = m->g[0][0] / det13;
+    m->gi[0][2] = m->gi[2][0] = -m->g[0][2] / det13;
+    m->gi[1][1] = 1.0 / sig;
+
+    /* derivatives with respect to r and theta, then d/dx1 = r d/dr */
+    const double dsig_r = 2.0 * r, dsig_t = -2.0 * a * a * st * ct;
+    const double dz_r = 2.0 / sig - 2.0 * r * dsig_r / (sig * sig);
+    const double dz_t = -2.0 * r * dsig_t / (sig * sig);
+    const double dz[2] = { dz_r, dz_t };
+    double dal[2], db1[2], dg11[2], dg13[2], dg22[2], dg33[2];
+    for (int q = 0; q < 2; q++) dal[q] = -0.5 * pow(opz, -1.5) * dz[q];
+    db1[0] = (r * dz_r - z * opz) / (r * r * opz * opz);
+    db1[1] = dz_t / (r * opz * opz);
+    dg11[0] = 2.0 * r * opz + r * r * dz_r;
+    dg11[1] = r * r * dz_t;
+    dg13[0] = -a * st * st * opz - a * r * st * st * dz_r;
+    dg13[1] = -a * r * (2.0 * st * ct * opz + st * st * dz_t);
+    dg22[0] = dsig_r;
+    dg22[1] = dsig_t;
+    dg33[0] = st * st * dsig_r + a * a * st * st * st * st * dz_r;
+    dg33[1] = 2.0 * st * ct * sig + st * st * dsig_t
+              + a * a * (4.0 * st * st * st * ct * opz + st * st * st * st * dz_t);
+    const double fac[2] = { r, 1.0 };          /* chain rule for x1 = ln r */
+    for (int j = 0; j < 2; j++) {
+        m->da[j] = fac[j] * dal[j];
+        m->db[j][0] = fac[j] * db1[j];
+        m->dg[j][0][0] = fac[j] * dg11[j];
+        m->dg[j][0][2] = m->dg[j][2][0] = fac[j] * dg13[j];
+        m->dg[j][1][1] = fac[j] * dg22[j];
+        m->dg[j][2][2] = fac[j] * dg33[j];
+    }
+}
+
+/* ---------------------------------------------------------------------------------
+ * Primitive -> conserved (reading: Valencia 3+1 variables with an ideal-gas EOS).
+ * P = (rho, u~^i = W v^i, p, B^i, psi); U = sqrt(gamma) (D, S_i, tau, B^i), psi.
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+    double rho, p, W, v[3], vl[3], B[3], Bl[3], B2, Bv, v2, h, xi, D, S[3], tau;
+} ostate;
+
+static void state_from_prim(const orc_params *p, const ometric *m, const double *P, ostate *s)
+{
+    const double gam = p->gamma_ad;
+    s->rho = P[IRHO];
+    s->p = P[IP];
+    double ul[3], u2 = 0.0;
+    for (int i = 0; i < 3; i++) {
+        ul[i] = 0.0;
+        for (int j = 0; j < 3; j++) ul[i] += m->g[i][j] * P[IU1 + j];
+    }
+    for (int i = 0; i < 3; i++) u2 += P[IU1 + i] * ul[i];
+    s->W = sqrt(1.0 + u2);
+    for (int i = 0; i < 3; i++) { s->v[i] = P[IU1 + i] / s->W; s->vl[i] = ul[i] / s->W; }
+    s->v2 = 0.0;
+    for (int i = 0; i < 3; i++) s->v2 += s->v[i] * s->vl[i];
+    for (int i = 0; i < 3; i++) s->B[i] = P[IB1 + i];
+    for (int i = 0; i < 3; i++) {
+        s->Bl[i] = 0.0;
+        for (int j = 0; j < 3; j++) s->Bl[i] += m->g[i][j] * s->B[j];
+    }
+    s->B2 = 0.0;
+    s->Bv = 0.0;
+    for (int i = 0; i < 3; i++) { s->B2 += s->B[i] * s->Bl[i]; s->Bv += s->B[i] * s->vl[i]; }
+    s->h = 1.0 + gam / (gam - 1.0) * s->p / s->rho;
+    s->xi = s->rho * s->h * s->W * s->W;
+    s->D = s->rho * s->W;
+    for (int i = 0; i < 3; i++) s->S[i] = (s->xi + s->B2) * s->vl[i] - s->Bv * s->Bl[i];
+    s->tau = s->xi + s->B2 - s->p - 0.5 * (s->Bv * s->Bv + s->B2 / (s->W * s->W)) - s->D;
+}
+
+static void p2c_point(const orc_params *p, const ometric *m, const double *P, double *U)
+{
+    ostate s;
+    state_from_prim(p, m, P, &s);
+    U[ID] = m->sqrtg * s.D;
+    for (int i = 0; i < 3; i++) U[IS1 + i] = m->sqrtg * s.S[i];
+    U[ITAU] = m->sqrtg * s.tau;
+    for (int i = 0; i < 3; i++) U[IB1 + i] = m->sqrtg * s.B[i];
+    U[IPSI] = P[IPSI];
+}
+
+/* ---------------------------------------------------------------------------------
+ * Physical flux along direction d and the fast-speed bounds (reading: 3+1 fluxes;
+ * isotropic fast-magnetosonic bound c_e^2 = c_s^2 + c_a^2 - c_s^2 c_a^2).
+ * The normal-field flux and the psi flux are left zero: the GLM solve sets them.
+ * ------------------------------------------------------------------------------- */
+static void phys_flux(const orc_params *p, const ometric *m, const double *P, int d,
+                      double *U, double *F, double *lminus, double *lplus)
+{
+    const double gam = p->gamma_ad;
+    ostate s;
+    state_from_prim(p, m, P, &s);
+    const double W2 = s.W * s.W;
+    const double b2 = s.B2 / W2 + s.Bv * s.Bv;
+    const double pt = s.p + 0.5 * b2;
+    double Sd = 0.0;
+    for (int k = 0; k < 3; k++) Sd += m->gi[d][k] * s.S[k];
+    const double sg = m->sqrtg, al = m->alpha;
+    const double vd = s.v[d], bd = m->beta[d];
+
+    U[ID] = sg * s.D;
+    for (int i = 0; i < 3; i++) U[IS1 + i] = sg * s.S[i];
+    U[ITAU] = sg * s.tau;
+    for (int i = 0; i < 3; i++) U[IB1 + i] = sg * s.B[i];
+    U[IPSI] = P[IPSI];
+
+    F[ID] = sg * s.D * (al * vd - bd);
+    for (int j = 0; j < 3; j++) {
+        double Wdj = Sd * s.vl[j] + (j == d ? pt : 0.0) - (s.B[d] / W2 + s.Bv * vd) * s.Bl[j];
+        F[IS1 + j] = sg * (al * Wdj - bd * s.S[j]);
+    }
+    F[ITAU] = sg * (al * (Sd - s.D * vd) - bd * s.tau);
+    for (int j = 0; j < 3; j++) {
+        if (j == d) { F[IB1 + j] = 0.0; continue; }
+        F[IB1 + j] = sg * ((al * vd - bd) * s.B[j] - (al * s.v[j] - m->beta[j]) * s.B[d]);
+    }
+    F[IPSI] = 0.0;
+
+    const double rhoh = s.rho * s.h;
+    const double cs2 = gam * s.p / rhoh;
+    const double ca2 = b2 / (rhoh + b2);
+    const double ce2 = cs2 + ca2 - cs2 * ca2;
+    const double v2 = s.v2;
+    double disc = ce2 * (1.0 - v2) * (m->gi[d][d] * (1.0 - v2 * ce2) - vd * vd * (1.0 - ce2));
+    if (disc < 0.0) disc = 0.0;
+    const double sq = sqrt(disc);
+    const double pre = al / (1.0 - v2 * ce2);
+    *lplus = pre * (vd * (1.0 - ce2) + sq) - bd;
+    *lminus = pre * (vd * (1.0 - ce2) - sq) - bd;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Face flux: exact solve of the (B~^d, psi) GLM subsystem, then HLL or TVDLF on
+ * the other variables (reading: Dedner mixed GLM in coordinate space).
+ * ------------------------------------------------------------------------------- */
+static double riemann(const orc_params *p, const ometric *mf, int d, const double *PL,
+                      const double *PR, double ch, double *F)
+{
+    const double sg = mf->sqrtg;
+    const double btl = sg * PL[IB1 + d], btr = sg * PR[IB1 + d];
+    const double psl = PL[IPSI], psr = PR[IPSI];
+    const double bstar = 0.5 * (btl + btr) - (psr - psl) / (2.0 * ch);
+    const double psistar = 0.5 * (psl + psr) - 0.5 * ch * (btr - btl);
+    double ql[NV], qr[NV];
+    memcpy(ql, PL, sizeof ql);
+    memcpy(qr, PR, sizeof qr);
+    ql[IB1 + d] = bstar / sg;
+    qr[IB1 + d] = bstar / sg;
+    double UL[NV], UR[NV], FL[NV], FR[NV], lml, lpl, lmr, lpr;
+    phys_flux(p, mf, ql, d, UL, FL, &lml, &lpl);
+    phys_flux(p, mf, qr, d, UR, FR, &lmr, &lpr);
+    for (int v = 0; v < NV; v++) {
+        if (v == IB1 + d || v == IPSI) continue;
+        if (p->flux == 0) {
+            double sr = 0.0, sl = 0.0;
+            if (lpl > sr) sr = lpl;
+            if (lpr > sr) sr = lpr;
+            if (lml < sl) sl = lml;
+            if (lmr < sl) sl = lmr;
+            if (sr == sl) F[v] = 0.5 * (FL[v] + FR[v]);
+            else F[v] = (sr * FL[v] - sl * FR[v] + sr * sl * (UR[v] - UL[v])) / (sr - sl);
+        } else {
+            double c = fabs(lml);
+            if (fabs(lpl) > c) c = fabs(lpl);
+            if (fabs(lmr) > c) c = fabs(lmr);
+            if (fabs(lpr) > c) c = fabs(lpr);
+            F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * c * (UR[v] - UL[v]);
+        }
+    }
+    F[IB1 + d] = psistar;
+    F[IPSI] = ch * ch * bstar;
+    double lam = fabs(lml);
+    if (fabs(lpl) > lam) lam = fabs(lpl);
+    if (fabs(lmr) > lam) lam = fabs(lmr);
+    if (fabs(lpr) > lam) lam = fabs(lpr);
+    return lam;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Reconstruction (Section 2: second order, or third order PPM).
+ * MC: monotonised-central limited slope. PPM: Colella-Woodward interface values
+ * from MC slopes, then the two monotonicity constraints, no flattening.
+ * ------------------------------------------------------------------------------- */
+static double mc_slope(double qm, double q0, double qp)
+{
+    const double dm = q0 - qm, dp = qp - q0;
+    if (dm * dp <= 0.0) return 0.0;
+    double s = 2.0 * fabs(dm);
+    if (2.0 * fabs(dp) < s) s = 2.0 * fabs(dp);
+    if (0.5 * fabs(dm + dp) < s) s = 0.5 * fabs(dm + dp);
+    return dp > 0.0 ? s : -s;
+}
+
+/* q[0..4] = cells c-2..c+2; returns the values at the cell's lower and upper faces */
+static void ppm_cell(const double *q, double *qminus, double *qplus)
+{
+    const double sm = mc_slope(q[0], q[1], q[2]);
+    const double s0 = mc_slope(q[1], q[2], q[3]);
+    const double sp = mc_slope(q[2], q[3], q[4]);
+    double ql = 0.5 * (q[1] + q[2]) - (s0 - sm) / 6.0;
+    double qr = 0.5 * (q[2] + q[3]) - (sp - s0) / 6.0;
+    const double qi = q[2];
+    if ((qr - qi) * (qi - ql) <= 0.0) {
+        ql = qi;
+        qr = qi;
+    } else if ((qr - ql) * (qi - 0.5 * (ql + qr)) > (qr - ql) * (qr - ql) / 6.0) {
+        ql = 3.0 * qi - 2.0 * qr;
+    } else if (-(qr - ql) * (qr - ql) / 6.0 > (qr - ql) * (qi - 0.5 * (ql + qr))) {
+        qr = 3.0 * qi - 2.0 * ql;
+    }
+    *qminus = ql;
+    *qplus = qr;
+}
+
+/* q[0..5] = cells i-3..i+2 around face i-1/2; left and right face states */
+static void recon_face(int method, const double *q, double *qL, double *qR)
+{
+    if (method == 0) {
+        *qL = q[2] + 0.5 * mc_slope(q[1], q[2], q[3]);
+        *qR = q[3] - 0.5 * mc_slope(q[2], q[3], q[4]);
+    } else {
+        double a, b;
+        ppm_cell(q + 0, &a, qL);      /* cell i-1 uses i-3..i+1 */
+        ppm_cell(q + 1, qR, &b);      /* cell i uses i-2..i+2 */
+    }
+}
+
+/* ---------------------------------------------------------------------------------
+ * Geometric sources (reading: stationary metric, extrinsic curvature eliminated,
+ * written with metric derivatives; equal to the Christoffel-symbol form).
+ * Conserved D, S_j, tau from U_stage; the rest from P_stage. GLM damping on psi.
+ * ------------------------------------------------------------------------------- */
+static void sources_point(const orc_params *p, const ometric *m, const double *P, const double *U,
+                          double kappa, double *S)
+{
+    ostate s;
+    state_from_prim(p, m, P, &s);
+    const double sg = m->sqrtg;
+    const double D = U[ID] / sg, tau = U[ITAU] / sg;
+    double Sl[3], Su[3];
+    for (int i = 0; i < 3; i++) Sl[i] = U[IS1 + i] / sg;
+    for (int i = 0; i < 3; i++) {
+        Su[i] = 0.0;
+        for (int k = 0; k < 3; k++) Su[i] += m->gi[i][k] * Sl[k];
+    }
+    const double W2 = s.W * s.W;
+    const double b2 = s.B2 / W2 + s.Bv * s.Bv;
+    const double pt = s.p + 0.5 * b2;
+    double Wuu[3][3], Wud[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int k = 0; k < 3; k++)
+            Wuu[i][k] = Su[i] * s.v[k] + pt * m->gi[i][k] - (s.B[i] / W2 + s.Bv * s.v[i]) * s.B[k];
+    for (int j = 0; j < 3; j++)
+        for (int i = 0; i < 3; i++) {
+            Wud[j][i] = 0.0;
+            for (int k = 0; k < 3; k++) Wud[j][i] += Wuu[j][k] * m->g[k][i];
+        }
+    for (int v = 0; v < NV; v++) S[v] = 0.0;
+    for (int j = 0; j < 3; j++) {
+        double t = 0.0;
+        for (int i = 0; i < 3; i++)
+            for (int k = 0; k < 3; k++) t += 0.5 * m->alpha * Wuu[i][k] * m->dg[j][i][k];
+        for (int i = 0; i < 3; i++) t += Sl[i] * m->db[j][i];
+        t -= (tau + D) * m->da[j];
+        S[IS1 + j] = sg * t;
+    }
+    double te = 0.0;
+    for (int j = 0; j < 3; j++) {
+        for (int i = 0; i < 3; i++)
+            for (int k = 0; k < 3; k++) te += 0.5 * Wuu[i][k] * m->beta[j] * m->dg[j][i][k];
+        for (int i = 0; i < 3; i++) te += Wud[j][i] * m->db[j][i];
+        te -= Su[j] * m->da[j];
+    }
+    S[ITAU] = sg * te;
+    S[IPSI] = -kappa * U[IPSI];
+}
+
+/* ---------------------------------------------------------------------------------
+ * Conserved -> primitive (Section 2: Newton-Raphson with a backup). Reading: 1-D
+ * Newton on xi = rho h W^2, safeguarded by bisection towards the previous iterate,
+ * stop at |dxi| <= tol xi plus one more step; floors after success; on failure the
+ * cell keeps its stage primitives (the backup) and is flagged.
+ * Returns 0 on success, 1 on failure. *nit = Newton steps taken.
+ * ------------------------------------------------------------------------------- */
+typedef struct { double D, Ut, S2, B2, SB, gam; } c2p_sys;
+
+static double c2p_v2(const c2p_sys *c, double xi)
+{
+    const double xb = xi + c->B2;
+    return (xi * xi * c->S2 + c->SB * c->SB * (c->B2 + 2.0 * xi)) / (xi * xi * xb * xb);
+}
+
+static void c2p_fdf(const c2p_sys *c, double xi, double *f, double *df)
+{
+    const double v2 = c2p_v2(c, xi);
+    const double w2inv = 1.0 - v2;
+    const double W = 1.0 / sqrt(w2inv);
+    const double rho = c->D / W;
+    const double gfac = (c->gam - 1.0) / c->gam;
+    const double p = gfac * (xi * w2inv - rho);
+    *f = xi - p + c->B2 - 0.5 * (c->B2 * w2inv + c->SB * c->SB / (xi * xi)) - c->Ut;
+    const double xb = xi + c->B2;
+    const double dv2 = -2.0 * c->S2 / (xb * xb * xb)
+                       - 2.0 * c->SB * c->SB * (3.0 * xi * xi + 3.0 * xi * c->B2 + c->B2 * c->B2)
+                             / (xi * xi * xi * xb * xb * xb);
+    const double dp = gfac * (w2inv + (0.5 * c->D * W - xi) * dv2);
+    *df = 1.0 - dp + 0.5 * c->B2 * dv2 + c->SB * c->SB / (xi * xi * xi);
+}
+
+static double c2p_step(const c2p_sys *c, double xi)
+{
+    double f, df;
+    c2p_fdf(c, xi, &f, &df);
+    double xn = xi - f / df;
+    int nh = 0;
+    while ((xn <= 0.0 || c2p_v2(c, xn) >= 1.0) && nh < 64) {
+        xn = 0.5 * (xn + xi);
+        nh++;
+    }
+    if (xn <= 0.0 || c2p_v2(c, xn) >= 1.0) return NAN;
+    return xn;
+}
+
+static int c2p_point(const orc_params *p, const ometric *m, const double *U, const double *Pg,
+                     double *Pout, int *nit, int *floored)
+{
+    const double sg = m->sqrtg;
+    *nit = 0;
+    *floored = 0;
+    c2p_sys c;
+    c.gam = p->gamma_ad;
+    c.D = U[ID] / sg;
+    const double tau = U[ITAU] / sg;
+    double Sl[3], B[3], Bl[3];
+    for (int i = 0; i < 3; i++) { Sl[i] = U[IS1 + i] / sg; B[i] = U[IB1 + i] / sg; }
+    c.Ut = tau + c.D;
+    c.S2 = 0.0;
+    c.B2 = 0.0;
+    c.SB = 0.0;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) c.S2 += m->gi[i][j] * Sl[i] * Sl[j];
+    for (int i = 0; i < 3; i++) {
+        Bl[i] = 0.0;
+        for (int j = 0; j < 3; j++) Bl[i] += m->g[i][j] * B[j];
+    }
+    for (int i = 0; i < 3; i++) { c.B2 += B[i] * Bl[i]; c.SB += Sl[i] * B[i]; }
+
+    int fail = 0;
+    double xi = 0.0;
+    if (!(c.D > 0.0) || !isfinite(c.Ut) || !isfinite(c.S2) || !isfinite(c.B2)) fail = 1;
+    if (!fail) {
+        ostate g;
+        state_from_prim(p, m, Pg, &g);
+        xi = g.xi;
+        if (!(xi > 0.0) || !isfinite(xi)) xi = c.Ut > c.D ? c.Ut : c.D;
+        int nrep = 0;
+        while (c2p_v2(&c, xi) >= 1.0 && nrep < 200) { xi *= 2.0; nrep++; }
+        if (!(c2p_v2(&c, xi) < 1.0)) fail = 1;
+    }
+    if (!fail) {
+        int conv = 0, it = 0;
+        while (it < p->c2p_maxit) {
+            const double xn = c2p_step(&c, xi);
+            it++;
+            if (!isfinite(xn)) { fail = 1; break; }
+            const int done = fabs(xn - xi) <= p->c2p_tol * xn;
+            xi = xn;
+            if (done) { conv = 1; break; }
+        }
+        if (!fail && !conv) fail = 1;
+        if (!fail) {
+            xi = c2p_step(&c, xi);      /* one more step after the stopping test */
+            it++;
+            if (!isfinite(xi)) fail = 1;
+        }
+        *nit = it;
+    }
+    double rho = 0.0, prs = 0.0, W = 1.0, ut[3] = { 0.0, 0.0, 0.0 };
+    if (!fail) {
+        const double v2 = c2p_v2(&c, xi);
+        if (!(v2 < 1.0)) fail = 1;
+        else {
+            W = 1.0 / sqrt(1.0 - v2);
+            rho = c.D / W;
+            prs = (c.gam - 1.0) / c.gam * (xi / (W * W) - rho);
+            if (!(rho > 0.0) || !(prs >= 0.0) || !isfinite(rho) || !isfinite(prs)) fail = 1;
+        }
+    }
+    if (fail) {
+        memcpy(Pout, Pg, NV * sizeof(double));
+        return 1;
+    }
+    double vl[3];
+    for (int i = 0; i < 3; i++) vl[i] = (Sl[i] + c.SB * Bl[i] / xi) / (xi + c.B2);
+    for (int i = 0; i < 3; i++) {
+        double vu = 0.0;
+        for (int j = 0; j < 3; j++) vu += m->gi[i][j] * vl[j];
+        ut[i] = W * vu;
+    }
+    if (rho < p->rho_floor) { rho = p->rho_floor; *floored = 1; }
+    if (prs < p->p_floor) { prs = p->p_floor; *floored = 1; }
+    if (W > p->w_max) {
+        const double f = sqrt(p->w_max * p->w_max - 1.0) / sqrt(W * W - 1.0);
+        for (int i = 0; i < 3; i++) ut[i] *= f;
+        *floored = 1;
+    }
+    Pout[IRHO] = rho;
+    for (int i = 0; i < 3; i++) Pout[IU1 + i] = ut[i];
+    Pout[IP] = prs;
+    for (int i = 0; i < 3; i++) Pout[IB1 + i] = B[i];
+    Pout[IPSI] = U[IPSI];
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Grid: block list, padded layout and same-level ghost fill (Section 4.3).
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+    int level, size[3];
+    int nslot[3];
+    int *occ;            /* block id per slot, -1 if free */
+} ogroup;
+
+typedef struct {
+    orc_params p;
+    int64_t nb;
+    orc_block *blk;
+    int64_t *off;         /* padded offset, nb+1 */
+    int64_t *ioff;        /* interior offset, nb+1 */
+    int *grp;             /* group of each block */
+    int ngroup;
+    ogroup *groups;
+    int gz;               /* ghost layers per axis */
+    int gd[3];
+    int maxlevel;
+} orc_grid;
+
+static int64_t ncell_axis(const orc_grid *G, int b, int e)
+{
+    return G->blk[b].size[e] + 2 * G->gd[e];
+}
+
+static int64_t pad_index(const orc_grid *G, int b, int i, int j, int k)
+{
+    /* i, j, k: local indices, interior is [0, size) */
+    const int64_t n0 = ncell_axis(G, b, 0), n1 = ncell_axis(G, b, 1);
+    return G->off[b] + ((int64_t)(k + G->gd[2]) * n1 + (j + G->gd[1])) * n0 + (i + G->gd[0]);
+}
+
+static double level_dx(const orc_grid *G, int level, int e)
+{
+    return (G->p.x_hi[e] - G->p.x_lo[e]) / ((double)G->p.ncell0[e] * (double)(1 << level));
+}
+
+void orc_grid_free(orc_grid *G)
+{
+    if (!G) return;
+    for (int q = 0; q < G->ngroup; q++) free(G->groups[q].occ);
+    free(G->groups);
+    free(G->grp);
+    free(G->off);
+    free(G->ioff);
+    free(G->blk);
+    free(G);
+}
+
+/* returns NULL on invalid input */
+orc_grid *orc_grid_new(const orc_params *p, const orc_block *blocks, int64_t nb)
+{
+    if (nb <= 0 || p->ndim < 2 || p->ndim > 3 || p->nghost < 1) return NULL;
+    orc_grid *G = calloc(1, sizeof *G);
+    G->p = *p;
+    G->nb = nb;
+    G->blk = malloc(nb * sizeof(orc_block));
+    memcpy(G->blk, blocks, nb * sizeof(orc_block));
+    for (int e = 0; e < 3; e++) G->gd[e] = e < p->ndim ? p->nghost : 0;
+    G->off = malloc((nb + 1) * sizeof(int64_t));
+    G->ioff = malloc((nb + 1) * sizeof(int64_t));
+    G->grp = malloc(nb * sizeof(int));
+    G->off[0] = 0;
+    G->ioff[0] = 0;
+    G->maxlevel = 0;
+    for (int64_t b = 0; b < nb; b++) {
+        const orc_block *B = &G->blk[b];
+        if (B->level < 0 || B->level > 20) goto bad;
+        if (B->level > G->maxlevel) G->maxlevel = B->level;
+        for (int e = 0; e < 3; e++) {
+            if (e >= p->ndim) {
+                if (B->size[e] != 1 || B->origin[e] != 0 || p->ncell0[e] != 1) goto bad;
+                continue;
+            }
+            const int64_t N = (int64_t)p->ncell0[e] << B->level;
+            if (B->size[e] < p->nghost || B->origin[e] < 0 || B->origin[e] % B->size[e] != 0) goto bad;
+            if (B->origin[e] + B->size[e] > N || N % B->size[e] != 0) goto bad;
+        }
+        G->off[b + 1] = G->off[b] + ncell_axis(G, b, 0) * ncell_axis(G, b, 1) * ncell_axis(G, b, 2);
+        G->ioff[b + 1] = G->ioff[b] + (int64_t)B->size[0] * B->size[1] * B->size[2];
+    }
+    /* same (level, size) lattices with their occupancy */
+    G->groups = NULL;
+    G->ngroup = 0;
+    for (int64_t b = 0; b < nb; b++) {
+        const orc_block *B = &G->blk[b];
+        int q;
+        for (q = 0; q < G->ngroup; q++) {
+            ogroup *g = &G->groups[q];
+            if (g->level == B->level && g->size[0] == B->size[0] && g->size[1] == B->size[1]
+                && g->size[2] == B->size[2]) break;
+        }
+        if (q == G->ngroup) {
+            G->groups = realloc(G->groups, (G->ngroup + 1) * sizeof(ogroup));
+            ogroup *g = &G->groups[G->ngroup++];
+            g->level = B->level;
+            int64_t tot = 1;
+            for (int e = 0; e < 3; e++) {
+                g->size[e] = B->size[e];
+                g->nslot[e] = e < p->ndim ? (int)(((int64_t)p->ncell0[e] << B->level) / B->size[e]) : 1;
+                tot *= g->nslot[e];
+            }
+            g->occ = malloc(tot * sizeof(int));
+            for (int64_t t = 0; t < tot; t++) g->occ[t] = -1;
+        }
+        ogroup *g = &G->groups[q];
+        G->grp[b] = q;
+        const int64_t s = ((int64_t)(B->origin[2] / B->size[2]) * g->nslot[1] + B->origin[1] / B->size[1])
+                          * g->nslot[0] + B->origin[0] / B->size[0];
+        if (g->occ[s] != -1) goto bad;   /* two blocks in one slot */
+        g->occ[s] = (int)b;
+    }
+    return G;
+bad:
+    orc_grid_free(G);
+    return NULL;
+}
+
+void orc_grid_layout(const orc_grid *G, int64_t *off, int64_t *ioff)
+{
+    memcpy(off, G->off, (G->nb + 1) * sizeof(int64_t));
+    memcpy(ioff, G->ioff, (G->nb + 1) * sizeof(int64_t));
+}
+
+/* Source of one ghost slot of block b at local (l0,l1,l2): (block, local index). */
+static void ghost_source(const orc_grid *G, int b, const int l[3], int *sb, int src[3])
+{
+    const orc_block *B = &G->blk[b];
+    const ogroup *g = &G->groups[G->grp[b]];
+    int64_t Gi[3];
+    int slot[3];
+    for (int e = 0; e < 3; e++) {
+        if (e >= G->p.ndim) { Gi[e] = 0; slot[e] = 0; continue; }
+        const int64_t N = (int64_t)G->p.ncell0[e] << B->level;
+        int64_t x = B->origin[e] + l[e];
+        if (x < 0 || x >= N) {
+            const int side = x < 0 ? 0 : 1;
+            if (G->p.bc[e][side] == 0) x = ((x % N) + N) % N;        /* periodic wrap */
+            else x = x < 0 ? 0 : N - 1;                              /* outflow clamp */
+        }
+        Gi[e] = x;
+        slot[e] = (int)(x / B->size[e]);
+    }
+    const int64_t s = ((int64_t)slot[2] * g->nslot[1] + slot[1]) * g->nslot[0] + slot[0];
+    const int nbk = g->occ[s];
+    if (nbk >= 0) {
+        *sb = nbk;
+        for (int e = 0; e < 3; e++) src[e] = (int)(Gi[e] - (int64_t)slot[e] * B->size[e]);
+    } else {
+        *sb = b;                        /* no same-level block there: copy own edge cell */
+        for (int e = 0; e < 3; e++) {
+            int x = l[e];
+            if (x < 0) x = 0;
+            if (x > B->size[e] - 1) x = B->size[e] - 1;
+            src[e] = x;
+        }
+    }
+}
+
+static void fill_block(const orc_grid *G, int b, double *P, int64_t ncp)
+{
+    const orc_block *B = &G->blk[b];
+    const int g0 = G->gd[0], g1 = G->gd[1], g2 = G->gd[2];
+    for (int k = -g2; k < B->size[2] + g2; k++)
+        for (int j = -g1; j < B->size[1] + g1; j++)
+            for (int i = -g0; i < B->size[0] + g0; i++) {
+                const int inside = i >= 0 && i < B->size[0] && j >= 0 && j < B->size[1] && k >= 0
+                                   && k < B->size[2];
+                if (inside) continue;
+                const int l[3] = { i, j, k };
+                int sb, src[3];
+                ghost_source(G, b, l, &sb, src);
+                const int64_t dst = pad_index(G, b, i, j, k);
+                const int64_t from = pad_index(G, sb, src[0], src[1], src[2]);
+                for (int v = 0; v < NV; v++) P[v * ncp + dst] = P[v * ncp + from];
+            }
+}
+
+/* blocks: subset of block ids (NULL = all) */
+void orc_fill_ghosts(const orc_grid *G, double *P, const int64_t *blocks, int64_t nsel)
+{
+    const int64_t ncp = G->off[G->nb];
+    const int64_t n = blocks ? nsel : G->nb;
+    for (int64_t q = 0; q < n; q++) fill_block(G, (int)(blocks ? blocks[q] : q), P, ncp);
+}
+
+static void cell_center(const orc_grid *G, int b, int i, int j, double *x1, double *x2)
+{
+    const orc_block *B = &G->blk[b];
+    *x1 = G->p.x_lo[0] + (B->origin[0] + i + 0.5) * level_dx(G, B->level, 0);
+    *x2 = G->p.x_lo[1] + (B->origin[1] + j + 0.5) * level_dx(G, B->level, 1);
+}
+
+void orc_prim2con(const orc_grid *G, const double *P, double *U, const int64_t *blocks, int64_t nsel)
+{
+    const int64_t ncp = G->off[G->nb];
+    const int64_t n = blocks ? nsel : G->nb;
+    for (int64_t q = 0; q < n; q++) {
+        const int b = (int)(blocks ? blocks[q] : q);
+        const orc_block *B = &G->blk[b];
+        for (int k = 0; k < B->size[2]; k++)
+            for (int j = 0; j < B->size[1]; j++)
+                for (int i = 0; i < B->size[0]; i++) {
+                    double x1, x2, Pc[NV], Uc[NV];
+                    ometric m;
+                    cell_center(G, b, i, j, &x1, &x2);
+                    metric_at(&G->p, x1, x2, &m);
+                    const int64_t c = pad_index(G, b, i, j, k);
+                    for (int v = 0; v < NV; v++) Pc[v] = P[v * ncp + c];
+                    p2c_point(&G->p, &m, Pc, Uc);
+                    for (int v = 0; v < NV; v++) U[v * ncp + c] = Uc[v];
+                }
+    }
+}
+
+/* Standalone inversion: P_inout holds the guess on entry. fail: int8 per padded cell (nullable). */
+void orc_con2prim(const orc_grid *G, const double *U, double *P, int8_t *fail, orc_state *st,
+                  const int64_t *blocks, int64_t nsel)
+{
+    const int64_t ncp = G->off[G->nb];
+    const int64_t n = blocks ? nsel : G->nb;
+    for (int64_t q = 0; q < n; q++) {
+        const int b = (int)(blocks ? blocks[q] : q);
+        const orc_block *B = &G->blk[b];
+        for (int k = 0; k < B->size[2]; k++)
+            for (int j = 0; j < B->size[1]; j++)
+                for (int i = 0; i < B->size[0]; i++) {
+                    double x1, x2, Pg[NV], Uc[NV], Po[NV];
+                    ometric m;
+                    cell_center(G, b, i, j, &x1, &x2);
+                    metric_at(&G->p, x1, x2, &m);
+                    const int64_t c = pad_index(G, b, i, j, k);
+                    for (int v = 0; v < NV; v++) { Pg[v] = P[v * ncp + c]; Uc[v] = U[v * ncp + c]; }
+                    int nit, fl;
+                    const int f = c2p_point(&G->p, &m, Uc, Pg, Po, &nit, &fl);
+                    for (int v = 0; v < NV; v++) P[v * ncp + c] = Po[v];
+                    if (fail) fail[c] = (int8_t)f;
+                    if (st) {
+                        st->c2p_fail += f;
+                        st->floor_hits += (!f && fl);
+                        if (nit > st->max_iter) st->max_iter = nit;
+                    }
+                }
+    }
+}
+
+/* ---------------------------------------------------------------------------------
+ * Time step (reading): per-direction maximum |lambda| over faces of the last
+ * substep, dt = C / sum_d(lam_d / dx_d) on the finest level present,
+ * c_h = C / (dt sum_d 1/dx_d), kappa = alpha_glm c_h / min_d dx_d.
+ * ------------------------------------------------------------------------------- */
+static double dt_from_lam(const orc_grid *G, const double *lam)
+{
+    double s = 0.0;
+    for (int d = 0; d < G->p.ndim; d++) s += lam[d] / level_dx(G, G->maxlevel, d);
+    return G->p.cfl / s;
+}
+
+void orc_compute_dt(const orc_grid *G, const double *P, orc_state *st)
+{
+    const int64_t ncp = G->off[G->nb];
+    double lam[3] = { 0.0, 0.0, 0.0 };
+    for (int64_t b = 0; b < G->nb; b++) {
+        const orc_block *B = &G->blk[b];
+        for (int k = 0; k < B->size[2]; k++)
+            for (int j = 0; j < B->size[1]; j++)
+                for (int i = 0; i < B->size[0]; i++) {
+                    double x1, x2, Pc[NV], U[NV], F[NV], lm, lp;
+                    ometric m;
+                    cell_center(G, (int)b, i, j, &x1, &x2);
+                    metric_at(&G->p, x1, x2, &m);
+                    const int64_t c = pad_index(G, (int)b, i, j, k);
+                    for (int v = 0; v < NV; v++) Pc[v] = P[v * ncp + c];
+                    for (int d = 0; d < G->p.ndim; d++) {
+                        phys_flux(&G->p, &m, Pc, d, U, F, &lm, &lp);
+                        if (fabs(lm) > lam[d]) lam[d] = fabs(lm);
+                        if (fabs(lp) > lam[d]) lam[d] = fabs(lp);
+                    }
+                }
+    }
+    st->dt_next = dt_from_lam(G, lam);
+    st->have_dt = 1;
+}
+
+void orc_set_dt(orc_state *st, double dt)
+{
+    st->dt_fixed = dt;
+    if (dt > 0.0) { st->dt_next = dt; st->have_dt = 1; }
+}
+
+/* ---------------------------------------------------------------------------------
+ * One Runge-Kutta substep (Section 2: second-order explicit stepping; Section 4.2
+ * counts each substep times the number of cells as the unit of work):
+ *   U_out = a U_base + b (U_stage + dt L(U_stage)),
+ *   L = -sum_d (F_{+1/2} - F_{-1/2}) / dx_d + S,
+ * then the inversion of U_out with P_stage as the initial guess.
+ * A substep with a == 0 starts a step and latches dt from the previous substep's
+ * wave speeds. P_stage ghost slots must be filled. blocks: subset (NULL = all).
+ * ------------------------------------------------------------------------------- */
+int orc_substep(const orc_grid *G, const double *Ub, const double *Us, const double *Ps, double *Uo,
+                double *Po, double a, double b, orc_state *st, const int64_t *blocks, int64_t nsel)
+{
+    if (!st->have_dt) return -1;
+    const orc_params *p = &G->p;
+    const int64_t ncp = G->off[G->nb];
+    if (a == 0.0) {
+        st->dt = st->dt_fixed > 0.0 ? st->dt_fixed : st->dt_next;
+        double sinv = 0.0, dmin = 1e300;
+        for (int d = 0; d < p->ndim; d++) {
+            const double dx = level_dx(G, G->maxlevel, d);
+            sinv += 1.0 / dx;
+            if (dx < dmin) dmin = dx;
+        }
+        st->ch = p->cfl / (st->dt * sinv);
+        st->kappa = p->glm_alpha * st->ch / dmin;
+    }
+    double lam[3] = { 0.0, 0.0, 0.0 };
+    const int64_t n = blocks ? nsel : G->nb;
+    for (int64_t q = 0; q < n; q++) {
+        const int bk = (int)(blocks ? blocks[q] : q);
+        const orc_block *B = &G->blk[bk];
+        const int s0 = B->size[0], s1 = B->size[1], s2 = B->size[2];
+        const int64_t ncell = (int64_t)s0 * s1 * s2;
+        double *F[3] = { NULL, NULL, NULL };
+        int fs[3][3];
+        for (int d = 0; d < p->ndim; d++) {
+            for (int e = 0; e < 3; e++) fs[d][e] = B->size[e] + (e == d);
+            const int64_t nf = (int64_t)fs[d][0] * fs[d][1] * fs[d][2];
+            F[d] = malloc(NV * nf * sizeof(double));
+            const double dx = level_dx(G, B->level, d);
+            for (int k = 0; k < fs[d][2]; k++)
+                for (int j = 0; j < fs[d][1]; j++)
+                    for (int i = 0; i < fs[d][0]; i++) {
+                        /* face between the cell at (i,j,k) - e_d and the cell at (i,j,k) */
+                        int c[3] = { i, j, k };
+                        double qv[6], PL[NV], PR[NV];
+                        /* MC reads cells i-2..i+1, PPM reads i-3..i+2 */
+                        const int t0 = p->recon == 0 ? 1 : 0, t1 = p->recon == 0 ? 5 : 6;
+                        for (int t = 0; t < 6; t++) qv[t] = 0.0;
+                        for (int v = 0; v < NV; v++) {
+                            for (int t = t0; t < t1; t++) {
+                                int cc[3] = { c[0], c[1], c[2] };
+                                cc[d] += t - 3;
+                                qv[t] = Ps[v * ncp + pad_index(G, bk, cc[0], cc[1], cc[2])];
+                            }
+                            recon_face(p->recon, qv, &PL[v], &PR[v]);
+                        }
+                        double x1, x2;
+                        cell_center(G, bk, i, j, &x1, &x2);
+                        if (d == 0) x1 = p->x_lo[0] + (B->origin[0] + i) * dx;
+                        if (d == 1) x2 = p->x_lo[1] + (B->origin[1] + j) * dx;
+                        ometric mf;
+                        metric_at(p, x1, x2, &mf);
+                        double Ff[NV];
+                        const double l = riemann(p, &mf, d, PL, PR, st->ch, Ff);
+                        if (l > lam[d]) lam[d] = l;
+                        const int64_t fi = ((int64_t)k * fs[d][1] + j) * fs[d][0] + i;
+                        for (int v = 0; v < NV; v++) F[d][v * nf + fi] = Ff[v];
+                    }
+        }
+        for (int k = 0; k < s2; k++)
+            for (int j = 0; j < s1; j++)
+                for (int i = 0; i < s0; i++) {
+                    const int64_t c = pad_index(G, bk, i, j, k);
+                    double x1, x2, Pc[NV], Uc[NV], Sv[NV], L[NV], Un[NV], Pn[NV];
+                    ometric m;
+                    cell_center(G, bk, i, j, &x1, &x2);
+                    metric_at(p, x1, x2, &m);
+                    for (int v = 0; v < NV; v++) { Pc[v] = Ps[v * ncp + c]; Uc[v] = Us[v * ncp + c]; }
+                    sources_point(p, &m, Pc, Uc, st->kappa, Sv);
+                    for (int v = 0; v < NV; v++) L[v] = 0.0;
+                    for (int d = 0; d < p->ndim; d++) {
+                        const double dx = level_dx(G, B->level, d);
+                        const int64_t nf = (int64_t)fs[d][0] * fs[d][1] * fs[d][2];
+                        int hi[3] = { i, j, k };
+                        hi[d] += 1;
+                        const int64_t flo = ((int64_t)k * fs[d][1] + j) * fs[d][0] + i;
+                        const int64_t fhi = ((int64_t)hi[2] * fs[d][1] + hi[1]) * fs[d][0] + hi[0];
+                        for (int v = 0; v < NV; v++) L[v] -= (F[d][v * nf + fhi] - F[d][v * nf + flo]) / dx;
+                    }
+                    for (int v = 0; v < NV; v++) {
+                        L[v] += Sv[v];
+                        Un[v] = a * Ub[v * ncp + c] + b * (Uc[v] + st->dt * L[v]);
+                    }
+                    int nit, fl;
+                    const int f = c2p_point(p, &m, Un, Pc, Pn, &nit, &fl);
+                    if (f || fl) p2c_point(p, &m, Pn, Un);
+                    st->c2p_fail += f;
+                    st->floor_hits += (!f && fl);
+                    if (nit > st->max_iter) st->max_iter = nit;
+                    for (int v = 0; v < NV; v++) { Uo[v * ncp + c] = Un[v]; Po[v * ncp + c] = Pn[v]; }
+                }
+        (void)ncell;
+        for (int d = 0; d < p->ndim; d++) free(F[d]);
+    }
+    for (int d = 0; d < 3; d++) st->lam[d] = lam[d];
+    st->dt_next = st->dt_fixed > 0.0 ? st->dt_fixed : dt_from_lam(G, lam);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Pointwise entry points for the unit pins.
+ * ------------------------------------------------------------------------------- */
+void orc_metric(const orc_params *p, double x1, double x2, double *out)
+{
+    /* out: alpha, beta[3], g[9], gi[9], sqrtg, da[3], db[9] ([j][i]), dg[27] ([j][i][k]) = 62 */
+    ometric m;
+    metric_at(p, x1, x2, &m);
+    int o = 0;
+    out[o++] = m.alpha;
+    for (int i = 0; i < 3; i++) out[o++] = m.beta[i];
+    for (int i = 0; i < 3; i++) for (int j = 0; j < 3; j++) out[o++] = m.g[i][j];
+    for (int i = 0; i < 3; i++) for (int j = 0; j < 3; j++) out[o++] = m.gi[i][j];
+    out[o++] = m.sqrtg;
+    for (int j = 0; j < 3; j++) out[o++] = m.da[j];
+    for (int j = 0; j < 3; j++) for (int i = 0; i < 3; i++) out[o++] = m.db[j][i];
+    for (int j = 0; j < 3; j++) for (int i = 0; i < 3; i++) for (int k = 0; k < 3; k++) out[o++] = m.dg[j][i][k];
+}
+
+void orc_p2c_point(const orc_params *p, double x1, double x2, const double *P, double *U)
+{
+    ometric m;
+    metric_at(p, x1, x2, &m);
+    p2c_point(p, &m, P, U);
+}
+
+/* info[0] = fail, info[1] = Newton steps, info[2] = floored */
+void orc_c2p_point(const orc_params *p, double x1, double x2, const double *U, const double *Pg,
+                   double *Pout, int *info)
+{
+    ometric m;
+    metric_at(p, x1, x2, &m);
+    int nit, fl;
+    info[0] = c2p_point(p, &m, U, Pg, Pout, &nit, &fl);
+    info[1] = nit;
+    info[2] = fl;
+}
+
+void orc_phys_flux(const orc_params *p, double x1, double x2, const double *P, int d, double *U,
+                   double *F, double *lam)
+{
+    ometric m;
+    metric_at(p, x1, x2, &m);
+    phys_flux(p, &m, P, d, U, F, &lam[0], &lam[1]);
+}
+
+double orc_riemann(const orc_params *p, double x1, double x2, int d, const double *PL,
+                   const double *PR, double ch, double *F)
+{
+    ometric m;
+    metric_at(p, x1, x2, &m);
+    return riemann(p, &m, d, PL, PR, ch, F);
+}
+
+void orc_recon_face(int method, const double *q, double *qLR)
+{
+    recon_face(method, q, &qLR[0], &qLR[1]);
+}
+
+void orc_sources(const orc_params *p, double x1, double x2, const double *P, const double *U,
+                 double kappa, double *S)
+{
+    ometric m;
+    metric_at(p, x1, x2, &m);
+    sources_point(p, &m, P, U, kappa, S);
+}

@@ -1,0 +1,329 @@
+"""Seeded synthetic inputs for the GRMHD substep (shared by the HIP path and the oracle).
+
+This module draws random numbers and evaluates coordinate geometry only. It
+holds none of the method's arithmetic: no spacetime metric, no equation of
+state, no conversion between primitive and conserved variables, no flux. That
+is what lets the HIP path and the independent CPU oracle start from the very
+same bytes without sharing any code that computes the method.
+
+Workloads
+---------
+The paper's scaling runs use an unspecified uniform-grid GRMHD setup with a
+fixed number of cells per core (Section 3). The cases below are the
+synthetic stand-ins: a 2-D special-relativistic MHD block, a magnetised torus
+around a Kerr black hole on uniform 16^3 blocks, and an AMR-like list of
+blocks of mixed size and level. Every draw comes from
+``numpy.random.default_rng(12240 + k)`` for case k, in a fixed order.
+
+Data layout handed to both sides
+--------------------------------
+``Case.prim`` is float64 ``[9][ncell_interior]``: the interior cells of block
+0, then block 1, ..., each block x-fastest (axis 0 fastest, axis 2 slowest).
+Variable order: rho, u~1, u~2, u~3 (Eulerian velocity times Lorentz factor,
+contravariant), p, B1, B2, B3 (Eulerian field, contravariant), psi (GLM scalar).
+``Case.blocks`` is int32 ``[nb][7]`` = (level, size0, size1, size2, origin0,
+origin1, origin2), origins in level-l cells.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+NVAR = 9
+RHO, U1, U2, U3, PRS, B1, B2, B3, PSI = range(NVAR)
+
+METRIC_MINKOWSKI_CART = 0
+METRIC_KS_SPH_LOGR = 1
+BC_PERIODIC, BC_OUTFLOW = 0, 1
+RECON_MC, RECON_PPM = 0, 1
+FLUX_HLL, FLUX_TVDLF = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+
+SPIN = 0.9375
+R_OUT = 50.0
+TH_CUT = 0.1
+TORUS_R0, TORUS_W = 12.0, 4.0
+RHO_ATM, P_ATM = 1.0e-4, 1.0e-6
+
+
+@dataclass
+class Case:
+    name: str
+    params: dict
+    blocks: np.ndarray
+    prim: np.ndarray
+    ioff: np.ndarray
+    steps: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nblocks(self) -> int:
+        return int(self.blocks.shape[0])
+
+    @property
+    def ncell_interior(self) -> int:
+        return int(self.ioff[-1])
+
+
+def base_params(**kw) -> dict:
+    p = dict(ndim=3, nghost=3, metric=METRIC_KS_SPH_LOGR, spin=SPIN, gamma_ad=4.0 / 3.0,
+             x_lo=[0.0, 0.0, 0.0], x_hi=[1.0, 1.0, 1.0], ncell0=[1, 1, 1],
+             bc=[[BC_OUTFLOW, BC_OUTFLOW], [BC_OUTFLOW, BC_OUTFLOW], [BC_PERIODIC, BC_PERIODIC]],
+             recon=RECON_PPM, flux=FLUX_HLL, precision=PREC_FP64, fused=0,
+             cfl=0.4, rho_floor=RHO_ATM, p_floor=P_ATM, w_max=50.0, glm_alpha=0.1,
+             c2p_tol=1.0e-13, c2p_maxit=50)
+    p.update(kw)
+    return p
+
+
+def _ioff(blocks: np.ndarray) -> np.ndarray:
+    n = blocks[:, 1].astype(np.int64) * blocks[:, 2] * blocks[:, 3]
+    return np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+
+
+def _block_cells(blk):
+    """Global level-l indices (g0, g1, g2) of a block's interior cells, x fastest."""
+    _, s0, s1, s2, o0, o1, o2 = (int(v) for v in blk)
+    k, j, i = np.meshgrid(np.arange(s2), np.arange(s1), np.arange(s0), indexing="ij")
+    return (o0 + i).ravel(), (o1 + j).ravel(), (o2 + k).ravel()
+
+
+# ----------------------------------------------------------------------------------
+# Case 1: 2-D special-relativistic MHD, one 64x64 periodic block.
+# ----------------------------------------------------------------------------------
+def case1(n: int = 64, seed: int = 12241) -> Case:
+    rng = np.random.default_rng(seed)
+    kx, ky = (int(v) for v in rng.integers(1, 4, size=2))
+    phi0 = float(rng.uniform(0.0, 2.0 * math.pi))
+    cm = rng.standard_normal(4)
+    pm = rng.integers(1, 4, size=4)
+    qm = rng.integers(1, 4, size=4)
+    chi = rng.uniform(0.0, 2.0 * math.pi, size=4)
+    u1 = rng.uniform(size=(n, n))          # [j][i]
+    u2 = rng.uniform(size=(n, n))
+
+    h = 1.0 / n
+    xc = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(xc, xc, indexing="xy")  # X[j][i] = x_i
+    prim = np.zeros((NVAR, n, n))
+    prim[RHO] = 1.0 + 0.1 * np.sin(2 * math.pi * (kx * X + ky * Y) + phi0)
+    prim[PRS] = 1.0
+    # |u~| <= 1/sqrt(3) is the same as |v| <= 1/2 for a unit spatial metric
+    umag = math.sqrt(1.0 / 3.0) * np.sqrt(u1)
+    ang = 2.0 * math.pi * u2
+    prim[U1] = umag * np.cos(ang)
+    prim[U2] = umag * np.sin(ang)
+
+    # field: uniform 0.5 x-hat plus the central-difference curl of a corner potential
+    xf = np.arange(n + 1) * h
+    XF, YF = np.meshgrid(xf, xf, indexing="xy")
+    A = np.zeros_like(XF)
+    for m in range(4):
+        A += cm[m] * np.sin(2 * math.pi * (pm[m] * XF + qm[m] * YF) + chi[m])
+    A *= 0.05 / (2 * math.pi)
+    # corners (j, i) .. (j+1, i+1) surround cell (j, i)
+    a00, a01, a10, a11 = A[:-1, :-1], A[:-1, 1:], A[1:, :-1], A[1:, 1:]
+    prim[B1] = 0.5 + ((a10 + a11) - (a00 + a01)) / (2 * h)
+    prim[B2] = -((a01 + a11) - (a00 + a10)) / (2 * h)
+
+    blocks = np.array([[0, n, n, 1, 0, 0, 0]], dtype=np.int32)
+    params = base_params(ndim=2, nghost=2, metric=METRIC_MINKOWSKI_CART, spin=0.0,
+                         x_lo=[0.0, 0.0, 0.0], x_hi=[1.0, 1.0, 1.0], ncell0=[n, n, 1],
+                         bc=[[BC_PERIODIC] * 2, [BC_PERIODIC] * 2, [BC_PERIODIC] * 2],
+                         recon=RECON_MC, flux=FLUX_TVDLF, rho_floor=1.0e-4, p_floor=1.0e-6)
+    return Case(f"case1_srmhd2d_{n}", params, blocks, prim.reshape(NVAR, n * n).copy(),
+                _ioff(blocks), steps=10, meta=dict(kx=kx, ky=ky))
+
+
+# ----------------------------------------------------------------------------------
+# Kerr-Schild torus cases (2, 3, 5 uniform; 4 AMR-like).
+# ----------------------------------------------------------------------------------
+def ks_domain(spin: float = SPIN):
+    """Logarithmic-radius spherical domain: r in [0.8 r_H, 50], theta in [0.1, pi-0.1], phi in [0, 2pi)."""
+    r_h = 1.0 + math.sqrt(1.0 - spin * spin)
+    x_lo = [math.log(0.8 * r_h), TH_CUT, 0.0]
+    x_hi = [math.log(R_OUT), math.pi - TH_CUT, 2.0 * math.pi]
+    return x_lo, x_hi
+
+
+def _torus_density(r, th):
+    w = r * np.sin(th)
+    zz = r * np.cos(th)
+    d2 = (w - TORUS_R0) ** 2 + zz ** 2
+    return np.maximum(0.0, 1.0 - d2 / TORUS_W ** 2) ** 3
+
+
+def _torus_cells(params, level, g0, g1, g2, noise_u):
+    """Primitive state of the synthetic torus at level-l cells (g0, g1, g2).
+
+    Coordinate geometry only: the orbital velocity, the field normalisation and
+    the volume factor use flat-space expressions in (ln r, theta, phi), so no
+    part of the spacetime metric enters the inputs.
+    """
+    x_lo, x_hi, n0 = params["x_lo"], params["x_hi"], params["ncell0"]
+    dx = [(x_hi[d] - x_lo[d]) / (n0[d] * 2 ** level) for d in range(3)]
+    x1 = x_lo[0] + (g0 + 0.5) * dx[0]
+    th = x_lo[1] + (g1 + 0.5) * dx[1]
+    r = np.exp(x1)
+    rho_t = _torus_density(r, th)
+    prim = np.zeros((NVAR, g0.size))
+    prim[RHO] = np.maximum(rho_t, RHO_ATM)
+    p = np.maximum(0.01 * rho_t ** (4.0 / 3.0), P_ATM)
+    inside = rho_t > 0.0
+    p = np.where(inside, p * (1.0 + 0.02 * (2.0 * noise_u - 1.0)), p)
+    prim[PRS] = p
+    w = r * np.sin(th)
+    omega = 1.0 / (w ** 1.5 + params["spin"])
+    prim[U3] = np.where(inside, omega, 0.0)
+    # poloidal field from A_phi = max(rho_t - 0.2, 0) at cell corners
+    def a_phi(c0, c1):
+        rr = np.exp(x_lo[0] + c0 * dx[0])
+        tt = x_lo[1] + c1 * dx[1]
+        return np.maximum(_torus_density(rr, tt) - 0.2, 0.0)
+    a00 = a_phi(g0, g1)
+    a10 = a_phi(g0 + 1, g1)
+    a01 = a_phi(g0, g1 + 1)
+    a11 = a_phi(g0 + 1, g1 + 1)
+    dA_dth = ((a01 + a11) - (a00 + a10)) / (2 * dx[1])
+    dA_dx1 = ((a10 + a11) - (a00 + a01)) / (2 * dx[0])
+    vol = r ** 3 * np.sin(th)
+    prim[B1] = dA_dth / vol
+    prim[B2] = -dA_dx1 / vol
+    return prim, r, th
+
+
+def _uniform_blocks(n, bs):
+    nb = [n[d] // bs for d in range(3)]
+    out = []
+    for b0 in range(nb[0]):
+        for b1 in range(nb[1]):
+            for b2 in range(nb[2]):          # phi-block index fastest
+                out.append([0, bs, bs, bs, b0 * bs, b1 * bs, b2 * bs])
+    return np.array(out, dtype=np.int32)
+
+
+def _finish_torus(params, blocks, prim, r, th, seed_rng, turbulence_n=None):
+    # field normalisation: max p / max(|B|^2/2) = 100 with the flat spatial metric
+    bsq = (r * prim[B1]) ** 2 + (r * prim[B2]) ** 2
+    bmax = float(bsq.max())
+    if bmax > 0.0:
+        scale = math.sqrt(float(prim[PRS].max()) / (100.0 * 0.5 * bmax))
+        prim[B1] *= scale
+        prim[B2] *= scale
+    return prim
+
+
+def case_torus(cfg: int, n=128, bs: int = 16, precision=None, fused=None) -> Case:
+    """Cases 2 (128^3, FP64 plain), 3 (192^3, mixed) and 5 (384^3, mixed + turbulence)."""
+    if isinstance(n, int):
+        n = (n, n, n)
+    assert all(v % bs == 0 for v in n)
+    rng = np.random.default_rng(12240 + cfg)
+    x_lo, x_hi = ks_domain()
+    prec = {2: PREC_FP64, 3: PREC_MIXED, 5: PREC_MIXED}[cfg] if precision is None else precision
+    fus = {2: 0, 3: 0, 5: 1}[cfg] if fused is None else fused
+    params = base_params(x_lo=x_lo, x_hi=x_hi, ncell0=list(n), precision=prec, fused=fus)
+    blocks = _uniform_blocks(n, bs)
+    ioff = _ioff(blocks)
+    noise = rng.uniform(size=int(ioff[-1]))
+    g = [np.concatenate(v) for v in zip(*(_block_cells(b) for b in blocks))]
+    prim, r, th = _torus_cells(params, 0, g[0], g[1], g[2], noise)
+    prim = _finish_torus(params, blocks, prim, r, th, rng)
+    if cfg == 5:
+        _add_turbulence(params, prim, r, th, g, n, rng)
+    steps = 100 if cfg == 5 else 10
+    return Case(f"case{cfg}_ks_torus_{n[0]}x{n[1]}x{n[2]}", params, blocks, prim, ioff, steps)
+
+
+def _add_turbulence(params, prim, r, th, g, n, rng):
+    """Seeded velocity field at Mach 0.3 of the Newtonian sound speed, torus cells only."""
+    nm = 32
+    kvec = rng.integers(-4, 5, size=(3, nm, 3))
+    amp = rng.standard_normal((3, nm))
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=(3, nm))
+    inside = prim[U3] != 0.0
+    if not inside.any():
+        return
+    gam = params["gamma_ad"]
+    cs = np.sqrt(gam * prim[PRS] / prim[RHO])
+    scale = [r, r, r * np.sin(th)]
+    for comp in range(3):
+        field_ = np.zeros(g[0].size)
+        for m in range(nm):
+            arg = 2 * math.pi * (kvec[comp, m, 0] * g[0] / n[0] + kvec[comp, m, 1] * g[1] / n[1]
+                                 + kvec[comp, m, 2] * g[2] / n[2]) + ph[comp, m]
+            field_ += amp[comp, m] * np.sin(arg)
+        rms = math.sqrt(float(np.mean(field_[inside] ** 2)))
+        du = 0.3 * cs * field_ / max(rms, 1e-300) / scale[comp]
+        prim[U1 + comp] = np.where(inside, prim[U1 + comp] + du, prim[U1 + comp])
+
+
+def case4(nblocks: int = 4096, n0: int = 96, levels: int = 3, precision=PREC_MIXED, fused=1) -> Case:
+    """AMR-like list: independent same-level patches of mixed size and level."""
+    rng = np.random.default_rng(12244)
+    x_lo, x_hi = ks_domain()
+    params = base_params(x_lo=x_lo, x_hi=x_hi, ncell0=[n0, n0, n0], precision=precision, fused=fused)
+    lev_p = np.array([2.0 ** l for l in range(levels)])
+    lev_p /= lev_p.sum()
+    lev = rng.choice(levels, size=nblocks, p=lev_p)
+    size = rng.choice(np.array([8, 12, 16]), size=nblocks, p=[0.5, 0.3, 0.2])
+    taken = {}
+    out = []
+    for b in range(nblocks):
+        l, s = int(lev[b]), int(size[b])
+        nslot = n0 * 2 ** l // s
+        used = taken.setdefault((l, s), set())
+        cap = nslot ** 3
+        if len(used) >= cap:
+            raise ValueError("lattice full")
+        while True:
+            slot = tuple(int(v) for v in rng.integers(0, nslot, size=3))
+            if slot not in used:
+                used.add(slot)
+                break
+        out.append([l, s, s, s, slot[0] * s, slot[1] * s, slot[2] * s])
+    blocks = np.array(out, dtype=np.int32)
+    ioff = _ioff(blocks)
+    noise = rng.uniform(size=int(ioff[-1]))
+    prim = np.zeros((NVAR, int(ioff[-1])))
+    rr = np.zeros(int(ioff[-1]))
+    tt = np.zeros(int(ioff[-1]))
+    for b in range(nblocks):
+        g0, g1, g2 = _block_cells(blocks[b])
+        sl = slice(int(ioff[b]), int(ioff[b + 1]))
+        prim[:, sl], rr[sl], tt[sl] = _torus_cells(params, int(blocks[b, 0]), g0, g1, g2, noise[sl])
+    prim = _finish_torus(params, blocks, prim, rr, tt, rng)
+    return Case(f"case4_amrlike_{nblocks}", params, blocks, prim, ioff, steps=10)
+
+
+def make_case(cfg: int, **kw) -> Case:
+    if cfg == 1:
+        return case1(**kw)
+    if cfg in (2, 3, 5):
+        return case_torus(cfg, **kw)
+    if cfg == 4:
+        return case4(**kw)
+    raise ValueError(cfg)
+
+
+def uniform_state(n=(16, 16, 16), bs=(16, 16, 16), ndim=3, prim_value=None, bc=BC_PERIODIC,
+                  metric=METRIC_MINKOWSKI_CART, recon=RECON_PPM, flux=FLUX_HLL) -> Case:
+    """A spatially uniform state on a periodic Cartesian grid (any block tiling)."""
+    if prim_value is None:
+        prim_value = [1.0, 0.3, -0.2, 0.1, 0.7, 0.4, -0.3, 0.2, 0.0]
+    nb = [n[d] // bs[d] for d in range(3)]
+    blocks = []
+    for b0 in range(nb[0]):
+        for b1 in range(nb[1]):
+            for b2 in range(nb[2]):
+                blocks.append([0, bs[0], bs[1], bs[2], b0 * bs[0], b1 * bs[1], b2 * bs[2]])
+    blocks = np.array(blocks, dtype=np.int32)
+    ioff = _ioff(blocks)
+    prim = np.repeat(np.asarray(prim_value, dtype=np.float64)[:, None], int(ioff[-1]), axis=1)
+    g = 3 if recon == RECON_PPM else 2
+    params = base_params(ndim=ndim, nghost=g, metric=metric, spin=0.0,
+                         x_lo=[0.0, 0.0, 0.0], x_hi=[1.0, 1.0, 1.0], ncell0=list(n),
+                         bc=[[bc] * 2] * 3, recon=recon, flux=flux)
+    return Case("uniform", params, blocks, prim, ioff, steps=10)

@@ -1,0 +1,127 @@
+"""Pins of the oracle's ghost fill (same-level fill, periodic wrap, outflow copy)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_12240_amd import inputs as I
+
+
+def uniform_blocks(n, bs, ndim=3):
+    nb = [n[d] // bs[d] for d in range(3)]
+    out = []
+    for b0 in range(nb[0]):
+        for b1 in range(nb[1]):
+            for b2 in range(nb[2]):
+                out.append([0, bs[0], bs[1], bs[2], b0 * bs[0], b1 * bs[1], b2 * bs[2]])
+    return np.array(out, dtype=np.int32)
+
+
+def global_ids(blocks, ndim, n_per_level):
+    """Value of every interior cell: a unique id of (level, global index), var-offset per var."""
+    vals = []
+    for blk in blocks:
+        l, s, o = blk[0], blk[1:4], blk[4:7]
+        k, j, i = np.meshgrid(np.arange(s[2]), np.arange(s[1]), np.arange(s[0]), indexing="ij")
+        N = n_per_level(l)
+        gid = ((o[2] + k) * N[1] + (o[1] + j)) * N[0] + (o[0] + i) + 1e7 * l
+        vals.append(gid.ravel())
+    v = np.concatenate(vals).astype(np.float64)
+    return np.stack([v + 1e9 * q for q in range(9)])
+
+
+def ghost_expectations(G, blocks, params):
+    """Brute force: for each ghost slot, the global cell it should copy, by searching the
+    block list directly (no lattice arithmetic)."""
+    nd, g = params["ndim"], params["nghost"]
+    out = []
+    for b, blk in enumerate(blocks):
+        l, s, o = int(blk[0]), blk[1:4], blk[4:7]
+        N = [params["ncell0"][e] * 2 ** l for e in range(3)]
+        gd = [g if e < nd else 0 for e in range(3)]
+        for k in range(-gd[2], s[2] + gd[2]):
+            for j in range(-gd[1], s[1] + gd[1]):
+                for i in range(-gd[0], s[0] + gd[0]):
+                    loc = [i, j, k]
+                    if all(0 <= loc[e] < s[e] for e in range(3)):
+                        continue
+                    tgt = []
+                    for e in range(3):
+                        x = o[e] + loc[e]
+                        if x < 0 or x >= N[e]:
+                            if params["bc"][e][0 if x < 0 else 1] == I.BC_PERIODIC:
+                                x %= N[e]
+                            else:
+                                x = min(max(x, 0), N[e] - 1)
+                        tgt.append(x)
+                    owner = None
+                    for c, cb in enumerate(blocks):
+                        if cb[0] == l and all(cb[1 + e] == s[e] for e in range(3)) and all(
+                                cb[4 + e] <= tgt[e] < cb[4 + e] + cb[1 + e] for e in range(3)):
+                            owner = c
+                            break
+                    if owner is None:
+                        tgt = [o[e] + min(max(loc[e], 0), s[e] - 1) for e in range(3)]
+                    pad = [loc[e] + gd[e] for e in range(3)]
+                    n0, n1 = s[0] + 2 * gd[0], s[1] + 2 * gd[1]
+                    idx = G.off[b] + (pad[2] * n1 + pad[1]) * n0 + pad[0]
+                    gid = (tgt[2] * N[1] + tgt[1]) * N[0] + tgt[0] + 1e7 * l
+                    out.append((idx, gid))
+    return out
+
+
+def check_fill(params, blocks):
+    G = O.OracleGrid(params, blocks)
+    n_per_level = lambda l: [params["ncell0"][e] * 2 ** l for e in range(3)]
+    P = G.pack(global_ids(blocks, params["ndim"], n_per_level))
+    G.fill_ghosts(P)
+    exp = ghost_expectations(G, blocks, params)
+    idx = np.array([e[0] for e in exp])
+    gid = np.array([e[1] for e in exp])
+    for q in range(9):
+        assert np.array_equal(P[q, idx], gid + 1e9 * q)
+    P2 = P.copy()
+    G.fill_ghosts(P2)
+    assert np.array_equal(P, P2)       # idempotent
+    return G, P
+
+
+@pytest.mark.parametrize("bc", [I.BC_PERIODIC, I.BC_OUTFLOW])
+@pytest.mark.parametrize("layout", [((8, 8, 8), (8, 8, 8)), ((16, 8, 8), (8, 8, 8)), ((16, 16, 8), (8, 8, 8)),
+                                    ((24, 16, 8), (8, 8, 8))])
+def test_uniform_layouts(bc, layout):
+    n, bs = layout
+    p = I.base_params(nghost=3, ncell0=list(n), bc=[[bc, bc]] * 3)
+    check_fill(p, uniform_blocks(n, bs))
+
+
+def test_mixed_boundaries_2d():
+    n, bs = (32, 16, 1), (16, 8, 1)
+    p = I.base_params(ndim=2, nghost=2, ncell0=list(n), bc=[[I.BC_PERIODIC] * 2, [I.BC_OUTFLOW] * 2, [0, 0]])
+    check_fill(p, uniform_blocks(n, bs))
+
+
+def test_periodic_wrap_closed_form_single_block():
+    n = (8, 8, 8)
+    p = I.base_params(nghost=3, ncell0=list(n), bc=[[I.BC_PERIODIC] * 2] * 3)
+    blocks = uniform_blocks(n, n)
+    G = O.OracleGrid(p, blocks)
+    ids = np.arange(512, dtype=np.float64)
+    P = G.pack(np.stack([ids] * 9))
+    G.fill_ghosts(P)
+    cube = P[0].reshape(14, 14, 14)
+    w = (np.arange(14) - 3) % 8
+    K, J, Ii = np.meshgrid(w, w, w, indexing="ij")
+    assert np.array_equal(cube, (K * 64 + J * 8 + Ii).astype(np.float64))
+
+
+def test_amr_like_list():
+    c = I.case4(nblocks=48, n0=48)
+    check_fill(c.params, c.blocks)
+
+
+def test_rejects_bad_block_lists():
+    p = I.base_params(nghost=3, ncell0=[16, 16, 16])
+    with pytest.raises(ValueError):
+        O.OracleGrid(p, np.array([[0, 8, 8, 8, 4, 0, 0]], dtype=np.int32))      # misaligned origin
+    with pytest.raises(ValueError):
+        O.OracleGrid(p, np.array([[0, 8, 8, 8, 0, 0, 0]] * 2, dtype=np.int32))  # two blocks in one slot
