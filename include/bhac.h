@@ -1,0 +1,222 @@
+/*
+ * bhac.h -- C ABI of the MI355X (gfx950) GRMHD substep library.
+ *
+ * The library advances the ideal-GRMHD equations on a list of logically
+ * Cartesian blocks with ghost layers by one Runge-Kutta substep at a time. The
+ * paper's Section 2 ("Code overview") lists the method: a high-resolution
+ * shock-capturing finite-volume scheme in covariant coordinates on block-based
+ * grids, second-order time stepping, second- or third-order (PPM) reconstruction
+ * and a Newton-Raphson conserved-to-primitive inversion with backups. Section 4.2
+ * counts the work as substeps times cells ("cellupdates"); Section 4.3 names the
+ * same-level ghost-cell fill; Section 5.1 the ghost-cell exchange. The formulas
+ * the paper does not print follow the standard 3+1 form of GRMHD (described with
+ * each call).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Return value: BHAC_OK (0) or a negative BHAC_E* code; bhac_last_error()
+ *    gives a message (thread-local). No call throws. Numerical trouble inside a
+ *    cell (an inversion that does not converge) is not an error: it is flagged
+ *    and counted (bhac_get_stats).
+ *  - Device calls are asynchronous on the caller's HIP stream (`stream` is a
+ *    hipStream_t; NULL means the default stream). Only bhac_get_dt,
+ *    bhac_get_timestep and bhac_get_stats synchronise that stream.
+ *  - Ownership: the caller owns every state array (device pointers, e.g. from
+ *    PyTorch). The library owns the grid metadata (ghost maps, metric tables,
+ *    work lists, time-step state, counters); bhac_alloc_blocks allocates it and
+ *    bhac_free_blocks releases it. No per-substep call allocates memory.
+ *  - State layout (structure of arrays): an array of nvar = 9 rows, each of
+ *    ncell_padded entries. Row order for primitives P: rho, u~1, u~2, u~3 (Lorentz
+ *    factor times Eulerian 3-velocity, contravariant), p, B1, B2, B3 (Eulerian
+ *    magnetic field), psi (GLM scalar). Row order for conserved U:
+ *    sqrt(gamma) * (D, S_1, S_2, S_3, tau, B1, B2, B3), psi. Inside a row, block
+ *    b occupies [block_offset[b], block_offset[b+1]): its (size+2g)-padded box,
+ *    x fastest, then y, then z (for ndim = 2 the z extent is 1 with no ghosts).
+ *  - Precision: P is double when precision == BHAC_PREC_FP64 and float when
+ *    precision == BHAC_PREC_MIXED. U is always double.
+ */
+#ifndef BHAC_H
+#define BHAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BHAC_OK = 0,
+    BHAC_EINVAL = -1,       /* invalid argument or block list */
+    BHAC_ENOMEM = -2,       /* device or host allocation failed */
+    BHAC_EDEVICE = -3,      /* no usable GPU, or a HIP runtime error */
+    BHAC_EALIAS = -4,       /* an output aliases an input it must not alias */
+    BHAC_EUNSUPPORTED = -5  /* a valid combination this build does not implement */
+};
+enum { BHAC_METRIC_MINKOWSKI_CART = 0, BHAC_METRIC_KS_SPH_LOGR = 1 };
+enum { BHAC_BC_PERIODIC = 0, BHAC_BC_OUTFLOW = 1 };
+enum { BHAC_RECON_MC = 0, BHAC_RECON_PPM = 1 };
+enum { BHAC_FLUX_HLL = 0, BHAC_FLUX_TVDLF = 1 };
+enum { BHAC_PREC_FP64 = 0, BHAC_PREC_MIXED = 1 };
+
+/* Problem definition. Units G = c = M = 1.
+ *  metric  BHAC_METRIC_MINKOWSKI_CART: flat space, Cartesian (x, y, z).
+ *          BHAC_METRIC_KS_SPH_LOGR: stationary Kerr-Schild spacetime of spin
+ *          `spin` in coordinates (ln r, theta, phi) (Section 2: any covariant
+ *          coordinate system).
+ *  x_lo, x_hi, ncell0   level-0 domain and cells per axis; level l has
+ *          ncell0 * 2^l cells per axis.
+ *  bc[d][side]          BHAC_BC_PERIODIC (both sides) or BHAC_BC_OUTFLOW.
+ *  recon, flux          MC or PPM reconstruction (Section 2); HLL or TVDLF flux.
+ *  precision            BHAC_PREC_FP64: everything in double.
+ *                       BHAC_PREC_MIXED: P stored in float; reconstruction, face
+ *                       fluxes and their divergence in float; metric, sources,
+ *                       the RK accumulation (compensated) and the inversion in
+ *                       double.
+ *  fused                0: bhac_substep reads P_stage ghost slots, which must be
+ *                       filled first by bhac_fill_ghosts.
+ *                       1: one persistent kernel per substep gathers each
+ *                       block's ghost halo itself (P ghost slots are not read
+ *                       and not written).
+ *  cfl                  Courant number C of dt = C / sum_d (lambda_d / dx_d).
+ *  rho_floor, p_floor, w_max   floors applied after a converged inversion.
+ *  glm_alpha            GLM damping: kappa = glm_alpha * c_h / min_d dx_d.
+ *  c2p_tol, c2p_maxit   Newton stopping tolerance on |dxi|/xi and iteration cap.
+ */
+typedef struct bhac_params {
+    int ndim;           /* 2 or 3 */
+    int nghost;         /* >= 2 for MC, >= 3 for PPM */
+    int metric;
+    double spin;
+    double gamma_ad;    /* ideal-gas adiabatic index */
+    double x_lo[3], x_hi[3];
+    int ncell0[3];
+    int bc[3][2];
+    int recon, flux, precision, fused;
+    double cfl, rho_floor, p_floor, w_max, glm_alpha, c2p_tol;
+    int c2p_maxit;
+} bhac_params;
+
+/* One block: refinement level, interior cells per axis, and origin in level-l
+ * cells. Blocks of one (level, size) must sit on that size's lattice
+ * (origin % size == 0) and must not overlap. */
+typedef struct bhac_block_desc {
+    int level;
+    int size[3];
+    int origin[3];
+} bhac_block_desc;
+
+/* Layout of the state arrays, filled by bhac_alloc_blocks. block_offset points
+ * to nblocks + 1 host entries owned by the grid (valid until bhac_free_blocks). */
+typedef struct bhac_layout {
+    int64_t ncell_padded;
+    int64_t ncell_interior;
+    int nvar;
+    int nghost;
+    const int64_t *block_offset;
+} bhac_layout;
+
+/* Time-step state as the device holds it. dt, ch and kappa belong to the step in
+ * progress; dt_next is what the next step will use; lam[d] is the largest
+ * |characteristic speed| along d seen by the last finished substep. */
+typedef struct bhac_timestep {
+    double dt, dt_next, ch, kappa;
+    double lam[3];
+} bhac_timestep;
+
+typedef struct bhac_grid bhac_grid;
+
+/* Build a grid on the current HIP device (Sections 2 and 4.3: blocks of cells
+ * with ghost layers). Validates the parameters and the block list, builds the
+ * same-level ghost gather map, the block neighbour tables, the FP64 metric
+ * tables and the work lists, copies them to the device and returns the handle
+ * and the state layout. Host-side cost is O(number of ghost cells).
+ * Errors: BHAC_EINVAL (bad params or blocks; *out untouched), BHAC_ENOMEM,
+ * BHAC_EDEVICE. */
+int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, int64_t nblocks,
+                      bhac_grid **out, bhac_layout *layout);
+
+/* Release the grid and its device memory (synchronises the device). NULL is a no-op. */
+int bhac_free_blocks(bhac_grid *grid);
+
+/* Same-level ghost-cell fill (Section 4.3's same-refinement-level fill): every
+ * ghost slot of every block receives, bit for bit, all 9 primitives of one
+ * interior cell. Rule per ghost slot at global level-l index G: wrap periodic
+ * axes, clamp outflow axes to the domain; if a block of the same level and size
+ * holds that cell, copy it; otherwise copy the own block's interior cell
+ * nearest to the slot (zero-gradient). prim: device, [9][ncell_padded], double
+ * or float per precision; written in ghost slots only. */
+int bhac_fill_ghosts(bhac_grid *grid, void *prim, void *stream);
+
+/* Primitive -> conserved at interior cells (Section 2's integrated conserved
+ * variables): W = sqrt(1 + gamma_ij u~^i u~^j), v^i = u~^i / W,
+ * xi = rho h W^2 with h = 1 + Gamma/(Gamma-1) p/rho, D = rho W,
+ * S_i = (xi + B^2) v_i - (B.v) B_i, tau = xi + B^2 - p - ((B.v)^2 + B^2/W^2)/2 - D,
+ * all densitised by sqrt(gamma); psi copied. cons: device double [9][ncell_padded]. */
+int bhac_prim2con(bhac_grid *grid, const void *prim, double *cons, void *stream);
+
+/* Conserved -> primitive at interior cells (Section 2: Newton-Raphson with a
+ * backup). One-dimensional Newton iteration on xi = rho h W^2 started from the
+ * primitives already in prim_inout, safeguarded by halving the step towards the
+ * previous iterate while xi <= 0 or v^2 >= 1; stops when |dxi| <= c2p_tol * xi,
+ * then takes one more step. Then floors on rho, p and W. On failure (no
+ * convergence in c2p_maxit steps, non-finite values, rho <= 0 or p < 0) the
+ * cell keeps its input primitives and fail[cell] = 1, else 0. fail: device
+ * int8 [ncell_padded], may be NULL. cons is not modified. */
+int bhac_con2prim(bhac_grid *grid, const double *cons, void *prim_inout, int8_t *fail, void *stream);
+
+/* One Runge-Kutta substep (Section 2's second-order time stepping; Section 4.2's
+ * unit of work): for every interior cell,
+ *   U_out = a U_base + b (U_stage + dt L),
+ *   L = -sum_d (F_d(i+1/2) - F_d(i-1/2)) / dx_d + S,
+ * with F the face fluxes from reconstructed P_stage (MC or PPM), an exact solve
+ * of the GLM (B~_normal, psi) subsystem and HLL or TVDLF for the rest, and S the
+ * geometric sources of the stationary metric plus GLM damping -kappa psi; then
+ * P_out = inversion of U_out started from P_stage (floors and backup as in
+ * bhac_con2prim; cells that hit a floor or the backup get U_out rewritten from
+ * P_out). SSP-RK2 is (a, b) = (0, 1) then (1/2, 1/2) with U_stage = U_base in
+ * the first stage.
+ * Time step: a substep with a == 0 starts a step and latches dt (and c_h, kappa)
+ * from the previous substep's wave speeds; every substep records its own maximum
+ * |lambda| per direction for the next latch. Call bhac_compute_dt or bhac_set_dt
+ * once before the first substep (else BHAC_EINVAL).
+ * Aliasing: U_out may alias U_base and/or U_stage; P_out must not alias P_stage
+ * (BHAC_EALIAS). P_out ghost slots are left unchanged. */
+int bhac_substep(bhac_grid *grid, const double *U_base, const double *U_stage, const void *P_stage,
+                 double *U_out, void *P_out, double a, double b, void *stream);
+
+/* Standalone wave-speed reduction over cell-centred states of prim (interior
+ * cells): sets dt_next = C / sum_d (lambda_d / dx_d), dx on the finest level. */
+int bhac_compute_dt(bhac_grid *grid, const void *prim, void *stream);
+
+/* dt > 0: every following step uses this fixed dt (and the c_h, kappa that
+ * follow from it). dt == 0: back to the CFL time step (which needs a wave-speed
+ * reduction first). dt < 0: BHAC_EINVAL. */
+int bhac_set_dt(bhac_grid *grid, double dt, void *stream);
+
+/* Host copy of dt_next (synchronises the stream given to the last call). */
+int bhac_get_dt(bhac_grid *grid, double *dt_host);
+
+/* Host copy of the whole time-step state (synchronises). */
+int bhac_get_timestep(bhac_grid *grid, bhac_timestep *out);
+
+/* Inversion statistics accumulated since alloc or the last reset: failed cells,
+ * floored cells and the largest Newton step count (synchronises). Any pointer
+ * may be NULL. */
+int bhac_get_stats(bhac_grid *grid, int64_t *c2p_fail, int64_t *floor_hits, int *max_iter);
+int bhac_reset_stats(bhac_grid *grid, void *stream);
+
+/* Host-only planning, no GPU needed: validates params and blocks and returns
+ * the layout offsets (nblocks + 1 entries, may be NULL) and the ghost gather
+ * map the library would use: *nslots ghost slots with destination and source
+ * padded-cell indices (dst/src may be NULL to query *nslots first). */
+int bhac_plan_ghosts(const bhac_params *params, const bhac_block_desc *blocks, int64_t nblocks,
+                     int64_t *block_offset, int64_t *nslots, int32_t *dst, int32_t *src);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *bhac_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BHAC_H */

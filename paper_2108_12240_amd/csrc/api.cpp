@@ -1,0 +1,334 @@
+// C ABI of the GRMHD substep library: argument checks, device memory of a grid,
+// and dispatch to the kernel launchers. No exception crosses this boundary.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "device.h"
+
+struct bhac_grid {
+    bhac::DeviceGrid dg;
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return BHAC_EDEVICE;
+}
+
+template <typename T>
+hipError_t upload(T **dst, const T *src, size_t n)
+{
+    *dst = nullptr;
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMalloc((void **)dst, n * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void release(bhac::DeviceGrid &G)
+{
+    void *ptrs[] = {G.d_blocks, G.d_levels, G.d_ctab, G.d_f0tab, G.d_f1tab, G.d_state, G.d_wcell,
+                    G.d_wface[0], G.d_wface[1], G.d_wface[2], G.d_gdst, G.d_gsrc, G.d_nbr, G.d_halo,
+                    G.d_flux[0], G.d_flux[1], G.d_flux[2]};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+int check_grid(bhac_grid *g)
+{
+    if (!g) return fail(BHAC_EINVAL, "null grid");
+    return BHAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bhac_last_error(void) { return g_err.c_str(); }
+
+int bhac_plan_ghosts(const bhac_params *params, const bhac_block_desc *blocks, int64_t nblocks, int64_t *block_offset,
+                     int64_t *nslots, int32_t *dst, int32_t *src)
+{
+    try {
+        bhac::Plan P;
+        std::string err;
+        const int rc = bhac::make_plan(params, blocks, nblocks, false, P, err);
+        if (rc != BHAC_OK) return fail(rc, err);
+        if (block_offset) std::memcpy(block_offset, P.off.data(), P.off.size() * sizeof(int64_t));
+        if (nslots) *nslots = (int64_t)P.gdst.size();
+        if (dst) std::memcpy(dst, P.gdst.data(), P.gdst.size() * sizeof(int32_t));
+        if (src) std::memcpy(src, P.gsrc.data(), P.gsrc.size() * sizeof(int32_t));
+        return BHAC_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(BHAC_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(BHAC_EINVAL, "planning failed");
+    }
+}
+
+int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, int64_t nblocks, bhac_grid **out,
+                      bhac_layout *layout)
+{
+    if (!out) return fail(BHAC_EINVAL, "null output handle");
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) return fail(BHAC_EDEVICE, "no HIP device available");
+    bhac_grid *g = nullptr;
+    try {
+        g = new bhac_grid();
+    } catch (...) {
+        return fail(BHAC_ENOMEM, "host allocation failed");
+    }
+    bhac::DeviceGrid &G = g->dg;
+    try {
+        std::string err;
+        const int rc = bhac::make_plan(params, blocks, nblocks, true, G.plan, err);
+        if (rc != BHAC_OK) {
+            delete g;
+            return fail(rc, err);
+        }
+    } catch (const std::bad_alloc &) {
+        delete g;
+        return fail(BHAC_ENOMEM, "host allocation failed");
+    }
+    if (params->fused) {
+        delete g;
+        return fail(BHAC_EUNSUPPORTED, "fused substep is not available in this build");
+    }
+    const bhac::Plan &P = G.plan;
+    const bhac_params &p = P.p;
+    (void)hipGetDevice(&G.device);
+    G.ks = p.metric == BHAC_METRIC_KS_SPH_LOGR;
+    G.mixed = p.precision == BHAC_PREC_MIXED;
+    bhac::KParams &kp = G.kp;
+    kp.gam = p.gamma_ad;
+    kp.gfac = p.gamma_ad / (p.gamma_ad - 1.0);
+    kp.gfac_inv = (p.gamma_ad - 1.0) / p.gamma_ad;
+    kp.rho_floor = p.rho_floor;
+    kp.p_floor = p.p_floor;
+    kp.w_max = p.w_max;
+    kp.c2p_tol = p.c2p_tol;
+    kp.c2p_maxit = p.c2p_maxit;
+    kp.cfl = p.cfl;
+    kp.glm_alpha = p.glm_alpha;
+    kp.ndim = p.ndim;
+    kp.recon = p.recon;
+    kp.flux = p.flux;
+    for (int d = 0; d < 3; d++) kp.g[d] = P.gd[d];
+    kp.ncp = P.off.back();
+    const bhac::DevLevel &fine = P.levels[P.maxlevel];
+    kp.sinv_fine = 0.0;
+    kp.dmin_fine = 1e300;
+    for (int d = 0; d < 3; d++) kp.inv_dx_fine[d] = 0.0;
+    for (int d = 0; d < p.ndim; d++) {
+        kp.sinv_fine += 1.0 / fine.dx[d];
+        kp.dmin_fine = fine.dx[d] < kp.dmin_fine ? fine.dx[d] : kp.dmin_fine;
+        kp.inv_dx_fine[d] = 1.0 / fine.dx[d];
+    }
+
+#define UP(dst, vec)                                                    \
+    do {                                                                \
+        e = upload(&(dst), (vec).data(), (vec).size());                 \
+        if (e != hipSuccess) goto hip_error;                            \
+    } while (0)
+    UP(G.d_blocks, P.dblocks);
+    UP(G.d_levels, P.levels);
+    UP(G.d_ctab, P.ctab);
+    UP(G.d_f0tab, P.f0tab);
+    UP(G.d_f1tab, P.f1tab);
+    UP(G.d_wcell, P.wcell);
+    for (int d = 0; d < 3; d++) UP(G.d_wface[d], P.wface[d]);
+    UP(G.d_gdst, P.gdst);
+    UP(G.d_gsrc, P.gsrc);
+    UP(G.d_nbr, P.nbr);
+    UP(G.d_halo, P.halo);
+#undef UP
+    G.nghost_slots = (long long)P.gdst.size();
+    {
+        const size_t rsz = G.mixed ? sizeof(float) : sizeof(double);
+        for (int d = 0; d < p.ndim; d++) {
+            e = hipMalloc(&G.d_flux[d], (size_t)bhac::NV * P.nface[d] * rsz);
+            if (e != hipSuccess) goto hip_error;
+        }
+        e = hipMalloc((void **)&G.d_state, sizeof(bhac::DevState));
+        if (e != hipSuccess) goto hip_error;
+        e = hipMemset(G.d_state, 0, sizeof(bhac::DevState));
+        if (e != hipSuccess) goto hip_error;
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) goto hip_error;
+    }
+    G.gd.blocks = G.d_blocks;
+    G.gd.levels = G.d_levels;
+    G.gd.ctab = G.d_ctab;
+    G.gd.f0tab = G.d_f0tab;
+    G.gd.f1tab = G.d_f1tab;
+    G.gd.nrec_c = P.nrec_c;
+    G.gd.nrec_f0 = P.nrec_f0;
+    G.gd.nrec_f1 = P.nrec_f1;
+    G.gd.st = G.d_state;
+    G.gd.nbr = G.d_nbr;
+    G.gd.halo = G.d_halo;
+    G.gd.hmax = P.hmax;
+    if (layout) {
+        layout->ncell_padded = P.off.back();
+        layout->ncell_interior = P.ncell_interior;
+        layout->nvar = bhac::NV;
+        layout->nghost = p.nghost;
+        layout->block_offset = P.off.data();
+    }
+    *out = g;
+    return BHAC_OK;
+hip_error:
+    {
+        const int rc = e == hipErrorOutOfMemory ? fail(BHAC_ENOMEM, "device allocation failed")
+                                                : hip_fail(e, "bhac_alloc_blocks");
+        release(G);
+        delete g;
+        return rc;
+    }
+}
+
+int bhac_free_blocks(bhac_grid *g)
+{
+    if (!g) return BHAC_OK;
+    (void)hipDeviceSynchronize();
+    release(g->dg);
+    delete g;
+    return BHAC_OK;
+}
+
+int bhac_fill_ghosts(bhac_grid *g, void *prim, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!prim) return fail(BHAC_EINVAL, "null prim");
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_fill(g->dg, prim, (hipStream_t)stream);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_fill_ghosts");
+}
+
+int bhac_prim2con(bhac_grid *g, const void *prim, double *cons, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!prim || !cons) return fail(BHAC_EINVAL, "null array");
+    if ((const void *)cons == prim) return fail(BHAC_EALIAS, "cons aliases prim");
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_prim2con(g->dg, prim, cons, (hipStream_t)stream);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_prim2con");
+}
+
+int bhac_con2prim(bhac_grid *g, const double *cons, void *prim_inout, int8_t *failflags, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!prim_inout || !cons) return fail(BHAC_EINVAL, "null array");
+    if ((const void *)cons == prim_inout) return fail(BHAC_EALIAS, "cons aliases prim");
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_con2prim(g->dg, cons, prim_inout, failflags, (hipStream_t)stream);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_con2prim");
+}
+
+int bhac_substep(bhac_grid *g, const double *U_base, const double *U_stage, const void *P_stage, double *U_out,
+                 void *P_out, double a, double b, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!U_base || !U_stage || !P_stage || !U_out || !P_out) return fail(BHAC_EINVAL, "null array");
+    if (P_out == P_stage) return fail(BHAC_EALIAS, "P_out aliases P_stage");
+    if ((const void *)U_out == P_stage || (void *)U_out == P_out || (const void *)U_base == P_out ||
+        (const void *)U_stage == P_out)
+        return fail(BHAC_EALIAS, "a conserved array aliases a primitive array");
+    if (!(a >= 0.0) || !(b > 0.0)) return fail(BHAC_EINVAL, "need a >= 0 and b > 0");
+    if (!g->dg.have_dt) return fail(BHAC_EINVAL, "time step not initialised: call bhac_compute_dt or bhac_set_dt");
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_substep(g->dg, U_base, U_stage, P_stage, U_out, P_out, a, b, (hipStream_t)stream);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_substep");
+}
+
+int bhac_compute_dt(bhac_grid *g, const void *prim, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!prim) return fail(BHAC_EINVAL, "null prim");
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_compute_dt(g->dg, prim, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "bhac_compute_dt");
+    g->dg.have_dt = true;
+    return BHAC_OK;
+}
+
+int bhac_set_dt(bhac_grid *g, double dt, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!(dt >= 0.0)) return fail(BHAC_EINVAL, "dt must be >= 0");
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_set_dt(g->dg, dt, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "bhac_set_dt");
+    if (dt > 0.0) g->dg.have_dt = true;
+    return BHAC_OK;
+}
+
+static int read_state(bhac_grid *g, bhac::DevState &st)
+{
+    hipError_t e = hipStreamSynchronize(g->last_stream);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronise");
+    e = hipMemcpy(&st, g->dg.d_state, sizeof st, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "state copy");
+    return BHAC_OK;
+}
+
+int bhac_get_dt(bhac_grid *g, double *dt_host)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!dt_host) return fail(BHAC_EINVAL, "null output");
+    bhac::DevState st;
+    if (int rc = read_state(g, st)) return rc;
+    *dt_host = st.dt_next;
+    return BHAC_OK;
+}
+
+int bhac_get_timestep(bhac_grid *g, bhac_timestep *out)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!out) return fail(BHAC_EINVAL, "null output");
+    bhac::DevState st;
+    if (int rc = read_state(g, st)) return rc;
+    out->dt = st.dt;
+    out->dt_next = st.dt_next;
+    out->ch = st.ch;
+    out->kappa = st.kappa;
+    for (int d = 0; d < 3; d++) out->lam[d] = st.lam_last[d];
+    return BHAC_OK;
+}
+
+int bhac_get_stats(bhac_grid *g, int64_t *c2p_fail, int64_t *floor_hits, int *max_iter)
+{
+    if (int rc = check_grid(g)) return rc;
+    bhac::DevState st;
+    if (int rc = read_state(g, st)) return rc;
+    if (c2p_fail) *c2p_fail = (int64_t)st.c2p_fail;
+    if (floor_hits) *floor_hits = (int64_t)st.floor_hits;
+    if (max_iter) *max_iter = st.max_iter;
+    return BHAC_OK;
+}
+
+int bhac_reset_stats(bhac_grid *g, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_reset_stats(g->dg, (hipStream_t)stream);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_reset_stats");
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal declarations of the GRMHD substep library (host planning <-> kernels <-> C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bhac.h"
+
+namespace bhac {
+
+constexpr int NV = 9;
+constexpr int WG = 256;          // work-group size of the unfused kernels (4 wave64)
+
+// Per-block description as the kernels see it.
+struct DevBlock {
+    long long off;               // first padded cell of the block in every state row
+    long long fofs[3];           // first face of the block in each direction's face array
+    int s[3];                    // interior cells per axis
+    int o[3];                    // origin in level cells
+    int n0, n1;                  // padded extents along x and y
+    int level;
+    int pad;
+};
+
+// Per-level constants. Metric tables are 2-D in (x1, x2) because both supported
+// metrics are independent of x3; records are stored field-major (SoA).
+struct DevLevel {
+    double dx[3], inv_dx[3];
+    long long ctab;              // first record of the centre table of this level
+    long long f0tab, f1tab;      // first record of the x1-face and x2-face tables
+    int N0, N1;                  // cells along x1 and x2 on this level
+    int pad[2];
+};
+
+// Centre-table fields. The first C_FACE_NF fields double as the face-table fields.
+enum CField {
+    C_ALPHA, C_BETA1, C_G11, C_G13, C_G22, C_G33, C_GI11, C_GI13, C_GI22, C_GI33, C_SG,
+    C_DA1, C_DA2, C_DB1, C_DB2, C_DG11_1, C_DG11_2, C_DG13_1, C_DG13_2, C_DG22_1, C_DG22_2,
+    C_DG33_1, C_DG33_2, C_NF
+};
+constexpr int C_FACE_NF = C_SG + 1;
+
+struct WorkItem { int block; int start; };
+
+// Fused-kernel halo addressing: for each block and axis, the source of every
+// padded local index l in [-g, s+g): which neighbour direction (-1, 0, +1) its
+// lattice slot lies in, and the local index to read there.
+struct HaloAxis { signed char dir; signed char pad; short src; };
+
+struct Plan {
+    bhac_params p{};
+    std::vector<bhac_block_desc> blocks;
+    std::vector<int64_t> off;            // padded offsets, nb + 1
+    int64_t ncell_interior = 0;
+    std::vector<DevBlock> dblocks;
+    std::vector<DevLevel> levels;        // indexed by level
+    int maxlevel = 0;
+    int gd[3] = {0, 0, 0};               // ghost layers per axis
+    std::vector<int32_t> gdst, gsrc;     // same-level ghost gather map
+    // metric tables (empty for flat space)
+    long long nrec_c = 0, nrec_f0 = 0, nrec_f1 = 0;
+    std::vector<double> ctab, f0tab, f1tab;
+    // work lists (one entry per work-group of WG items inside one block)
+    std::vector<WorkItem> wcell, wface[3];
+    long long nface[3] = {0, 0, 0};
+    // fused-kernel neighbour data
+    std::vector<int32_t> nbr;            // 27 per block: block id of neighbour slot (dir+1 base 3), -1 if none
+    std::vector<HaloAxis> halo;          // per block: 3 axes x hmax entries
+    int hmax = 0;                        // max padded extent over axes and blocks
+    int smax[3] = {0, 0, 0};             // max interior size per axis
+};
+
+// Validate and build everything the device needs. tables == false skips the
+// metric tables (host-only planning). Returns a BHAC_* code; err gets a message.
+int make_plan(const bhac_params *p, const bhac_block_desc *blocks, int64_t nb, bool tables, Plan &out,
+              std::string &err);
+
+}  // namespace bhac

@@ -1,0 +1,464 @@
+// Unfused kernels of the GRMHD substep for gfx950 (wave64), plus the pointwise
+// kernels (ghost fill, prim2con, con2prim, wave-speed reduction) and their launchers.
+//
+// Unfused substep = ghost fill (separate call) -> one face-flux kernel per direction
+// (reconstruct P_stage at the face, GLM + HLL/TVDLF, |lambda| max) -> one update
+// kernel per interior cell (flux divergence, sources, RK combine, inversion).
+// State rows are structure-of-arrays, so every load and store below is coalesced
+// along x inside a block.
+#include <hip/hip_runtime.h>
+
+#include "physics.h"
+
+namespace bhac {
+
+// ---------------------------------------------------------------------------------
+// Ghost fill: one thread per ghost slot copies the 9 rows (bit-exact copies).
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(WG) void k_fill(const int32_t *__restrict__ dst, const int32_t *__restrict__ src,
+                                             long long n, T *__restrict__ P, long long ncp)
+{
+    const long long i = (long long)blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    const long long d = dst[i], s = src[i];
+#pragma unroll
+    for (int v = 0; v < NV; v++) P[v * ncp + d] = P[v * ncp + s];
+}
+
+// cell (i, j, k) of a work item: returns false for the tail threads
+__device__ __forceinline__ bool cell_of(const DevBlock &B, int item, int &i, int &j, int &k)
+{
+    const int nc = B.s[0] * B.s[1] * B.s[2];
+    if (item >= nc) return false;
+    i = item % B.s[0];
+    const int t = item / B.s[0];
+    j = t % B.s[1];
+    k = t / B.s[1];
+    return true;
+}
+
+__device__ __forceinline__ long long pad_index(const DevBlock &B, const KParams &kp, int i, int j, int k)
+{
+    return B.off + ((long long)(k + kp.g[2]) * B.n1 + (j + kp.g[1])) * B.n0 + (i + kp.g[0]);
+}
+
+template <bool KS>
+__device__ __forceinline__ CentM centre_metric(const GridDev &gd, const DevBlock &B, int i, int j)
+{
+    if constexpr (!KS) {
+        return load_centre_metric<false>(nullptr, 0, 0);
+    } else {
+        const DevLevel &L = gd.levels[B.level];
+        const long long r = L.ctab + (long long)(B.o[1] + j) * L.N0 + (B.o[0] + i);
+        return load_centre_metric<true>(gd.ctab, gd.nrec_c, r);
+    }
+}
+
+template <typename R, int D, bool KS>
+__device__ __forceinline__ FaceM<R> face_metric(const GridDev &gd, const DevBlock &B, int i, int j)
+{
+    if constexpr (!KS) {
+        return load_face_metric<R, false>(nullptr, 0, 0);
+    } else {
+        const DevLevel &L = gd.levels[B.level];
+        const int gi = B.o[0] + i, gj = B.o[1] + j;
+        if constexpr (D == 0) return load_face_metric<R, true>(gd.f0tab, gd.nrec_f0, L.f0tab + (long long)gj * (L.N0 + 1) + gi);
+        else if constexpr (D == 1) return load_face_metric<R, true>(gd.f1tab, gd.nrec_f1, L.f1tab + (long long)gj * L.N0 + gi);
+        else return load_face_metric<R, true>(gd.ctab, gd.nrec_c, L.ctab + (long long)gj * L.N0 + gi);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Face fluxes along D: one thread per face of a block (faces 0..s_D along D).
+// ---------------------------------------------------------------------------------
+template <typename R, int D, int RECON, int FLUX, bool KS>
+__global__ __launch_bounds__(WG) void k_flux(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+                                             const R *__restrict__ P, R *__restrict__ F, long long nftot)
+{
+    __shared__ double red[WG / 64];
+    const WorkItem w = work[blockIdx.x];
+    const DevBlock B = gd.blocks[w.block];
+    const int fs0 = B.s[0] + (D == 0), fs1 = B.s[1] + (D == 1), fs2 = B.s[2] + (D == 2);
+    const int item = w.start + threadIdx.x;
+    double lam = 0.0;
+    if (item < fs0 * fs1 * fs2) {
+        const int i = item % fs0;
+        const int t = item / fs0;
+        const int j = t % fs1;
+        const int k = t / fs1;
+        const long long pc = pad_index(B, kp, i, j, k);
+        const long long st = D == 0 ? 1 : (D == 1 ? (long long)B.n0 : (long long)B.n0 * B.n1);
+        R qL[NV], qR[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const R *row = P + v * kp.ncp + pc;
+            R q[6];
+            if constexpr (RECON == BHAC_RECON_PPM) {
+#pragma unroll
+                for (int s = 0; s < 6; s++) q[s] = row[(s - 3) * st];
+            } else {
+                q[0] = q[5] = R(0);
+#pragma unroll
+                for (int s = 1; s < 5; s++) q[s] = row[(s - 3) * st];
+            }
+            recon_face<R, RECON>(q, qL[v], qR[v]);
+        }
+        const FaceM<R> m = face_metric<R, D, KS>(gd, B, i, j);
+        const R ch = (R)gd.st->ch;
+        R Ff[NV];
+        lam = (double)face_flux<R, D, FLUX>(qL, qR, m, ch, (R)kp.gam, (R)kp.gfac, Ff);
+        R *out = F + B.fofs[D] + item;
+#pragma unroll
+        for (int v = 0; v < NV; v++) out[v * nftot] = Ff[v];
+    }
+    const double m = wg_max<WG>(lam, red);
+    if (threadIdx.x == 0) atomicMax(&gd.st->lam_acc[D], (unsigned long long)__double_as_longlong(m));
+}
+
+// ---------------------------------------------------------------------------------
+// Update: divergence (in R), sources, RK combine (double), inversion (double).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+template <typename R, bool KS>
+__global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+                                               const double *Ub, const double *Us, const R *__restrict__ Ps,
+                                               double *Uo, R *__restrict__ Po, const R *__restrict__ F0,
+                                               const R *__restrict__ F1, const R *__restrict__ F2, long long nf0,
+                                               long long nf1, long long nf2, double a, double b)
+{
+    __shared__ long long redl[WG / 64];
+    __shared__ int redi[WG / 64];
+    const WorkItem w = work[blockIdx.x];
+    const DevBlock B = gd.blocks[w.block];
+    int i, j, k;
+    int fail = 0, floored = 0, nit = 0;
+    if (cell_of(B, w.start + threadIdx.x, i, j, k)) {
+        const long long c = pad_index(B, kp, i, j, k);
+        const DevLevel &L = gd.levels[B.level];
+        // flux divergence, summed with a compensation term (Neumaier) in double
+        double sum = 0.0, comp = 0.0;
+        double Lv[NV];
+        const R *Fd[3] = {F0, F1, F2};
+        const long long nf[3] = {nf0, nf1, nf2};
+        double div[3][NV];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            if (d >= kp.ndim) {
+#pragma unroll
+                for (int v = 0; v < NV; v++) div[d][v] = 0.0;
+                continue;
+            }
+            const int fs0 = B.s[0] + (d == 0), fs1 = B.s[1] + (d == 1);
+            const long long lo = B.fofs[d] + ((long long)k * fs1 + j) * fs0 + i;
+            const long long hi = lo + (d == 0 ? 1 : (d == 1 ? fs0 : (long long)fs0 * fs1));
+            const R idx = (R)L.inv_dx[d];
+#pragma unroll
+            for (int v = 0; v < NV; v++) div[d][v] = (double)((Fd[d][v * nf[d] + hi] - Fd[d][v * nf[d] + lo]) * idx);
+        }
+        double q[NV], Uc[NV], S[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            q[v] = (double)Ps[v * kp.ncp + c];
+            Uc[v] = Us[v * kp.ncp + c];
+        }
+        const CentM m = centre_metric<KS>(gd, B, i, j);
+        const double dt = gd.st->dt, kappa = gd.st->kappa;
+        geometric_sources(q, Uc, m, kappa, S);
+        double Un[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            // L = -(div_0 + div_1 + div_2) + S with Neumaier compensation
+            sum = -div[0][v];
+            comp = 0.0;
+#pragma unroll
+            for (int d = 1; d < 3; d++) {
+                const double t = sum - div[d][v];
+                comp += fabs(sum) >= fabs(div[d][v]) ? (sum - t) - div[d][v] : (-div[d][v] - t) + sum;
+                sum = t;
+            }
+            {
+                const double t = sum + S[v];
+                comp += fabs(sum) >= fabs(S[v]) ? (sum - t) + S[v] : (S[v] - t) + sum;
+                sum = t;
+            }
+            Lv[v] = sum + comp;
+            // U_out = a U_base + b (U_stage + dt L): the stage sum as an exact pair
+            double s, e;
+            two_sum(Uc[v], dt * Lv[v], s, e);
+            Un[v] = a * Ub[v * kp.ncp + c] + (b * s + b * e);
+        }
+        double Pn[NV];
+        fail = con_to_prim(Un, q, m, kp, Pn, nit, floored);
+        if (fail || floored) prim_to_cons(Pn, m, kp.gfac, Un);
+        floored = fail ? 0 : floored;
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            Uo[v * kp.ncp + c] = Un[v];
+            Po[v * kp.ncp + c] = (R)Pn[v];
+        }
+    }
+    const long long nfail = wg_sum<WG>(fail, redl);
+    const long long nfl = wg_sum<WG>(floored, redl);
+    const int mit = wg_imax<WG>(nit, redi);
+    if (threadIdx.x == 0) {
+        if (nfail) atomicAdd(&gd.st->c2p_fail, (unsigned long long)nfail);
+        if (nfl) atomicAdd(&gd.st->floor_hits, (unsigned long long)nfl);
+        if (mit) atomicMax(&gd.st->max_iter, mit);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Pointwise kernels.
+// ---------------------------------------------------------------------------------
+template <typename R, bool KS>
+__global__ __launch_bounds__(WG) void k_prim2con(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+                                                 const R *__restrict__ P, double *__restrict__ U)
+{
+    const WorkItem w = work[blockIdx.x];
+    const DevBlock B = gd.blocks[w.block];
+    int i, j, k;
+    if (!cell_of(B, w.start + threadIdx.x, i, j, k)) return;
+    const long long c = pad_index(B, kp, i, j, k);
+    double q[NV], Uc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) q[v] = (double)P[v * kp.ncp + c];
+    prim_to_cons(q, centre_metric<KS>(gd, B, i, j), kp.gfac, Uc);
+#pragma unroll
+    for (int v = 0; v < NV; v++) U[v * kp.ncp + c] = Uc[v];
+}
+
+template <typename R, bool KS>
+__global__ __launch_bounds__(WG) void k_con2prim(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+                                                 const double *__restrict__ U, R *__restrict__ P,
+                                                 int8_t *__restrict__ flags)
+{
+    __shared__ long long redl[WG / 64];
+    __shared__ int redi[WG / 64];
+    const WorkItem w = work[blockIdx.x];
+    const DevBlock B = gd.blocks[w.block];
+    int i, j, k;
+    int fail = 0, floored = 0, nit = 0;
+    if (cell_of(B, w.start + threadIdx.x, i, j, k)) {
+        const long long c = pad_index(B, kp, i, j, k);
+        double q[NV], Uc[NV], Pn[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            q[v] = (double)P[v * kp.ncp + c];
+            Uc[v] = U[v * kp.ncp + c];
+        }
+        fail = con_to_prim(Uc, q, centre_metric<KS>(gd, B, i, j), kp, Pn, nit, floored);
+        floored = fail ? 0 : floored;
+#pragma unroll
+        for (int v = 0; v < NV; v++) P[v * kp.ncp + c] = (R)Pn[v];
+        if (flags) flags[c] = (int8_t)fail;
+    }
+    const long long nfail = wg_sum<WG>(fail, redl);
+    const long long nfl = wg_sum<WG>(floored, redl);
+    const int mit = wg_imax<WG>(nit, redi);
+    if (threadIdx.x == 0) {
+        if (nfail) atomicAdd(&gd.st->c2p_fail, (unsigned long long)nfail);
+        if (nfl) atomicAdd(&gd.st->floor_hits, (unsigned long long)nfl);
+        if (mit) atomicMax(&gd.st->max_iter, mit);
+    }
+}
+
+template <typename R, bool KS>
+__global__ __launch_bounds__(WG) void k_cell_speeds(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+                                                    const R *__restrict__ P)
+{
+    __shared__ double red[WG / 64];
+    const WorkItem w = work[blockIdx.x];
+    const DevBlock B = gd.blocks[w.block];
+    int i, j, k;
+    double lam[3] = {0.0, 0.0, 0.0};
+    if (cell_of(B, w.start + threadIdx.x, i, j, k)) {
+        const long long c = pad_index(B, kp, i, j, k);
+        double q[NV], dummy[NV], lm, lp;
+#pragma unroll
+        for (int v = 0; v < NV; v++) q[v] = (double)P[v * kp.ncp + c];
+        const FaceM<double> m = centre_as_face(centre_metric<KS>(gd, B, i, j));
+        face_state<double, 0, false>(q, m, kp.gam, kp.gfac, dummy, dummy, lm, lp);
+        lam[0] = fmax(fabs(lm), fabs(lp));
+        face_state<double, 1, false>(q, m, kp.gam, kp.gfac, dummy, dummy, lm, lp);
+        lam[1] = fmax(fabs(lm), fabs(lp));
+        if (kp.ndim == 3) {
+            face_state<double, 2, false>(q, m, kp.gam, kp.gfac, dummy, dummy, lm, lp);
+            lam[2] = fmax(fabs(lm), fabs(lp));
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const double mx = wg_max<WG>(lam[d], red);
+        if (threadIdx.x == 0) atomicMax(&gd.st->lam_acc[d], (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Time-step bookkeeping (single thread).
+// ---------------------------------------------------------------------------------
+__global__ void k_begin(KParams kp, DevState *st, int latch)
+{
+    if (latch) {
+        st->dt = st->dt_fixed > 0.0 ? st->dt_fixed : st->dt_next;
+        st->ch = kp.cfl / (st->dt * kp.sinv_fine);
+        st->kappa = kp.glm_alpha * st->ch / kp.dmin_fine;
+    }
+    st->lam_acc[0] = st->lam_acc[1] = st->lam_acc[2] = 0ull;
+}
+
+__global__ void k_end(KParams kp, DevState *st)
+{
+    double s = 0.0;
+    for (int d = 0; d < kp.ndim; d++) {
+        const double l = __longlong_as_double((long long)st->lam_acc[d]);
+        st->lam_last[d] = l;
+        s += l * kp.inv_dx_fine[d];
+    }
+    st->dt_next = st->dt_fixed > 0.0 ? st->dt_fixed : kp.cfl / s;
+}
+
+__global__ void k_set_dt(DevState *st, double dt)
+{
+    st->dt_fixed = dt;
+    if (dt > 0.0) st->dt_next = dt;
+}
+
+__global__ void k_reset_stats(DevState *st)
+{
+    st->c2p_fail = 0ull;
+    st->floor_hits = 0ull;
+    st->max_iter = 0;
+}
+
+// ---------------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------------
+namespace {
+inline unsigned nblk(long long n) { return (unsigned)((n + WG - 1) / WG); }
+}
+
+hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s)
+{
+    if (G.nghost_slots == 0) return hipSuccess;
+    if (G.mixed)
+        hipLaunchKernelGGL(k_fill<float>, dim3(nblk(G.nghost_slots)), dim3(WG), 0, s, G.d_gdst, G.d_gsrc,
+                           G.nghost_slots, (float *)P, G.kp.ncp);
+    else
+        hipLaunchKernelGGL(k_fill<double>, dim3(nblk(G.nghost_slots)), dim3(WG), 0, s, G.d_gdst, G.d_gsrc,
+                           G.nghost_slots, (double *)P, G.kp.ncp);
+    return hipGetLastError();
+}
+
+template <typename R, bool KS>
+static void p2c_typed(const DeviceGrid &G, const void *P, double *U, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_prim2con<R, KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell,
+                       (const R *)P, U);
+}
+
+hipError_t launch_prim2con(const DeviceGrid &G, const void *P, double *U, hipStream_t s)
+{
+    if (G.mixed) { if (G.ks) p2c_typed<float, true>(G, P, U, s); else p2c_typed<float, false>(G, P, U, s); }
+    else { if (G.ks) p2c_typed<double, true>(G, P, U, s); else p2c_typed<double, false>(G, P, U, s); }
+    return hipGetLastError();
+}
+
+template <typename R, bool KS>
+static void c2p_typed(const DeviceGrid &G, const double *U, void *P, int8_t *f, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_con2prim<R, KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, U,
+                       (R *)P, f);
+}
+
+hipError_t launch_con2prim(const DeviceGrid &G, const double *U, void *P, int8_t *fail, hipStream_t s)
+{
+    if (G.mixed) { if (G.ks) c2p_typed<float, true>(G, U, P, fail, s); else c2p_typed<float, false>(G, U, P, fail, s); }
+    else { if (G.ks) c2p_typed<double, true>(G, U, P, fail, s); else c2p_typed<double, false>(G, U, P, fail, s); }
+    return hipGetLastError();
+}
+
+template <typename R, bool KS>
+static void speeds_typed(const DeviceGrid &G, const void *P, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_cell_speeds<R, KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell,
+                       (const R *)P);
+}
+
+hipError_t launch_compute_dt(const DeviceGrid &G, const void *P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, G.kp, G.d_state, 0);
+    if (G.mixed) { if (G.ks) speeds_typed<float, true>(G, P, s); else speeds_typed<float, false>(G, P, s); }
+    else { if (G.ks) speeds_typed<double, true>(G, P, s); else speeds_typed<double, false>(G, P, s); }
+    hipLaunchKernelGGL(k_end, dim3(1), dim3(1), 0, s, G.kp, G.d_state);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_dt(const DeviceGrid &G, double dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, s, G.d_state, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_stats(const DeviceGrid &G, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(1), 0, s, G.d_state);
+    return hipGetLastError();
+}
+
+template <typename R, int D, int RECON, int FLUX, bool KS>
+static void flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
+{
+    const std::vector<WorkItem> &w = G.plan.wface[D];
+    hipLaunchKernelGGL((k_flux<R, D, RECON, FLUX, KS>), dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D],
+                       (const R *)Ps, (R *)G.d_flux[D], G.plan.nface[D]);
+}
+
+template <typename R, int RECON, int FLUX, bool KS>
+static void substep_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
+                          void *Po, double a, double b, hipStream_t s)
+{
+    flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, s);
+    flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, s);
+    if (G.kp.ndim == 3) flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, s);
+    hipLaunchKernelGGL((k_update<R, KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, Ub, Us,
+                       (const R *)Ps, Uo, (R *)Po, (const R *)G.d_flux[0], (const R *)G.d_flux[1],
+                       (const R *)G.d_flux[2], G.plan.nface[0], G.plan.nface[1], G.plan.nface[2], a, b);
+}
+
+template <typename R, int RECON, int FLUX>
+static void substep_metric(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
+                           void *Po, double a, double b, hipStream_t s)
+{
+    if (G.ks) substep_typed<R, RECON, FLUX, true>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    else substep_typed<R, RECON, FLUX, false>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+}
+
+template <typename R>
+static void substep_prec(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
+                         void *Po, double a, double b, hipStream_t s)
+{
+    const int r = G.kp.recon, f = G.kp.flux;
+    if (r == BHAC_RECON_PPM && f == BHAC_FLUX_HLL) substep_metric<R, BHAC_RECON_PPM, BHAC_FLUX_HLL>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    else if (r == BHAC_RECON_PPM) substep_metric<R, BHAC_RECON_PPM, BHAC_FLUX_TVDLF>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    else if (f == BHAC_FLUX_HLL) substep_metric<R, BHAC_RECON_MC, BHAC_FLUX_HLL>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    else substep_metric<R, BHAC_RECON_MC, BHAC_FLUX_TVDLF>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+}
+
+hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
+                          void *Po, double a, double b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, G.kp, G.d_state, a == 0.0 ? 1 : 0);
+    if (G.mixed) substep_prec<float>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    else substep_prec<double>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    hipLaunchKernelGGL(k_end, dim3(1), dim3(1), 0, s, G.kp, G.d_state);
+    return hipGetLastError();
+}
+
+}  // namespace bhac

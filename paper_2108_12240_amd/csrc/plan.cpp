@@ -1,0 +1,346 @@
+// Host-side planning for the GRMHD substep library: parameter and block-list
+// validation, the padded state layout, the same-level ghost gather map, fused-kernel
+// halo tables, FP64 metric tables and the work lists of the unfused kernels.
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace bhac {
+namespace {
+
+// ---------------------------------------------------------------------------------
+// Kerr-Schild metric in (ln r, theta, phi), M = 1, written once over a scalar type
+// so that forward-mode dual numbers give exact first derivatives of every table
+// entry (no hand-derived derivative formulas).
+// ---------------------------------------------------------------------------------
+struct Dual {
+    double v, d;
+};
+inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+inline Dual operator/(Dual a, Dual b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+inline Dual operator*(double s, Dual a) { return {s * a.v, s * a.d}; }
+inline Dual operator+(double s, Dual a) { return {s + a.v, a.d}; }
+inline Dual dsqrt(Dual a) { double r = std::sqrt(a.v); return {r, 0.5 * a.d / r}; }
+inline Dual dexp(Dual a) { double e = std::exp(a.v); return {e, e * a.d}; }
+inline Dual dsin(Dual a) { return {std::sin(a.v), std::cos(a.v) * a.d}; }
+inline Dual dcos(Dual a) { return {std::cos(a.v), -std::sin(a.v) * a.d}; }
+
+// alpha, beta^1, gamma_11, gamma_13, gamma_22, gamma_33 (the only non-zero entries)
+struct KsParts { Dual alpha, beta1, g11, g13, g22, g33; };
+
+KsParts ks_parts(double spin, Dual x1, Dual x2)
+{
+    const Dual r = dexp(x1), st = dsin(x2), ct = dcos(x2);
+    const Dual a2c2 = (spin * spin) * (ct * ct);
+    const Dual sigma = r * r + a2c2;
+    const Dual z = 2.0 * r / sigma;
+    const Dual one_z = 1.0 + z;
+    const Dual st2 = st * st;
+    KsParts k;
+    k.alpha = Dual{1.0, 0.0} / dsqrt(one_z);
+    k.beta1 = z / (r * one_z);                       // beta^r = z/(1+z), and beta^1 = beta^r / r
+    k.g11 = r * r * one_z;                           // gamma_rr r^2
+    k.g13 = (-spin) * r * st2 * one_z;               // gamma_r-phi r
+    k.g22 = sigma;
+    k.g33 = st2 * (sigma + (spin * spin) * st2 * one_z);
+    return k;
+}
+
+void ks_record(double spin, double x1, double x2, double *rec)
+{
+    const KsParts v = ks_parts(spin, {x1, 0.0}, {x2, 0.0});
+    const KsParts d1 = ks_parts(spin, {x1, 1.0}, {x2, 0.0});
+    const KsParts d2 = ks_parts(spin, {x1, 0.0}, {x2, 1.0});
+    const double g11 = v.g11.v, g13 = v.g13.v, g22 = v.g22.v, g33 = v.g33.v;
+    const double det13 = g11 * g33 - g13 * g13;
+    rec[C_ALPHA] = v.alpha.v;
+    rec[C_BETA1] = v.beta1.v;
+    rec[C_G11] = g11;
+    rec[C_G13] = g13;
+    rec[C_G22] = g22;
+    rec[C_G33] = g33;
+    rec[C_GI11] = g33 / det13;
+    rec[C_GI13] = -g13 / det13;
+    rec[C_GI22] = 1.0 / g22;
+    rec[C_GI33] = g11 / det13;
+    rec[C_SG] = std::sqrt(det13 * g22);
+    rec[C_DA1] = d1.alpha.d;
+    rec[C_DA2] = d2.alpha.d;
+    rec[C_DB1] = d1.beta1.d;
+    rec[C_DB2] = d2.beta1.d;
+    rec[C_DG11_1] = d1.g11.d;
+    rec[C_DG11_2] = d2.g11.d;
+    rec[C_DG13_1] = d1.g13.d;
+    rec[C_DG13_2] = d2.g13.d;
+    rec[C_DG22_1] = d1.g22.d;
+    rec[C_DG22_2] = d2.g22.d;
+    rec[C_DG33_1] = d1.g33.d;
+    rec[C_DG33_2] = d2.g33.d;
+}
+
+// Lattice key of a same-(level, size) slot.
+struct Key {
+    int level, s0, s1, s2, c0, c1, c2;
+    bool operator==(const Key &o) const
+    {
+        return level == o.level && s0 == o.s0 && s1 == o.s1 && s2 == o.s2 && c0 == o.c0 && c1 == o.c1 &&
+               c2 == o.c2;
+    }
+};
+struct KeyHash {
+    size_t operator()(const Key &k) const
+    {
+        uint64_t h = 1469598103934665603ull;
+        const int v[7] = {k.level, k.s0, k.s1, k.s2, k.c0, k.c1, k.c2};
+        for (int x : v) { h ^= (uint64_t)(uint32_t)x; h *= 1099511628211ull; }
+        return (size_t)h;
+    }
+};
+
+bool bad(std::string &err, const std::string &msg)
+{
+    err = msg;
+    return false;
+}
+
+bool check_params(const bhac_params &p, std::string &err)
+{
+    if (p.ndim != 2 && p.ndim != 3) return bad(err, "ndim must be 2 or 3");
+    if (p.metric != BHAC_METRIC_MINKOWSKI_CART && p.metric != BHAC_METRIC_KS_SPH_LOGR)
+        return bad(err, "unknown metric");
+    if (p.recon != BHAC_RECON_MC && p.recon != BHAC_RECON_PPM) return bad(err, "unknown reconstruction");
+    if (p.flux != BHAC_FLUX_HLL && p.flux != BHAC_FLUX_TVDLF) return bad(err, "unknown flux");
+    if (p.precision != BHAC_PREC_FP64 && p.precision != BHAC_PREC_MIXED) return bad(err, "unknown precision");
+    if (p.fused != 0 && p.fused != 1) return bad(err, "fused must be 0 or 1");
+    const int gmin = p.recon == BHAC_RECON_PPM ? 3 : 2;
+    if (p.nghost < gmin || p.nghost > 8) return bad(err, "nghost must be >= 2 (MC) or >= 3 (PPM) and <= 8");
+    if (!(std::fabs(p.spin) < 1.0)) return bad(err, "|spin| must be < 1");
+    if (!(p.gamma_ad > 1.0)) return bad(err, "gamma_ad must be > 1");
+    if (!(p.cfl > 0.0) || !(p.glm_alpha >= 0.0)) return bad(err, "cfl must be > 0 and glm_alpha >= 0");
+    if (!(p.rho_floor >= 0.0) || !(p.p_floor >= 0.0) || !(p.w_max > 1.0)) return bad(err, "bad floors");
+    if (!(p.c2p_tol > 0.0) || p.c2p_maxit < 1 || p.c2p_maxit > 1000) return bad(err, "bad inversion controls");
+    for (int e = 0; e < 3; e++) {
+        if (p.ncell0[e] < 1) return bad(err, "ncell0 must be >= 1");
+        if (e >= p.ndim) {
+            if (p.ncell0[e] != 1) return bad(err, "ncell0 along an unused axis must be 1");
+            continue;
+        }
+        if (!(p.x_hi[e] > p.x_lo[e])) return bad(err, "x_hi must exceed x_lo");
+        for (int s = 0; s < 2; s++)
+            if (p.bc[e][s] != BHAC_BC_PERIODIC && p.bc[e][s] != BHAC_BC_OUTFLOW) return bad(err, "unknown bc");
+        if ((p.bc[e][0] == BHAC_BC_PERIODIC) != (p.bc[e][1] == BHAC_BC_PERIODIC))
+            return bad(err, "periodic boundaries must be periodic on both sides");
+    }
+    if (p.metric == BHAC_METRIC_KS_SPH_LOGR && !(p.x_lo[1] > 0.0 && p.x_hi[1] < M_PI))
+        return bad(err, "Kerr-Schild theta range must lie inside (0, pi)");
+    return true;
+}
+
+}  // namespace
+
+int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, bool tables, Plan &P,
+              std::string &err)
+{
+    if (!pp || !blocks || nb <= 0) { err = "null params/blocks or nblocks <= 0"; return BHAC_EINVAL; }
+    const bhac_params &p = *pp;
+    if (!check_params(p, err)) return BHAC_EINVAL;
+    if (nb > (1ll << 30)) { err = "too many blocks"; return BHAC_EINVAL; }
+    P.p = p;
+    P.blocks.assign(blocks, blocks + nb);
+    for (int e = 0; e < 3; e++) P.gd[e] = e < p.ndim ? p.nghost : 0;
+
+    // blocks, lattice occupancy, layout
+    std::unordered_map<Key, int, KeyHash> lattice;
+    lattice.reserve((size_t)nb * 2);
+    P.off.assign(nb + 1, 0);
+    P.dblocks.resize(nb);
+    P.maxlevel = 0;
+    P.ncell_interior = 0;
+    for (int e = 0; e < 3; e++) P.smax[e] = 0;
+    for (int64_t b = 0; b < nb; b++) {
+        const bhac_block_desc &B = blocks[b];
+        if (B.level < 0 || B.level > 16) { err = "block level out of range"; return BHAC_EINVAL; }
+        for (int e = 0; e < 3; e++) {
+            if (e >= p.ndim) {
+                if (B.size[e] != 1 || B.origin[e] != 0) { err = "unused axis needs size 1, origin 0"; return BHAC_EINVAL; }
+                continue;
+            }
+            const long long N = (long long)p.ncell0[e] << B.level;
+            if (B.size[e] < p.nghost || B.size[e] > 1024) { err = "block size must be in [nghost, 1024]"; return BHAC_EINVAL; }
+            if (N % B.size[e] != 0) { err = "block size must divide the level's cell count"; return BHAC_EINVAL; }
+            if (B.origin[e] < 0 || B.origin[e] % B.size[e] != 0 || B.origin[e] + B.size[e] > N) {
+                err = "block origin must lie on its size lattice inside the domain";
+                return BHAC_EINVAL;
+            }
+        }
+        Key k{B.level, B.size[0], B.size[1], B.size[2], B.origin[0] / B.size[0], B.origin[1] / B.size[1],
+              B.origin[2] / B.size[2]};
+        if (!lattice.emplace(k, (int)b).second) { err = "two blocks occupy one lattice slot"; return BHAC_EINVAL; }
+        if (B.level > P.maxlevel) P.maxlevel = B.level;
+        DevBlock &D = P.dblocks[b];
+        for (int e = 0; e < 3; e++) {
+            D.s[e] = B.size[e];
+            D.o[e] = B.origin[e];
+            if (B.size[e] > P.smax[e]) P.smax[e] = B.size[e];
+        }
+        D.n0 = B.size[0] + 2 * P.gd[0];
+        D.n1 = B.size[1] + 2 * P.gd[1];
+        D.level = B.level;
+        D.off = P.off[b];
+        const long long ncell = (long long)D.n0 * D.n1 * (B.size[2] + 2 * P.gd[2]);
+        P.off[b + 1] = P.off[b] + ncell;
+        P.ncell_interior += (long long)B.size[0] * B.size[1] * B.size[2];
+    }
+    if (P.off[nb] >= (1ll << 31)) { err = "more than 2^31 padded cells"; return BHAC_EINVAL; }
+
+    // levels
+    P.levels.assign(P.maxlevel + 1, DevLevel{});
+    for (int l = 0; l <= P.maxlevel; l++) {
+        DevLevel &L = P.levels[l];
+        for (int e = 0; e < 3; e++) {
+            L.dx[e] = (p.x_hi[e] - p.x_lo[e]) / ((double)p.ncell0[e] * (double)(1 << l));
+            L.inv_dx[e] = 1.0 / L.dx[e];
+        }
+        L.N0 = p.ncell0[0] << l;
+        L.N1 = p.ncell0[1] << l;
+    }
+
+    // face offsets and work lists
+    for (int d = 0; d < 3; d++) { P.wface[d].clear(); P.nface[d] = 0; }
+    P.wcell.clear();
+    for (int64_t b = 0; b < nb; b++) {
+        DevBlock &D = P.dblocks[b];
+        const long long nc = (long long)D.s[0] * D.s[1] * D.s[2];
+        for (long long st = 0; st < nc; st += WG) P.wcell.push_back({(int)b, (int)st});
+        for (int d = 0; d < p.ndim; d++) {
+            const long long nf = (long long)(D.s[0] + (d == 0)) * (D.s[1] + (d == 1)) * (D.s[2] + (d == 2));
+            D.fofs[d] = P.nface[d];
+            P.nface[d] += nf;
+            for (long long st = 0; st < nf; st += WG) P.wface[d].push_back({(int)b, (int)st});
+        }
+        for (int d = p.ndim; d < 3; d++) D.fofs[d] = 0;
+    }
+
+    // halo sources per axis and neighbour slots (used by the gather map and the fused kernel)
+    const int g = p.nghost;
+    P.hmax = 0;
+    for (int e = 0; e < 3; e++) P.hmax = std::max(P.hmax, P.smax[e] + 2 * P.gd[e]);
+    P.halo.assign((size_t)nb * 3 * P.hmax, HaloAxis{0, 0, 0});
+    P.nbr.assign((size_t)nb * 27, -1);
+    for (int64_t b = 0; b < nb; b++) {
+        const bhac_block_desc &B = blocks[b];
+        int own[3], slot_of_dir[3][3];
+        for (int e = 0; e < 3; e++) {
+            own[e] = B.origin[e] / B.size[e];
+            const long long N = e < p.ndim ? ((long long)p.ncell0[e] << B.level) : 1;
+            const int ge = P.gd[e];
+            for (int dd = 0; dd < 3; dd++) slot_of_dir[e][dd] = own[e];
+            for (int l = -ge; l < B.size[e] + ge; l++) {
+                long long G = B.origin[e] + l;
+                if (G < 0 || G >= N) {
+                    if (p.bc[e][G < 0 ? 0 : 1] == BHAC_BC_PERIODIC) G = ((G % N) + N) % N;
+                    else G = G < 0 ? 0 : N - 1;
+                }
+                const int slot = (int)(G / B.size[e]);
+                int dir = 0;
+                if (slot != own[e]) dir = l < 0 ? -1 : 1;
+                slot_of_dir[e][dir + 1] = slot;
+                HaloAxis &h = P.halo[((size_t)b * 3 + e) * P.hmax + (l + ge)];
+                h.dir = (signed char)dir;
+                h.src = (short)(G - (long long)slot * B.size[e]);
+            }
+        }
+        for (int d2 = 0; d2 < 3; d2++)
+            for (int d1 = 0; d1 < 3; d1++)
+                for (int d0 = 0; d0 < 3; d0++) {
+                    Key k{B.level, B.size[0], B.size[1], B.size[2], slot_of_dir[0][d0], slot_of_dir[1][d1],
+                          slot_of_dir[2][d2]};
+                    auto it = lattice.find(k);
+                    P.nbr[(size_t)b * 27 + d0 + 3 * d1 + 9 * d2] = it == lattice.end() ? -1 : it->second;
+                }
+    }
+
+    // same-level ghost gather map, one entry per ghost slot in padded order
+    P.gdst.clear();
+    P.gsrc.clear();
+    for (int64_t b = 0; b < nb; b++) {
+        const DevBlock &D = P.dblocks[b];
+        const int n2 = D.s[2] + 2 * P.gd[2];
+        for (int pk = 0; pk < n2; pk++)
+            for (int pj = 0; pj < D.n1; pj++)
+                for (int pi = 0; pi < D.n0; pi++) {
+                    const int l[3] = {pi - P.gd[0], pj - P.gd[1], pk - P.gd[2]};
+                    if (l[0] >= 0 && l[0] < D.s[0] && l[1] >= 0 && l[1] < D.s[1] && l[2] >= 0 && l[2] < D.s[2])
+                        continue;
+                    int dir[3], src[3];
+                    for (int e = 0; e < 3; e++) {
+                        const HaloAxis &h = P.halo[((size_t)b * 3 + e) * P.hmax + (l[e] + P.gd[e])];
+                        dir[e] = h.dir;
+                        src[e] = h.src;
+                    }
+                    int sb = P.nbr[(size_t)b * 27 + (dir[0] + 1) + 3 * (dir[1] + 1) + 9 * (dir[2] + 1)];
+                    if (sb < 0) {
+                        sb = (int)b;
+                        for (int e = 0; e < 3; e++) src[e] = std::min(std::max(l[e], 0), D.s[e] - 1);
+                    }
+                    const DevBlock &S = P.dblocks[sb];
+                    const long long from =
+                        S.off + ((long long)(src[2] + P.gd[2]) * S.n1 + (src[1] + P.gd[1])) * S.n0 + (src[0] + P.gd[0]);
+                    const long long to = D.off + ((long long)pk * D.n1 + pj) * D.n0 + pi;
+                    P.gdst.push_back((int32_t)to);
+                    P.gsrc.push_back((int32_t)from);
+                }
+    }
+    (void)g;
+
+    // metric tables
+    P.nrec_c = P.nrec_f0 = P.nrec_f1 = 0;
+    P.ctab.clear();
+    P.f0tab.clear();
+    P.f1tab.clear();
+    if (tables && p.metric == BHAC_METRIC_KS_SPH_LOGR) {
+        for (int l = 0; l <= P.maxlevel; l++) {
+            DevLevel &L = P.levels[l];
+            L.ctab = P.nrec_c;
+            L.f0tab = P.nrec_f0;
+            L.f1tab = P.nrec_f1;
+            P.nrec_c += (long long)L.N0 * L.N1;
+            P.nrec_f0 += (long long)(L.N0 + 1) * L.N1;
+            P.nrec_f1 += (long long)L.N0 * (L.N1 + 1);
+        }
+        P.ctab.assign((size_t)P.nrec_c * C_NF, 0.0);
+        P.f0tab.assign((size_t)P.nrec_f0 * C_FACE_NF, 0.0);
+        P.f1tab.assign((size_t)P.nrec_f1 * C_FACE_NF, 0.0);
+        double rec[C_NF];
+        for (int l = 0; l <= P.maxlevel; l++) {
+            const DevLevel &L = P.levels[l];
+            for (int j = 0; j <= L.N1; j++)
+                for (int i = 0; i <= L.N0; i++) {
+                    const double xc1 = p.x_lo[0] + (i + 0.5) * L.dx[0], xc2 = p.x_lo[1] + (j + 0.5) * L.dx[1];
+                    const double xf1 = p.x_lo[0] + i * L.dx[0], xf2 = p.x_lo[1] + j * L.dx[1];
+                    if (i < L.N0 && j < L.N1) {
+                        ks_record(p.spin, xc1, xc2, rec);
+                        const long long r = L.ctab + (long long)j * L.N0 + i;
+                        for (int f = 0; f < C_NF; f++) P.ctab[(size_t)f * P.nrec_c + r] = rec[f];
+                    }
+                    if (j < L.N1) {
+                        ks_record(p.spin, xf1, xc2, rec);
+                        const long long r = L.f0tab + (long long)j * (L.N0 + 1) + i;
+                        for (int f = 0; f < C_FACE_NF; f++) P.f0tab[(size_t)f * P.nrec_f0 + r] = rec[f];
+                    }
+                    if (i < L.N0) {
+                        ks_record(p.spin, xc1, xf2, rec);
+                        const long long r = L.f1tab + (long long)j * L.N0 + i;
+                        for (int f = 0; f < C_FACE_NF; f++) P.f1tab[(size_t)f * P.nrec_f1 + r] = rec[f];
+                    }
+                }
+        }
+    }
+    return BHAC_OK;
+}
+
+}  // namespace bhac

@@ -1,0 +1,150 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_12240_amd import bhac as B
+from paper_2108_12240_amd import inputs as I
+from tests.parity import rel_l1, linf
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-11     # relative L1 per field after 10 steps, FP64 path
+MIXED_TOL = 1e-5     # relative L1 per field after 10 steps, mixed path
+
+
+def banner(msg):
+    print(f"\n[parity] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a ROCm device"
+    return T
+
+
+def with_prec(c, precision, fused=0):
+    c.params = dict(c.params, precision=precision, fused=fused)
+    return c
+
+
+def test_fill_ghosts_bitwise(torch):
+    for c in (I.case1(), I.case_torus(2, n=(48, 32, 32)), I.case4(nblocks=64, n0=48)):
+        for prec in (I.PREC_FP64, I.PREC_MIXED):
+            banner(f"fill {c.name} prec={prec}")
+            c = with_prec(c, prec)
+            G = B.Grid(c.params, c.blocks)
+            Og = O.OracleGrid(c.params, c.blocks)
+            ids = np.zeros((9, G.ncp))
+            for q in range(9):
+                ids[q] = (np.arange(G.ncp) % 1000003) + 1.5 * q   # exact in float32
+            P = torch.from_numpy(ids).to("cuda", G.pdtype)
+            G.fill_ghosts(P)
+            ref = ids.copy()
+            Og.fill_ghosts(ref)
+            got = P.cpu().double().numpy()
+            assert np.array_equal(got, ref)
+            G.close()
+
+
+@pytest.mark.parametrize("cfg", ["case1", "torus"])
+def test_prim2con_con2prim_compute_dt(torch, cfg):
+    c = I.case1() if cfg == "case1" else I.case_torus(2, n=32)
+    banner(f"pointwise {c.name}")
+    G = B.Grid(c.params, c.blocks)
+    Og = O.OracleGrid(c.params, c.blocks)
+    U0, P0 = Og.init(c.prim)
+    Ud, Pd = G.init(c.prim)
+    idx = Og.interior_index()
+    assert np.allclose(G.unpack(Ud), U0[:, idx], rtol=1e-13, atol=1e-15 * np.abs(U0).max())
+    assert G.timestep()["dt_next"] == pytest.approx(Og.state.dt_next, rel=1e-13)
+    # inversion from a perturbed guess
+    guess = c.prim.copy()
+    guess[0] *= 1.01
+    guess[4] *= 0.98
+    Pg = G.pack(guess)
+    G.con2prim(Ud, Pg)
+    Po = Og.pack(guess)
+    Og.con2prim(U0, Po)
+    assert np.allclose(G.unpack(Pg), Po[:, idx], rtol=1e-12, atol=1e-14)
+    G.close()
+
+
+def run_both(c, steps):
+    G = B.Grid(c.params, c.blocks)
+    Og = O.OracleGrid(c.params, c.blocks)
+    Uo, Po = Og.run(c.prim, steps)
+    Ud, Pd = G.run(c.prim, steps)
+    import torch
+    torch.cuda.synchronize()
+    idx = Og.interior_index()
+    res = dict(U=rel_l1(G.unpack(Ud), Uo[:, idx]), P=rel_l1(G.unpack(Pd), Po[:, idx]),
+               Uinf=linf(G.unpack(Ud), Uo[:, idx]), gpu_stats=G.stats(), cpu_stats=Og.stats(),
+               gpu_dt=G.timestep(), cpu_dt=Og.stats()["dt_next"])
+    G.close()
+    return res
+
+
+FP64_CASES = [
+    ("case1_64", lambda: I.case1()),
+    ("torus_32", lambda: I.case_torus(2, n=32)),
+    ("torus_48x32x32", lambda: I.case_torus(2, n=(48, 32, 32))),
+    ("amr_like_64", lambda: with_prec(I.case4(nblocks=64, n0=48), I.PREC_FP64, 0)),
+]
+
+
+@pytest.mark.parametrize("name,make", FP64_CASES)
+def test_fp64_ten_steps(torch, name, make):
+    c = with_prec(make(), I.PREC_FP64)
+    banner(f"fp64 10 steps {name}")
+    r = run_both(c, 10)
+    print("  rel-L1 U", r["U"], "\n  rel-L1 P", r["P"], "\n  stats", r["gpu_stats"], r["cpu_stats"], flush=True)
+    assert (r["U"] <= FP64_TOL).all(), r["U"]
+    assert (r["P"] <= FP64_TOL).all(), r["P"]
+    assert r["gpu_dt"]["dt_next"] == pytest.approx(r["cpu_dt"], rel=1e-9)
+    assert r["gpu_stats"]["c2p_fail"] == r["cpu_stats"]["c2p_fail"]
+
+
+MIXED_CASES = [
+    ("case1_64", lambda: I.case1()),
+    ("torus_32", lambda: I.case_torus(2, n=32)),
+    ("amr_like_64", lambda: I.case4(nblocks=64, n0=48)),
+]
+
+
+@pytest.mark.parametrize("name,make", MIXED_CASES)
+def test_mixed_ten_steps(torch, name, make):
+    c = with_prec(make(), I.PREC_MIXED, 0)
+    banner(f"mixed 10 steps {name}")
+    r = run_both(c, 10)
+    print("  rel-L1 U", r["U"], "\n  rel-L1 P", r["P"], flush=True)
+    assert (r["U"] <= MIXED_TOL).all(), r["U"]
+    assert (r["P"] <= MIXED_TOL).all(), r["P"]
+
+
+def test_uniform_state_bitwise_on_gpu(torch):
+    for recon, flux in ((I.RECON_MC, I.FLUX_TVDLF), (I.RECON_PPM, I.FLUX_HLL)):
+        c = I.uniform_state(n=(16, 16, 16), bs=(8, 8, 8), recon=recon, flux=flux)
+        banner(f"uniform recon={recon}")
+        G = B.Grid(c.params, c.blocks)
+        U0, P0 = G.init(c.prim)
+        U0 = U0.clone()
+        U, P = G.run(c.prim, 10)
+        assert torch.equal(U[:, G.interior_index()], U0[:, G.interior_index()])
+        G.close()
+
+
+def test_substep_rejects_aliasing_and_uninitialised_dt(torch):
+    c = I.case1()
+    G = B.Grid(c.params, c.blocks)
+    P = G.pack(c.prim)
+    U = G.new_state("U")
+    with pytest.raises(B.BhacError) as e:
+        G.substep(U, U, P, U, P, 0.0, 1.0)
+    assert e.value.code == B.BHAC_EALIAS
+    P2 = G.new_state("P")
+    with pytest.raises(B.BhacError) as e:
+        G.substep(U, U, P, U, P2, 0.0, 1.0)
+    assert e.value.code == B.BHAC_EINVAL
+    G.close()
