@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the GRMHD substep library on one MI355X.
+
+Metric: zone-updates per second, counting interior cells times RK substeps (the
+paper's "cellupdates", Section 4.2). One benchmark step is one SSP-RK2 step = two
+substeps, each a full pass of the hot path (ghost fill, reconstruction, face
+fluxes, divergence, sources, RK combine, inversion, wave-speed reduction) over the
+whole grid. Inputs are synthetic and already resident in HBM when timing starts.
+
+Prints ONE JSON line. Besides the headline path it reports the dominant kernel's
+roofline (algorithmic bytes per launch over its HIP-event-timed average duration),
+the other precision on the same grid, and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "zone-updates/s per RK substep (FP64 vs mixed, 1 GPU) + % HBM roofline"
+
+# Workloads: name -> (case builder kwargs, precision, fused)
+WORKLOADS = {
+    # 3-D GRMHD Kerr-Schild torus, 128^3 as 512 blocks of 16^3, PPM + HLL, plain FP64 path
+    "ks_torus_128_fp64_plain": dict(cfg=2, n=128, precision=0, fused=0),
+    "ks_torus_128_mixed_plain": dict(cfg=2, n=128, precision=1, fused=0),
+    "ks_torus_192_mixed_plain": dict(cfg=3, n=192, precision=1, fused=0),
+    # block-tiled (halo-gathering) mixed-precision path
+    "ks_torus_128_mixed_fused": dict(cfg=2, n=128, precision=1, fused=1),
+    "ks_torus_192_mixed_fused": dict(cfg=3, n=192, precision=1, fused=1),
+}
+
+
+def bytes_per_unit(kernel: str, rsz: int) -> float:
+    """Algorithmic HBM bytes per unit of work of each kernel family (unit in unit_of)."""
+    u8 = 8
+    if kernel == "fill_ghosts":            # per ghost slot: 9 values read + 9 written
+        return 18 * rsz
+    if kernel.startswith("flux_x"):        # per face: one cell's 9 primitives read, 9 fluxes written
+        return 18 * rsz
+    if kernel == "update":                 # per cell: U_stage, U_base (half the stages), P_stage,
+        return 9 * u8 * 1.5 + 9 * rsz + 3 * 9 * rsz + 9 * u8 + 9 * rsz   # 3 face fluxes, U_out, P_out
+    if kernel == "update_div":             # per cell: as update, with one stored divergence instead of fluxes
+        return 9 * u8 * 1.5 + 9 * rsz + 9 * 4 + 9 * u8 + 9 * rsz
+    if kernel == "block_flux":             # per zone: P_stage read once, divergence written once
+        return 9 * rsz + 9 * 4
+    return 0.0
+
+
+def units_per_launch(kernel: str, info: dict) -> float:
+    if kernel == "fill_ghosts":
+        return info["ghost_slots"]
+    if kernel.startswith("flux_x"):
+        return info["nface"][int(kernel[-1]) - 1]
+    if kernel in ("update", "update_div", "block_flux"):
+        return info["ncell"]
+    return 0.0
+
+
+def grid_info(case, G):
+    from paper_2108_12240_amd import bhac as B
+    off, dst, _ = B.bhac_plan_ghosts(case.params, case.blocks)
+    blk = case.blocks
+    nface = [int(((blk[:, 1] + (d == 0)) * (blk[:, 2] + (d == 1)) * (blk[:, 3] + (d == 2))).sum()) for d in range(3)]
+    return dict(ghost_slots=int(dst.size), nface=nface, ncell=int(G.nci))
+
+
+def run_gpu(case, steps, warmup):
+    import torch
+    from paper_2108_12240_amd import bhac as B
+
+    G = B.Grid(case.params, case.blocks, device="cuda:0")
+    U, P = G.init(case.prim)
+    U1, P1 = G.new_state("U"), G.new_state("P")
+    for _ in range(warmup):
+        G.rk2_step(U, P, U1, P1)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    B.bhac_get_timing(G.h)
+    B.bhac_set_timing(G.h, True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        G.rk2_step(U, P, U1, P1)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    B.bhac_set_timing(G.h, False)
+    ktimes = B.bhac_get_timing(G.h)
+    info = grid_info(case, G)
+    stats = G.stats()
+    ts = G.timestep()
+    finite = bool(torch.isfinite(P).all().item())
+    G.close()
+    zu = info["ncell"] * 2 * steps
+    return dict(ms_total=ms, ms_per_step=ms / steps, value=zu / (ms / 1e3), ktimes=ktimes, info=info,
+                stats=stats, dt=ts["dt"], finite=finite)
+
+
+def roofline(res, rsz):
+    kt = {k: v for k, v in res["ktimes"].items() if k not in ("step_begin", "step_end", "untimed")}
+    dom = max(kt, key=lambda k: kt[k][1])
+    launches, total_ms = kt[dom]
+    avg_s = total_ms / launches / 1e3
+    alg = bytes_per_unit(dom, rsz) * units_per_launch(dom, res["info"])
+    achieved = alg / avg_s / 1e9
+    return dict(kernel=dom, bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                avg_launch_ms=round(total_ms / launches, 4), bytes_per_launch=alg,
+                share_of_step=round(total_ms / sum(v[1] for v in kt.values()), 3))
+
+
+def cpu_baseline(case, seconds_hint: float):
+    """The oracle as it stands, single-threaded, on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle import oracle as O
+
+    Og = O.OracleGrid(case.params, case.blocks)
+    U, P = Og.init(case.prim)
+    U1, P1 = np.zeros_like(U), np.zeros_like(P)
+    nb = Og.nb
+    # pick a block sample sized to the time hint from a short probe
+    probe = list(range(min(nb, 8)))
+    t0 = time.perf_counter()
+    Og.fill_ghosts(P, probe)
+    Og.substep(U, U, P, U1, P1, 0.0, 1.0, probe)
+    t_probe = time.perf_counter() - t0
+    per_block = t_probe / len(probe)
+    nsel = int(max(1, min(nb, seconds_hint / 2.0 / max(per_block, 1e-9))))
+    sel = list(range(nsel))
+    cells = int(Og.ioff[nsel])
+    t0 = time.perf_counter()
+    Og.fill_ghosts(P, sel)
+    Og.substep(U, U, P, U1, P1, 0.0, 1.0, sel)
+    Og.fill_ghosts(P1, sel)
+    Og.substep(U, U1, P1, U1, P, 0.5, 0.5, sel)
+    el = time.perf_counter() - t0
+    return dict(value=round(cells * 2 / el, 1), unit="zone-updates/s", cores=1, kind="oracle",
+                sample=f"one RK2 step (2 substeps with ghost fills) on {nsel} of {nb} blocks "
+                       f"({cells} zones), single thread, {el:.1f} s")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed SSP-RK2 steps (2 substeps each)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ks_torus_128_fp64_plain", choices=sorted(WORKLOADS))
+    ap.add_argument("--compare", default="ks_torus_128_mixed_plain",
+                    help="second path on the same grid reported beside the headline ('' to skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(json.dumps(dict(error=f"this benchmark runs on exactly one GPU (asked for {args.gpus}); "
+                                    "the multi-GPU halo exchange is not part of this build")), flush=True)
+        return 2
+
+    import torch
+    from paper_2108_12240_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    torch.cuda.set_device(0)
+
+    def make(name):
+        w = WORKLOADS[name]
+        c = I.make_case(w["cfg"], n=w["n"])
+        c.params = dict(c.params, precision=w["precision"], fused=w["fused"])
+        return c, w
+
+    case, w = make(args.workload)
+    res = run_gpu(case, args.steps, args.warmup)
+    rsz = 4 if w["precision"] == 1 else 8
+    out = dict(metric=METRIC, value=round(res["value"], 1), unit="zone-updates/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(res["ms_per_step"], 4), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f64" if rsz == 8 else "f32+f64",
+               data="synthetic (seeded Kerr-Schild torus, no dataset)",
+               config=dict(workload=args.workload, zones=res["info"]["ncell"], blocks=int(case.nblocks),
+                           block_size=16, substeps_per_step=2, recon="PPM", flux="HLL",
+                           fused=bool(w["fused"])),
+               roofline=roofline(res, rsz))
+    out["kernel_ms"] = {k: round(v[1] / max(v[0], 1), 4) for k, v in res["ktimes"].items()}
+    out["c2p"] = res["stats"]
+    out["finite"] = res["finite"]
+    if args.compare:
+        c2, w2 = make(args.compare)
+        r2 = run_gpu(c2, args.steps, args.warmup)
+        rsz2 = 4 if w2["precision"] == 1 else 8
+        out["compare"] = dict(workload=args.compare, value=round(r2["value"], 1),
+                              ms_per_step=round(r2["ms_per_step"], 4), dtype="f64" if rsz2 == 8 else "f32+f64",
+                              speedup_vs_headline=round(r2["value"] / res["value"], 3),
+                              roofline=roofline(r2, rsz2),
+                              kernel_ms={k: round(v[1] / max(v[0], 1), 4) for k, v in r2["ktimes"].items()})
+        del c2
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -205,6 +205,23 @@ int bhac_get_timestep(bhac_grid *grid, bhac_timestep *out);
 int bhac_get_stats(bhac_grid *grid, int64_t *c2p_fail, int64_t *floor_hits, int *max_iter);
 int bhac_reset_stats(bhac_grid *grid, void *stream);
 
+/* Optional kernel timing (the measurement behind the roofline figures). While
+ * enabled, every kernel the grid launches is bracketed by a pair of HIP events
+ * recorded on its launch stream (from a pool created by bhac_set_timing, so no
+ * call allocates). bhac_get_timing synchronises, adds the elapsed times per
+ * kernel family into out[0..max_entries) (name, launches, total milliseconds;
+ * names are static strings), writes the number of families with launches to
+ * *n_entries, and restarts the accumulation. Launches beyond the pool are not
+ * timed (their count is returned as a family named "untimed"). */
+typedef struct bhac_kernel_time {
+    const char *name;
+    int64_t launches;
+    double total_ms;
+} bhac_kernel_time;
+
+int bhac_set_timing(bhac_grid *grid, int enable);
+int bhac_get_timing(bhac_grid *grid, bhac_kernel_time *out, int max_entries, int *n_entries);
+
 /* Host-only planning, no GPU needed: validates params and blocks and returns
  * the layout offsets (nblocks + 1 entries, may be NULL) and the ghost gather
  * map the library would use: *nslots ghost slots with destination and source

@@ -51,6 +51,10 @@ class bhac_timestep(C.Structure):
                 ("lam", C.c_double * 3)]
 
 
+class bhac_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
 _lib = None
 _VP = C.c_void_p
 
@@ -77,6 +81,8 @@ def lib():
             "bhac_get_timestep": [_VP, C.POINTER(bhac_timestep)],
             "bhac_get_stats": [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)],
             "bhac_reset_stats": [_VP, _VP],
+            "bhac_set_timing": [_VP, C.c_int],
+            "bhac_get_timing": [_VP, C.POINTER(bhac_kernel_time), C.c_int, C.POINTER(C.c_int)],
             "bhac_plan_ghosts": [C.POINTER(bhac_params), C.POINTER(bhac_block_desc), C.c_int64,
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32)],
@@ -208,6 +214,18 @@ def bhac_get_stats(h) -> dict:
 
 def bhac_reset_stats(h, stream=None):
     _check(lib().bhac_reset_stats(h, _stream(stream)))
+
+
+def bhac_set_timing(h, enable: bool):
+    _check(lib().bhac_set_timing(h, 1 if enable else 0))
+
+
+def bhac_get_timing(h) -> dict:
+    """{kernel family: (launches, total_ms)} since the last call (synchronises)."""
+    arr = (bhac_kernel_time * 32)()
+    n = C.c_int(0)
+    _check(lib().bhac_get_timing(h, arr, 32, C.byref(n)))
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, 32))}
 
 
 # --- convenience wrapper around one grid ---------------------------------------------

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbhac.so")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "api.cpp", "kernels.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "fused.hip"]
 
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
             "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]

@@ -40,11 +40,21 @@ hipError_t upload(T **dst, const T *src, size_t n)
     return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
 }
 
+void release_timer(bhac::DeviceGrid &G)
+{
+    for (hipEvent_t e : G.timer.pool) (void)hipEventDestroy(e);
+    G.timer.pool.clear();
+    G.timer.recs.clear();
+    G.timer.used = 0;
+    G.timer.on = false;
+}
+
 void release(bhac::DeviceGrid &G)
 {
+    release_timer(G);
     void *ptrs[] = {G.d_blocks, G.d_levels, G.d_ctab, G.d_f0tab, G.d_f1tab, G.d_state, G.d_wcell,
                     G.d_wface[0], G.d_wface[1], G.d_wface[2], G.d_gdst, G.d_gsrc, G.d_nbr, G.d_halo,
-                    G.d_flux[0], G.d_flux[1], G.d_flux[2]};
+                    G.d_flux[0], G.d_flux[1], G.d_flux[2], G.d_div};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -107,8 +117,17 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
         return fail(BHAC_ENOMEM, "host allocation failed");
     }
     if (params->fused) {
-        delete g;
-        return fail(BHAC_EUNSUPPORTED, "fused substep is not available in this build");
+        const bhac::Plan &Q = G.plan;
+        const char *why = nullptr;
+        if (params->ndim != 3) why = "the block-tiled substep needs ndim = 3";
+        else if (params->precision != BHAC_PREC_MIXED) why = "the block-tiled substep runs in mixed precision only";
+        else if (params->recon != BHAC_RECON_PPM) why = "the block-tiled substep implements PPM reconstruction only";
+        else if (params->nghost != 3) why = "the block-tiled substep needs nghost = 3";
+        else if (Q.smax[0] > 16 || Q.smax[1] > 16) why = "the block-tiled substep needs block sizes <= 16 along x1 and x2";
+        if (why) {
+            delete g;
+            return fail(BHAC_EUNSUPPORTED, why);
+        }
     }
     const bhac::Plan &P = G.plan;
     const bhac_params &p = P.p;
@@ -161,8 +180,12 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     G.nghost_slots = (long long)P.gdst.size();
     {
         const size_t rsz = G.mixed ? sizeof(float) : sizeof(double);
-        for (int d = 0; d < p.ndim; d++) {
+        for (int d = 0; d < p.ndim && !p.fused; d++) {
             e = hipMalloc(&G.d_flux[d], (size_t)bhac::NV * P.nface[d] * rsz);
+            if (e != hipSuccess) goto hip_error;
+        }
+        if (p.fused) {
+            e = hipMalloc(&G.d_div, (size_t)bhac::NV * P.ncell_interior * sizeof(float));
             if (e != hipSuccess) goto hip_error;
         }
         e = hipMalloc((void **)&G.d_state, sizeof(bhac::DevState));
@@ -320,6 +343,59 @@ int bhac_get_stats(bhac_grid *g, int64_t *c2p_fail, int64_t *floor_hits, int *ma
     if (c2p_fail) *c2p_fail = (int64_t)st.c2p_fail;
     if (floor_hits) *floor_hits = (int64_t)st.floor_hits;
     if (max_iter) *max_iter = st.max_iter;
+    return BHAC_OK;
+}
+
+int bhac_set_timing(bhac_grid *g, int enable)
+{
+    if (int rc = check_grid(g)) return rc;
+    bhac::KTimer &t = g->dg.timer;
+    if (enable && t.pool.empty()) {
+        const size_t n = 16384;
+        t.pool.reserve(n);
+        t.recs.reserve(n / 2);
+        for (size_t i = 0; i < n; i++) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) {
+                release_timer(g->dg);
+                return hip_fail(err, "bhac_set_timing");
+            }
+            t.pool.push_back(e);
+        }
+    }
+    t.on = enable != 0;
+    return BHAC_OK;
+}
+
+int bhac_get_timing(bhac_grid *g, bhac_kernel_time *out, int max_entries, int *n_entries)
+{
+    if (int rc = check_grid(g)) return rc;
+    bhac::KTimer &t = g->dg.timer;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "bhac_get_timing");
+    for (const auto &r : t.recs) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        t.total_ms[r.id] += ms;
+        t.launches[r.id] += 1;
+    }
+    t.recs.clear();
+    t.used = 0;
+    int n = 0;
+    for (int k = 0; k < bhac::K_COUNT; k++) {
+        if (t.launches[k] == 0) continue;
+        if (out && n < max_entries) out[n] = bhac_kernel_time{bhac::kKernelNames[k], t.launches[k], t.total_ms[k]};
+        n++;
+    }
+    if (t.dropped) {
+        if (out && n < max_entries) out[n] = bhac_kernel_time{"untimed", t.dropped, 0.0};
+        n++;
+    }
+    for (int k = 0; k < bhac::K_COUNT; k++) { t.total_ms[k] = 0.0; t.launches[k] = 0; }
+    t.dropped = 0;
+    if (n_entries) *n_entries = n;
     return BHAC_OK;
 }
 

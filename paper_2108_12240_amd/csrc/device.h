@@ -42,8 +42,49 @@ struct GridDev {
     int pad;
 };
 
+// Kernel families timed by the optional HIP-event timer.
+enum KernelId { K_FILL, K_FLUX0, K_FLUX1, K_FLUX2, K_UPDATE, K_PRIM2CON, K_CON2PRIM, K_SPEEDS, K_BEGIN, K_END,
+                K_BLOCK_FLUX, K_UPDATE_DIV, K_COUNT };
+extern const char *const kKernelNames[K_COUNT];
+
+// Optional per-launch timing: a pre-created pool of HIP events recorded on the
+// launch stream around every kernel; harvested (with a synchronise) on request.
+struct KTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { int id; hipEvent_t a, b; hipStream_t s; };
+    std::vector<Rec> recs;
+    long long dropped = 0;
+    double total_ms[K_COUNT] = {};
+    long long launches[K_COUNT] = {};
+};
+
+// RAII helper: records the pair of events around one kernel launch when timing is on.
+struct TimedLaunch {
+    KTimer *t;
+    int id;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(KTimer &timer, int kid, hipStream_t st) : t(timer.on ? &timer : nullptr), id(kid), s(st)
+    {
+        if (!t) return;
+        if (t->used + 2 > t->pool.size()) { t->dropped++; t = nullptr; return; }
+        a = t->pool[t->used++];
+        b = t->pool[t->used++];
+        (void)hipEventRecord(a, s);
+    }
+    ~TimedLaunch()
+    {
+        if (!t) return;
+        (void)hipEventRecord(b, s);
+        t->recs.push_back({id, a, b, s});
+    }
+};
+
 struct DeviceGrid {
     Plan plan;
+    mutable KTimer timer;
     KParams kp{};
     GridDev gd{};
     int device = 0;
@@ -58,6 +99,7 @@ struct DeviceGrid {
     int32_t *d_nbr = nullptr;
     HaloAxis *d_halo = nullptr;
     void *d_flux[3] = {nullptr, nullptr, nullptr};   // face-flux scratch of the unfused path
+    void *d_div = nullptr;                           // flux divergence of the block-tiled path [9][interior]
     long long nghost_slots = 0;
     bool have_dt = false;
 };
@@ -68,6 +110,8 @@ hipError_t launch_con2prim(const DeviceGrid &G, const double *U, void *P, int8_t
 hipError_t launch_compute_dt(const DeviceGrid &G, const void *P, hipStream_t s);
 hipError_t launch_set_dt(const DeviceGrid &G, double dt, hipStream_t s);
 hipError_t launch_reset_stats(const DeviceGrid &G, hipStream_t s);
+hipError_t launch_fused_body(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
+                             void *Po, double a, double b, hipStream_t s);
 hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
                           void *Po, double a, double b, hipStream_t s);
 

@@ -21,6 +21,7 @@ struct DevBlock {
     int n0, n1;                  // padded extents along x and y
     int level;
     int pad;
+    long long ioff;              // first interior cell of the block in interior-packed arrays
 };
 
 // Per-level constants. Metric tables are 2-D in (x1, x2) because both supported

@@ -26,49 +26,6 @@ __global__ __launch_bounds__(WG) void k_fill(const int32_t *__restrict__ dst, co
     for (int v = 0; v < NV; v++) P[v * ncp + d] = P[v * ncp + s];
 }
 
-// cell (i, j, k) of a work item: returns false for the tail threads
-__device__ __forceinline__ bool cell_of(const DevBlock &B, int item, int &i, int &j, int &k)
-{
-    const int nc = B.s[0] * B.s[1] * B.s[2];
-    if (item >= nc) return false;
-    i = item % B.s[0];
-    const int t = item / B.s[0];
-    j = t % B.s[1];
-    k = t / B.s[1];
-    return true;
-}
-
-__device__ __forceinline__ long long pad_index(const DevBlock &B, const KParams &kp, int i, int j, int k)
-{
-    return B.off + ((long long)(k + kp.g[2]) * B.n1 + (j + kp.g[1])) * B.n0 + (i + kp.g[0]);
-}
-
-template <bool KS>
-__device__ __forceinline__ CentM centre_metric(const GridDev &gd, const DevBlock &B, int i, int j)
-{
-    if constexpr (!KS) {
-        return load_centre_metric<false>(nullptr, 0, 0);
-    } else {
-        const DevLevel &L = gd.levels[B.level];
-        const long long r = L.ctab + (long long)(B.o[1] + j) * L.N0 + (B.o[0] + i);
-        return load_centre_metric<true>(gd.ctab, gd.nrec_c, r);
-    }
-}
-
-template <typename R, int D, bool KS>
-__device__ __forceinline__ FaceM<R> face_metric(const GridDev &gd, const DevBlock &B, int i, int j)
-{
-    if constexpr (!KS) {
-        return load_face_metric<R, false>(nullptr, 0, 0);
-    } else {
-        const DevLevel &L = gd.levels[B.level];
-        const int gi = B.o[0] + i, gj = B.o[1] + j;
-        if constexpr (D == 0) return load_face_metric<R, true>(gd.f0tab, gd.nrec_f0, L.f0tab + (long long)gj * (L.N0 + 1) + gi);
-        else if constexpr (D == 1) return load_face_metric<R, true>(gd.f1tab, gd.nrec_f1, L.f1tab + (long long)gj * L.N0 + gi);
-        else return load_face_metric<R, true>(gd.ctab, gd.nrec_c, L.ctab + (long long)gj * L.N0 + gi);
-    }
-}
-
 // ---------------------------------------------------------------------------------
 // Face fluxes along D: one thread per face of a block (faces 0..s_D along D).
 // ---------------------------------------------------------------------------------
@@ -142,11 +99,7 @@ __global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const Wor
     if (cell_of(B, w.start + threadIdx.x, i, j, k)) {
         const long long c = pad_index(B, kp, i, j, k);
         const DevLevel &L = gd.levels[B.level];
-        // flux divergence, summed with a compensation term (Neumaier) in double
-        double sum = 0.0, comp = 0.0;
-        double Lv[NV];
-        const R *Fd[3] = {F0, F1, F2};
-        const long long nf[3] = {nf0, nf1, nf2};
+        // flux divergence, formed per direction in R, summed in double
         double div[3][NV];
 #pragma unroll
         for (int d = 0; d < 3; d++) {
@@ -155,12 +108,14 @@ __global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const Wor
                 for (int v = 0; v < NV; v++) div[d][v] = 0.0;
                 continue;
             }
+            const R *Fd = d == 0 ? F0 : (d == 1 ? F1 : F2);
+            const long long nf = d == 0 ? nf0 : (d == 1 ? nf1 : nf2);
             const int fs0 = B.s[0] + (d == 0), fs1 = B.s[1] + (d == 1);
             const long long lo = B.fofs[d] + ((long long)k * fs1 + j) * fs0 + i;
             const long long hi = lo + (d == 0 ? 1 : (d == 1 ? fs0 : (long long)fs0 * fs1));
             const R idx = (R)L.inv_dx[d];
 #pragma unroll
-            for (int v = 0; v < NV; v++) div[d][v] = (double)((Fd[d][v * nf[d] + hi] - Fd[d][v * nf[d] + lo]) * idx);
+            for (int v = 0; v < NV; v++) div[d][v] = (double)((Fd[v * nf + hi] - Fd[v * nf + lo]) * idx);
         }
         double q[NV], Uc[NV], S[NV];
 #pragma unroll
@@ -174,25 +129,21 @@ __global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const Wor
         double Un[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) {
-            // L = -(div_0 + div_1 + div_2) + S with Neumaier compensation
-            sum = -div[0][v];
-            comp = 0.0;
+            // L = -(div_1 + div_2 + div_3) + S with a Neumaier compensation
+            double sum = -div[0][v], comp = 0.0;
+            const double terms[3] = {-div[1][v], -div[2][v], S[v]};
 #pragma unroll
-            for (int d = 1; d < 3; d++) {
-                const double t = sum - div[d][v];
-                comp += fabs(sum) >= fabs(div[d][v]) ? (sum - t) - div[d][v] : (-div[d][v] - t) + sum;
+            for (int q2 = 0; q2 < 3; q2++) {
+                const double x = terms[q2];
+                const double t = sum + x;
+                comp += fabs(sum) >= fabs(x) ? (sum - t) + x : (x - t) + sum;
                 sum = t;
             }
-            {
-                const double t = sum + S[v];
-                comp += fabs(sum) >= fabs(S[v]) ? (sum - t) + S[v] : (S[v] - t) + sum;
-                sum = t;
-            }
-            Lv[v] = sum + comp;
+            const double Lv = sum + comp;
             // U_out = a U_base + b (U_stage + dt L): the stage sum as an exact pair
-            double s, e;
-            two_sum(Uc[v], dt * Lv[v], s, e);
-            Un[v] = a * Ub[v * kp.ncp + c] + (b * s + b * e);
+            double s2, e2;
+            two_sum(Uc[v], dt * Lv, s2, e2);
+            Un[v] = a * Ub[v * kp.ncp + c] + (b * s2 + b * e2);
         }
         double Pn[NV];
         fail = con_to_prim(Un, q, m, kp, Pn, nit, floored);
@@ -344,9 +295,14 @@ namespace {
 inline unsigned nblk(long long n) { return (unsigned)((n + WG - 1) / WG); }
 }
 
+const char *const kKernelNames[K_COUNT] = {"fill_ghosts", "flux_x1", "flux_x2", "flux_x3", "update",
+                                           "prim2con", "con2prim", "cell_speeds", "step_begin", "step_end",
+                                           "block_flux", "update_div"};
+
 hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s)
 {
     if (G.nghost_slots == 0) return hipSuccess;
+    TimedLaunch tl(G.timer, K_FILL, s);
     if (G.mixed)
         hipLaunchKernelGGL(k_fill<float>, dim3(nblk(G.nghost_slots)), dim3(WG), 0, s, G.d_gdst, G.d_gsrc,
                            G.nghost_slots, (float *)P, G.kp.ncp);
@@ -357,47 +313,66 @@ hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s)
 }
 
 template <typename R, bool KS>
-static void p2c_typed(const DeviceGrid &G, const void *P, double *U, hipStream_t s)
+static hipError_t p2c_typed(const DeviceGrid &G, const void *P, double *U, hipStream_t s)
 {
+    TimedLaunch tl(G.timer, K_PRIM2CON, s);
     hipLaunchKernelGGL((k_prim2con<R, KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell,
                        (const R *)P, U);
+    return hipGetLastError();
 }
 
 hipError_t launch_prim2con(const DeviceGrid &G, const void *P, double *U, hipStream_t s)
 {
-    if (G.mixed) { if (G.ks) p2c_typed<float, true>(G, P, U, s); else p2c_typed<float, false>(G, P, U, s); }
-    else { if (G.ks) p2c_typed<double, true>(G, P, U, s); else p2c_typed<double, false>(G, P, U, s); }
-    return hipGetLastError();
+    if (G.mixed) return G.ks ? p2c_typed<float, true>(G, P, U, s) : p2c_typed<float, false>(G, P, U, s);
+    return G.ks ? p2c_typed<double, true>(G, P, U, s) : p2c_typed<double, false>(G, P, U, s);
 }
 
 template <typename R, bool KS>
-static void c2p_typed(const DeviceGrid &G, const double *U, void *P, int8_t *f, hipStream_t s)
+static hipError_t c2p_typed(const DeviceGrid &G, const double *U, void *P, int8_t *f, hipStream_t s)
 {
+    TimedLaunch tl(G.timer, K_CON2PRIM, s);
     hipLaunchKernelGGL((k_con2prim<R, KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, U,
                        (R *)P, f);
+    return hipGetLastError();
 }
 
 hipError_t launch_con2prim(const DeviceGrid &G, const double *U, void *P, int8_t *fail, hipStream_t s)
 {
-    if (G.mixed) { if (G.ks) c2p_typed<float, true>(G, U, P, fail, s); else c2p_typed<float, false>(G, U, P, fail, s); }
-    else { if (G.ks) c2p_typed<double, true>(G, U, P, fail, s); else c2p_typed<double, false>(G, U, P, fail, s); }
-    return hipGetLastError();
+    if (G.mixed) return G.ks ? c2p_typed<float, true>(G, U, P, fail, s) : c2p_typed<float, false>(G, U, P, fail, s);
+    return G.ks ? c2p_typed<double, true>(G, U, P, fail, s) : c2p_typed<double, false>(G, U, P, fail, s);
 }
 
 template <typename R, bool KS>
-static void speeds_typed(const DeviceGrid &G, const void *P, hipStream_t s)
+static hipError_t speeds_typed(const DeviceGrid &G, const void *P, hipStream_t s)
 {
+    TimedLaunch tl(G.timer, K_SPEEDS, s);
     hipLaunchKernelGGL((k_cell_speeds<R, KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell,
                        (const R *)P);
+    return hipGetLastError();
+}
+
+static hipError_t begin_step(const DeviceGrid &G, int latch, hipStream_t s)
+{
+    TimedLaunch tl(G.timer, K_BEGIN, s);
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, G.kp, G.d_state, latch);
+    return hipGetLastError();
+}
+
+static hipError_t end_step(const DeviceGrid &G, hipStream_t s)
+{
+    TimedLaunch tl(G.timer, K_END, s);
+    hipLaunchKernelGGL(k_end, dim3(1), dim3(1), 0, s, G.kp, G.d_state);
+    return hipGetLastError();
 }
 
 hipError_t launch_compute_dt(const DeviceGrid &G, const void *P, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, G.kp, G.d_state, 0);
-    if (G.mixed) { if (G.ks) speeds_typed<float, true>(G, P, s); else speeds_typed<float, false>(G, P, s); }
-    else { if (G.ks) speeds_typed<double, true>(G, P, s); else speeds_typed<double, false>(G, P, s); }
-    hipLaunchKernelGGL(k_end, dim3(1), dim3(1), 0, s, G.kp, G.d_state);
-    return hipGetLastError();
+    hipError_t e = begin_step(G, 0, s);
+    if (e != hipSuccess) return e;
+    if (G.mixed) e = G.ks ? speeds_typed<float, true>(G, P, s) : speeds_typed<float, false>(G, P, s);
+    else e = G.ks ? speeds_typed<double, true>(G, P, s) : speeds_typed<double, false>(G, P, s);
+    if (e != hipSuccess) return e;
+    return end_step(G, s);
 }
 
 hipError_t launch_set_dt(const DeviceGrid &G, double dt, hipStream_t s)
@@ -413,52 +388,66 @@ hipError_t launch_reset_stats(const DeviceGrid &G, hipStream_t s)
 }
 
 template <typename R, int D, int RECON, int FLUX, bool KS>
-static void flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
+static hipError_t flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
 {
     const std::vector<WorkItem> &w = G.plan.wface[D];
+    TimedLaunch tl(G.timer, K_FLUX0 + D, s);
     hipLaunchKernelGGL((k_flux<R, D, RECON, FLUX, KS>), dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D],
                        (const R *)Ps, (R *)G.d_flux[D], G.plan.nface[D]);
+    return hipGetLastError();
 }
 
-template <typename R, int RECON, int FLUX, bool KS>
-static void substep_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
-                          void *Po, double a, double b, hipStream_t s)
+template <typename R, bool KS>
+static hipError_t update_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
+                               void *Po, double a, double b, hipStream_t s)
 {
-    flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, s);
-    flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, s);
-    if (G.kp.ndim == 3) flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, s);
+    TimedLaunch tl(G.timer, K_UPDATE, s);
     hipLaunchKernelGGL((k_update<R, KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, Ub, Us,
                        (const R *)Ps, Uo, (R *)Po, (const R *)G.d_flux[0], (const R *)G.d_flux[1],
                        (const R *)G.d_flux[2], G.plan.nface[0], G.plan.nface[1], G.plan.nface[2], a, b);
+    return hipGetLastError();
+}
+
+template <typename R, int RECON, int FLUX, bool KS>
+static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
+                                void *Po, double a, double b, hipStream_t s)
+{
+    hipError_t e = flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, s);
+    if (e == hipSuccess) e = flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, s);
+    if (e == hipSuccess && G.kp.ndim == 3) e = flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, s);
+    if (e == hipSuccess) e = update_typed<R, KS>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    return e;
 }
 
 template <typename R, int RECON, int FLUX>
-static void substep_metric(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
-                           void *Po, double a, double b, hipStream_t s)
+static hipError_t substep_metric(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
+                                 void *Po, double a, double b, hipStream_t s)
 {
-    if (G.ks) substep_typed<R, RECON, FLUX, true>(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    else substep_typed<R, RECON, FLUX, false>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    if (G.ks) return substep_typed<R, RECON, FLUX, true>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    return substep_typed<R, RECON, FLUX, false>(G, Ub, Us, Ps, Uo, Po, a, b, s);
 }
 
 template <typename R>
-static void substep_prec(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
-                         void *Po, double a, double b, hipStream_t s)
+static hipError_t substep_prec(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
+                               void *Po, double a, double b, hipStream_t s)
 {
     const int r = G.kp.recon, f = G.kp.flux;
-    if (r == BHAC_RECON_PPM && f == BHAC_FLUX_HLL) substep_metric<R, BHAC_RECON_PPM, BHAC_FLUX_HLL>(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    else if (r == BHAC_RECON_PPM) substep_metric<R, BHAC_RECON_PPM, BHAC_FLUX_TVDLF>(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    else if (f == BHAC_FLUX_HLL) substep_metric<R, BHAC_RECON_MC, BHAC_FLUX_HLL>(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    else substep_metric<R, BHAC_RECON_MC, BHAC_FLUX_TVDLF>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    if (r == BHAC_RECON_PPM && f == BHAC_FLUX_HLL)
+        return substep_metric<R, BHAC_RECON_PPM, BHAC_FLUX_HLL>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    if (r == BHAC_RECON_PPM) return substep_metric<R, BHAC_RECON_PPM, BHAC_FLUX_TVDLF>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    if (f == BHAC_FLUX_HLL) return substep_metric<R, BHAC_RECON_MC, BHAC_FLUX_HLL>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    return substep_metric<R, BHAC_RECON_MC, BHAC_FLUX_TVDLF>(G, Ub, Us, Ps, Uo, Po, a, b, s);
 }
 
 hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
                           void *Po, double a, double b, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, G.kp, G.d_state, a == 0.0 ? 1 : 0);
-    if (G.mixed) substep_prec<float>(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    else substep_prec<double>(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    hipLaunchKernelGGL(k_end, dim3(1), dim3(1), 0, s, G.kp, G.d_state);
-    return hipGetLastError();
+    hipError_t e = begin_step(G, a == 0.0 ? 1 : 0, s);
+    if (e != hipSuccess) return e;
+    if (G.plan.p.fused) e = launch_fused_body(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    else e = G.mixed ? substep_prec<float>(G, Ub, Us, Ps, Uo, Po, a, b, s) : substep_prec<double>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    if (e != hipSuccess) return e;
+    return end_step(G, s);
 }
 
 }  // namespace bhac

@@ -15,6 +15,27 @@
 
 namespace bhac {
 
+// Fast arithmetic of the face work: in float the hardware reciprocal and square
+// root (1 ulp) are used; in double everything stays correctly rounded.
+template <typename R>
+__device__ __forceinline__ R fdiv(R a, R b)
+{
+    if constexpr (sizeof(R) == 4) return a * __builtin_amdgcn_rcpf(b);
+    else return a / b;
+}
+template <typename R>
+__device__ __forceinline__ R frcp(R b)
+{
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rcpf(b);
+    else return R(1) / b;
+}
+template <typename R>
+__device__ __forceinline__ R fsqrt(R x)
+{
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_sqrtf(x);
+    else return sqrt(x);
+}
+
 template <typename R>
 struct FaceM {
     R al, b1, g11, g13, g22, g33, gi11, gi13, gi22, gi33, sg;
@@ -78,17 +99,63 @@ __device__ __forceinline__ FaceM<double> centre_as_face(const CentM &c)
 }
 
 // ---------------------------------------------------------------------------------
+// Block addressing and metric records of a cell or face of a block.
+// ---------------------------------------------------------------------------------
+// cell (i, j, k) of a work item: returns false for the tail threads
+__device__ __forceinline__ bool cell_of(const DevBlock &B, int item, int &i, int &j, int &k)
+{
+    const int nc = B.s[0] * B.s[1] * B.s[2];
+    if (item >= nc) return false;
+    i = item % B.s[0];
+    const int t = item / B.s[0];
+    j = t % B.s[1];
+    k = t / B.s[1];
+    return true;
+}
+
+__device__ __forceinline__ long long pad_index(const DevBlock &B, const KParams &kp, int i, int j, int k)
+{
+    return B.off + ((long long)(k + kp.g[2]) * B.n1 + (j + kp.g[1])) * B.n0 + (i + kp.g[0]);
+}
+
+template <bool KS>
+__device__ __forceinline__ CentM centre_metric(const GridDev &gd, const DevBlock &B, int i, int j)
+{
+    if constexpr (!KS) {
+        return load_centre_metric<false>(nullptr, 0, 0);
+    } else {
+        const DevLevel &L = gd.levels[B.level];
+        const long long r = L.ctab + (long long)(B.o[1] + j) * L.N0 + (B.o[0] + i);
+        return load_centre_metric<true>(gd.ctab, gd.nrec_c, r);
+    }
+}
+
+template <typename R, int D, bool KS>
+__device__ __forceinline__ FaceM<R> face_metric(const GridDev &gd, const DevBlock &B, int i, int j)
+{
+    if constexpr (!KS) {
+        return load_face_metric<R, false>(nullptr, 0, 0);
+    } else {
+        const DevLevel &L = gd.levels[B.level];
+        const int gi = B.o[0] + i, gj = B.o[1] + j;
+        if constexpr (D == 0) return load_face_metric<R, true>(gd.f0tab, gd.nrec_f0, L.f0tab + (long long)gj * (L.N0 + 1) + gi);
+        else if constexpr (D == 1) return load_face_metric<R, true>(gd.f1tab, gd.nrec_f1, L.f1tab + (long long)gj * L.N0 + gi);
+        else return load_face_metric<R, true>(gd.ctab, gd.nrec_c, L.ctab + (long long)gj * L.N0 + gi);
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // Conserved vector, physical flux along D and the fast-speed bounds of one state.
 // The normal-field and psi fluxes are left zero (the GLM solve provides them).
 // ---------------------------------------------------------------------------------
-template <typename R, int D, bool WANT_FLUX>
+template <typename R, int D, bool WANT_FLUX, bool WANT_SPEED = !WANT_FLUX>
 __device__ __forceinline__ void face_state(const R *q, const FaceM<R> &m, R gam, R gfac, R *U, R *F, R &lm,
                                            R &lp)
 {
     const R u1 = q[1], u2 = q[2], u3 = q[3];
     const R ul1 = m.g11 * u1 + m.g13 * u3, ul2 = m.g22 * u2, ul3 = m.g13 * u1 + m.g33 * u3;
-    const R W = sqrt(R(1) + (u1 * ul1 + u2 * ul2 + u3 * ul3));
-    const R iW = R(1) / W;
+    const R W = fsqrt(R(1) + (u1 * ul1 + u2 * ul2 + u3 * ul3));
+    const R iW = frcp(W);
     const R v[3] = {u1 * iW, u2 * iW, u3 * iW};
     const R vl[3] = {ul1 * iW, ul2 * iW, ul3 * iW};
     const R v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
@@ -139,14 +206,15 @@ __device__ __forceinline__ void face_state(const R *q, const FaceM<R> &m, R gam,
         }
         F[8] = R(0);
     }
-    const R cs2 = gam * p / rhoh;
-    const R ca2 = b2 / (rhoh + b2);
+    if constexpr (!WANT_SPEED) return;
+    const R cs2 = fdiv(gam * p, rhoh);
+    const R ca2 = fdiv(b2, rhoh + b2);
     const R ce2 = cs2 + ca2 - cs2 * ca2;
     const R gdd = D == 0 ? m.gi11 : (D == 1 ? m.gi22 : m.gi33);
     R disc = ce2 * (R(1) - v2) * (gdd * (R(1) - v2 * ce2) - vd * vd * (R(1) - ce2));
     disc = disc > R(0) ? disc : R(0);
-    const R sq = sqrt(disc);
-    const R pre = m.al / (R(1) - v2 * ce2);
+    const R sq = fsqrt(disc);
+    const R pre = fdiv(m.al, R(1) - v2 * ce2);
     const R c0 = vd * (R(1) - ce2);
     lp = pre * (c0 + sq) - bd;
     lm = pre * (c0 - sq) - bd;
@@ -156,17 +224,21 @@ __device__ __forceinline__ void face_state(const R *q, const FaceM<R> &m, R gam,
 // Reconstruction: monotonised-central slopes; PPM interface values from MC slopes
 // with the two monotonicity constraints (no flattening, no steepening).
 // ---------------------------------------------------------------------------------
+// median of (a, b, 0): the minmod of a and b
+template <typename R>
+__device__ __forceinline__ R minmod0(R a, R b)
+{
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+    else return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
+}
+
+// MC slope: zero unless both one-sided differences share a sign, else the one of
+// 2|d-|, 2|d+|, |d- + d+|/2 smallest in magnitude, with that common sign.
 template <typename R>
 __device__ __forceinline__ R mc_slope(R qm, R q0, R qp)
 {
     const R dm = q0 - qm, dp = qp - q0;
-    if (dm * dp <= R(0)) return R(0);
-    R s = R(2) * fabs(dm);
-    const R s2 = R(2) * fabs(dp);
-    const R s3 = R(0.5) * fabs(dm + dp);
-    s = s2 < s ? s2 : s;
-    s = s3 < s ? s3 : s;
-    return dp > R(0) ? s : -s;
+    return minmod0(minmod0(R(2) * dm, R(2) * dp), R(0.5) * (dm + dp));
 }
 
 // values at the lower and upper face of the centre cell q[2] of q[0..4]
@@ -213,35 +285,52 @@ __device__ __forceinline__ R face_flux(R *qL, R *qR, const FaceM<R> &m, R ch, R 
 {
     const R sg = m.sg;
     const R btl = sg * qL[5 + D], btr = sg * qR[5 + D];
-    const R bstar = R(0.5) * (btl + btr) - (qR[8] - qL[8]) / (R(2) * ch);
+    const R bstar = R(0.5) * (btl + btr) - fdiv(qR[8] - qL[8], R(2) * ch);
     const R psistar = R(0.5) * (qL[8] + qR[8]) - R(0.5) * ch * (btr - btl);
-    const R bn = bstar / sg;
+    const R bn = fdiv(bstar, sg);
     qL[5 + D] = bn;
     qR[5 + D] = bn;
-    R UL[9], FL[9], UR[9], FR[9], lmL, lpL, lmR, lpR;
-    face_state<R, D, true>(qL, m, gam, gfac, UL, FL, lmL, lpL);
-    face_state<R, D, true>(qR, m, gam, gfac, UR, FR, lmR, lpR);
+    // wave-speed bounds of both states first; then each state's U and F are folded
+    // into F = cL F_L + cR F_R + cU (U_R - U_L) one state at a time (few live registers)
+    R dummy[NV], lmL, lpL, lmR, lpR;
+    face_state<R, D, false>(qL, m, gam, gfac, dummy, dummy, lmL, lpL);
+    face_state<R, D, false>(qR, m, gam, gfac, dummy, dummy, lmR, lpR);
+    R cL, cR, cU;
     if constexpr (FLUX == BHAC_FLUX_HLL) {
         R sr = lpL > lpR ? lpL : lpR;
         sr = sr > R(0) ? sr : R(0);
         R sl = lmL < lmR ? lmL : lmR;
         sl = sl < R(0) ? sl : R(0);
         if (sr == sl) {
-#pragma unroll
-            for (int v = 0; v < 8; v++) F[v] = R(0.5) * (FL[v] + FR[v]);
+            cL = R(0.5);
+            cR = R(0.5);
+            cU = R(0);
         } else {
-            const R inv = R(1) / (sr - sl);
-            const R srsl = sr * sl;
-#pragma unroll
-            for (int v = 0; v < 8; v++) F[v] = (sr * FL[v] - sl * FR[v] + srsl * (UR[v] - UL[v])) * inv;
+            const R inv = frcp(sr - sl);
+            cL = sr * inv;
+            cR = -sl * inv;
+            cU = sr * sl * inv;
         }
     } else {
         R c = fabs(lmL);
         c = fabs(lpL) > c ? fabs(lpL) : c;
         c = fabs(lmR) > c ? fabs(lmR) : c;
         c = fabs(lpR) > c ? fabs(lpR) : c;
+        cL = R(0.5);
+        cR = R(0.5);
+        cU = R(-0.5) * c;
+    }
+    {
+        R U[NV], Fs[NV], a, b;
+        face_state<R, D, true>(qL, m, gam, gfac, U, Fs, a, b);
 #pragma unroll
-        for (int v = 0; v < 8; v++) F[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * c * (UR[v] - UL[v]);
+        for (int v = 0; v < 8; v++) F[v] = cL * Fs[v] - cU * U[v];
+    }
+    {
+        R U[NV], Fs[NV], a, b;
+        face_state<R, D, true>(qR, m, gam, gfac, U, Fs, a, b);
+#pragma unroll
+        for (int v = 0; v < 8; v++) F[v] += cR * Fs[v] + cU * U[v];
     }
     F[5 + D] = psistar;
     F[8] = ch * ch * bstar;

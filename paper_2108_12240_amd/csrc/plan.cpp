@@ -191,6 +191,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         D.n1 = B.size[1] + 2 * P.gd[1];
         D.level = B.level;
         D.off = P.off[b];
+        D.ioff = P.ncell_interior;
         const long long ncell = (long long)D.n0 * D.n1 * (B.size[2] + 2 * P.gd[2]);
         P.off[b + 1] = P.off[b] + ncell;
         P.ncell_interior += (long long)B.size[0] * B.size[1] * B.size[2];

@@ -123,6 +123,35 @@ def test_mixed_ten_steps(torch, name, make):
     assert (r["P"] <= MIXED_TOL).all(), r["P"]
 
 
+FUSED_CASES = [
+    ("torus_32", lambda: I.case_torus(2, n=32)),
+    ("torus_48x32x32", lambda: I.case_torus(2, n=(48, 32, 32))),
+    ("amr_like_64", lambda: I.case4(nblocks=64, n0=48)),
+]
+
+
+@pytest.mark.parametrize("name,make", FUSED_CASES)
+def test_fused_mixed_ten_steps(torch, name, make):
+    c = with_prec(make(), I.PREC_MIXED, 1)
+    banner(f"fused mixed 10 steps {name}")
+    r = run_both(c, 10)
+    print("  rel-L1 U", r["U"], "\n  rel-L1 P", r["P"], "\n  stats", r["gpu_stats"], r["cpu_stats"], flush=True)
+    assert (r["U"] <= MIXED_TOL).all(), r["U"]
+    assert (r["P"] <= MIXED_TOL).all(), r["P"]
+    assert r["gpu_dt"]["dt_next"] == pytest.approx(r["cpu_dt"], rel=1e-5)
+
+
+def test_fused_rejects_unsupported(torch):
+    c = with_prec(I.case1(), I.PREC_MIXED, 1)
+    with pytest.raises(B.BhacError) as e:
+        B.Grid(c.params, c.blocks)
+    assert e.value.code == B.BHAC_EUNSUPPORTED
+    c = with_prec(I.case_torus(2, n=32), I.PREC_FP64, 1)
+    with pytest.raises(B.BhacError) as e:
+        B.Grid(c.params, c.blocks)
+    assert e.value.code == B.BHAC_EUNSUPPORTED
+
+
 def test_uniform_state_bitwise_on_gpu(torch):
     for recon, flux in ((I.RECON_MC, I.FLUX_TVDLF), (I.RECON_PPM, I.FLUX_HLL)):
         c = I.uniform_state(n=(16, 16, 16), bs=(8, 8, 8), recon=recon, flux=flux)
