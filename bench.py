@@ -159,7 +159,22 @@ def main(argv=None):
                     help="second path on the same grid reported beside the headline ('' to skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (to calibrate HBM byte counters)")
     args = ap.parse_args(argv)
+
+    if args.copy_probe:
+        import torch
+        torch.cuda.set_device(0)
+        n = 1 << 28
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_probe_bytes=n * 4, repeats=3)), flush=True)
+        return 0
 
     if args.gpus != 1:
         print(json.dumps(dict(error=f"this benchmark runs on exactly one GPU (asked for {args.gpus}); "

@@ -52,7 +52,8 @@ void release_timer(bhac::DeviceGrid &G)
 void release(bhac::DeviceGrid &G)
 {
     release_timer(G);
-    void *ptrs[] = {G.d_blocks, G.d_levels, G.d_ctab, G.d_f0tab, G.d_f1tab, G.d_state, G.d_wcell,
+    void *ptrs[] = {G.d_blocks, G.d_levels, G.d_ctab, G.d_f0tab, G.d_f1tab, G.d_ctab32, G.d_f0tab32, G.d_f1tab32,
+                    G.d_state, G.d_wcell,
                     G.d_wface[0], G.d_wface[1], G.d_wface[2], G.d_gdst, G.d_gsrc, G.d_nbr, G.d_halo,
                     G.d_flux[0], G.d_flux[1], G.d_flux[2], G.d_div};
     for (void *p : ptrs)
@@ -170,6 +171,9 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     UP(G.d_ctab, P.ctab);
     UP(G.d_f0tab, P.f0tab);
     UP(G.d_f1tab, P.f1tab);
+    UP(G.d_ctab32, P.ctab32);
+    UP(G.d_f0tab32, P.f0tab32);
+    UP(G.d_f1tab32, P.f1tab32);
     UP(G.d_wcell, P.wcell);
     for (int d = 0; d < 3; d++) UP(G.d_wface[d], P.wface[d]);
     UP(G.d_gdst, P.gdst);
@@ -200,6 +204,9 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     G.gd.ctab = G.d_ctab;
     G.gd.f0tab = G.d_f0tab;
     G.gd.f1tab = G.d_f1tab;
+    G.gd.ctab32 = G.d_ctab32;
+    G.gd.f0tab32 = G.d_f0tab32;
+    G.gd.f1tab32 = G.d_f1tab32;
     G.gd.nrec_c = P.nrec_c;
     G.gd.nrec_f0 = P.nrec_f0;
     G.gd.nrec_f1 = P.nrec_f1;

@@ -34,6 +34,7 @@ struct GridDev {
     const DevBlock *blocks;
     const DevLevel *levels;
     const double *ctab, *f0tab, *f1tab;
+    const float *ctab32, *f0tab32, *f1tab32;
     long long nrec_c, nrec_f0, nrec_f1;
     DevState *st;
     const int32_t *nbr;              // fused: 27 neighbour ids per block
@@ -93,6 +94,7 @@ struct DeviceGrid {
     DevBlock *d_blocks = nullptr;
     DevLevel *d_levels = nullptr;
     double *d_ctab = nullptr, *d_f0tab = nullptr, *d_f1tab = nullptr;
+    float *d_ctab32 = nullptr, *d_f0tab32 = nullptr, *d_f1tab32 = nullptr;
     DevState *d_state = nullptr;
     WorkItem *d_wcell = nullptr, *d_wface[3] = {nullptr, nullptr, nullptr};
     int32_t *d_gdst = nullptr, *d_gsrc = nullptr;

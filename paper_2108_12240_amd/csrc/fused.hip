@@ -26,7 +26,6 @@ constexpr int FSM = 16;            // largest block edge along x1 and x2
 constexpr int FG = 3;              // halo width read by PPM
 constexpr int TWX = FSM + 2 * FG;  // staged row length along x1
 constexpr int FWG = 256;           // threads per work-group
-constexpr int NXCD = 8;
 
 // LDS carve-up, in floats.
 struct Lay {
@@ -291,7 +290,7 @@ __global__ __launch_bounds__(FWG, 2) void k_block_flux(KParams kp, GridDev gd, i
         // (the face-metric rows are re-read from cache every plane rather than held in
         // registers across the march: the opaque copy stops them being hoisted)
         GridDev gk = gd;
-        asm volatile("" : "+s"(gk.f0tab), "+s"(gk.f1tab));
+        asm volatile("" : "+s"(gk.f0tab32), "+s"(gk.f1tab32));
         auto flux_x = [&](int jj, int ii) {
             float qL[NV], qR[NV], F[NV];
 #pragma unroll
@@ -387,6 +386,7 @@ __global__ __launch_bounds__(WG) void k_update_div(KParams kp, GridDev gd, const
     __shared__ long long redl[WG / 64];
     __shared__ int redi[WG / 64];
     const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
     const DevBlock B = gd.blocks[w.block];
     int i, j, k;
     int fail = 0, floored = 0, nit = 0;

@@ -11,6 +11,7 @@ namespace bhac {
 
 constexpr int NV = 9;
 constexpr int WG = 256;          // work-group size of the unfused kernels (4 wave64)
+constexpr int NXCD = 8;          // XCDs of an MI355X; work-groups are dealt to them round-robin
 
 // Per-block description as the kernels see it.
 struct DevBlock {
@@ -62,6 +63,7 @@ struct Plan {
     // metric tables (empty for flat space)
     long long nrec_c = 0, nrec_f0 = 0, nrec_f1 = 0;
     std::vector<double> ctab, f0tab, f1tab;
+    std::vector<float> ctab32, f0tab32, f1tab32;   // face fields in float (face work of the mixed path)
     // work lists (one entry per work-group of WG items inside one block)
     std::vector<WorkItem> wcell, wface[3];
     long long nface[3] = {0, 0, 0};

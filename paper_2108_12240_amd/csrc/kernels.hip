@@ -35,6 +35,7 @@ __global__ __launch_bounds__(WG) void k_flux(KParams kp, GridDev gd, const WorkI
 {
     __shared__ double red[WG / 64];
     const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
     const DevBlock B = gd.blocks[w.block];
     const int fs0 = B.s[0] + (D == 0), fs1 = B.s[1] + (D == 1), fs2 = B.s[2] + (D == 2);
     const int item = w.start + threadIdx.x;
@@ -93,6 +94,7 @@ __global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const Wor
     __shared__ long long redl[WG / 64];
     __shared__ int redi[WG / 64];
     const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
     const DevBlock B = gd.blocks[w.block];
     int i, j, k;
     int fail = 0, floored = 0, nit = 0;
@@ -173,6 +175,7 @@ __global__ __launch_bounds__(WG) void k_prim2con(KParams kp, GridDev gd, const W
                                                  const R *__restrict__ P, double *__restrict__ U)
 {
     const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
     const DevBlock B = gd.blocks[w.block];
     int i, j, k;
     if (!cell_of(B, w.start + threadIdx.x, i, j, k)) return;
@@ -193,6 +196,7 @@ __global__ __launch_bounds__(WG) void k_con2prim(KParams kp, GridDev gd, const W
     __shared__ long long redl[WG / 64];
     __shared__ int redi[WG / 64];
     const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
     const DevBlock B = gd.blocks[w.block];
     int i, j, k;
     int fail = 0, floored = 0, nit = 0;
@@ -226,6 +230,7 @@ __global__ __launch_bounds__(WG) void k_cell_speeds(KParams kp, GridDev gd, cons
 {
     __shared__ double red[WG / 64];
     const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
     const DevBlock B = gd.blocks[w.block];
     int i, j, k;
     double lam[3] = {0.0, 0.0, 0.0};

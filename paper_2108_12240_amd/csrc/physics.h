@@ -46,8 +46,8 @@ struct CentM {
     double da1, da2, db1, db2, dg11_1, dg11_2, dg13_1, dg13_2, dg22_1, dg22_2, dg33_1, dg33_2;
 };
 
-template <typename R, bool KS>
-__device__ __forceinline__ FaceM<R> load_face_metric(const double *__restrict__ tab, long long nrec, long long r)
+template <typename R, bool KS, typename T>
+__device__ __forceinline__ FaceM<R> load_face_metric(const T *__restrict__ tab, long long nrec, long long r)
 {
     FaceM<R> m;
     if constexpr (!KS) {
@@ -134,13 +134,21 @@ template <typename R, int D, bool KS>
 __device__ __forceinline__ FaceM<R> face_metric(const GridDev &gd, const DevBlock &B, int i, int j)
 {
     if constexpr (!KS) {
-        return load_face_metric<R, false>(nullptr, 0, 0);
+        return load_face_metric<R, false, double>(nullptr, 0, 0);
     } else {
         const DevLevel &L = gd.levels[B.level];
         const int gi = B.o[0] + i, gj = B.o[1] + j;
-        if constexpr (D == 0) return load_face_metric<R, true>(gd.f0tab, gd.nrec_f0, L.f0tab + (long long)gj * (L.N0 + 1) + gi);
-        else if constexpr (D == 1) return load_face_metric<R, true>(gd.f1tab, gd.nrec_f1, L.f1tab + (long long)gj * L.N0 + gi);
-        else return load_face_metric<R, true>(gd.ctab, gd.nrec_c, L.ctab + (long long)gj * L.N0 + gi);
+        long long r;
+        if constexpr (D == 0) r = L.f0tab + (long long)gj * (L.N0 + 1) + gi;
+        else if constexpr (D == 1) r = L.f1tab + (long long)gj * L.N0 + gi;
+        else r = L.ctab + (long long)gj * L.N0 + gi;
+        if constexpr (sizeof(R) == 4) {
+            const float *t = D == 0 ? gd.f0tab32 : (D == 1 ? gd.f1tab32 : gd.ctab32);
+            return load_face_metric<R, true, float>(t, D == 0 ? gd.nrec_f0 : (D == 1 ? gd.nrec_f1 : gd.nrec_c), r);
+        } else {
+            const double *t = D == 0 ? gd.f0tab : (D == 1 ? gd.f1tab : gd.ctab);
+            return load_face_metric<R, true, double>(t, D == 0 ? gd.nrec_f0 : (D == 1 ? gd.nrec_f1 : gd.nrec_c), r);
+        }
     }
 }
 

@@ -226,6 +226,18 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         for (int d = p.ndim; d < 3; d++) D.fofs[d] = 0;
     }
 
+    // XCD-aware order: work-group p runs on XCD p % NXCD, so item q is placed at
+    // p = (q % per) * NXCD + q / per. Each XCD then walks a contiguous range of items
+    // (neighbouring planes and blocks share its L2). Padding entries have block -1.
+    auto xcd_order = [](std::vector<WorkItem> &w) {
+        const size_t n = w.size(), per = (n + NXCD - 1) / NXCD;
+        std::vector<WorkItem> out(per * NXCD, WorkItem{-1, 0});
+        for (size_t q = 0; q < n; q++) out[(q % per) * NXCD + q / per] = w[q];
+        w.swap(out);
+    };
+    xcd_order(P.wcell);
+    for (int d = 0; d < p.ndim; d++) xcd_order(P.wface[d]);
+
     // halo sources per axis and neighbour slots (used by the gather map and the fused kernel)
     const int g = p.nghost;
     P.hmax = 0;
@@ -303,6 +315,9 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     P.ctab.clear();
     P.f0tab.clear();
     P.f1tab.clear();
+    P.ctab32.clear();
+    P.f0tab32.clear();
+    P.f1tab32.clear();
     if (tables && p.metric == BHAC_METRIC_KS_SPH_LOGR) {
         for (int l = 0; l <= P.maxlevel; l++) {
             DevLevel &L = P.levels[l];
@@ -340,6 +355,12 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                     }
                 }
         }
+    }
+    if (!P.ctab.empty()) {
+        P.ctab32.resize((size_t)P.nrec_c * C_FACE_NF);
+        for (size_t q = 0; q < P.ctab32.size(); q++) P.ctab32[q] = (float)P.ctab[q];
+        P.f0tab32.assign(P.f0tab.begin(), P.f0tab.end());
+        P.f1tab32.assign(P.f1tab.begin(), P.f1tab.end());
     }
     return BHAC_OK;
 }
