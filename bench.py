@@ -73,27 +73,39 @@ def grid_info(case, G):
     return dict(ghost_slots=int(dst.size), nface=nface, ncell=int(G.nci))
 
 
-def run_gpu(case, steps, warmup):
+def run_gpu(case, steps, warmup, graph=True):
+    """Time `steps` RK2 steps. With graph=True the timed loop replays the captured step
+    graph; per-kernel durations then come from a second, eager pass of the same number
+    of steps with HIP events around every launch (same kernels, same stream)."""
     import torch
     from paper_2108_12240_amd import bhac as B
 
     G = B.Grid(case.params, case.blocks, device="cuda:0")
     U, P = G.init(case.prim)
     U1, P1 = G.new_state("U"), G.new_state("P")
+    if graph:
+        G.capture_rk2_step(U, P, U1, P1)
+    step = G.launch_rk2_step if graph else (lambda: G.rk2_step(U, P, U1, P1))
     for _ in range(warmup):
-        G.rk2_step(U, P, U1, P1)
+        step()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     B.bhac_get_timing(G.h)
-    B.bhac_set_timing(G.h, True)
+    if not graph:
+        B.bhac_set_timing(G.h, True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
     for _ in range(steps):
-        G.rk2_step(U, P, U1, P1)
+        step()
     stop.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
+    if graph:
+        B.bhac_set_timing(G.h, True)
+        for _ in range(steps):
+            G.rk2_step(U, P, U1, P1)
+        torch.cuda.synchronize()
     B.bhac_set_timing(G.h, False)
     ktimes = B.bhac_get_timing(G.h)
     info = grid_info(case, G)
@@ -103,7 +115,7 @@ def run_gpu(case, steps, warmup):
     G.close()
     zu = info["ncell"] * 2 * steps
     return dict(ms_total=ms, ms_per_step=ms / steps, value=zu / (ms / 1e3), ktimes=ktimes, info=info,
-                stats=stats, dt=ts["dt"], finite=finite)
+                stats=stats, dt=ts["dt"], finite=finite, graph=graph)
 
 
 def roofline(res, rsz):
@@ -158,6 +170,7 @@ def main(argv=None):
     ap.add_argument("--compare", default="ks_torus_128_mixed_plain",
                     help="second path on the same grid reported beside the headline ('' to skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of the captured step graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (to calibrate HBM byte counters)")
@@ -194,7 +207,7 @@ def main(argv=None):
         return c, w
 
     case, w = make(args.workload)
-    res = run_gpu(case, args.steps, args.warmup)
+    res = run_gpu(case, args.steps, args.warmup, graph=not args.eager)
     rsz = 4 if w["precision"] == 1 else 8
     out = dict(metric=METRIC, value=round(res["value"], 1), unit="zone-updates/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(res["ms_per_step"], 4), higher_is_better=True,
@@ -202,14 +215,14 @@ def main(argv=None):
                data="synthetic (seeded Kerr-Schild torus, no dataset)",
                config=dict(workload=args.workload, zones=res["info"]["ncell"], blocks=int(case.nblocks),
                            block_size=16, substeps_per_step=2, recon="PPM", flux="HLL",
-                           fused=bool(w["fused"])),
+                           fused=bool(w["fused"]), graph=res["graph"]),
                roofline=roofline(res, rsz))
     out["kernel_ms"] = {k: round(v[1] / max(v[0], 1), 4) for k, v in res["ktimes"].items()}
     out["c2p"] = res["stats"]
     out["finite"] = res["finite"]
     if args.compare:
         c2, w2 = make(args.compare)
-        r2 = run_gpu(c2, args.steps, args.warmup)
+        r2 = run_gpu(c2, args.steps, args.warmup, graph=not args.eager)
         rsz2 = 4 if w2["precision"] == 1 else 8
         out["compare"] = dict(workload=args.compare, value=round(r2["value"], 1),
                               ms_per_step=round(r2["ms_per_step"], 4), dtype="f64" if rsz2 == 8 else "f32+f64",

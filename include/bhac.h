@@ -205,6 +205,19 @@ int bhac_get_timestep(bhac_grid *grid, bhac_timestep *out);
 int bhac_get_stats(bhac_grid *grid, int64_t *c2p_fail, int64_t *floor_hits, int *max_iter);
 int bhac_reset_stats(bhac_grid *grid, void *stream);
 
+/* One whole SSP-RK2 step as a HIP graph (the launch-bound inner loop of a run).
+ * bhac_capture_rk2_step records, on a stream the grid owns, the kernels of
+ *   [ghost fill of P] -> substep(U, U, P -> U1, P1, 0, 1)
+ *   -> [ghost fill of P1] -> substep(U, U1, P1 -> U, P, 1/2, 1/2)
+ * (ghost fills only when fused == 0) for these exact buffers, and instantiates it;
+ * a new capture replaces the previous graph. bhac_launch_rk2_step replays it on
+ * the caller's stream: one call per step, same results as the four calls made
+ * one by one. The time-step state lives on the device, so replays need no host
+ * work. Needs an initialised time step (BHAC_EINVAL otherwise); P/P1 aliasing
+ * rules as for bhac_substep. Launching before a capture returns BHAC_EINVAL. */
+int bhac_capture_rk2_step(bhac_grid *grid, double *U, void *P, double *U1, void *P1);
+int bhac_launch_rk2_step(bhac_grid *grid, void *stream);
+
 /* Optional kernel timing (the measurement behind the roofline figures). While
  * enabled, every kernel the grid launches is bracketed by a pair of HIP events
  * recorded on its launch stream (from a pool created by bhac_set_timing, so no

@@ -82,6 +82,8 @@ def lib():
             "bhac_get_stats": [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)],
             "bhac_reset_stats": [_VP, _VP],
             "bhac_set_timing": [_VP, C.c_int],
+            "bhac_capture_rk2_step": [_VP, _VP, _VP, _VP, _VP],
+            "bhac_launch_rk2_step": [_VP, _VP],
             "bhac_get_timing": [_VP, C.POINTER(bhac_kernel_time), C.c_int, C.POINTER(C.c_int)],
             "bhac_plan_ghosts": [C.POINTER(bhac_params), C.POINTER(bhac_block_desc), C.c_int64,
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
@@ -216,6 +218,14 @@ def bhac_reset_stats(h, stream=None):
     _check(lib().bhac_reset_stats(h, _stream(stream)))
 
 
+def bhac_capture_rk2_step(h, U, P, U1, P1):
+    _check(lib().bhac_capture_rk2_step(h, _ptr(U), _ptr(P), _ptr(U1), _ptr(P1)))
+
+
+def bhac_launch_rk2_step(h, stream=None):
+    _check(lib().bhac_launch_rk2_step(h, _stream(stream)))
+
+
 def bhac_set_timing(h, enable: bool):
     _check(lib().bhac_set_timing(h, 1 if enable else 0))
 
@@ -321,6 +331,12 @@ class Grid:
         if not fused:
             self.fill_ghosts(P1)
         self.substep(U, U1, P1, U, P, 0.5, 0.5)
+
+    def capture_rk2_step(self, U, P, U1, P1):
+        bhac_capture_rk2_step(self.h, U, P, U1, P1)
+
+    def launch_rk2_step(self):
+        bhac_launch_rk2_step(self.h)
 
     def run(self, prim_interior, steps):
         U, P = self.init(prim_interior)

@@ -12,6 +12,9 @@
 struct bhac_grid {
     bhac::DeviceGrid dg;
     hipStream_t last_stream = nullptr;
+    hipStream_t cap_stream = nullptr;      // owned: capture of the RK2-step graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -233,10 +236,20 @@ hip_error:
     }
 }
 
+static void release_graph(bhac_grid *g)
+{
+    if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->graph_exec = nullptr;
+    g->graph = nullptr;
+}
+
 int bhac_free_blocks(bhac_grid *g)
 {
     if (!g) return BHAC_OK;
     (void)hipDeviceSynchronize();
+    release_graph(g);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     release(g->dg);
     delete g;
     return BHAC_OK;
@@ -351,6 +364,61 @@ int bhac_get_stats(bhac_grid *g, int64_t *c2p_fail, int64_t *floor_hits, int *ma
     if (floor_hits) *floor_hits = (int64_t)st.floor_hits;
     if (max_iter) *max_iter = st.max_iter;
     return BHAC_OK;
+}
+
+int bhac_capture_rk2_step(bhac_grid *g, double *U, void *P, double *U1, void *P1)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!U || !P || !U1 || !P1) return fail(BHAC_EINVAL, "null array");
+    if (P == P1 || (void *)U == (void *)U1) return fail(BHAC_EALIAS, "stage buffers must differ");
+    if (!g->dg.have_dt) return fail(BHAC_EINVAL, "time step not initialised: call bhac_compute_dt or bhac_set_dt");
+    hipError_t e;
+    if (!g->cap_stream) {
+        e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "capture stream");
+    }
+    // work queued earlier on other streams must not race the capture's own launches
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "bhac_capture_rk2_step");
+    release_graph(g);
+    const bool timing = g->dg.timer.on;
+    g->dg.timer.on = false;                 // no event records inside the graph
+    hipStream_t s = g->cap_stream;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        g->dg.timer.on = timing;
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    const bool fused = g->dg.plan.p.fused != 0;
+    hipError_t le = hipSuccess;
+    if (!fused) le = bhac::launch_fill(g->dg, P, s);
+    if (le == hipSuccess) le = bhac::launch_substep(g->dg, U, U, P, U1, P1, 0.0, 1.0, s);
+    if (le == hipSuccess && !fused) le = bhac::launch_fill(g->dg, P1, s);
+    if (le == hipSuccess) le = bhac::launch_substep(g->dg, U, U1, P1, U, P, 0.5, 0.5, s);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    g->dg.timer.on = timing;
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "capture of the RK2 step");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    g->graph = graph;
+    e = hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        release_graph(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return BHAC_OK;
+}
+
+int bhac_launch_rk2_step(bhac_grid *g, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!g->graph_exec) return fail(BHAC_EINVAL, "no captured RK2 step");
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = hipGraphLaunch(g->graph_exec, (hipStream_t)stream);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "hipGraphLaunch");
 }
 
 int bhac_set_timing(bhac_grid *g, int enable)

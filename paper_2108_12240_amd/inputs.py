@@ -204,7 +204,7 @@ def _uniform_blocks(n, bs):
     return np.array(out, dtype=np.int32)
 
 
-def _finish_torus(params, blocks, prim, r, th, seed_rng, turbulence_n=None):
+def _finish_torus(prim, r):
     # field normalisation: max p / max(|B|^2/2) = 100 with the flat spatial metric
     bsq = (r * prim[B1]) ** 2 + (r * prim[B2]) ** 2
     bmax = float(bsq.max())
@@ -230,7 +230,7 @@ def case_torus(cfg: int, n=128, bs: int = 16, precision=None, fused=None) -> Cas
     noise = rng.uniform(size=int(ioff[-1]))
     g = [np.concatenate(v) for v in zip(*(_block_cells(b) for b in blocks))]
     prim, r, th = _torus_cells(params, 0, g[0], g[1], g[2], noise)
-    prim = _finish_torus(params, blocks, prim, r, th, rng)
+    prim = _finish_torus(prim, r)
     if cfg == 5:
         _add_turbulence(params, prim, r, th, g, n, rng)
     steps = 100 if cfg == 5 else 10
@@ -243,21 +243,22 @@ def _add_turbulence(params, prim, r, th, g, n, rng):
     kvec = rng.integers(-4, 5, size=(3, nm, 3))
     amp = rng.standard_normal((3, nm))
     ph = rng.uniform(0.0, 2.0 * math.pi, size=(3, nm))
-    inside = prim[U3] != 0.0
-    if not inside.any():
+    inside = np.flatnonzero(prim[U3] != 0.0)
+    if inside.size == 0:
         return
     gam = params["gamma_ad"]
-    cs = np.sqrt(gam * prim[PRS] / prim[RHO])
-    scale = [r, r, r * np.sin(th)]
+    cs = np.sqrt(gam * prim[PRS, inside] / prim[RHO, inside])
+    ri, ti = r[inside], th[inside]
+    scale = [ri, ri, ri * np.sin(ti)]
+    gx = [g[0][inside] / n[0], g[1][inside] / n[1], g[2][inside] / n[2]]
     for comp in range(3):
-        field_ = np.zeros(g[0].size)
+        field_ = np.zeros(inside.size)
         for m in range(nm):
-            arg = 2 * math.pi * (kvec[comp, m, 0] * g[0] / n[0] + kvec[comp, m, 1] * g[1] / n[1]
-                                 + kvec[comp, m, 2] * g[2] / n[2]) + ph[comp, m]
+            arg = 2 * math.pi * (kvec[comp, m, 0] * gx[0] + kvec[comp, m, 1] * gx[1]
+                                 + kvec[comp, m, 2] * gx[2]) + ph[comp, m]
             field_ += amp[comp, m] * np.sin(arg)
-        rms = math.sqrt(float(np.mean(field_[inside] ** 2)))
-        du = 0.3 * cs * field_ / max(rms, 1e-300) / scale[comp]
-        prim[U1 + comp] = np.where(inside, prim[U1 + comp] + du, prim[U1 + comp])
+        rms = math.sqrt(float(np.mean(field_ ** 2)))
+        prim[U1 + comp, inside] += 0.3 * cs * field_ / max(rms, 1e-300) / scale[comp]
 
 
 def case4(nblocks: int = 4096, n0: int = 96, levels: int = 3, precision=PREC_MIXED, fused=1) -> Case:
@@ -294,7 +295,7 @@ def case4(nblocks: int = 4096, n0: int = 96, levels: int = 3, precision=PREC_MIX
         g0, g1, g2 = _block_cells(blocks[b])
         sl = slice(int(ioff[b]), int(ioff[b + 1]))
         prim[:, sl], rr[sl], tt[sl] = _torus_cells(params, int(blocks[b, 0]), g0, g1, g2, noise[sl])
-    prim = _finish_torus(params, blocks, prim, rr, tt, rng)
+    prim = _finish_torus(prim, rr)
     return Case(f"case4_amrlike_{nblocks}", params, blocks, prim, ioff, steps=10)
 
 

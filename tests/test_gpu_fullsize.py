@@ -1,0 +1,129 @@
+"""GPU parity at the full benchmark sizes, on sampled blocks.
+
+The HIP path advances the whole grid by one SSP-RK2 step in exactly the launch
+configuration bench.py times. The oracle recomputes the step for a sample of
+blocks only: it builds a grid of the samples' two-deep same-level neighbourhood
+(enough for exact ghost data through both stages), runs stage 1 on the one-deep
+neighbourhood and stage 2 on the samples. Both sides use the same fixed dt, so no
+global reduction is needed on the CPU.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_12240_amd import bhac as B
+from paper_2108_12240_amd import inputs as I
+from tests.parity import rel_l1
+
+pytestmark = pytest.mark.gpu
+
+
+def neighbourhood(blocks, params, sel):
+    """Blocks whose same-(level, size) lattice slot is within one slot of a block in sel."""
+    blk = np.asarray(blocks)
+    lev, size, org = blk[:, 0], blk[:, 1:4], blk[:, 4:7]
+    slot = org // size
+    out = set(int(b) for b in sel)
+    for b in sel:
+        same = (lev == lev[b]) & (size == size[b]).all(axis=1)
+        d = np.abs(slot - slot[b])
+        for e in range(3):
+            if params["bc"][e][0] == I.BC_PERIODIC:
+                nslot = params["ncell0"][e] * 2 ** int(lev[b]) // int(size[b, e])
+                d[:, e] = np.minimum(d[:, e], nslot - d[:, e])
+        out.update(int(x) for x in np.flatnonzero(same & (d <= 1).all(axis=1)))
+    return sorted(out)
+
+
+def sample_blocks(c, k=6, seed=3):
+    nb = c.nblocks
+    rng = np.random.default_rng(seed)
+    picks = {0, nb - 1, nb // 2}
+    # a block holding the densest torus cell
+    dens = np.array([c.prim[0, c.ioff[b]:c.ioff[b + 1]].max() for b in range(nb)])
+    picks.add(int(dens.argmax()))
+    while len(picks) < k:
+        picks.add(int(rng.integers(nb)))
+    return sorted(picks)
+
+
+def interior_of(c, blocks_sel):
+    return np.concatenate([np.arange(c.ioff[b], c.ioff[b + 1]) for b in blocks_sel])
+
+
+CASES = [
+    ("case2_128_fp64_plain", lambda: I.case_torus(2, n=128), I.PREC_FP64, 0, 1e-12),
+    ("case2_128_mixed_plain", lambda: I.case_torus(2, n=128), I.PREC_MIXED, 0, 1e-5),
+    ("case2_128_mixed_fused", lambda: I.case_torus(2, n=128), I.PREC_MIXED, 1, 1e-5),
+    ("case3_192_mixed_fused", lambda: I.case_torus(3, n=192), I.PREC_MIXED, 1, 1e-5),
+    ("case4_4096_mixed_fused", lambda: I.case4(), I.PREC_MIXED, 1, 1e-5),
+]
+
+
+@pytest.mark.parametrize("name,make,prec,fused,tol", CASES)
+def test_one_step_sampled_blocks(name, make, prec, fused, tol):
+    import torch
+    print(f"\n[fullsize] {name}", flush=True)
+    c = make()
+    c.params = dict(c.params, precision=prec, fused=fused)
+    sel = sample_blocks(c)
+    n1 = neighbourhood(c.blocks, c.params, sel)
+    n2 = neighbourhood(c.blocks, c.params, n1)
+    # c_h and kappa follow the finest level present: keep one such block in the sub-grid
+    lmax = int(c.blocks[:, 0].max())
+    if not (c.blocks[n2, 0] == lmax).any():
+        n2 = sorted(set(n2) | {int(np.flatnonzero(c.blocks[:, 0] == lmax)[0])})
+    dt = 2e-3
+
+    # HIP path on the whole grid
+    G = B.Grid(c.params, c.blocks)
+    U, P = G.init(c.prim)
+    G.set_dt(dt)
+    U1, P1 = G.new_state("U"), G.new_state("P")
+    G.rk2_step(U, P, U1, P1)
+    torch.cuda.synchronize()
+    pidx = G.interior_index()[interior_of(c, sel)]
+    pidx_t = torch.from_numpy(pidx).to(U.device)
+    Ug = U[:, pidx_t].double().cpu().numpy()
+    Pg = P[:, pidx_t].double().cpu().numpy()
+    st = G.stats()
+    G.close()
+
+    # oracle on the sampled neighbourhood
+    sub = c.blocks[n2]
+    Og = O.OracleGrid(c.params, sub)
+    prim_sub = np.concatenate([c.prim[:, c.ioff[b]:c.ioff[b + 1]] for b in n2], axis=1)
+    Uo, Po = Og.init(prim_sub)
+    Og.set_dt(dt)
+    pos = {b: q for q, b in enumerate(n2)}
+    s1 = [pos[b] for b in n1]
+    s0 = [pos[b] for b in sel]
+    U1o, P1o = np.zeros_like(Uo), np.zeros_like(Po)
+    Og.fill_ghosts(Po, s1)
+    Og.substep(Uo, Uo, Po, U1o, P1o, 0.0, 1.0, s1)
+    Og.fill_ghosts(P1o, s0)
+    Og.substep(Uo, U1o, P1o, Uo, Po, 0.5, 0.5, s0)
+    oidx = np.concatenate([Og.interior_index()[Og.ioff[q]:Og.ioff[q + 1]] for q in s0])
+    eU = rel_l1(Ug, Uo[:, oidx])
+    eP = rel_l1(Pg, Po[:, oidx])
+    print(f"  blocks {sel} (neighbourhood {len(n1)}/{len(n2)})\n  rel-L1 U {eU}\n  rel-L1 P {eP}\n  gpu stats {st}",
+          flush=True)
+    assert (eU <= tol).all(), eU
+    assert (eP <= tol).all(), eP
+
+
+@pytest.mark.parametrize("name,make,prec", [("case2_128", lambda: I.case_torus(2, n=128), I.PREC_FP64),
+                                            ("case4_4096", lambda: I.case4(), I.PREC_MIXED)])
+def test_initial_time_step_full_grid(name, make, prec):
+    """The standalone wave-speed reduction over the whole grid gives the oracle's dt."""
+    print(f"\n[fullsize dt] {name}", flush=True)
+    c = make()
+    c.params = dict(c.params, precision=prec, fused=0)
+    G = B.Grid(c.params, c.blocks)
+    G.init(c.prim)
+    dt_gpu = G.timestep()["dt_next"]
+    G.close()
+    Og = O.OracleGrid(c.params, c.blocks)
+    Og.init(c.prim)
+    tol = 1e-13 if prec == I.PREC_FP64 else 1e-6
+    assert dt_gpu == pytest.approx(Og.state.dt_next, rel=tol)
