@@ -25,13 +25,15 @@
  *    PyTorch). The library owns the grid metadata (ghost maps, metric tables,
  *    work lists, time-step state, counters); bhac_alloc_blocks allocates it and
  *    bhac_free_blocks releases it. No per-substep call allocates memory.
- *  - State layout (structure of arrays): an array of nvar = 9 rows, each of
- *    ncell_padded entries. Row order for primitives P: rho, u~1, u~2, u~3 (Lorentz
- *    factor times Eulerian 3-velocity, contravariant), p, B1, B2, B3 (Eulerian
- *    magnetic field), psi (GLM scalar). Row order for conserved U:
- *    sqrt(gamma) * (D, S_1, S_2, S_3, tau, B1, B2, B3), psi. Inside a row, block
- *    b occupies [block_offset[b], block_offset[b+1]): its (size+2g)-padded box,
- *    x fastest, then y, then z (for ndim = 2 the z extent is 1 with no ghosts).
+ *  - State layout (structure of arrays, 9 rows). Primitives P: rows rho, u~1,
+ *    u~2, u~3 (Lorentz factor times Eulerian 3-velocity, contravariant), p, B1,
+ *    B2, B3 (Eulerian magnetic field), psi (GLM scalar); each row has
+ *    ncell_padded entries and block b occupies [block_offset[b],
+ *    block_offset[b+1]): its (size+2g)-padded box, x fastest, then y, then z (for
+ *    ndim = 2 the z extent is 1 with no ghosts). Conserved U: rows
+ *    sqrt(gamma) * (D, S_1, S_2, S_3, tau, B1, B2, B3), psi; conserved variables
+ *    need no ghost cells, so each row has ncell_interior entries and block b
+ *    occupies [block_interior_offset[b], block_interior_offset[b+1]), x fastest.
  *  - Precision: P is double when precision == BHAC_PREC_FP64 and float when
  *    precision == BHAC_PREC_MIXED. U is always double.
  */
@@ -105,14 +107,16 @@ typedef struct bhac_block_desc {
     int origin[3];
 } bhac_block_desc;
 
-/* Layout of the state arrays, filled by bhac_alloc_blocks. block_offset points
- * to nblocks + 1 host entries owned by the grid (valid until bhac_free_blocks). */
+/* Layout of the state arrays, filled by bhac_alloc_blocks. block_offset (padded
+ * primitive rows) and block_interior_offset (conserved rows) point to nblocks + 1
+ * host entries owned by the grid (valid until bhac_free_blocks). */
 typedef struct bhac_layout {
     int64_t ncell_padded;
     int64_t ncell_interior;
     int nvar;
     int nghost;
     const int64_t *block_offset;
+    const int64_t *block_interior_offset;
 } bhac_layout;
 
 /* Time-step state as the device holds it. dt, ch and kappa belong to the step in
@@ -151,7 +155,7 @@ int bhac_fill_ghosts(bhac_grid *grid, void *prim, void *stream);
  * variables): W = sqrt(1 + gamma_ij u~^i u~^j), v^i = u~^i / W,
  * xi = rho h W^2 with h = 1 + Gamma/(Gamma-1) p/rho, D = rho W,
  * S_i = (xi + B^2) v_i - (B.v) B_i, tau = xi + B^2 - p - ((B.v)^2 + B^2/W^2)/2 - D,
- * all densitised by sqrt(gamma); psi copied. cons: device double [9][ncell_padded]. */
+ * all densitised by sqrt(gamma); psi copied. cons: device double [9][ncell_interior]. */
 int bhac_prim2con(bhac_grid *grid, const void *prim, double *cons, void *stream);
 
 /* Conserved -> primitive at interior cells (Section 2: Newton-Raphson with a
@@ -160,8 +164,9 @@ int bhac_prim2con(bhac_grid *grid, const void *prim, double *cons, void *stream)
  * previous iterate while xi <= 0 or v^2 >= 1; stops when |dxi| <= c2p_tol * xi,
  * then takes one more step. Then floors on rho, p and W. On failure (no
  * convergence in c2p_maxit steps, non-finite values, rho <= 0 or p < 0) the
- * cell keeps its input primitives and fail[cell] = 1, else 0. fail: device
- * int8 [ncell_padded], may be NULL. cons is not modified. */
+ * cell keeps its input primitives and fail[cell] = 1, else 0. cons: device double
+ * [9][ncell_interior]; fail: device int8 [ncell_interior], may be NULL. cons is not
+ * modified. */
 int bhac_con2prim(bhac_grid *grid, const double *cons, void *prim_inout, int8_t *fail, void *stream);
 
 /* One Runge-Kutta substep (Section 2's second-order time stepping; Section 4.2's

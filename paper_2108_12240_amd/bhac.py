@@ -43,7 +43,8 @@ class bhac_block_desc(C.Structure):
 
 class bhac_layout(C.Structure):
     _fields_ = [("ncell_padded", C.c_int64), ("ncell_interior", C.c_int64), ("nvar", C.c_int),
-                ("nghost", C.c_int), ("block_offset", C.POINTER(C.c_int64))]
+                ("nghost", C.c_int), ("block_offset", C.POINTER(C.c_int64)),
+                ("block_interior_offset", C.POINTER(C.c_int64))]
 
 
 class bhac_timestep(C.Structure):
@@ -152,8 +153,9 @@ def bhac_alloc_blocks(params: dict, blocks: np.ndarray):
     lay = bhac_layout()
     _check(lib().bhac_alloc_blocks(C.byref(p), arr, len(arr), C.byref(h), C.byref(lay)))
     off = np.ctypeslib.as_array(lay.block_offset, shape=(len(arr) + 1,)).copy()
+    ioff = np.ctypeslib.as_array(lay.block_interior_offset, shape=(len(arr) + 1,)).copy()
     return h, dict(ncell_padded=int(lay.ncell_padded), ncell_interior=int(lay.ncell_interior),
-                   nvar=int(lay.nvar), nghost=int(lay.nghost), block_offset=off)
+                   nvar=int(lay.nvar), nghost=int(lay.nghost), block_offset=off, block_interior_offset=ioff)
 
 
 def bhac_free_blocks(h):
@@ -252,6 +254,7 @@ class Grid:
         self.ncp = lay["ncell_padded"]
         self.nci = lay["ncell_interior"]
         self.off = lay["block_offset"]
+        self.ioff = lay["block_interior_offset"]
         self.pdtype = torch.float32 if int(params["precision"]) == 1 else torch.float64
         self._pidx = None
 
@@ -282,17 +285,22 @@ class Grid:
         return self._pidx
 
     def new_state(self, kind="P"):
-        dt = self.pdtype if kind == "P" else self.torch.float64
-        return self.torch.zeros((NVAR, self.ncp), dtype=dt, device=self.device)
+        """Primitive state [9][ncell_padded] (float or double) or conserved [9][ncell_interior]."""
+        if kind == "P":
+            return self.torch.zeros((NVAR, self.ncp), dtype=self.pdtype, device=self.device)
+        return self.torch.zeros((NVAR, self.nci), dtype=self.torch.float64, device=self.device)
 
-    def pack(self, prim_interior: np.ndarray, kind="P"):
+    def pack(self, prim_interior: np.ndarray):
+        """Interior-packed primitives -> padded device array (ghost slots zero)."""
         out = np.zeros((NVAR, self.ncp), dtype=np.float64)
         out[:, self.interior_index()] = prim_interior
-        t = self.torch.from_numpy(out)
-        return t.to(device=self.device, dtype=self.pdtype if kind == "P" else self.torch.float64)
+        return self.torch.from_numpy(out).to(device=self.device, dtype=self.pdtype)
 
     def unpack(self, t) -> np.ndarray:
+        """Device state -> interior-packed float64 host array (P or U)."""
         a = t.detach().to("cpu", self.torch.float64).numpy()
+        if a.shape[1] == self.nci and self.nci != self.ncp:
+            return np.ascontiguousarray(a)
         return np.ascontiguousarray(a[:, self.interior_index()])
 
     def fill_ghosts(self, P):

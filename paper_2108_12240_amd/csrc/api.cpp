@@ -154,6 +154,7 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     kp.flux = p.flux;
     for (int d = 0; d < 3; d++) kp.g[d] = P.gd[d];
     kp.ncp = P.off.back();
+    kp.nci = P.ncell_interior;
     const bhac::DevLevel &fine = P.levels[P.maxlevel];
     kp.sinv_fine = 0.0;
     kp.dmin_fine = 1e300;
@@ -223,6 +224,7 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
         layout->nvar = bhac::NV;
         layout->nghost = p.nghost;
         layout->block_offset = P.off.data();
+        layout->block_interior_offset = P.ioff.data();
     }
     *out = g;
     return BHAC_OK;

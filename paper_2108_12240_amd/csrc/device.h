@@ -14,7 +14,8 @@ struct KParams {
     double cfl, glm_alpha;
     double sinv_fine, dmin_fine;     // sum_d 1/dx_d and min_d dx_d on the finest level
     double inv_dx_fine[3];
-    long long ncp;                   // padded cells per state row
+    long long ncp;                   // padded cells per primitive row
+    long long nci;                   // interior cells per conserved row
     int c2p_maxit, ndim;
     int g[3];
     int recon, flux;

@@ -366,11 +366,11 @@ __global__ __launch_bounds__(FWG, 2) void k_block_flux(KParams kp, GridDev gd, i
     }
 
     const double m0 = wg_max<FWG>((double)lam0, red);
-    if (t == 0) atomicMax(&gd.st->lam_acc[0], (unsigned long long)__double_as_longlong(m0));
+    if (t == 0) raise_max(&gd.st->lam_acc[0], m0);
     const double m1 = wg_max<FWG>((double)lam1, red);
-    if (t == 0) atomicMax(&gd.st->lam_acc[1], (unsigned long long)__double_as_longlong(m1));
+    if (t == 0) raise_max(&gd.st->lam_acc[1], m1);
     const double m2 = wg_max<FWG>((double)lam2, red);
-    if (t == 0) atomicMax(&gd.st->lam_acc[2], (unsigned long long)__double_as_longlong(m2));
+    if (t == 0) raise_max(&gd.st->lam_acc[2], m2);
 }
 
 // ---------------------------------------------------------------------------------
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(WG) void k_update_div(KParams kp, GridDev gd, const
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             q[v] = (double)Ps[v * kp.ncp + c];
-            Uc[v] = Us[v * kp.ncp + c];
+            Uc[v] = Us[v * kp.nci + ic];
         }
         const CentM m = centre_metric<KS>(gd, B, i, j);
         const double dt = gd.st->dt, kappa = gd.st->kappa;
@@ -410,14 +410,14 @@ __global__ __launch_bounds__(WG) void k_update_div(KParams kp, GridDev gd, const
             const double s = Uc[v] + x;
             const double bb = s - Uc[v];
             const double e = (Uc[v] - (s - bb)) + (x - bb);
-            Un[v] = a * Ub[v * kp.ncp + c] + (b * s + b * e);
+            Un[v] = (a == 0.0 ? 0.0 : a * Ub[v * kp.nci + ic]) + (b * s + b * e);
         }
         fail = con_to_prim(Un, q, m, kp, Pn, nit, floored);
         if (fail || floored) prim_to_cons(Pn, m, kp.gfac, Un);
         floored = fail ? 0 : floored;
 #pragma unroll
         for (int v = 0; v < NV; v++) {
-            Uo[v * kp.ncp + c] = Un[v];
+            Uo[v * kp.nci + ic] = Un[v];
             Po[v * kp.ncp + c] = (float)Pn[v];
         }
     }
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(WG) void k_update_div(KParams kp, GridDev gd, const
     if (threadIdx.x == 0) {
         if (nfail) atomicAdd(&gd.st->c2p_fail, (unsigned long long)nfail);
         if (nfl) atomicAdd(&gd.st->floor_hits, (unsigned long long)nfl);
-        if (mit) atomicMax(&gd.st->max_iter, mit);
+        if (mit) raise_max(&gd.st->max_iter, mit);
     }
 }
 

@@ -54,6 +54,7 @@ struct Plan {
     bhac_params p{};
     std::vector<bhac_block_desc> blocks;
     std::vector<int64_t> off;            // padded offsets, nb + 1
+    std::vector<int64_t> ioff;           // interior offsets, nb + 1
     int64_t ncell_interior = 0;
     std::vector<DevBlock> dblocks;
     std::vector<DevLevel> levels;        // indexed by level

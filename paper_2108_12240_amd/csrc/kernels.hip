@@ -19,7 +19,10 @@ template <typename T>
 __global__ __launch_bounds__(WG) void k_fill(const int32_t *__restrict__ dst, const int32_t *__restrict__ src,
                                              long long n, T *__restrict__ P, long long ncp)
 {
-    const long long i = (long long)blockIdx.x * WG + threadIdx.x;
+    // XCD-ordered chunks: XCD x copies the contiguous slot range of chunks [x per, (x+1) per)
+    const unsigned per = (gridDim.x + NXCD - 1) / NXCD;
+    const long long chunk = (long long)(blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+    const long long i = chunk * WG + threadIdx.x;
     if (i >= n) return;
     const long long d = dst[i], s = src[i];
 #pragma unroll
@@ -71,7 +74,7 @@ __global__ __launch_bounds__(WG) void k_flux(KParams kp, GridDev gd, const WorkI
         for (int v = 0; v < NV; v++) out[v * nftot] = Ff[v];
     }
     const double m = wg_max<WG>(lam, red);
-    if (threadIdx.x == 0) atomicMax(&gd.st->lam_acc[D], (unsigned long long)__double_as_longlong(m));
+    if (threadIdx.x == 0) raise_max(&gd.st->lam_acc[D], m);
 }
 
 // ---------------------------------------------------------------------------------
@@ -100,6 +103,7 @@ __global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const Wor
     int fail = 0, floored = 0, nit = 0;
     if (cell_of(B, w.start + threadIdx.x, i, j, k)) {
         const long long c = pad_index(B, kp, i, j, k);
+        const long long ci = B.ioff + w.start + threadIdx.x;   // interior-packed index of U
         const DevLevel &L = gd.levels[B.level];
         // flux divergence, formed per direction in R, summed in double
         double div[3][NV];
@@ -123,7 +127,7 @@ __global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const Wor
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             q[v] = (double)Ps[v * kp.ncp + c];
-            Uc[v] = Us[v * kp.ncp + c];
+            Uc[v] = Us[v * kp.nci + ci];
         }
         const CentM m = centre_metric<KS>(gd, B, i, j);
         const double dt = gd.st->dt, kappa = gd.st->kappa;
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const Wor
             // U_out = a U_base + b (U_stage + dt L): the stage sum as an exact pair
             double s2, e2;
             two_sum(Uc[v], dt * Lv, s2, e2);
-            Un[v] = a * Ub[v * kp.ncp + c] + (b * s2 + b * e2);
+            Un[v] = (a == 0.0 ? 0.0 : a * Ub[v * kp.nci + ci]) + (b * s2 + b * e2);
         }
         double Pn[NV];
         fail = con_to_prim(Un, q, m, kp, Pn, nit, floored);
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const Wor
         floored = fail ? 0 : floored;
 #pragma unroll
         for (int v = 0; v < NV; v++) {
-            Uo[v * kp.ncp + c] = Un[v];
+            Uo[v * kp.nci + ci] = Un[v];
             Po[v * kp.ncp + c] = (R)Pn[v];
         }
     }
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const Wor
     if (threadIdx.x == 0) {
         if (nfail) atomicAdd(&gd.st->c2p_fail, (unsigned long long)nfail);
         if (nfl) atomicAdd(&gd.st->floor_hits, (unsigned long long)nfl);
-        if (mit) atomicMax(&gd.st->max_iter, mit);
+        if (mit) raise_max(&gd.st->max_iter, mit);
     }
 }
 
@@ -180,12 +184,13 @@ __global__ __launch_bounds__(WG) void k_prim2con(KParams kp, GridDev gd, const W
     int i, j, k;
     if (!cell_of(B, w.start + threadIdx.x, i, j, k)) return;
     const long long c = pad_index(B, kp, i, j, k);
+    const long long ci = B.ioff + w.start + threadIdx.x;
     double q[NV], Uc[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) q[v] = (double)P[v * kp.ncp + c];
     prim_to_cons(q, centre_metric<KS>(gd, B, i, j), kp.gfac, Uc);
 #pragma unroll
-    for (int v = 0; v < NV; v++) U[v * kp.ncp + c] = Uc[v];
+    for (int v = 0; v < NV; v++) U[v * kp.nci + ci] = Uc[v];
 }
 
 template <typename R, bool KS>
@@ -202,17 +207,18 @@ __global__ __launch_bounds__(WG) void k_con2prim(KParams kp, GridDev gd, const W
     int fail = 0, floored = 0, nit = 0;
     if (cell_of(B, w.start + threadIdx.x, i, j, k)) {
         const long long c = pad_index(B, kp, i, j, k);
+        const long long ci = B.ioff + w.start + threadIdx.x;
         double q[NV], Uc[NV], Pn[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             q[v] = (double)P[v * kp.ncp + c];
-            Uc[v] = U[v * kp.ncp + c];
+            Uc[v] = U[v * kp.nci + ci];
         }
         fail = con_to_prim(Uc, q, centre_metric<KS>(gd, B, i, j), kp, Pn, nit, floored);
         floored = fail ? 0 : floored;
 #pragma unroll
         for (int v = 0; v < NV; v++) P[v * kp.ncp + c] = (R)Pn[v];
-        if (flags) flags[c] = (int8_t)fail;
+        if (flags) flags[ci] = (int8_t)fail;
     }
     const long long nfail = wg_sum<WG>(fail, redl);
     const long long nfl = wg_sum<WG>(floored, redl);
@@ -220,7 +226,7 @@ __global__ __launch_bounds__(WG) void k_con2prim(KParams kp, GridDev gd, const W
     if (threadIdx.x == 0) {
         if (nfail) atomicAdd(&gd.st->c2p_fail, (unsigned long long)nfail);
         if (nfl) atomicAdd(&gd.st->floor_hits, (unsigned long long)nfl);
-        if (mit) atomicMax(&gd.st->max_iter, mit);
+        if (mit) raise_max(&gd.st->max_iter, mit);
     }
 }
 
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(WG) void k_cell_speeds(KParams kp, GridDev gd, cons
 #pragma unroll
     for (int d = 0; d < 3; d++) {
         const double mx = wg_max<WG>(lam[d], red);
-        if (threadIdx.x == 0) atomicMax(&gd.st->lam_acc[d], (unsigned long long)__double_as_longlong(mx));
+        if (threadIdx.x == 0) raise_max(&gd.st->lam_acc[d], mx);
     }
 }
 
@@ -308,12 +314,14 @@ hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s)
 {
     if (G.nghost_slots == 0) return hipSuccess;
     TimedLaunch tl(G.timer, K_FILL, s);
+    const unsigned nchunk = nblk(G.nghost_slots);
+    const unsigned grid = ((nchunk + NXCD - 1) / NXCD) * NXCD;
     if (G.mixed)
-        hipLaunchKernelGGL(k_fill<float>, dim3(nblk(G.nghost_slots)), dim3(WG), 0, s, G.d_gdst, G.d_gsrc,
-                           G.nghost_slots, (float *)P, G.kp.ncp);
+        hipLaunchKernelGGL(k_fill<float>, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, G.nghost_slots,
+                           (float *)P, G.kp.ncp);
     else
-        hipLaunchKernelGGL(k_fill<double>, dim3(nblk(G.nghost_slots)), dim3(WG), 0, s, G.d_gdst, G.d_gsrc,
-                           G.nghost_slots, (double *)P, G.kp.ncp);
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, G.nghost_slots,
+                           (double *)P, G.kp.ncp);
     return hipGetLastError();
 }
 

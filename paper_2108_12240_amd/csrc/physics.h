@@ -232,6 +232,26 @@ __device__ __forceinline__ void face_state(const R *q, const FaceM<R> &m, R gam,
 // Reconstruction: monotonised-central slopes; PPM interface values from MC slopes
 // with the two monotonicity constraints (no flattening, no steepening).
 // ---------------------------------------------------------------------------------
+// Double-precision reciprocal and reciprocal square root for the inversion and the
+// sources: the hardware seed refined by two Newton-Raphson steps (r <- r (2 - x r),
+// y <- y (3 - x y^2) / 2), good to about one ulp for the positive, normal arguments
+// used there, at a third of the cost of the correctly rounded sequences.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
+
 // median of (a, b, 0): the minmod of a and b
 template <typename R>
 __device__ __forceinline__ R minmod0(R a, R b)
@@ -383,14 +403,13 @@ __device__ __forceinline__ void prim_to_cons(const double *q, const CentM &m, do
 __device__ __forceinline__ void geometric_sources(const double *q, const double *U, const CentM &m, double kappa,
                                                   double *S)
 {
-    const double isg = 1.0 / m.sg;
+    const double isg = rcp_nr(m.sg);
     const double D = U[0] * isg, tau = U[4] * isg;
     const double Sl1 = U[1] * isg, Sl2 = U[2] * isg, Sl3 = U[3] * isg;
     const double Su[3] = {m.gi11 * Sl1 + m.gi13 * Sl3, m.gi22 * Sl2, m.gi13 * Sl1 + m.gi33 * Sl3};
     const double u1 = q[1], u2 = q[2], u3 = q[3];
     const double ul1 = m.g11 * u1 + m.g13 * u3, ul2 = m.g22 * u2, ul3 = m.g13 * u1 + m.g33 * u3;
-    const double W = sqrt(1.0 + (u1 * ul1 + u2 * ul2 + u3 * ul3));
-    const double iW = 1.0 / W, iW2 = iW * iW;
+    const double iW = rsqrt_nr(1.0 + (u1 * ul1 + u2 * ul2 + u3 * ul3)), iW2 = iW * iW;
     const double v[3] = {u1 * iW, u2 * iW, u3 * iW};
     const double B[3] = {q[5], q[6], q[7]};
     const double Bl[3] = {m.g11 * B[0] + m.g13 * B[2], m.g22 * B[1], m.g13 * B[0] + m.g33 * B[2]};
@@ -434,24 +453,25 @@ struct C2PSys {
 __device__ __forceinline__ double c2p_vsq(const C2PSys &c, double xi)
 {
     const double xb = xi + c.B2;
-    return (xi * xi * c.S2 + c.SB2 * (c.B2 + 2.0 * xi)) / (xi * xi * xb * xb);
+    return (xi * xi * c.S2 + c.SB2 * (c.B2 + 2.0 * xi)) * rcp_nr(xi * xi * xb * xb);
 }
 
 __device__ __forceinline__ double c2p_newton_step(const C2PSys &c, double xi)
 {
     const double xb = xi + c.B2;
-    const double ixi = 1.0 / xi, ixb = 1.0 / xb;
+    const double ixi = rcp_nr(xi), ixb = rcp_nr(xb);
     const double ixi2 = ixi * ixi, ixb2 = ixb * ixb;
     const double v2 = (xi * xi * c.S2 + c.SB2 * (c.B2 + 2.0 * xi)) * ixi2 * ixb2;
     const double w2inv = 1.0 - v2;
-    const double W = 1.0 / sqrt(w2inv);
-    const double p = c.gfac_inv * (xi * w2inv - c.D / W);
+    const double iW = w2inv * rsqrt_nr(w2inv);      // 1/W = sqrt(1 - v^2)
+    const double W = rsqrt_nr(w2inv);
+    const double p = c.gfac_inv * (xi * w2inv - c.D * iW);
     const double f = xi - p + c.B2 - 0.5 * (c.B2 * w2inv + c.SB2 * ixi2) - c.E;
     const double dv2 = -2.0 * c.S2 * ixb2 * ixb
                        - 2.0 * c.SB2 * (3.0 * xi * xi + 3.0 * xi * c.B2 + c.B2 * c.B2) * ixi2 * ixi * ixb2 * ixb;
     const double dp = c.gfac_inv * (w2inv + (0.5 * c.D * W - xi) * dv2);
     const double df = 1.0 - dp + 0.5 * c.B2 * dv2 + c.SB2 * ixi2 * ixi;
-    double xn = xi - f / df;
+    double xn = xi - f * rcp_nr(df);
     for (int h = 0; h < 64 && (xn <= 0.0 || c2p_vsq(c, xn) >= 1.0); h++) xn = 0.5 * (xn + xi);
     if (xn <= 0.0 || !(c2p_vsq(c, xn) < 1.0)) return __builtin_nan("");
     return xn;
@@ -463,7 +483,7 @@ __device__ __forceinline__ int con_to_prim(const double *U, const double *g, con
 {
     nit = 0;
     floored = 0;
-    const double isg = 1.0 / m.sg;
+    const double isg = rcp_nr(m.sg);
     C2PSys c;
     c.gfac_inv = kp.gfac_inv;
     c.D = U[0] * isg;
@@ -511,9 +531,10 @@ __device__ __forceinline__ int con_to_prim(const double *U, const double *g, con
         const double v2 = c2p_vsq(c, xi);
         if (!(v2 < 1.0)) fail = true;
         else {
-            W = 1.0 / sqrt(1.0 - v2);
-            rho = c.D / W;
-            p = c.gfac_inv * (xi / (W * W) - rho);
+            const double w2inv = 1.0 - v2;
+            W = rsqrt_nr(w2inv);
+            rho = c.D * (w2inv * W);
+            p = c.gfac_inv * (xi * w2inv - rho);
             if (!(rho > 0.0) || !(p >= 0.0) || !isfinite(rho) || !isfinite(p)) fail = true;
         }
     }
@@ -521,7 +542,7 @@ __device__ __forceinline__ int con_to_prim(const double *U, const double *g, con
         for (int v = 0; v < NV; v++) out[v] = g[v];
         return 1;
     }
-    const double ixb = 1.0 / (xi + c.B2), sbx = c.SB / xi;
+    const double ixb = rcp_nr(xi + c.B2), sbx = c.SB * rcp_nr(xi);
     const double vl[3] = {(Sl[0] + sbx * Bl[0]) * ixb, (Sl[1] + sbx * Bl[1]) * ixb, (Sl[2] + sbx * Bl[2]) * ixb};
     double ut[3] = {W * (m.gi11 * vl[0] + m.gi13 * vl[2]), W * (m.gi22 * vl[1]), W * (m.gi13 * vl[0] + m.gi33 * vl[2])};
     if (rho < kp.rho_floor) { rho = kp.rho_floor; floored = 1; }
@@ -543,6 +564,21 @@ __device__ __forceinline__ int con_to_prim(const double *U, const double *g, con
     out[7] = B[2];
     out[8] = U[8];
     return 0;
+}
+
+// ---------------------------------------------------------------------------------
+// Global maxima kept by many work-groups: read the current value first and only
+// issue the atomic when this work-group raises it (thousands of same-address
+// atomics per launch would otherwise serialise at one L2 channel).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ void raise_max(unsigned long long *acc, double v)
+{
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    if (bits > __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(acc, bits);
+}
+__device__ __forceinline__ void raise_max(int *acc, int v)
+{
+    if (v > __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(acc, v);
 }
 
 // ---------------------------------------------------------------------------------

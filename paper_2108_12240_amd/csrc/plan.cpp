@@ -157,6 +157,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     std::unordered_map<Key, int, KeyHash> lattice;
     lattice.reserve((size_t)nb * 2);
     P.off.assign(nb + 1, 0);
+    P.ioff.assign(nb + 1, 0);
     P.dblocks.resize(nb);
     P.maxlevel = 0;
     P.ncell_interior = 0;
@@ -195,6 +196,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         const long long ncell = (long long)D.n0 * D.n1 * (B.size[2] + 2 * P.gd[2]);
         P.off[b + 1] = P.off[b] + ncell;
         P.ncell_interior += (long long)B.size[0] * B.size[1] * B.size[2];
+        P.ioff[b + 1] = P.ncell_interior;
     }
     if (P.off[nb] >= (1ll << 31)) { err = "more than 2^31 padded cells"; return BHAC_EINVAL; }
 

@@ -82,9 +82,9 @@ def test_one_step_sampled_blocks(name, make, prec, fused, tol):
     U1, P1 = G.new_state("U"), G.new_state("P")
     G.rk2_step(U, P, U1, P1)
     torch.cuda.synchronize()
-    pidx = G.interior_index()[interior_of(c, sel)]
-    pidx_t = torch.from_numpy(pidx).to(U.device)
-    Ug = U[:, pidx_t].double().cpu().numpy()
+    iidx = interior_of(c, sel)
+    pidx_t = torch.from_numpy(G.interior_index()[iidx]).to(U.device)
+    Ug = U[:, torch.from_numpy(iidx).to(U.device)].double().cpu().numpy()
     Pg = P[:, pidx_t].double().cpu().numpy()
     st = G.stats()
     G.close()

@@ -160,7 +160,7 @@ def test_uniform_state_bitwise_on_gpu(torch):
         U0, P0 = G.init(c.prim)
         U0 = U0.clone()
         U, P = G.run(c.prim, 10)
-        assert torch.equal(U[:, G.interior_index()], U0[:, G.interior_index()])
+        assert torch.equal(U, U0)
         G.close()
 
 
