@@ -66,7 +66,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
-                               "(run paper_2108_12240_amd/build.py or __graft_entry__.build())")
+                               "(run paper_2108_12240_amd/build.py)")
         L = C.CDLL(LIB_PATH)
         sig = {
             "bhac_alloc_blocks": [C.POINTER(bhac_params), C.POINTER(bhac_block_desc), C.c_int64,

@@ -15,25 +15,44 @@
 
 namespace bhac {
 
-// Fast arithmetic of the face work: in float the hardware reciprocal and square
-// root (1 ulp) are used; in double everything stays correctly rounded.
-template <typename R>
-__device__ __forceinline__ R fdiv(R a, R b)
+// Double-precision reciprocal and reciprocal square root for the inversion and the
+// sources: the hardware seed refined by two Newton-Raphson steps (r <- r (2 - x r),
+// y <- y (3 - x y^2) / 2), good to about one ulp for the positive, normal arguments
+// used there, at a third of the cost of the correctly rounded sequences.
+__device__ __forceinline__ double rcp_nr(double x)
 {
-    if constexpr (sizeof(R) == 4) return a * __builtin_amdgcn_rcpf(b);
-    else return a / b;
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
 }
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
+
+// Fast arithmetic of the face work: in float the hardware reciprocal and square
+// root (1 ulp); in double the Newton-refined versions above (about 1 ulp).
 template <typename R>
 __device__ __forceinline__ R frcp(R b)
 {
     if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rcpf(b);
-    else return R(1) / b;
+    else return rcp_nr(b);
+}
+template <typename R>
+__device__ __forceinline__ R fdiv(R a, R b)
+{
+    return a * frcp(b);
 }
 template <typename R>
 __device__ __forceinline__ R fsqrt(R x)
 {
     if constexpr (sizeof(R) == 4) return __builtin_amdgcn_sqrtf(x);
-    else return sqrt(x);
+    else return x > 0.0 ? x * rsqrt_nr(x) : 0.0;
 }
 
 template <typename R>
@@ -232,26 +251,6 @@ __device__ __forceinline__ void face_state(const R *q, const FaceM<R> &m, R gam,
 // Reconstruction: monotonised-central slopes; PPM interface values from MC slopes
 // with the two monotonicity constraints (no flattening, no steepening).
 // ---------------------------------------------------------------------------------
-// Double-precision reciprocal and reciprocal square root for the inversion and the
-// sources: the hardware seed refined by two Newton-Raphson steps (r <- r (2 - x r),
-// y <- y (3 - x y^2) / 2), good to about one ulp for the positive, normal arguments
-// used there, at a third of the cost of the correctly rounded sequences.
-__device__ __forceinline__ double rcp_nr(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-__device__ __forceinline__ double rsqrt_nr(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
-    return y * fma(-h * y, y, 1.5);
-}
-
 // median of (a, b, 0): the minmod of a and b
 template <typename R>
 __device__ __forceinline__ R minmod0(R a, R b)
