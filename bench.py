@@ -36,6 +36,17 @@ WORKLOADS = {
     # block-tiled (halo-gathering) mixed-precision path
     "ks_torus_128_mixed_fused": dict(cfg=2, n=128, precision=1, fused=1),
     "ks_torus_192_mixed_fused": dict(cfg=3, n=192, precision=1, fused=1),
+    # AMR-like list: 4096 blocks of 8^3/12^3/16^3 on three levels, mixed precision
+    "amr_like_4096_mixed_plain": dict(cfg=4, precision=1, fused=0),
+    "amr_like_4096_mixed_fused": dict(cfg=4, precision=1, fused=1),
+    # 384^3 torus with seeded turbulence, 13824 blocks of 16^3, mixed precision
+    "ks_turb_384_mixed_plain": dict(cfg=5, n=384, precision=1, fused=0),
+    "ks_turb_384_mixed_fused": dict(cfg=5, n=384, precision=1, fused=1),
+    # mixed precision, substep implementation chosen by the autotuner
+    "ks_torus_128_mixed_auto": dict(cfg=2, n=128, precision=1, fused="auto"),
+    "ks_torus_192_mixed_auto": dict(cfg=3, n=192, precision=1, fused="auto"),
+    "amr_like_4096_mixed_auto": dict(cfg=4, precision=1, fused="auto"),
+    "ks_turb_384_mixed_auto": dict(cfg=5, n=384, precision=1, fused="auto"),
 }
 
 
@@ -167,7 +178,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10, help="timed SSP-RK2 steps (2 substeps each)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="ks_torus_128_fp64_plain", choices=sorted(WORKLOADS))
-    ap.add_argument("--compare", default="ks_torus_128_mixed_plain",
+    ap.add_argument("--compare", default="ks_torus_128_mixed_auto",
                     help="second path on the same grid reported beside the headline ('' to skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of the captured step graph")
@@ -201,8 +212,13 @@ def main(argv=None):
     torch.cuda.set_device(0)
 
     def make(name):
-        w = WORKLOADS[name]
-        c = I.make_case(w["cfg"], n=w["n"])
+        w = dict(WORKLOADS[name])
+        c = I.make_case(w["cfg"], **({"n": w["n"]} if "n" in w else {}))
+        if w["fused"] == "auto":
+            from paper_2108_12240_amd import autotune
+            params, report = autotune.tune(dict(c.params, precision=w["precision"]), c.blocks, c.prim)
+            w["fused"] = int(params["fused"])
+            w["autotune"] = report
         c.params = dict(c.params, precision=w["precision"], fused=w["fused"])
         return c, w
 
@@ -214,9 +230,13 @@ def main(argv=None):
                scaling="weak", vs_baseline=None, dtype="f64" if rsz == 8 else "f32+f64",
                data="synthetic (seeded Kerr-Schild torus, no dataset)",
                config=dict(workload=args.workload, zones=res["info"]["ncell"], blocks=int(case.nblocks),
-                           block_size=16, substeps_per_step=2, recon="PPM", flux="HLL",
+                           block_sizes=sorted(set(int(v) for v in case.blocks[:, 1])),
+                           levels=sorted(set(int(v) for v in case.blocks[:, 0])), substeps_per_step=2,
+                           recon="PPM", flux="HLL",
                            fused=bool(w["fused"]), graph=res["graph"]),
                roofline=roofline(res, rsz))
+    if "autotune" in w:
+        out["config"]["autotune"] = {str(t["choice"]["fused"]): t["ms_per_step"] for t in w["autotune"]["timings"]}
     out["kernel_ms"] = {k: round(v[1] / max(v[0], 1), 4) for k, v in res["ktimes"].items()}
     out["c2p"] = res["stats"]
     out["finite"] = res["finite"]
@@ -224,7 +244,7 @@ def main(argv=None):
         c2, w2 = make(args.compare)
         r2 = run_gpu(c2, args.steps, args.warmup, graph=not args.eager)
         rsz2 = 4 if w2["precision"] == 1 else 8
-        out["compare"] = dict(workload=args.compare, value=round(r2["value"], 1),
+        out["compare"] = dict(workload=args.compare, fused=bool(w2["fused"]), value=round(r2["value"], 1),
                               ms_per_step=round(r2["ms_per_step"], 4), dtype="f64" if rsz2 == 8 else "f32+f64",
                               speedup_vs_headline=round(r2["value"] / res["value"], 3),
                               roofline=roofline(r2, rsz2),

@@ -75,7 +75,8 @@ enum { BHAC_PREC_FP64 = 0, BHAC_PREC_MIXED = 1 };
  *                       the RK accumulation (compensated) and the inversion in
  *                       double.
  *  fused                0: bhac_substep reads P_stage ghost slots, which must be
- *                       filled first by bhac_fill_ghosts.
+ *                       filled first by bhac_fill_ghosts (or, enough for the
+ *                       substep, bhac_fill_ghost_faces).
  *                       1: one persistent kernel per substep gathers each
  *                       block's ghost halo itself (P ghost slots are not read
  *                       and not written).
@@ -151,6 +152,12 @@ int bhac_free_blocks(bhac_grid *grid);
  * or float per precision; written in ghost slots only. */
 int bhac_fill_ghosts(bhac_grid *grid, void *prim, void *stream);
 
+/* The same fill restricted to the face-adjacent ghost slabs (slots with exactly
+ * one coordinate outside the block): the only ghost cells the unfused substep's
+ * dimension-by-dimension stencils read. Edge and corner slots are left as they
+ * are. Same arguments and errors as bhac_fill_ghosts. */
+int bhac_fill_ghost_faces(bhac_grid *grid, void *prim, void *stream);
+
 /* Primitive -> conserved at interior cells (Section 2's integrated conserved
  * variables): W = sqrt(1 + gamma_ij u~^i u~^j), v^i = u~^i / W,
  * xi = rho h W^2 with h = 1 + Gamma/(Gamma-1) p/rho, D = rho W,
@@ -212,8 +219,8 @@ int bhac_reset_stats(bhac_grid *grid, void *stream);
 
 /* One whole SSP-RK2 step as a HIP graph (the launch-bound inner loop of a run).
  * bhac_capture_rk2_step records, on a stream the grid owns, the kernels of
- *   [ghost fill of P] -> substep(U, U, P -> U1, P1, 0, 1)
- *   -> [ghost fill of P1] -> substep(U, U1, P1 -> U, P, 1/2, 1/2)
+ *   [face-ghost fill of P] -> substep(U, U, P -> U1, P1, 0, 1)
+ *   -> [face-ghost fill of P1] -> substep(U, U1, P1 -> U, P, 1/2, 1/2)
  * (ghost fills only when fused == 0) for these exact buffers, and instantiates it;
  * a new capture replaces the previous graph. bhac_launch_rk2_step replays it on
  * the caller's stream: one call per step, same results as the four calls made

@@ -73,6 +73,7 @@ def lib():
                                   C.POINTER(_VP), C.POINTER(bhac_layout)],
             "bhac_free_blocks": [_VP],
             "bhac_fill_ghosts": [_VP, _VP, _VP],
+            "bhac_fill_ghost_faces": [_VP, _VP, _VP],
             "bhac_prim2con": [_VP, _VP, _VP, _VP],
             "bhac_con2prim": [_VP, _VP, _VP, _VP, _VP],
             "bhac_substep": [_VP, _VP, _VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP],
@@ -175,6 +176,10 @@ def _stream(stream):
 
 def bhac_fill_ghosts(h, prim, stream=None):
     _check(lib().bhac_fill_ghosts(h, _ptr(prim), _stream(stream)))
+
+
+def bhac_fill_ghost_faces(h, prim, stream=None):
+    _check(lib().bhac_fill_ghost_faces(h, _ptr(prim), _stream(stream)))
 
 
 def bhac_prim2con(h, prim, cons, stream=None):
@@ -306,6 +311,9 @@ class Grid:
     def fill_ghosts(self, P):
         bhac_fill_ghosts(self.h, P)
 
+    def fill_ghost_faces(self, P):
+        bhac_fill_ghost_faces(self.h, P)
+
     def prim2con(self, P, U):
         bhac_prim2con(self.h, P, U)
 
@@ -334,10 +342,10 @@ class Grid:
         """One SSP-RK2 step in place on (U, P) with scratch (U1, P1)."""
         fused = int(self.params["fused"]) == 1
         if not fused:
-            self.fill_ghosts(P)
+            self.fill_ghost_faces(P)
         self.substep(U, U, P, U1, P1, 0.0, 1.0)
         if not fused:
-            self.fill_ghosts(P1)
+            self.fill_ghost_faces(P1)
         self.substep(U, U1, P1, U, P, 0.5, 0.5)
 
     def capture_rk2_step(self, U, P, U1, P1):

@@ -186,6 +186,7 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     UP(G.d_halo, P.halo);
 #undef UP
     G.nghost_slots = (long long)P.gdst.size();
+    G.nface_slots = P.nface_slots;
     {
         const size_t rsz = G.mixed ? sizeof(float) : sizeof(double);
         for (int d = 0; d < p.ndim && !p.fused; d++) {
@@ -264,6 +265,15 @@ int bhac_fill_ghosts(bhac_grid *g, void *prim, void *stream)
     g->last_stream = (hipStream_t)stream;
     hipError_t e = bhac::launch_fill(g->dg, prim, (hipStream_t)stream);
     return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_fill_ghosts");
+}
+
+int bhac_fill_ghost_faces(bhac_grid *g, void *prim, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!prim) return fail(BHAC_EINVAL, "null prim");
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_fill(g->dg, prim, (hipStream_t)stream, true);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_fill_ghost_faces");
 }
 
 int bhac_prim2con(bhac_grid *g, const void *prim, double *cons, void *stream)
@@ -393,9 +403,9 @@ int bhac_capture_rk2_step(bhac_grid *g, double *U, void *P, double *U1, void *P1
     }
     const bool fused = g->dg.plan.p.fused != 0;
     hipError_t le = hipSuccess;
-    if (!fused) le = bhac::launch_fill(g->dg, P, s);
+    if (!fused) le = bhac::launch_fill(g->dg, P, s, true);
     if (le == hipSuccess) le = bhac::launch_substep(g->dg, U, U, P, U1, P1, 0.0, 1.0, s);
-    if (le == hipSuccess && !fused) le = bhac::launch_fill(g->dg, P1, s);
+    if (le == hipSuccess && !fused) le = bhac::launch_fill(g->dg, P1, s, true);
     if (le == hipSuccess) le = bhac::launch_substep(g->dg, U, U1, P1, U, P, 0.5, 0.5, s);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);

@@ -104,10 +104,11 @@ struct DeviceGrid {
     void *d_flux[3] = {nullptr, nullptr, nullptr};   // face-flux scratch of the unfused path
     void *d_div = nullptr;                           // flux divergence of the block-tiled path [9][interior]
     long long nghost_slots = 0;
+    long long nface_slots = 0;                       // leading slots of the map with one axis outside
     bool have_dt = false;
 };
 
-hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s);
+hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only = false);
 hipError_t launch_prim2con(const DeviceGrid &G, const void *P, double *U, hipStream_t s);
 hipError_t launch_con2prim(const DeviceGrid &G, const double *U, void *P, int8_t *fail, hipStream_t s);
 hipError_t launch_compute_dt(const DeviceGrid &G, const void *P, hipStream_t s);

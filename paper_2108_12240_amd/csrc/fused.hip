@@ -174,7 +174,7 @@ __global__ __launch_bounds__(FWG, 2) void k_block_flux(KParams kp, GridDev gd, i
             q2[v] = w[5][v];
             sg1[v] = sd;
         }
-        lam2 = fmaxf(lam2, face_flux<float, 2, FLUX>(qpL, qmL, mz, ch, gam, gfac, fzp));
+        lam2 = fmaxf(lam2, face_flux_lean<float, 2, FLUX>(qpL, qmL, mz, ch, gam, gfac, fzp));
     }
 
     const int nhx = 6 * s1, nhy = 6 * s0;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(FWG, 2) void k_block_flux(KParams kp, GridDev gd, i
                 qR[v] = qx(0, v, jj, ii);
             }
             const FaceM<float> m = face_metric<float, 0, KS>(gk, B, ii, jj);
-            lam0 = fmaxf(lam0, face_flux<float, 0, FLUX>(qL, qR, m, ch, gam, gfac, F));
+            lam0 = fmaxf(lam0, face_flux_lean<float, 0, FLUX>(qL, qR, m, ch, gam, gfac, F));
 #pragma unroll
             for (int v = 0; v < NV; v++) fx(v, jj, ii) = F[v];
         };
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(FWG, 2) void k_block_flux(KParams kp, GridDev gd, i
                 qR[v] = qy(0, v, jj, ii);
             }
             const FaceM<float> m = face_metric<float, 1, KS>(gk, B, ii, jj);
-            lam1 = fmaxf(lam1, face_flux<float, 1, FLUX>(qL, qR, m, ch, gam, gfac, F));
+            lam1 = fmaxf(lam1, face_flux_lean<float, 1, FLUX>(qL, qR, m, ch, gam, gfac, F));
 #pragma unroll
             for (int v = 0; v < NV; v++) fy(v, jj, ii) = F[v];
         };
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(FWG, 2) void k_block_flux(KParams kp, GridDev gd, i
             float qL[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) qL[v] = qp[v];
-            lam2 = fmaxf(lam2, face_flux<float, 2, FLUX>(qL, qm1, mz, ch, gam, gfac, fz));
+            lam2 = fmaxf(lam2, face_flux_lean<float, 2, FLUX>(qL, qm1, mz, ch, gam, gfac, fz));
         }
         __syncthreads();
 

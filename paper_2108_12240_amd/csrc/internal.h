@@ -60,7 +60,8 @@ struct Plan {
     std::vector<DevLevel> levels;        // indexed by level
     int maxlevel = 0;
     int gd[3] = {0, 0, 0};               // ghost layers per axis
-    std::vector<int32_t> gdst, gsrc;     // same-level ghost gather map
+    std::vector<int32_t> gdst, gsrc;     // same-level ghost gather map: face-adjacent slots first,
+    long long nface_slots = 0;           // then edge and corner slots
     // metric tables (empty for flat space)
     long long nrec_c = 0, nrec_f0 = 0, nrec_f1 = 0;
     std::vector<double> ctab, f0tab, f1tab;

@@ -88,7 +88,7 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
 }
 
 template <typename R, bool KS>
-__global__ __launch_bounds__(WG) void k_update(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+__global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
                                                const double *Ub, const double *Us, const R *__restrict__ Ps,
                                                double *Uo, R *__restrict__ Po, const R *__restrict__ F0,
                                                const R *__restrict__ F1, const R *__restrict__ F2, long long nf0,
@@ -310,18 +310,18 @@ const char *const kKernelNames[K_COUNT] = {"fill_ghosts", "flux_x1", "flux_x2", 
                                            "prim2con", "con2prim", "cell_speeds", "step_begin", "step_end",
                                            "block_flux", "update_div"};
 
-hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s)
+hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only)
 {
-    if (G.nghost_slots == 0) return hipSuccess;
+    // the face-adjacent slots come first in the gather map (see make_plan)
+    const long long n = faces_only ? G.nface_slots : G.nghost_slots;
+    if (n == 0) return hipSuccess;
     TimedLaunch tl(G.timer, K_FILL, s);
-    const unsigned nchunk = nblk(G.nghost_slots);
+    const unsigned nchunk = nblk(n);
     const unsigned grid = ((nchunk + NXCD - 1) / NXCD) * NXCD;
     if (G.mixed)
-        hipLaunchKernelGGL(k_fill<float>, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, G.nghost_slots,
-                           (float *)P, G.kp.ncp);
+        hipLaunchKernelGGL(k_fill<float>, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (float *)P, G.kp.ncp);
     else
-        hipLaunchKernelGGL(k_fill<double>, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, G.nghost_slots,
-                           (double *)P, G.kp.ncp);
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (double *)P, G.kp.ncp);
     return hipGetLastError();
 }
 

@@ -279,9 +279,12 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                 }
     }
 
-    // same-level ghost gather map, one entry per ghost slot in padded order
+    // same-level ghost gather map, one entry per ghost slot in padded order: the
+    // slots with exactly one coordinate outside the block (the face slabs, which
+    // are all a dimension-by-dimension stencil reads) first, then edges and corners
     P.gdst.clear();
     P.gsrc.clear();
+    std::vector<int32_t> edst, esrc;
     for (int64_t b = 0; b < nb; b++) {
         const DevBlock &D = P.dblocks[b];
         const int n2 = D.s[2] + 2 * P.gd[2];
@@ -289,8 +292,9 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
             for (int pj = 0; pj < D.n1; pj++)
                 for (int pi = 0; pi < D.n0; pi++) {
                     const int l[3] = {pi - P.gd[0], pj - P.gd[1], pk - P.gd[2]};
-                    if (l[0] >= 0 && l[0] < D.s[0] && l[1] >= 0 && l[1] < D.s[1] && l[2] >= 0 && l[2] < D.s[2])
-                        continue;
+                    int nout = 0;
+                    for (int e = 0; e < 3; e++) nout += (l[e] < 0 || l[e] >= D.s[e]);
+                    if (nout == 0) continue;
                     int dir[3], src[3];
                     for (int e = 0; e < 3; e++) {
                         const HaloAxis &h = P.halo[((size_t)b * 3 + e) * P.hmax + (l[e] + P.gd[e])];
@@ -306,10 +310,15 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                     const long long from =
                         S.off + ((long long)(src[2] + P.gd[2]) * S.n1 + (src[1] + P.gd[1])) * S.n0 + (src[0] + P.gd[0]);
                     const long long to = D.off + ((long long)pk * D.n1 + pj) * D.n0 + pi;
-                    P.gdst.push_back((int32_t)to);
-                    P.gsrc.push_back((int32_t)from);
+                    std::vector<int32_t> &vd = nout == 1 ? P.gdst : edst;
+                    std::vector<int32_t> &vs = nout == 1 ? P.gsrc : esrc;
+                    vd.push_back((int32_t)to);
+                    vs.push_back((int32_t)from);
                 }
     }
+    P.nface_slots = (long long)P.gdst.size();
+    P.gdst.insert(P.gdst.end(), edst.begin(), edst.end());
+    P.gsrc.insert(P.gsrc.end(), esrc.begin(), esrc.end());
     (void)g;
 
     // metric tables

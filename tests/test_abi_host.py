@@ -78,3 +78,14 @@ def test_ghost_plan_matches_oracle_fill_bitwise(name, make):
     interior[G.interior_index()] = True
     assert len(np.unique(dst)) == len(dst) == G.ncp - G.nci
     assert interior[src].all() and not interior[dst].any()
+
+
+def test_autotune_signature_is_host_logic():
+    from paper_2108_12240_amd import autotune
+    c = I.case4(nblocks=32, n0=48)
+    sig = autotune.signature(c.params, c.blocks)
+    assert sum(sig["blocks"].values()) == 32
+    assert sig["precision"] == c.params["precision"]
+    k1 = autotune._key("gfx950", sig)
+    assert k1 == autotune._key("gfx950", autotune.signature(c.params, c.blocks))
+    assert k1 != autotune._key("gfx942", sig)

@@ -109,6 +109,7 @@ def test_fp64_ten_steps(torch, name, make):
 MIXED_CASES = [
     ("case1_64", lambda: I.case1()),
     ("torus_32", lambda: I.case_torus(2, n=32)),
+    ("turbulent_torus_48", lambda: I.case_torus(5, n=48)),
     ("amr_like_64", lambda: I.case4(nblocks=64, n0=48)),
 ]
 
@@ -125,6 +126,7 @@ def test_mixed_ten_steps(torch, name, make):
 
 FUSED_CASES = [
     ("torus_32", lambda: I.case_torus(2, n=32)),
+    ("turbulent_torus_48", lambda: I.case_torus(5, n=48)),
     ("torus_48x32x32", lambda: I.case_torus(2, n=(48, 32, 32))),
     ("amr_like_64", lambda: I.case4(nblocks=64, n0=48)),
 ]
@@ -177,3 +179,32 @@ def test_substep_rejects_aliasing_and_uninitialised_dt(torch):
         G.substep(U, U, P, U, P2, 0.0, 1.0)
     assert e.value.code == B.BHAC_EINVAL
     G.close()
+
+
+def test_fill_ghost_faces_fills_exactly_the_face_slabs(torch):
+    for c in (I.case_torus(2, n=(48, 32, 32)), I.case4(nblocks=64, n0=48)):
+        banner(f"face fill {c.name}")
+        G = B.Grid(c.params, c.blocks)
+        Og = O.OracleGrid(c.params, c.blocks)
+        ids = np.zeros((9, G.ncp))
+        for q in range(9):
+            ids[q] = (np.arange(G.ncp) % 1000003) + 1.5 * q     # exact in float32
+        ref = ids.copy()
+        Og.fill_ghosts(ref)
+        P = torch.from_numpy(ids).to("cuda", G.pdtype)
+        G.fill_ghost_faces(P)
+        got = P.cpu().double().numpy()
+        # classify every padded cell by how many coordinates lie outside its block
+        g = c.params["nghost"]
+        nout = np.zeros(G.ncp, dtype=np.int64)
+        for b, blk in enumerate(c.blocks):
+            s = blk[1:4]
+            n = s + 2 * g
+            k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+            cnt = sum(((x - g) < 0) | ((x - g) >= s[e]) for e, x in enumerate((i, j, k)))
+            nout[G.off[b]:G.off[b + 1]] = cnt.ravel()
+        face = nout == 1
+        assert np.array_equal(got[:, face], ref[:, face])
+        assert np.array_equal(got[:, nout >= 2], ids[:, nout >= 2])
+        assert np.array_equal(got[:, nout == 0], ids[:, nout == 0])
+        G.close()
