@@ -74,12 +74,13 @@ enum { BHAC_PREC_FP64 = 0, BHAC_PREC_MIXED = 1 };
  *                       fluxes and their divergence in float; metric, sources,
  *                       the RK accumulation (compensated) and the inversion in
  *                       double.
- *  fused                0: bhac_substep reads P_stage ghost slots, which must be
- *                       filled first by bhac_fill_ghosts (or, enough for the
- *                       substep, bhac_fill_ghost_faces).
- *                       1: one persistent kernel per substep gathers each
- *                       block's ghost halo itself (P ghost slots are not read
- *                       and not written).
+ *  fused                0: one kernel per direction computes the face fluxes,
+ *                       one kernel per cell the update.
+ *                       1: a block-tiled kernel per substep stages each block
+ *                       with its halo in LDS, then the per-cell update.
+ *                       Either way bhac_substep reads the halo of a block from
+ *                       its neighbours' interior cells, by the rule of
+ *                       bhac_fill_ghosts, and no ghost slot of P_stage.
  *  cfl                  Courant number C of dt = C / sum_d (lambda_d / dx_d).
  *  rho_floor, p_floor, w_max   floors applied after a converged inversion.
  *  glm_alpha            GLM damping: kappa = glm_alpha * c_h / min_d dx_d.
@@ -153,8 +154,8 @@ int bhac_free_blocks(bhac_grid *grid);
 int bhac_fill_ghosts(bhac_grid *grid, void *prim, void *stream);
 
 /* The same fill restricted to the face-adjacent ghost slabs (slots with exactly
- * one coordinate outside the block): the only ghost cells the unfused substep's
- * dimension-by-dimension stencils read. Edge and corner slots are left as they
+ * one coordinate outside the block): the halo cells that dimension-by-dimension
+ * stencils (such as the substep's) read. Edge and corner slots are left as they
  * are. Same arguments and errors as bhac_fill_ghosts. */
 int bhac_fill_ghost_faces(bhac_grid *grid, void *prim, void *stream);
 
@@ -192,7 +193,10 @@ int bhac_con2prim(bhac_grid *grid, const double *cons, void *prim_inout, int8_t 
  * |lambda| per direction for the next latch. Call bhac_compute_dt or bhac_set_dt
  * once before the first substep (else BHAC_EINVAL).
  * Aliasing: U_out may alias U_base and/or U_stage; P_out must not alias P_stage
- * (BHAC_EALIAS). P_out ghost slots are left unchanged. */
+ * (BHAC_EALIAS). The halo cells of each block are read from the neighbouring
+ * blocks' interiors (or the own edge cell, where bhac_fill_ghosts would copy
+ * that), so the ghost slots of P_stage need not be filled; the ghost slots of
+ * P_out are left unchanged. */
 int bhac_substep(bhac_grid *grid, const double *U_base, const double *U_stage, const void *P_stage,
                  double *U_out, void *P_out, double a, double b, void *stream);
 
@@ -219,14 +223,13 @@ int bhac_reset_stats(bhac_grid *grid, void *stream);
 
 /* One whole SSP-RK2 step as a HIP graph (the launch-bound inner loop of a run).
  * bhac_capture_rk2_step records, on a stream the grid owns, the kernels of
- *   [face-ghost fill of P] -> substep(U, U, P -> U1, P1, 0, 1)
- *   -> [face-ghost fill of P1] -> substep(U, U1, P1 -> U, P, 1/2, 1/2)
- * (ghost fills only when fused == 0) for these exact buffers, and instantiates it;
- * a new capture replaces the previous graph. bhac_launch_rk2_step replays it on
- * the caller's stream: one call per step, same results as the four calls made
- * one by one. The time-step state lives on the device, so replays need no host
- * work. Needs an initialised time step (BHAC_EINVAL otherwise); P/P1 aliasing
- * rules as for bhac_substep. Launching before a capture returns BHAC_EINVAL. */
+ *   substep(U, U, P -> U1, P1, 0, 1) -> substep(U, U1, P1 -> U, P, 1/2, 1/2)
+ * for these exact buffers, and instantiates it; a new capture replaces the
+ * previous graph. bhac_launch_rk2_step replays it on the caller's stream: one
+ * call per step, same results as the two calls made one by one. The time-step
+ * state lives on the device, so replays need no host work. Needs an initialised
+ * time step (BHAC_EINVAL otherwise); P/P1 aliasing rules as for bhac_substep.
+ * Launching before a capture returns BHAC_EINVAL. */
 int bhac_capture_rk2_step(bhac_grid *grid, double *U, void *P, double *U1, void *P1);
 int bhac_launch_rk2_step(bhac_grid *grid, void *stream);
 

@@ -339,13 +339,9 @@ class Grid:
         return U, P
 
     def rk2_step(self, U, P, U1, P1):
-        """One SSP-RK2 step in place on (U, P) with scratch (U1, P1)."""
-        fused = int(self.params["fused"]) == 1
-        if not fused:
-            self.fill_ghost_faces(P)
+        """One SSP-RK2 step in place on (U, P) with scratch (U1, P1). The substeps
+        read each block's halo from its neighbours, so no ghost fill is needed."""
         self.substep(U, U, P, U1, P1, 0.0, 1.0)
-        if not fused:
-            self.fill_ghost_faces(P1)
         self.substep(U, U1, P1, U, P, 0.5, 0.5)
 
     def capture_rk2_step(self, U, P, U1, P1):

@@ -401,11 +401,9 @@ int bhac_capture_rk2_step(bhac_grid *g, double *U, void *P, double *U1, void *P1
         g->dg.timer.on = timing;
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    const bool fused = g->dg.plan.p.fused != 0;
-    hipError_t le = hipSuccess;
-    if (!fused) le = bhac::launch_fill(g->dg, P, s, true);
-    if (le == hipSuccess) le = bhac::launch_substep(g->dg, U, U, P, U1, P1, 0.0, 1.0, s);
-    if (le == hipSuccess && !fused) le = bhac::launch_fill(g->dg, P1, s, true);
+    // every substep reads its halo cells from the neighbouring blocks' interiors,
+    // so the step needs no ghost fill
+    hipError_t le = bhac::launch_substep(g->dg, U, U, P, U1, P1, 0.0, 1.0, s);
     if (le == hipSuccess) le = bhac::launch_substep(g->dg, U, U1, P1, U, P, 0.5, 0.5, s);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);

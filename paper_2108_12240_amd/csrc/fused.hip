@@ -377,7 +377,8 @@ __global__ __launch_bounds__(FWG, 2) void k_block_flux(KParams kp, GridDev gd, i
 // Update from the stored divergence: sources (FP64), compensated RK combine,
 // inversion (FP64). One thread per interior cell.
 // ---------------------------------------------------------------------------------
-template <bool KS>
+// BASE: a != 0, so U_base is read (a template parameter keeps the loads in one block)
+template <bool KS, bool BASE>
 __global__ __launch_bounds__(WG) void k_update_div(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
                                                    const double *Ub, const double *Us, const float *__restrict__ Ps,
                                                    double *Uo, float *__restrict__ Po, const float *__restrict__ dU,
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(WG) void k_update_div(KParams kp, GridDev gd, const
             const double s = Uc[v] + x;
             const double bb = s - Uc[v];
             const double e = (Uc[v] - (s - bb)) + (x - bb);
-            Un[v] = (a == 0.0 ? 0.0 : a * Ub[v * kp.nci + ic]) + (b * s + b * e);
+            Un[v] = (BASE ? a * Ub[v * kp.nci + ic] : 0.0) + (b * s + b * e);
         }
         fail = con_to_prim(Un, q, m, kp, Pn, nit, floored);
         if (fail || floored) prim_to_cons(Pn, m, kp.gfac, Un);
@@ -449,7 +450,8 @@ static hipError_t fused_typed(const DeviceGrid &G, const double *Ub, const doubl
         if (e != hipSuccess) return e;
     }
     TimedLaunch tl(G.timer, K_UPDATE_DIV, s);
-    hipLaunchKernelGGL((k_update_div<KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, Ub, Us,
+    auto kern = a != 0.0 ? k_update_div<KS, true> : k_update_div<KS, false>;
+    hipLaunchKernelGGL(kern, dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, Ub, Us,
                        (const float *)Ps, Uo, (float *)Po, (const float *)G.d_div, G.plan.ncell_interior, a, b);
     return hipGetLastError();
 }

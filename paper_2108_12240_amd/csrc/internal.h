@@ -21,8 +21,11 @@ struct DevBlock {
     int o[3];                    // origin in level cells
     int n0, n1;                  // padded extents along x and y
     int level;
-    int pad;
+    int hclamp;                  // bit 2e+side: halo of axis e on that side (0 low, 1 high) is the
+                                 // block's own edge cell (zero-gradient); else a neighbour's cells
     long long ioff;              // first interior cell of the block in interior-packed arrays
+    long long hshift[3][2];      // added to an own-frame padded index past the low / high end of
+                                 // axis e, gives the same cell's padded index in that neighbour
 };
 
 // Per-level constants. Metric tables are 2-D in (x1, x2) because both supported

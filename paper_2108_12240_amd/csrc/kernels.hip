@@ -1,9 +1,10 @@
 // Unfused kernels of the GRMHD substep for gfx950 (wave64), plus the pointwise
 // kernels (ghost fill, prim2con, con2prim, wave-speed reduction) and their launchers.
 //
-// Unfused substep = ghost fill (separate call) -> one face-flux kernel per direction
-// (reconstruct P_stage at the face, GLM + HLL/TVDLF, |lambda| max) -> one update
-// kernel per interior cell (flux divergence, sources, RK combine, inversion).
+// Unfused substep = one face-flux kernel per direction (reconstruct P_stage at the
+// face from a stencil that reaches into the neighbouring blocks' interiors, GLM +
+// HLL/TVDLF, |lambda| max) -> one update kernel per interior cell (flux divergence,
+// sources, RK combine, inversion). No ghost fill is needed between substeps.
 // State rows are structure-of-arrays, so every load and store below is coalesced
 // along x inside a block.
 #include <hip/hip_runtime.h>
@@ -32,8 +33,23 @@ __global__ __launch_bounds__(WG) void k_fill(const int32_t *__restrict__ dst, co
 // ---------------------------------------------------------------------------------
 // Face fluxes along D: one thread per face of a block (faces 0..s_D along D).
 // ---------------------------------------------------------------------------------
+// waves per SIMD the face kernels are compiled for: the scheduler hoists the
+// stencil loads of all nine variables as far as this register budget allows
+#ifndef BHAC_FLUX_OCC_F32
+#define BHAC_FLUX_OCC_F32 6
+#endif
+#ifndef BHAC_FLUX_OCC_F64
+#define BHAC_FLUX_OCC_F64 4
+#endif
+// (double MC, whose branch-free slopes let the scheduler hoist more, gets one less)
+template <typename R, int RECON>
+constexpr int flux_occupancy()
+{
+    return sizeof(R) == 4 ? BHAC_FLUX_OCC_F32 : (RECON == BHAC_RECON_MC ? BHAC_FLUX_OCC_F64 - 1 : BHAC_FLUX_OCC_F64);
+}
+
 template <typename R, int D, int RECON, int FLUX, bool KS>
-__global__ __launch_bounds__(WG) void k_flux(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+__global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
                                              const R *__restrict__ P, R *__restrict__ F, long long nftot)
 {
     __shared__ double red[WG / 64];
@@ -50,20 +66,45 @@ __global__ __launch_bounds__(WG) void k_flux(KParams kp, GridDev gd, const WorkI
         const int k = t / fs1;
         const long long pc = pad_index(B, kp, i, j, k);
         const long long st = D == 0 ? 1 : (D == 1 ? (long long)B.n0 : (long long)B.n0 * B.n1);
+        // stencil cells l = f-3 .. f+2 along D; past either end of the block they are
+        // read from the neighbour's interior (or the own edge cell where the halo is
+        // zero-gradient), so no ghost slot of P is read
+        const int f = D == 0 ? i : (D == 1 ? j : k);
+        const int sD = B.s[D];
+        const bool clo = (B.hclamp >> (2 * D)) & 1, chi = (B.hclamp >> (2 * D + 1)) & 1;
+        constexpr int S0 = RECON == BHAC_RECON_PPM ? 0 : 1, S1 = RECON == BHAC_RECON_PPM ? 6 : 5;
+        long long cell[6];
+#pragma unroll
+        for (int s = S0; s < S1; s++) {
+            const int l = f + s - 3;
+            const long long in = pc + (s - 3) * st;
+            const long long lo = clo ? pc - f * st : in + B.hshift[D][0];
+            const long long hi = chi ? pc + (sD - 1 - f) * st : in + B.hshift[D][1];
+            cell[s] = l < 0 ? lo : (l >= sD ? hi : in);
+        }
+        // In float the reconstruction is branch-free and every stencil load of the
+        // face is written first, so all of them are in flight before the first wait.
+        // In double the nine variables' stencils do not fit the register budget
+        // together; the loop keeps them a variable at a time.
+        R q[NV][6];
         R qL[NV], qR[NV];
+        if constexpr (sizeof(R) == 4) {
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
-            const R *row = P + v * kp.ncp + pc;
-            R q[6];
-            if constexpr (RECON == BHAC_RECON_PPM) {
+            for (int v = 0; v < NV; v++) {
+                q[v][0] = q[v][5] = R(0);
 #pragma unroll
-                for (int s = 0; s < 6; s++) q[s] = row[(s - 3) * st];
-            } else {
-                q[0] = q[5] = R(0);
-#pragma unroll
-                for (int s = 1; s < 5; s++) q[s] = row[(s - 3) * st];
+                for (int s = S0; s < S1; s++) q[v][s] = P[v * kp.ncp + cell[s]];
             }
-            recon_face<R, RECON>(q, qL[v], qR[v]);
+#pragma unroll
+            for (int v = 0; v < NV; v++) recon_face<R, RECON>(q[v], qL[v], qR[v]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                q[v][0] = q[v][5] = R(0);
+#pragma unroll
+                for (int s = S0; s < S1; s++) q[v][s] = P[v * kp.ncp + cell[s]];
+                recon_face<R, RECON>(q[v], qL[v], qR[v]);
+            }
         }
         const FaceM<R> m = face_metric<R, D, KS>(gd, B, i, j);
         const R ch = (R)gd.st->ch;
@@ -87,7 +128,11 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
     e = (a - (s - bb)) + (b - bb);
 }
 
-template <typename R, bool KS>
+// ND3: three dimensions (else two); BASE: a != 0, so U_base is read. Both are
+// template parameters so that every load of a cell sits in one basic block and is
+// issued before the first wait (a uniform run-time branch per value would split
+// the loads into serial round trips).
+template <typename R, bool KS, bool ND3, bool BASE>
 __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
                                                const double *Ub, const double *Us, const R *__restrict__ Ps,
                                                double *Uo, R *__restrict__ Po, const R *__restrict__ F0,
@@ -108,12 +153,9 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
         // flux divergence, formed per direction in R, summed in double
         double div[3][NV];
 #pragma unroll
-        for (int d = 0; d < 3; d++) {
-            if (d >= kp.ndim) {
+        for (int v = 0; v < NV; v++) div[2][v] = 0.0;
 #pragma unroll
-                for (int v = 0; v < NV; v++) div[d][v] = 0.0;
-                continue;
-            }
+        for (int d = 0; d < (ND3 ? 3 : 2); d++) {
             const R *Fd = d == 0 ? F0 : (d == 1 ? F1 : F2);
             const long long nf = d == 0 ? nf0 : (d == 1 ? nf1 : nf2);
             const int fs0 = B.s[0] + (d == 0), fs1 = B.s[1] + (d == 1);
@@ -149,7 +191,7 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
             // U_out = a U_base + b (U_stage + dt L): the stage sum as an exact pair
             double s2, e2;
             two_sum(Uc[v], dt * Lv, s2, e2);
-            Un[v] = (a == 0.0 ? 0.0 : a * Ub[v * kp.nci + ci]) + (b * s2 + b * e2);
+            Un[v] = (BASE ? a * Ub[v * kp.nci + ci] : 0.0) + (b * s2 + b * e2);
         }
         double Pn[NV];
         fail = con_to_prim(Un, q, m, kp, Pn, nit, floored);
@@ -415,7 +457,10 @@ static hipError_t update_typed(const DeviceGrid &G, const double *Ub, const doub
                                void *Po, double a, double b, hipStream_t s)
 {
     TimedLaunch tl(G.timer, K_UPDATE, s);
-    hipLaunchKernelGGL((k_update<R, KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, Ub, Us,
+    const bool nd3 = G.kp.ndim == 3, base = a != 0.0;
+    auto kern = nd3 ? (base ? k_update<R, KS, true, true> : k_update<R, KS, true, false>)
+                    : (base ? k_update<R, KS, false, true> : k_update<R, KS, false, false>);
+    hipLaunchKernelGGL(kern, dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, Ub, Us,
                        (const R *)Ps, Uo, (R *)Po, (const R *)G.d_flux[0], (const R *)G.d_flux[1],
                        (const R *)G.d_flux[2], G.plan.nface[0], G.plan.nface[1], G.plan.nface[2], a, b);
     return hipGetLastError();

@@ -273,20 +273,33 @@ template <typename R>
 __device__ __forceinline__ void ppm_cell(R q0, R q1, R q2, R q3, R q4, R &qm, R &qp)
 {
     const R sm = mc_slope(q0, q1, q2), s0 = mc_slope(q1, q2, q3), sp = mc_slope(q2, q3, q4);
-    R l = R(0.5) * (q1 + q2) - (s0 - sm) * R(1.0 / 6.0);
-    R r = R(0.5) * (q2 + q3) - (sp - s0) * R(1.0 / 6.0);
+    const R l = R(0.5) * (q1 + q2) - (s0 - sm) * R(1.0 / 6.0);
+    const R r = R(0.5) * (q2 + q3) - (sp - s0) * R(1.0 / 6.0);
     const R dq = r - l;
     const R dev = q2 - R(0.5) * (l + r);
-    if ((r - q2) * (q2 - l) <= R(0)) {
-        l = q2;
-        r = q2;
-    } else if (dq * dev > dq * dq * R(1.0 / 6.0)) {
-        l = R(3) * q2 - R(2) * r;
-    } else if (-(dq * dq) * R(1.0 / 6.0) > dq * dev) {
-        r = R(3) * q2 - R(2) * l;
+    if constexpr (sizeof(R) == 8) {
+        // double: as branches, which keep each variable's stencil in a block of its
+        // own, so the face kernel fits four waves per SIMD without spilling
+        R lc = l, rc = r;
+        if ((r - q2) * (q2 - l) <= R(0)) {
+            lc = q2;
+            rc = q2;
+        } else if (dq * dev > dq * dq * R(1.0 / 6.0)) {
+            lc = R(3) * q2 - R(2) * r;
+        } else if (-(dq * dq) * R(1.0 / 6.0) > dq * dev) {
+            rc = R(3) * q2 - R(2) * l;
+        }
+        qm = lc;
+        qp = rc;
+        return;
     }
-    qm = l;
-    qp = r;
+    // float: as selects (no branches), so the stencil loads of all variables can be
+    // scheduled ahead of this arithmetic
+    const bool extremum = (r - q2) * (q2 - l) <= R(0);
+    const bool fix_l = dq * dev > dq * dq * R(1.0 / 6.0);
+    const bool fix_r = -(dq * dq) * R(1.0 / 6.0) > dq * dev;
+    qm = extremum ? q2 : (fix_l ? R(3) * q2 - R(2) * r : l);
+    qp = extremum ? q2 : (!fix_l && fix_r ? R(3) * q2 - R(2) * l : r);
 }
 
 // face i-1/2 from cells q[0..5] = i-3..i+2 (MC reads q[1..4])
@@ -327,14 +340,26 @@ __device__ __forceinline__ R face_flux(R *qL, R *qR, const FaceM<R> &m, R ch, R 
         sr = sr > R(0) ? sr : R(0);
         R sl = lmL < lmR ? lmL : lmR;
         sl = sl < R(0) ? sl : R(0);
-        if (sr == sl) {
+        if constexpr (sizeof(R) == 8) {
+            // double: a branch (fewer live registers than computing both forms)
+            if (sr == sl) {
 #pragma unroll
-            for (int v = 0; v < 8; v++) F[v] = R(0.5) * (FL[v] + FR[v]);
+                for (int v = 0; v < 8; v++) F[v] = R(0.5) * (FL[v] + FR[v]);
+            } else {
+                const R inv = frcp(sr - sl);
+                const R srsl = sr * sl;
+#pragma unroll
+                for (int v = 0; v < 8; v++) F[v] = (sr * FL[v] - sl * FR[v] + srsl * (UR[v] - UL[v])) * inv;
+            }
         } else {
-            const R inv = frcp(sr - sl);
+            const bool same = sr == sl;      // both bounds zero: the central average
+            const R inv = frcp(same ? R(1) : sr - sl);
             const R srsl = sr * sl;
 #pragma unroll
-            for (int v = 0; v < 8; v++) F[v] = (sr * FL[v] - sl * FR[v] + srsl * (UR[v] - UL[v])) * inv;
+            for (int v = 0; v < 8; v++) {
+                const R hll = (sr * FL[v] - sl * FR[v] + srsl * (UR[v] - UL[v])) * inv;
+                F[v] = same ? R(0.5) * (FL[v] + FR[v]) : hll;
+            }
         }
     } else {
         R c = fabs(lmL);

@@ -1,8 +1,10 @@
 // Host-side planning for the GRMHD substep library: parameter and block-list
 // validation, the padded state layout, the same-level ghost gather map, fused-kernel
 // halo tables, FP64 metric tables and the work lists of the unfused kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <tuple>
 #include <unordered_map>
 
 #include "internal.h"
@@ -223,9 +225,28 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
             const long long nf = (long long)(D.s[0] + (d == 0)) * (D.s[1] + (d == 1)) * (D.s[2] + (d == 2));
             D.fofs[d] = P.nface[d];
             P.nface[d] += nf;
-            for (long long st = 0; st < nf; st += WG) P.wface[d].push_back({(int)b, (int)st});
         }
         for (int d = p.ndim; d < 3; d++) D.fofs[d] = 0;
+    }
+    // face work of direction d walks the blocks in rows along d (level, size, the
+    // other two lattice coordinates, then the coordinate along d), so the blocks
+    // whose interiors a block's stencils reach are its neighbours in the list and,
+    // after the XCD split below, mostly on the same XCD (one L2)
+    for (int d = 0; d < p.ndim; d++) {
+        std::vector<int> ord(nb);
+        for (int64_t b = 0; b < nb; b++) ord[b] = (int)b;
+        const int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+        auto key = [&](int b) {
+            const bhac_block_desc &B = blocks[b];
+            return std::make_tuple(B.level, B.size[0], B.size[1], B.size[2], B.origin[e2] / B.size[e2],
+                                   B.origin[e1] / B.size[e1], B.origin[d] / B.size[d]);
+        };
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) < key(b); });
+        for (int b : ord) {
+            const DevBlock &D = P.dblocks[b];
+            const long long nf = (long long)(D.s[0] + (d == 0)) * (D.s[1] + (d == 1)) * (D.s[2] + (d == 2));
+            for (long long st = 0; st < nf; st += WG) P.wface[d].push_back({b, (int)st});
+        }
     }
 
     // XCD-aware order: work-group p runs on XCD p % NXCD, so item q is placed at
@@ -279,6 +300,36 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                 }
     }
 
+    // halo sides: for each block, axis and side, either the neighbour whose interior
+    // continues the block (same size, so local index l maps to l +- s there) or the
+    // zero-gradient clamp to the block's own edge cell. The unfused flux kernels read
+    // their halo through these; the face part of the gather map below is checked
+    // against them.
+    for (int64_t b = 0; b < nb; b++) {
+        DevBlock &D = P.dblocks[b];
+        D.hclamp = 0;
+        for (int e = 0; e < 3; e++) {
+            D.hshift[e][0] = D.hshift[e][1] = 0;
+            if (e >= p.ndim) continue;
+            const long long st = e == 0 ? 1 : (e == 1 ? (long long)D.n0 : (long long)D.n0 * D.n1);
+            const int pw = e == 0 ? 1 : (e == 1 ? 3 : 9);
+            for (int side = 0; side < 2; side++) {
+                const int l = side == 0 ? -1 : D.s[e];
+                const HaloAxis &h = P.halo[((size_t)b * 3 + e) * P.hmax + (l + P.gd[e])];
+                const int nbk = P.nbr[(size_t)b * 27 + 13 + h.dir * pw];
+                const int cont = side == 0 ? D.s[e] - 1 : 0;    // source index of a continuation
+                if (nbk >= 0 && h.src == cont) {
+                    D.hshift[e][side] = P.off[nbk] - P.off[b] + (side == 0 ? 1 : -1) * (long long)D.s[e] * st;
+                } else if (nbk < 0 || (h.dir == 0 && h.src == (side == 0 ? 0 : D.s[e] - 1))) {
+                    D.hclamp |= 1 << (2 * e + side);
+                } else {
+                    err = "internal: unexpected halo source";
+                    return BHAC_EINVAL;
+                }
+            }
+        }
+    }
+
     // same-level ghost gather map, one entry per ghost slot in padded order: the
     // slots with exactly one coordinate outside the block (the face slabs, which
     // are all a dimension-by-dimension stencil reads) first, then edges and corners
@@ -310,6 +361,22 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                     const long long from =
                         S.off + ((long long)(src[2] + P.gd[2]) * S.n1 + (src[1] + P.gd[1])) * S.n0 + (src[0] + P.gd[0]);
                     const long long to = D.off + ((long long)pk * D.n1 + pj) * D.n0 + pi;
+                    if (nout == 1) {
+                        // the halo-side rule must name the same source cell
+                        int e = 0;
+                        while (l[e] >= 0 && l[e] < D.s[e]) e++;
+                        const int side = l[e] < 0 ? 0 : 1;
+                        const long long st = e == 0 ? 1 : (e == 1 ? (long long)D.n0 : (long long)D.n0 * D.n1);
+                        long long expect;
+                        if (D.hclamp >> (2 * e + side) & 1)
+                            expect = to + (long long)((side == 0 ? 0 : D.s[e] - 1) - l[e]) * st;
+                        else
+                            expect = to + D.hshift[e][side];
+                        if (expect != from) {
+                            err = "internal: halo-side rule disagrees with the ghost gather map";
+                            return BHAC_EINVAL;
+                        }
+                    }
                     std::vector<int32_t> &vd = nout == 1 ? P.gdst : edst;
                     std::vector<int32_t> &vs = nout == 1 ? P.gsrc : esrc;
                     vd.push_back((int32_t)to);

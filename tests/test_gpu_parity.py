@@ -181,6 +181,59 @@ def test_substep_rejects_aliasing_and_uninitialised_dt(torch):
     G.close()
 
 
+def outside_count(c, G):
+    """For every padded cell: how many of its coordinates lie outside its block."""
+    g = c.params["nghost"]
+    nd = c.params["ndim"]
+    nout = np.zeros(G.ncp, dtype=np.int64)
+    for b, blk in enumerate(c.blocks):
+        s = blk[1:4]
+        n = np.array([s[e] + (2 * g if e < nd else 0) for e in range(3)])
+        k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+        cnt = sum(((x - (g if e < nd else 0)) < 0) | ((x - (g if e < nd else 0)) >= s[e])
+                  for e, x in enumerate((i, j, k)))
+        nout[G.off[b]:G.off[b + 1]] = cnt.ravel()
+    return nout
+
+
+@pytest.mark.parametrize("name,make,prec,fused", [
+    ("case1_fp64", lambda: I.case1(), I.PREC_FP64, 0),
+    ("torus_fp64", lambda: I.case_torus(2, n=(48, 32, 32)), I.PREC_FP64, 0),
+    ("torus_mixed", lambda: I.case_torus(2, n=(48, 32, 32)), I.PREC_MIXED, 0),
+    ("case4_mixed", lambda: I.case4(nblocks=64, n0=48), I.PREC_MIXED, 0),
+    ("torus_mixed_fused", lambda: I.case_torus(2, n=(48, 32, 32)), I.PREC_MIXED, 1),
+])
+def test_substep_reads_no_ghost_slot(torch, name, make, prec, fused):
+    """The substep takes its halo from the neighbouring blocks' interiors: with every
+    ghost slot of P_stage poisoned (NaN) it gives bit-identical results, and it
+    writes no ghost slot of P_out."""
+    banner(f"substep halo {name}")
+    c = with_prec(make(), prec, fused)
+    G = B.Grid(c.params, c.blocks)
+    U, P = G.init(c.prim)
+    G.set_dt(1e-3)            # both calls latch the same dt
+    nout = torch.from_numpy(outside_count(c, G)).to(P.device)
+    ids = np.zeros((9, G.ncp))
+    for q in range(9):
+        ids[q] = (np.arange(G.ncp) % 1000003) + 1.5 * q     # exact in float32
+    outs = []
+    for poison in (False, True):
+        if poison:
+            P[:, nout > 0] = float("nan")
+        U1 = G.new_state("U")
+        P1 = torch.from_numpy(ids).to("cuda", G.pdtype)
+        G.substep(U, U, P, U1, P1, 0.0, 1.0)
+        torch.cuda.synchronize()
+        outs.append((U1.cpu().numpy(), P1.cpu().double().numpy()))
+    (Ua, Pa), (Ub, Pb) = outs
+    assert np.array_equal(Ua, Ub)
+    assert np.array_equal(Pa, Pb)
+    ghost = outside_count(c, G) > 0
+    assert np.array_equal(Pb[:, ghost], ids[:, ghost])
+    assert np.isfinite(Ub).all()
+    G.close()
+
+
 def test_fill_ghost_faces_fills_exactly_the_face_slabs(torch):
     for c in (I.case_torus(2, n=(48, 32, 32)), I.case4(nblocks=64, n0=48)):
         banner(f"face fill {c.name}")
@@ -194,15 +247,7 @@ def test_fill_ghost_faces_fills_exactly_the_face_slabs(torch):
         P = torch.from_numpy(ids).to("cuda", G.pdtype)
         G.fill_ghost_faces(P)
         got = P.cpu().double().numpy()
-        # classify every padded cell by how many coordinates lie outside its block
-        g = c.params["nghost"]
-        nout = np.zeros(G.ncp, dtype=np.int64)
-        for b, blk in enumerate(c.blocks):
-            s = blk[1:4]
-            n = s + 2 * g
-            k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
-            cnt = sum(((x - g) < 0) | ((x - g) >= s[e]) for e, x in enumerate((i, j, k)))
-            nout[G.off[b]:G.off[b + 1]] = cnt.ravel()
+        nout = outside_count(c, G)
         face = nout == 1
         assert np.array_equal(got[:, face], ref[:, face])
         assert np.array_equal(got[:, nout >= 2], ids[:, nout >= 2])
