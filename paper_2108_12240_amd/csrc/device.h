@@ -98,6 +98,7 @@ struct DeviceGrid {
     float *d_ctab32 = nullptr, *d_f0tab32 = nullptr, *d_f1tab32 = nullptr;
     DevState *d_state = nullptr;
     WorkItem *d_wcell = nullptr, *d_wface[3] = {nullptr, nullptr, nullptr};
+    MarchItem *d_wmarch[3] = {nullptr, nullptr, nullptr};
     int32_t *d_gdst = nullptr, *d_gsrc = nullptr;
     int32_t *d_nbr = nullptr;
     HaloAxis *d_halo = nullptr;
@@ -116,6 +117,7 @@ hipError_t launch_set_dt(const DeviceGrid &G, double dt, hipStream_t s);
 hipError_t launch_reset_stats(const DeviceGrid &G, hipStream_t s);
 hipError_t launch_fused_body(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
                              void *Po, double a, double b, hipStream_t s);
+hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStream_t s);
 hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
                           void *Po, double a, double b, hipStream_t s);
 

@@ -48,6 +48,17 @@ constexpr int C_FACE_NF = C_SG + 1;
 
 struct WorkItem { int block; int start; };
 
+// Line-marching face kernels: a work item is MWG lines of one block (lines along D,
+// numbered with the fastest other axis first) and the faces [f0, f1) along D.
+constexpr int MWG = 64;
+struct MarchItem { int block; int line0; int f0; int f1; };
+// Directions whose faces are computed by lines (bit D) and the longest segment a
+// line is cut into (a longer line is split into equal segments, each with its own
+// warm-up, for parallelism).
+constexpr int MARCH_MASK_F32 = 4;
+constexpr int MARCH_MASK_F64 = 6;
+constexpr int MARCH_MAX_FACES = 17;
+
 // Fused-kernel halo addressing: for each block and axis, the source of every
 // padded local index l in [-g, s+g): which neighbour direction (-1, 0, +1) its
 // lattice slot lies in, and the local index to read there.
@@ -71,6 +82,8 @@ struct Plan {
     std::vector<float> ctab32, f0tab32, f1tab32;   // face fields in float (face work of the mixed path)
     // work lists (one entry per work-group of WG items inside one block)
     std::vector<WorkItem> wcell, wface[3];
+    std::vector<MarchItem> wmarch[3];
+    int march_mask = 0;                  // bit D: direction D uses the line kernel
     long long nface[3] = {0, 0, 0};
     // fused-kernel neighbour data
     std::vector<int32_t> nbr;            // 27 per block: block id of neighbour slot (dir+1 base 3), -1 if none

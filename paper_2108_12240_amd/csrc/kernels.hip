@@ -470,9 +470,12 @@ template <typename R, int RECON, int FLUX, bool KS>
 static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
                                 void *Po, double a, double b, hipStream_t s)
 {
-    hipError_t e = flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, s);
-    if (e == hipSuccess) e = flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, s);
-    if (e == hipSuccess && G.kp.ndim == 3) e = flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, s);
+    // each direction by faces or by lines, as planned
+    const int mm = G.plan.march_mask;
+    hipError_t e = mm & 1 ? launch_flux_march(G, 0, Ps, s) : flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, s);
+    if (e == hipSuccess) e = mm & 2 ? launch_flux_march(G, 1, Ps, s) : flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, s);
+    if (e == hipSuccess && G.kp.ndim == 3)
+        e = mm & 4 ? launch_flux_march(G, 2, Ps, s) : flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, s);
     if (e == hipSuccess) e = update_typed<R, KS>(G, Ub, Us, Ps, Uo, Po, a, b, s);
     return e;
 }

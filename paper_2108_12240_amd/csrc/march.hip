@@ -1,0 +1,203 @@
+// Face fluxes along one direction by columns (gfx950, wave64).
+//
+// One thread walks a line of cells along D through a block and produces the
+// fluxes of that line's faces in order. Each cell is loaded once and its MC slope,
+// PPM interface value and limited face values are computed once (the face kernel
+// recomputes them for both faces of a cell); the Riemann solve per face is the same
+// code. The line's halo past either end of the block is read from the neighbouring
+// block's interior (or the own edge cell where the halo is zero-gradient), by the
+// same rule as the face kernel. Lanes run along the fastest other axis, so every
+// load and store is coalesced.
+//
+// A work item is one wave of lines of one block and a range [f0, f1) of faces
+// along D (long lines may be cut into segments for parallelism; each segment
+// starts with its own three-cell warm-up).
+#include <hip/hip_runtime.h>
+
+#include "physics.h"
+
+namespace bhac {
+
+template <typename R, int D, int RECON, int FLUX, bool KS>
+__global__ __launch_bounds__(MWG) void k_flux_march(KParams kp, GridDev gd, const MarchItem *__restrict__ work,
+                                                    const R *__restrict__ P, R *__restrict__ F, long long nftot)
+{
+    __shared__ double red[MWG / 64];
+    const MarchItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
+    const DevBlock B = gd.blocks[w.block];
+    constexpr int A = D == 0 ? 1 : 0;             // fastest axis across the lines
+    constexpr int C = D == 2 ? 1 : 2;
+    const int sD = B.s[D];
+    const int line = w.line0 + threadIdx.x;
+    double lam = 0.0;
+    if (line < B.s[A] * B.s[C]) {
+        int ix[3];
+        ix[A] = line % B.s[A];
+        ix[C] = line / B.s[A];
+        ix[D] = 0;
+        const long long base = pad_index(B, kp, ix[0], ix[1], ix[2]);
+        const long long st = D == 0 ? 1 : (D == 1 ? (long long)B.n0 : (long long)B.n0 * B.n1);
+        const bool clo = (B.hclamp >> (2 * D)) & 1, chi = (B.hclamp >> (2 * D + 1)) & 1;
+        const long long sh_lo = B.hshift[D][0], sh_hi = B.hshift[D][1];
+        const long long ncp = kp.ncp;
+        // padded index of cell l of the line (l in [-3, sD + 2])
+        auto cell = [&](int l) -> long long {
+            const long long in = base + l * st;
+            if (l < 0) return clo ? base : in + sh_lo;
+            if (l >= sD) return chi ? base + (sD - 1) * st : in + sh_hi;
+            return in;
+        };
+        auto load = [&](int l, R *q) {
+            const long long c = cell(l);
+#pragma unroll
+            for (int v = 0; v < NV; v++) q[v] = P[v * ncp + c];
+        };
+        // index of face f of the line in the direction-D face array
+        const int fs0 = B.s[0] + (D == 0), fs1 = B.s[1] + (D == 1);
+        const long long fA = D == 0 ? 1 : (D == 1 ? (long long)fs0 : (long long)fs0 * fs1);
+        int f0ix[3] = {ix[0], ix[1], ix[2]};
+        const long long face0 = B.fofs[D] + ((long long)f0ix[2] * fs1 + f0ix[1]) * fs0 + f0ix[0];
+        const R ch = (R)gd.st->ch, gam = (R)kp.gam, gfac = (R)kp.gfac;
+        // x3 faces of a line share one metric record (the metrics do not depend on
+        // x3); along x1 and x2 the record of the next face is fetched one face ahead
+        auto metric = [&](int f) -> FaceM<R> {
+            if constexpr (D == 2) return face_metric<R, D, KS>(gd, B, ix[0], ix[1]);
+            else if constexpr (D == 0) return face_metric<R, D, KS>(gd, B, f, ix[1]);
+            else return face_metric<R, D, KS>(gd, B, ix[0], f);
+        };
+        FaceM<R> mnext = metric(w.f0);
+        R lmax = R(0);
+
+        auto solve = [&](int f, R *qL, R *qR) {
+            const FaceM<R> m = mnext;
+            if constexpr (D != 2) {
+                if (f + 1 < w.f1) mnext = metric(f + 1);
+            }
+            R Ff[NV];
+            const R l = face_flux<R, D, FLUX>(qL, qR, m, ch, gam, gfac, Ff);
+            lmax = l > lmax ? l : lmax;
+            R *out = F + face0 + f * fA;
+#pragma unroll
+            for (int v = 0; v < NV; v++) out[v * nftot] = Ff[v];
+        };
+
+        if constexpr (RECON == BHAC_RECON_PPM) {
+            // state before cell c: q_c, q_{c+1}, q_{c+2}, MC slope s_c, interface
+            // value a_{c-1/2}, and the limited upper value qp_{c-1} of cell c-1
+            R qc[NV], qn[NV], q2[NV], sc[NV], am[NV], qpp[NV];
+            {
+                R qa[NV], qb[NV];
+                load(w.f0 - 3, qa);
+                load(w.f0 - 2, qb);
+                load(w.f0 - 1, qc);
+                load(w.f0, qn);
+                load(w.f0 + 1, q2);
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    const R sb = mc_slope(qa[v], qb[v], qc[v]);
+                    sc[v] = mc_slope(qb[v], qc[v], qn[v]);
+                    am[v] = ppm_iface(qb[v], qc[v], sb, sc[v]);
+                    qpp[v] = R(0);
+                }
+            }
+            for (int c = w.f0 - 1; c < w.f1; c++) {
+                R q3[NV];
+                if (c + 1 < w.f1) load(c + 3, q3);        // next iteration's q_{c+3}
+                R qm[NV], qp[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    const R sn = mc_slope(qc[v], qn[v], q2[v]);
+                    const R ap = ppm_iface(qc[v], qn[v], sc[v], sn);
+                    ppm_limit(qc[v], am[v], ap, qm[v], qp[v]);
+                    sc[v] = sn;
+                    am[v] = ap;
+                }
+                if (c >= w.f0) solve(c, qpp, qm);          // face c: cell c-1 | cell c
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    qpp[v] = qp[v];
+                    qc[v] = qn[v];
+                    qn[v] = q2[v];
+                    q2[v] = q3[v];
+                }
+            }
+        } else {
+            // MC: state before face c: q_{c-1}, q_c, q_{c+1}, slope s_{c-1}
+            R qa[NV], qc[NV], qn[NV], sa[NV];
+            {
+                R qb[NV];
+                load(w.f0 - 2, qb);
+                load(w.f0 - 1, qa);
+                load(w.f0, qc);
+                load(w.f0 + 1, qn);
+#pragma unroll
+                for (int v = 0; v < NV; v++) sa[v] = mc_slope(qb[v], qa[v], qc[v]);
+            }
+            for (int c = w.f0; c < w.f1; c++) {
+                R q2[NV];
+                if (c + 1 < w.f1) load(c + 2, q2);
+                R qL[NV], qR[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    const R s = mc_slope(qa[v], qc[v], qn[v]);
+                    qL[v] = qa[v] + R(0.5) * sa[v];
+                    qR[v] = qc[v] - R(0.5) * s;
+                    sa[v] = s;
+                }
+                solve(c, qL, qR);
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    qa[v] = qc[v];
+                    qc[v] = qn[v];
+                    qn[v] = q2[v];
+                }
+            }
+        }
+        lam = (double)lmax;
+    }
+    const double mx = wg_max<MWG>(lam, red);
+    if (threadIdx.x == 0) raise_max(&gd.st->lam_acc[D], mx);
+}
+
+template <typename R, int D, int RECON, int FLUX, bool KS>
+hipError_t launch_flux_march_typed(const DeviceGrid &G, const void *Ps, hipStream_t s)
+{
+    const std::vector<MarchItem> &w = G.plan.wmarch[D];
+    TimedLaunch tl(G.timer, K_FLUX0 + D, s);
+    hipLaunchKernelGGL((k_flux_march<R, D, RECON, FLUX, KS>), dim3(w.size()), dim3(MWG), 0, s, G.kp, G.gd,
+                       G.d_wmarch[D], (const R *)Ps, (R *)G.d_flux[D], G.plan.nface[D]);
+    return hipGetLastError();
+}
+
+template <typename R, int D>
+static hipError_t march_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
+{
+    const int r = G.kp.recon, f = G.kp.flux;
+    if (G.ks) {
+        if (r == BHAC_RECON_PPM)
+            return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_HLL, true>(G, Ps, s)
+                                      : launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_TVDLF, true>(G, Ps, s);
+        return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_HLL, true>(G, Ps, s)
+                                  : launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_TVDLF, true>(G, Ps, s);
+    }
+    if (r == BHAC_RECON_PPM)
+        return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_HLL, false>(G, Ps, s)
+                                  : launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_TVDLF, false>(G, Ps, s);
+    return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_HLL, false>(G, Ps, s)
+                              : launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_TVDLF, false>(G, Ps, s);
+}
+
+hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStream_t s)
+{
+    if (G.mixed) {
+        if (D == 0) return march_dir<float, 0>(G, Ps, s);
+        if (D == 1) return march_dir<float, 1>(G, Ps, s);
+        return march_dir<float, 2>(G, Ps, s);
+    }
+    if (D == 0) return march_dir<double, 0>(G, Ps, s);
+    if (D == 1) return march_dir<double, 1>(G, Ps, s);
+    return march_dir<double, 2>(G, Ps, s);
+}
+
+}  // namespace bhac

@@ -268,13 +268,19 @@ __device__ __forceinline__ R mc_slope(R qm, R q0, R qp)
     return minmod0(minmod0(R(2) * dm, R(2) * dp), R(0.5) * (dm + dp));
 }
 
-// values at the lower and upper face of the centre cell q[2] of q[0..4]
+// PPM interface value between cells a and b from their values and MC slopes
 template <typename R>
-__device__ __forceinline__ void ppm_cell(R q0, R q1, R q2, R q3, R q4, R &qm, R &qp)
+__device__ __forceinline__ R ppm_iface(R qa, R qb, R sa, R sb)
 {
-    const R sm = mc_slope(q0, q1, q2), s0 = mc_slope(q1, q2, q3), sp = mc_slope(q2, q3, q4);
-    const R l = R(0.5) * (q1 + q2) - (s0 - sm) * R(1.0 / 6.0);
-    const R r = R(0.5) * (q2 + q3) - (sp - s0) * R(1.0 / 6.0);
+    return R(0.5) * (qa + qb) - (sb - sa) * R(1.0 / 6.0);
+}
+
+// PPM monotonicity constraints of a cell with value q and raw face values l, r:
+// flat at an extremum, else the face value that would overshoot is moved so that
+// the parabola stays monotone
+template <typename R>
+__device__ __forceinline__ void ppm_limit(R q2, R l, R r, R &qm, R &qp)
+{
     const R dq = r - l;
     const R dev = q2 - R(0.5) * (l + r);
     if constexpr (sizeof(R) == 8) {
@@ -291,15 +297,23 @@ __device__ __forceinline__ void ppm_cell(R q0, R q1, R q2, R q3, R q4, R &qm, R 
         }
         qm = lc;
         qp = rc;
-        return;
+    } else {
+        // float: as selects (no branches), so the stencil loads of all variables can
+        // be scheduled ahead of this arithmetic
+        const bool extremum = (r - q2) * (q2 - l) <= R(0);
+        const bool fix_l = dq * dev > dq * dq * R(1.0 / 6.0);
+        const bool fix_r = -(dq * dq) * R(1.0 / 6.0) > dq * dev;
+        qm = extremum ? q2 : (fix_l ? R(3) * q2 - R(2) * r : l);
+        qp = extremum ? q2 : (!fix_l && fix_r ? R(3) * q2 - R(2) * l : r);
     }
-    // float: as selects (no branches), so the stencil loads of all variables can be
-    // scheduled ahead of this arithmetic
-    const bool extremum = (r - q2) * (q2 - l) <= R(0);
-    const bool fix_l = dq * dev > dq * dq * R(1.0 / 6.0);
-    const bool fix_r = -(dq * dq) * R(1.0 / 6.0) > dq * dev;
-    qm = extremum ? q2 : (fix_l ? R(3) * q2 - R(2) * r : l);
-    qp = extremum ? q2 : (!fix_l && fix_r ? R(3) * q2 - R(2) * l : r);
+}
+
+// values at the lower and upper face of the centre cell q[2] of q[0..4]
+template <typename R>
+__device__ __forceinline__ void ppm_cell(R q0, R q1, R q2, R q3, R q4, R &qm, R &qp)
+{
+    const R sm = mc_slope(q0, q1, q2), s0 = mc_slope(q1, q2, q3), sp = mc_slope(q2, q3, q4);
+    ppm_limit(q2, ppm_iface(q1, q2, sm, s0), ppm_iface(q2, q3, s0, sp), qm, qp);
 }
 
 // face i-1/2 from cells q[0..5] = i-3..i+2 (MC reads q[1..4])

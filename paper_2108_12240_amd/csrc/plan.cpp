@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <tuple>
+#include <type_traits>
 #include <unordered_map>
 
 #include "internal.h"
@@ -215,7 +216,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     }
 
     // face offsets and work lists
-    for (int d = 0; d < 3; d++) { P.wface[d].clear(); P.nface[d] = 0; }
+    for (int d = 0; d < 3; d++) { P.wface[d].clear(); P.wmarch[d].clear(); P.nface[d] = 0; }
     P.wcell.clear();
     for (int64_t b = 0; b < nb; b++) {
         DevBlock &D = P.dblocks[b];
@@ -246,20 +247,31 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
             const DevBlock &D = P.dblocks[b];
             const long long nf = (long long)(D.s[0] + (d == 0)) * (D.s[1] + (d == 1)) * (D.s[2] + (d == 2));
             for (long long st = 0; st < nf; st += WG) P.wface[d].push_back({b, (int)st});
+            // lines along d: MWG per item, faces cut into nseg near-equal segments
+            const int a = d == 0 ? 1 : 0, c = d == 2 ? 1 : 2;
+            const int nline = D.s[a] * D.s[c], nfd = D.s[d] + 1;
+            const int nseg = (nfd + MARCH_MAX_FACES - 1) / MARCH_MAX_FACES;
+            for (int l0 = 0; l0 < nline; l0 += MWG)
+                for (int q = 0; q < nseg; q++)
+                    P.wmarch[d].push_back({b, l0, (int)((long long)nfd * q / nseg), (int)((long long)nfd * (q + 1) / nseg)});
         }
     }
+    P.march_mask = (p.precision == BHAC_PREC_MIXED ? MARCH_MASK_F32 : MARCH_MASK_F64) & ((1 << p.ndim) - 1);
 
     // XCD-aware order: work-group p runs on XCD p % NXCD, so item q is placed at
     // p = (q % per) * NXCD + q / per. Each XCD then walks a contiguous range of items
     // (neighbouring planes and blocks share its L2). Padding entries have block -1.
-    auto xcd_order = [](std::vector<WorkItem> &w) {
+    auto xcd_order = [](auto &w, auto pad) {
         const size_t n = w.size(), per = (n + NXCD - 1) / NXCD;
-        std::vector<WorkItem> out(per * NXCD, WorkItem{-1, 0});
+        std::remove_reference_t<decltype(w)> out(per * NXCD, pad);
         for (size_t q = 0; q < n; q++) out[(q % per) * NXCD + q / per] = w[q];
         w.swap(out);
     };
-    xcd_order(P.wcell);
-    for (int d = 0; d < p.ndim; d++) xcd_order(P.wface[d]);
+    xcd_order(P.wcell, WorkItem{-1, 0});
+    for (int d = 0; d < p.ndim; d++) {
+        xcd_order(P.wface[d], WorkItem{-1, 0});
+        xcd_order(P.wmarch[d], MarchItem{-1, 0, 0, 0});
+    }
 
     // halo sources per axis and neighbour slots (used by the gather map and the fused kernel)
     const int g = p.nghost;
