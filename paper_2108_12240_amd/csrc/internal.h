@@ -55,6 +55,10 @@ struct MarchItem { int block; int line0; int f0; int f1; };
 // Directions whose faces are computed by lines (bit D) and the longest segment a
 // line is cut into (a longer line is split into equal segments, each with its own
 // warm-up, for parallelism).
+// x1 faces with LDS-staged rows: cells one work-group stages at most (rows it
+// touches times the padded row length), per precision
+template <typename R>
+constexpr int x1s_max_cells() { return sizeof(R) == 4 ? 600 : 400; }
 constexpr int MARCH_MASK_F32 = 4;
 constexpr int MARCH_MASK_F64 = 6;
 constexpr int MARCH_MAX_FACES = 17;
@@ -84,6 +88,7 @@ struct Plan {
     std::vector<WorkItem> wcell, wface[3];
     std::vector<MarchItem> wmarch[3];
     int march_mask = 0;                  // bit D: direction D uses the line kernel
+    bool x1_staged = false;              // x1 faces by the LDS-staged face kernel
     long long nface[3] = {0, 0, 0};
     // fused-kernel neighbour data
     std::vector<int32_t> nbr;            // 27 per block: block id of neighbour slot (dir+1 base 3), -1 if none

@@ -119,6 +119,64 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KPara
 }
 
 // ---------------------------------------------------------------------------------
+// x1 face fluxes with the work-group's rows staged in LDS: the cells of every row
+// its 256 faces touch (halo included, from the neighbours as above) are loaded
+// once, coalesced along the row; each face then reads its stencil from LDS.
+// Along x1 a face's stencil lies in one padded row, so without staging every
+// load instruction of a wave touches several rows and the neighbours' halo lines.
+// ---------------------------------------------------------------------------------
+template <typename R, int RECON, int FLUX, bool KS>
+__global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(KParams kp, GridDev gd,
+                                                                            const WorkItem *__restrict__ work,
+                                                                            const R *__restrict__ P,
+                                                                            R *__restrict__ F, long long nftot)
+{
+    __shared__ R tile[NV][x1s_max_cells<R>()];
+    __shared__ double red[WG / 64];
+    const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
+    const DevBlock B = gd.blocks[w.block];
+    const int s0 = B.s[0], fs0 = s0 + 1, nface = fs0 * B.s[1] * B.s[2];
+    const int r0 = w.start / fs0;
+    const int r1 = (min(w.start + WG, nface) - 1) / fs0;
+    const int rowlen = s0 + 6;                    // cells -3 .. s0+2 of a row
+    const int ncell = (r1 - r0 + 1) * rowlen;
+    const bool clo = B.hclamp & 1, chi = (B.hclamp >> 1) & 1;
+    for (int t = threadIdx.x; t < ncell; t += WG) {
+        const int row = r0 + t / rowlen, l = t % rowlen - 3;
+        const long long base = pad_index(B, kp, 0, row % B.s[1], row / B.s[1]);
+        long long c = base + l;
+        if (l < 0) c = clo ? base : c + B.hshift[0][0];
+        else if (l >= s0) c = chi ? base + s0 - 1 : c + B.hshift[0][1];
+#pragma unroll
+        for (int v = 0; v < NV; v++) tile[v][t] = P[v * kp.ncp + c];
+    }
+    __syncthreads();
+    const int item = w.start + threadIdx.x;
+    double lam = 0.0;
+    if (item < nface) {
+        const int i = item % fs0, row = item / fs0;
+        const int t0 = (row - r0) * rowlen + i;   // tile slot of cell i - 3
+        R qL[NV], qR[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            R q[6];
+#pragma unroll
+            for (int s = 0; s < 6; s++) q[s] = tile[v][t0 + s];
+            recon_face<R, RECON>(q, qL[v], qR[v]);
+        }
+        const FaceM<R> m = face_metric<R, 0, KS>(gd, B, i, row % B.s[1]);
+        R Ff[NV];
+        lam = (double)face_flux<R, 0, FLUX>(qL, qR, m, (R)gd.st->ch, (R)kp.gam, (R)kp.gfac, Ff);
+        R *out = F + B.fofs[0] + item;
+#pragma unroll
+        for (int v = 0; v < NV; v++) out[v * nftot] = Ff[v];
+    }
+    const double mx = wg_max<WG>(lam, red);
+    if (threadIdx.x == 0) raise_max(&gd.st->lam_acc[0], mx);
+}
+
+// ---------------------------------------------------------------------------------
 // Update: divergence (in R), sources, RK combine (double), inversion (double).
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
@@ -447,6 +505,11 @@ static hipError_t flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
 {
     const std::vector<WorkItem> &w = G.plan.wface[D];
     TimedLaunch tl(G.timer, K_FLUX0 + D, s);
+    if (D == 0 && G.plan.x1_staged) {
+        hipLaunchKernelGGL((k_flux_x1s<R, RECON, FLUX, KS>), dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd,
+                           G.d_wface[0], (const R *)Ps, (R *)G.d_flux[0], G.plan.nface[0]);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_flux<R, D, RECON, FLUX, KS>), dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D],
                        (const R *)Ps, (R *)G.d_flux[D], G.plan.nface[D]);
     return hipGetLastError();
