@@ -50,6 +50,30 @@ WORKLOADS = {
 }
 
 
+# Measured HBM traffic per launch of the dominant kernel: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a plain
+# 1 GiB device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0), averaged over the launches
+# of one RK2 step. Each entry records the digest of the kernel sources it was taken
+# on; with any other sources the field is reported as null.
+TRAFFIC = {
+    # (workload, kernel family): (bytes per launch, source digest)
+    ("ks_torus_128_fp64_plain", "update"): (1265119648, "e2c7d7dc5e63a76a"),
+    ("ks_torus_128_mixed_plain", "update"): (838038170, "e2c7d7dc5e63a76a"),
+    ("ks_torus_128_mixed_auto", "update"): (838038170, "e2c7d7dc5e63a76a"),
+}
+
+
+def source_digest() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for d in (os.path.join(ROOT, "paper_2108_12240_amd", "csrc"), os.path.join(ROOT, "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".h", ".cpp")):
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def bytes_per_unit(kernel: str, rsz: int) -> float:
     """Algorithmic HBM bytes per unit of work of each kernel family (unit in unit_of)."""
     u8 = 8
@@ -129,15 +153,18 @@ def run_gpu(case, steps, warmup, graph=True):
                 stats=stats, dt=ts["dt"], finite=finite, graph=graph)
 
 
-def roofline(res, rsz):
+def roofline(res, rsz, workload):
     kt = {k: v for k, v in res["ktimes"].items() if k not in ("step_begin", "step_end", "untimed")}
     dom = max(kt, key=lambda k: kt[k][1])
     launches, total_ms = kt[dom]
     avg_s = total_ms / launches / 1e3
     alg = bytes_per_unit(dom, rsz) * units_per_launch(dom, res["info"])
     achieved = alg / avg_s / 1e9
+    measured = TRAFFIC.get((workload, dom))
+    traffic = measured[0] if measured and measured[1] == source_digest() else None
     return dict(kernel=dom, bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                traffic_over_algorithmic=round(traffic / alg, 3) if traffic else None,
                 avg_launch_ms=round(total_ms / launches, 4), bytes_per_launch=alg,
                 share_of_step=round(total_ms / sum(v[1] for v in kt.values()), 3))
 
@@ -197,7 +224,14 @@ def main(argv=None):
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps(dict(copy_probe_bytes=n * 4, repeats=3)), flush=True)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(10):
+            dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        gbs = 2 * n * 4 * 10 / (a.elapsed_time(b) / 1e3) / 1e9
+        print(json.dumps(dict(copy_probe_bytes=n * 4, repeats=13, read_plus_write_GBps=round(gbs, 1))), flush=True)
         return 0
 
     if args.gpus != 1:
@@ -234,7 +268,7 @@ def main(argv=None):
                            levels=sorted(set(int(v) for v in case.blocks[:, 0])), substeps_per_step=2,
                            recon="PPM", flux="HLL",
                            fused=bool(w["fused"]), graph=res["graph"]),
-               roofline=roofline(res, rsz))
+               roofline=roofline(res, rsz, args.workload))
     if "autotune" in w:
         out["config"]["autotune"] = {str(t["choice"]["fused"]): t["ms_per_step"] for t in w["autotune"]["timings"]}
     out["kernel_ms"] = {k: round(v[1] / max(v[0], 1), 4) for k, v in res["ktimes"].items()}
@@ -247,7 +281,7 @@ def main(argv=None):
         out["compare"] = dict(workload=args.compare, fused=bool(w2["fused"]), value=round(r2["value"], 1),
                               ms_per_step=round(r2["ms_per_step"], 4), dtype="f64" if rsz2 == 8 else "f32+f64",
                               speedup_vs_headline=round(r2["value"] / res["value"], 3),
-                              roofline=roofline(r2, rsz2),
+                              roofline=roofline(r2, rsz2, args.compare),
                               kernel_ms={k: round(v[1] / max(v[0], 1), 4) for k, v in r2["ktimes"].items()})
         del c2
     if not args.no_cpu_baseline:
