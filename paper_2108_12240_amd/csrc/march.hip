@@ -19,10 +19,12 @@
 namespace bhac {
 
 template <typename R, int D, int RECON, int FLUX, bool KS>
-__global__ __launch_bounds__(MWG) void k_flux_march(KParams kp, GridDev gd, const MarchItem *__restrict__ work,
+__global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KParams kp, GridDev gd, const MarchItem *__restrict__ work,
                                                     const R *__restrict__ P, R *__restrict__ F, long long nftot)
 {
     __shared__ double red[MWG / 64];
+    constexpr bool LST = sizeof(R) == 8;          // march state in LDS (double)
+    __shared__ R lst[LST ? 3 : 1][NV][LST ? MWG : 1];
     const MarchItem w = work[blockIdx.x];
     if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
     const DevBlock B = gd.blocks[w.block];
@@ -66,12 +68,18 @@ __global__ __launch_bounds__(MWG) void k_flux_march(KParams kp, GridDev gd, cons
             else if constexpr (D == 0) return face_metric<R, D, KS>(gd, B, f, ix[1]);
             else return face_metric<R, D, KS>(gd, B, ix[0], f);
         };
-        FaceM<R> mnext = metric(w.f0);
+        FaceM<R> mnext;
+        if constexpr (D == 2 || !LST) mnext = metric(w.f0);
         R lmax = R(0);
 
         auto solve = [&](int f, R *qL, R *qR) {
-            const FaceM<R> m = mnext;
-            if constexpr (D != 2) {
+            FaceM<R> m;
+            if constexpr (D == 2) {
+                m = mnext;
+            } else if constexpr (LST) {
+                m = metric(f);
+            } else {
+                m = mnext;
                 if (f + 1 < w.f1) mnext = metric(f + 1);
             }
             R Ff[NV];
@@ -83,43 +91,61 @@ __global__ __launch_bounds__(MWG) void k_flux_march(KParams kp, GridDev gd, cons
         };
 
         if constexpr (RECON == BHAC_RECON_PPM) {
-            // state before cell c: q_c, q_{c+1}, q_{c+2}, MC slope s_c, interface
-            // value a_{c-1/2}, and the limited upper value qp_{c-1} of cell c-1
-            R qc[NV], qn[NV], q2[NV], sc[NV], am[NV], qpp[NV];
+            // state before cell c: q_c, q_{c+1}, q_{c+2} (registers), and per
+            // variable the MC slope s_c, the interface value a_{c-1/2} and the
+            // limited upper value qp_{c-1} of cell c-1 (registers in float; in
+            // double they live in this lane's LDS slots, which keeps the kernel
+            // within the register budget of two waves per SIMD)
+            R qc[NV], qn[NV], q2[NV];
+            R sreg[LST ? 1 : 3][NV];
+            auto get = [&](int a, int v) -> R {
+                if constexpr (LST) return lst[a][v][threadIdx.x];
+                else return sreg[a][v];
+            };
+            auto put = [&](int a, int v, R x) {
+                if constexpr (LST) lst[a][v][threadIdx.x] = x;
+                else sreg[a][v] = x;
+            };
             {
                 R qa[NV], qb[NV];
                 load(w.f0 - 3, qa);
                 load(w.f0 - 2, qb);
                 load(w.f0 - 1, qc);
                 load(w.f0, qn);
-                load(w.f0 + 1, q2);
+                if constexpr (!LST) load(w.f0 + 1, q2);
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     const R sb = mc_slope(qa[v], qb[v], qc[v]);
-                    sc[v] = mc_slope(qb[v], qc[v], qn[v]);
-                    am[v] = ppm_iface(qb[v], qc[v], sb, sc[v]);
-                    qpp[v] = R(0);
+                    const R s0 = mc_slope(qb[v], qc[v], qn[v]);
+                    put(0, v, s0);
+                    put(1, v, ppm_iface(qb[v], qc[v], sb, s0));
+                    put(2, v, R(0));
                 }
             }
             for (int c = w.f0 - 1; c < w.f1; c++) {
-                R q3[NV];
-                if (c + 1 < w.f1) load(c + 3, q3);        // next iteration's q_{c+3}
-                R qm[NV], qp[NV];
+                // float: q_{c+3} is fetched one cell ahead; double loads q_{c+2} here
+                // (no room for a second set; the other wave on the SIMD hides it)
+                R q3[LST ? 1 : NV];
+                if constexpr (LST) load(c + 2, q2);
+                else if (c + 1 < w.f1) load(c + 3, q3);
+                R qm[NV], qL[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     const R sn = mc_slope(qc[v], qn[v], q2[v]);
-                    const R ap = ppm_iface(qc[v], qn[v], sc[v], sn);
-                    ppm_limit(qc[v], am[v], ap, qm[v], qp[v]);
-                    sc[v] = sn;
-                    am[v] = ap;
+                    const R ap = ppm_iface(qc[v], qn[v], get(0, v), sn);
+                    R qp;
+                    ppm_limit(qc[v], get(1, v), ap, qm[v], qp);
+                    qL[v] = get(2, v);                      // qp_{c-1}
+                    put(0, v, sn);
+                    put(1, v, ap);
+                    put(2, v, qp);
                 }
-                if (c >= w.f0) solve(c, qpp, qm);          // face c: cell c-1 | cell c
+                if (c >= w.f0) solve(c, qL, qm);           // face c: cell c-1 | cell c
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
-                    qpp[v] = qp[v];
                     qc[v] = qn[v];
                     qn[v] = q2[v];
-                    q2[v] = q3[v];
+                    if constexpr (!LST) q2[v] = q3[v];
                 }
             }
         } else {
