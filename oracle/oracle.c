@@ -42,6 +42,7 @@ typedef struct {
     int recon, flux;                   /* recon: 0 MC, 1 PPM; flux: 0 HLL, 1 TVDLF */
     double cfl, rho_floor, p_floor, w_max, glm_alpha, c2p_tol;
     int c2p_maxit;
+    int amr;                           /* 0 independent same-level patches, 1 2:1 block tree */
 } orc_params;
 
 typedef struct { int level, size[3], origin[3]; } orc_block;
@@ -558,6 +559,26 @@ void orc_grid_free(orc_grid *G)
     free(G);
 }
 
+/* Block of the given level whose region holds level-`level` cell c (each axis in
+ * [0, N_level)), among blocks of the first block's size; -1 if none. Used by the
+ * block-tree ghost rule, where all blocks share one size. */
+static int leaf_at(const orc_grid *G, int level, const int64_t c[3])
+{
+    const orc_block *B0 = &G->blk[0];
+    for (int q = 0; q < G->ngroup; q++) {
+        const ogroup *g = &G->groups[q];
+        if (g->level != level || g->size[0] != B0->size[0] || g->size[1] != B0->size[1]
+            || g->size[2] != B0->size[2]) continue;
+        int64_t sl[3];
+        for (int e = 0; e < 3; e++) {
+            sl[e] = c[e] / g->size[e];
+            if (c[e] < 0 || sl[e] >= g->nslot[e]) return -1;
+        }
+        return g->occ[(sl[2] * g->nslot[1] + sl[1]) * g->nslot[0] + sl[0]];
+    }
+    return -1;
+}
+
 /* returns NULL on invalid input */
 orc_grid *orc_grid_new(const orc_params *p, const orc_block *blocks, int64_t nb)
 {
@@ -621,6 +642,22 @@ orc_grid *orc_grid_new(const orc_params *p, const orc_block *blocks, int64_t nb)
         if (g->occ[s] != -1) goto bad;   /* two blocks in one slot */
         g->occ[s] = (int)b;
     }
+    if (p->amr) {
+        /* block tree: one block size, even along every axis in use, and no leaf
+         * inside another leaf's region (no ancestor slot occupied) */
+        for (int64_t b = 0; b < nb; b++) {
+            const orc_block *B = &G->blk[b];
+            for (int e = 0; e < 3; e++) {
+                if (B->size[e] != G->blk[0].size[e]) goto bad;
+                if (e < p->ndim && B->size[e] % 2 != 0) goto bad;
+            }
+            for (int l = 0; l < B->level; l++) {
+                int64_t c[3];
+                for (int e = 0; e < 3; e++) c[e] = e < p->ndim ? (int64_t)B->origin[e] >> (B->level - l) : 0;
+                if (leaf_at(G, l, c) >= 0) goto bad;
+            }
+        }
+    }
     return G;
 bad:
     orc_grid_free(G);
@@ -668,6 +705,147 @@ static void ghost_source(const orc_grid *G, int b, const int l[3], int *sb, int 
     }
 }
 
+/* ---------------------------------------------------------------------------------
+ * Block-tree ghost rule (amr = 1): the leaves of a 2:1-balanced tree of equal-size
+ * blocks (Section 2's block-based adaptive mesh). A ghost position of a level-l
+ * block is, after the domain's periodic wrap or outflow clamp at level l:
+ *   held by a level-l leaf    -> that cell, copied;
+ *   held by level-(l+1) leaves -> restriction: the mean of the 2^ndim fine cells
+ *                                 covering it, summed z-outer, x-inner;
+ *   held by a level-(l-1) leaf -> prolongation: coarse value q plus, per axis d,
+ *                                 (+1/4 for the upper, -1/4 for the lower half of
+ *                                 the coarse cell) times minmod(q - q_lo, q_hi - q),
+ *                                 added in axis order; q_lo, q_hi are the coarse
+ *                                 block's neighbour cells, taken from its interior
+ *                                 or, outside it, by this rule without the
+ *                                 prolongation case (a neighbour that would need it
+ *                                 gives a zero slope on that axis);
+ *   held by no leaf           -> the block's own nearest interior cell.
+ * Every case reads interior cells only, so the fill is one pass in any order.
+ * ------------------------------------------------------------------------------- */
+static void ghost_global(const orc_grid *G, int b, const int l[3], int64_t Gi[3])
+{
+    const orc_block *B = &G->blk[b];
+    for (int e = 0; e < 3; e++) {
+        if (e >= G->p.ndim) { Gi[e] = 0; continue; }
+        const int64_t N = (int64_t)G->p.ncell0[e] << B->level;
+        int64_t x = B->origin[e] + l[e];
+        if (x < 0 || x >= N) {
+            if (G->p.bc[e][x < 0 ? 0 : 1] == 0) x = ((x % N) + N) % N;
+            else x = x < 0 ? 0 : N - 1;
+        }
+        Gi[e] = x;
+    }
+}
+
+static double minmod2(double a, double b)
+{
+    if (a > 0.0 && b > 0.0) return a < b ? a : b;
+    if (a < 0.0 && b < 0.0) return a > b ? a : b;
+    return 0.0;
+}
+
+static void copy_cell(const orc_grid *G, const double *P, int64_t ncp, int b, const int64_t Gi[3], double *out)
+{
+    const orc_block *B = &G->blk[b];
+    const int64_t i = pad_index(G, b, (int)(Gi[0] - B->origin[0]), (int)(Gi[1] - B->origin[1]),
+                                (int)(Gi[2] - B->origin[2]));
+    for (int v = 0; v < NV; v++) out[v] = P[v * ncp + i];
+}
+
+static int tree_value(const orc_grid *G, const double *P, int64_t ncp, int b, const int l[3], int allow_prolong,
+                      double *out);
+
+/* value of coarse block cb at local position a (interior, or one cell outside along
+ * one axis); 0 if that position would need prolongation */
+static int coarse_neighbour(const orc_grid *G, const double *P, int64_t ncp, int cb, const int a[3], double *out)
+{
+    const orc_block *C = &G->blk[cb];
+    int inside = 1;
+    for (int e = 0; e < 3; e++) inside = inside && a[e] >= 0 && a[e] < C->size[e];
+    if (inside) {
+        const int64_t i = pad_index(G, cb, a[0], a[1], a[2]);
+        for (int v = 0; v < NV; v++) out[v] = P[v * ncp + i];
+        return 1;
+    }
+    return tree_value(G, P, ncp, cb, a, 0, out);
+}
+
+static void prolong(const orc_grid *G, const double *P, int64_t ncp, int cb, const int64_t c[3],
+                    const int64_t Gi[3], double *out)
+{
+    const orc_block *C = &G->blk[cb];
+    const int nd = G->p.ndim;
+    const int lc[3] = { (int)(c[0] - C->origin[0]), (int)(c[1] - C->origin[1]), (int)(c[2] - C->origin[2]) };
+    const int64_t ic = pad_index(G, cb, lc[0], lc[1], lc[2]);
+    double lo[3][NV], hi[3][NV];
+    int ok[3] = { 0, 0, 0 };
+    for (int d = 0; d < nd; d++) {
+        int a[3] = { lc[0], lc[1], lc[2] };
+        a[d] = lc[d] - 1;
+        const int okl = coarse_neighbour(G, P, ncp, cb, a, lo[d]);
+        a[d] = lc[d] + 1;
+        const int okh = coarse_neighbour(G, P, ncp, cb, a, hi[d]);
+        ok[d] = okl && okh;
+    }
+    for (int v = 0; v < NV; v++) {
+        const double q = P[v * ncp + ic];
+        double val = q;
+        for (int d = 0; d < nd; d++) {
+            const double sl = ok[d] ? minmod2(q - lo[d][v], hi[d][v] - q) : 0.0;
+            val += ((Gi[d] & 1) ? 0.25 : -0.25) * sl;
+        }
+        out[v] = val;
+    }
+}
+
+static int tree_value(const orc_grid *G, const double *P, int64_t ncp, int b, const int l[3], int allow_prolong,
+                      double *out)
+{
+    const orc_block *B = &G->blk[b];
+    const int nd = G->p.ndim;
+    int64_t Gi[3];
+    ghost_global(G, b, l, Gi);
+    int nbk = leaf_at(G, B->level, Gi);
+    if (nbk >= 0) {
+        copy_cell(G, P, ncp, nbk, Gi, out);
+        return 1;
+    }
+    const int64_t f[3] = { 2 * Gi[0], nd > 1 ? 2 * Gi[1] : 0, nd > 2 ? 2 * Gi[2] : 0 };
+    nbk = leaf_at(G, B->level + 1, f);
+    if (nbk >= 0) {
+        const orc_block *F = &G->blk[nbk];
+        double sum[NV];
+        for (int v = 0; v < NV; v++) sum[v] = 0.0;
+        for (int dz = 0; dz < (nd > 2 ? 2 : 1); dz++)
+            for (int dy = 0; dy < 2; dy++)
+                for (int dx = 0; dx < 2; dx++) {
+                    const int64_t i = pad_index(G, nbk, (int)(f[0] + dx - F->origin[0]), (int)(f[1] + dy - F->origin[1]),
+                                                (int)(f[2] + dz - F->origin[2]));
+                    for (int v = 0; v < NV; v++) sum[v] += P[v * ncp + i];
+                }
+        const double w = nd > 2 ? 0.125 : 0.25;
+        for (int v = 0; v < NV; v++) out[v] = sum[v] * w;
+        return 1;
+    }
+    if (B->level >= 1) {
+        const int64_t c[3] = { Gi[0] >> 1, nd > 1 ? Gi[1] >> 1 : 0, nd > 2 ? Gi[2] >> 1 : 0 };
+        nbk = leaf_at(G, B->level - 1, c);
+        if (nbk >= 0) {
+            if (!allow_prolong) return 0;
+            prolong(G, P, ncp, nbk, c, Gi, out);
+            return 1;
+        }
+    }
+    int x[3];
+    for (int e = 0; e < 3; e++) {
+        x[e] = l[e] < 0 ? 0 : (l[e] > B->size[e] - 1 ? B->size[e] - 1 : l[e]);
+    }
+    const int64_t i = pad_index(G, b, x[0], x[1], x[2]);
+    for (int v = 0; v < NV; v++) out[v] = P[v * ncp + i];
+    return 1;
+}
+
 static void fill_block(const orc_grid *G, int b, double *P, int64_t ncp)
 {
     const orc_block *B = &G->blk[b];
@@ -679,9 +857,15 @@ static void fill_block(const orc_grid *G, int b, double *P, int64_t ncp)
                                    && k < B->size[2];
                 if (inside) continue;
                 const int l[3] = { i, j, k };
+                const int64_t dst = pad_index(G, b, i, j, k);
+                if (G->p.amr) {
+                    double val[NV];
+                    tree_value(G, P, ncp, b, l, 1, val);
+                    for (int v = 0; v < NV; v++) P[v * ncp + dst] = val[v];
+                    continue;
+                }
                 int sb, src[3];
                 ghost_source(G, b, l, &sb, src);
-                const int64_t dst = pad_index(G, b, i, j, k);
                 const int64_t from = pad_index(G, sb, src[0], src[1], src[2]);
                 for (int v = 0; v < NV; v++) P[v * ncp + dst] = P[v * ncp + from];
             }

@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("recon", C.c_int), ("flux", C.c_int),
                 ("cfl", C.c_double), ("rho_floor", C.c_double), ("p_floor", C.c_double),
                 ("w_max", C.c_double), ("glm_alpha", C.c_double), ("c2p_tol", C.c_double),
-                ("c2p_maxit", C.c_int)]
+                ("c2p_maxit", C.c_int), ("amr", C.c_int)]
 
 
 class Block(C.Structure):
@@ -91,6 +91,7 @@ def make_params(d: dict) -> Params:
     p = Params()
     for k in ("ndim", "nghost", "metric", "recon", "flux", "c2p_maxit"):
         setattr(p, k, int(d[k]))
+    p.amr = int(d.get("amr", 0))
     for k in ("spin", "gamma_ad", "cfl", "rho_floor", "p_floor", "w_max", "glm_alpha", "c2p_tol"):
         setattr(p, k, float(d[k]))
     for e in range(3):

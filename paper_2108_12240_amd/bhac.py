@@ -34,7 +34,7 @@ class bhac_params(C.Structure):
                 ("ncell0", C.c_int * 3), ("bc", (C.c_int * 2) * 3), ("recon", C.c_int), ("flux", C.c_int),
                 ("precision", C.c_int), ("fused", C.c_int), ("cfl", C.c_double), ("rho_floor", C.c_double),
                 ("p_floor", C.c_double), ("w_max", C.c_double), ("glm_alpha", C.c_double),
-                ("c2p_tol", C.c_double), ("c2p_maxit", C.c_int)]
+                ("c2p_tol", C.c_double), ("c2p_maxit", C.c_int), ("amr", C.c_int)]
 
 
 class bhac_block_desc(C.Structure):
@@ -110,6 +110,7 @@ def make_params(d: dict) -> bhac_params:
     p = bhac_params()
     for k in ("ndim", "nghost", "metric", "recon", "flux", "precision", "fused", "c2p_maxit"):
         setattr(p, k, int(d[k]))
+    p.amr = int(d.get("amr", 0))
     for k in ("spin", "gamma_ad", "cfl", "rho_floor", "p_floor", "w_max", "glm_alpha", "c2p_tol"):
         setattr(p, k, float(d[k]))
     for e in range(3):

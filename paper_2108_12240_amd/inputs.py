@@ -73,7 +73,7 @@ def base_params(**kw) -> dict:
              bc=[[BC_OUTFLOW, BC_OUTFLOW], [BC_OUTFLOW, BC_OUTFLOW], [BC_PERIODIC, BC_PERIODIC]],
              recon=RECON_PPM, flux=FLUX_HLL, precision=PREC_FP64, fused=0,
              cfl=0.4, rho_floor=RHO_ATM, p_floor=P_ATM, w_max=50.0, glm_alpha=0.1,
-             c2p_tol=1.0e-13, c2p_maxit=50)
+             c2p_tol=1.0e-13, c2p_maxit=50, amr=0)
     p.update(kw)
     return p
 
@@ -297,6 +297,95 @@ def case4(nblocks: int = 4096, n0: int = 96, levels: int = 3, precision=PREC_MIX
         prim[:, sl], rr[sl], tt[sl] = _torus_cells(params, int(blocks[b, 0]), g0, g1, g2, noise[sl])
     prim = _finish_torus(prim, rr)
     return Case(f"case4_amrlike_{nblocks}", params, blocks, prim, ioff, steps=10)
+
+
+def _tree_leaves(params, bs, levels, thresholds):
+    """Leaves (level, i, j, k) of a 2:1-balanced tree of bs^3 blocks over the level-0
+    lattice: a block is refined while the synthetic torus density sampled at its
+    cells exceeds the threshold of its level, then coarse leaves next to leaves two
+    levels finer (across faces, edges or corners) are refined until none is."""
+    n0 = params["ncell0"]
+    per = [params["bc"][d][0] == BC_PERIODIC for d in range(3)]
+    nsl0 = [n0[d] // bs for d in range(3)]
+    leaves = {(0, i, j, k) for i in range(nsl0[0]) for j in range(nsl0[1]) for k in range(nsl0[2])}
+
+    def rho_max(lf):
+        l, i, j, _ = lf
+        x_lo, x_hi = params["x_lo"], params["x_hi"]
+        dx = [(x_hi[d] - x_lo[d]) / (n0[d] * 2 ** l) for d in range(2)]
+        g0 = i * bs + np.arange(bs) + 0.5
+        g1 = j * bs + np.arange(bs) + 0.5
+        r = np.exp(x_lo[0] + g0 * dx[0])[:, None]
+        th = (x_lo[1] + g1 * dx[1])[None, :]
+        return float(_torus_density(r, th).max())
+
+    def refine(lf):
+        l, i, j, k = lf
+        leaves.remove(lf)
+        for a in range(2):
+            for b in range(2):
+                for c in range(2):
+                    leaves.add((l + 1, 2 * i + a, 2 * j + b, 2 * k + c))
+
+    def covering(l, idx):
+        for m in range(l, -1, -1):
+            key = (m,) + tuple(v >> (l - m) for v in idx)
+            if key in leaves:
+                return key
+        return None
+
+    def balance():
+        changed = True
+        while changed:
+            changed = False
+            for lf in sorted(leaves, reverse=True):
+                if lf not in leaves or lf[0] < 2:
+                    continue
+                l = lf[0]
+                for di in (-1, 0, 1):
+                    for dj in (-1, 0, 1):
+                        for dk in (-1, 0, 1):
+                            idx = [lf[1] + di, lf[2] + dj, lf[3] + dk]
+                            ok = True
+                            for d in range(3):
+                                n = nsl0[d] << l
+                                if per[d]:
+                                    idx[d] %= n
+                                elif not 0 <= idx[d] < n:
+                                    ok = False
+                            cov = covering(l, idx) if ok else None
+                            if cov is not None and cov[0] < l - 1:
+                                refine(cov)
+                                changed = True
+
+    for l in range(levels - 1):
+        for lf in sorted(lf for lf in leaves if lf[0] == l):
+            if rho_max(lf) > thresholds[l]:
+                refine(lf)
+        balance()
+    return sorted(leaves)
+
+
+def case_tree(n0: int = 64, bs: int = 16, levels: int = 3, precision=PREC_MIXED, seed: int = 12246) -> Case:
+    """Block tree: equal-size blocks refined around the synthetic torus (level 1
+    where it is present, level 2 where its density exceeds 0.3), 2:1 balanced,
+    with the cross-level ghost rule (params amr = 1). Blocks are listed by level,
+    phi-fastest; each is sampled at its own level's resolution."""
+    rng = np.random.default_rng(seed)
+    x_lo, x_hi = ks_domain()
+    params = base_params(x_lo=x_lo, x_hi=x_hi, ncell0=[n0, n0, n0], precision=precision, fused=0, amr=1)
+    leaves = _tree_leaves(params, bs, levels, thresholds=[0.0, 0.3] + [0.6] * max(0, levels - 3))
+    blocks = np.array([[l, bs, bs, bs, i * bs, j * bs, k * bs] for (l, i, j, k) in leaves], dtype=np.int32)
+    ioff = _ioff(blocks)
+    noise = rng.uniform(size=int(ioff[-1]))
+    prim = np.zeros((NVAR, int(ioff[-1])))
+    rr = np.zeros(int(ioff[-1]))
+    for b in range(len(blocks)):
+        g0, g1, g2 = _block_cells(blocks[b])
+        sl = slice(int(ioff[b]), int(ioff[b + 1]))
+        prim[:, sl], rr[sl], _ = _torus_cells(params, int(blocks[b, 0]), g0, g1, g2, noise[sl])
+    prim = _finish_torus(prim, rr)
+    return Case(f"tree_{n0}_{bs}_{levels}", params, blocks, prim, ioff, steps=10)
 
 
 def make_case(cfg: int, **kw) -> Case:
