@@ -47,6 +47,10 @@ WORKLOADS = {
     "ks_torus_192_mixed_auto": dict(cfg=3, n=192, precision=1, fused="auto"),
     "amr_like_4096_mixed_auto": dict(cfg=4, precision=1, fused="auto"),
     "ks_turb_384_mixed_auto": dict(cfg=5, n=384, precision=1, fused="auto"),
+    # 2:1 block tree of 16^3 blocks on three levels around the torus (96^3 base,
+    # 972 blocks, 4.0 M zones), with restriction / prolongation between levels
+    "amr_tree_96_mixed_plain": dict(cfg="tree", n0=96, bs=16, levels=3, precision=1, fused=0),
+    "amr_tree_96_fp64_plain": dict(cfg="tree", n0=96, bs=16, levels=3, precision=0, fused=0),
 }
 
 
@@ -247,7 +251,8 @@ def main(argv=None):
 
     def make(name):
         w = dict(WORKLOADS[name])
-        c = I.make_case(w["cfg"], **({"n": w["n"]} if "n" in w else {}))
+        kw = {k: w[k] for k in ("n", "n0", "bs", "levels") if k in w}
+        c = I.make_case(w["cfg"], **kw)
         if w["fused"] == "auto":
             from paper_2108_12240_amd import autotune
             params, report = autotune.tune(dict(c.params, precision=w["precision"]), c.blocks, c.prim)

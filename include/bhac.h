@@ -85,6 +85,17 @@ enum { BHAC_PREC_FP64 = 0, BHAC_PREC_MIXED = 1 };
  *  rho_floor, p_floor, w_max   floors applied after a converged inversion.
  *  glm_alpha            GLM damping: kappa = glm_alpha * c_h / min_d dx_d.
  *  c2p_tol, c2p_maxit   Newton stopping tolerance on |dxi|/xi and iteration cap.
+ *  amr                  0: the blocks are independent patches; a block's halo comes
+ *                       from blocks of its own (level, size) only.
+ *                       1: the blocks are the leaves of a 2:1-balanced block tree
+ *                       (Section 2's block-based adaptive mesh): one block size,
+ *                       even and >= 2 * nghost along every axis in use (so every
+ *                       ghost layer lies in a leaf adjacent to the block), no
+ *                       leaf inside another;
+ *                       where a block borders coarser or finer leaves its ghost
+ *                       cells come from prolongation or restriction (see
+ *                       bhac_fill_ghosts). Needs fused = 0 (else
+ *                       BHAC_EUNSUPPORTED).
  */
 typedef struct bhac_params {
     int ndim;           /* 2 or 3 */
@@ -98,6 +109,7 @@ typedef struct bhac_params {
     int recon, flux, precision, fused;
     double cfl, rho_floor, p_floor, w_max, glm_alpha, c2p_tol;
     int c2p_maxit;
+    int amr;            /* 0 independent patches, 1 block tree */
 } bhac_params;
 
 /* One block: refinement level, interior cells per axis, and origin in level-l
@@ -144,13 +156,23 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
 /* Release the grid and its device memory (synchronises the device). NULL is a no-op. */
 int bhac_free_blocks(bhac_grid *grid);
 
-/* Same-level ghost-cell fill (Section 4.3's same-refinement-level fill): every
- * ghost slot of every block receives, bit for bit, all 9 primitives of one
- * interior cell. Rule per ghost slot at global level-l index G: wrap periodic
- * axes, clamp outflow axes to the domain; if a block of the same level and size
- * holds that cell, copy it; otherwise copy the own block's interior cell
- * nearest to the slot (zero-gradient). prim: device, [9][ncell_padded], double
- * or float per precision; written in ghost slots only. */
+/* Ghost-cell fill (Section 4.3's same-refinement-level fill; with amr = 1 also
+ * the exchange between refinement levels of Section 2's block-based mesh).
+ * Rule per ghost slot at global level-l index G: wrap periodic axes, clamp
+ * outflow axes to the domain; if a block of the same level and size holds that
+ * cell, copy it bit for bit (all 9 primitives). Otherwise, with amr = 1:
+ *   a level-(l+1) leaf holds it: restriction, the mean of the 2^ndim fine cells
+ *     under it (summed z-outer, x-inner, times 1/2^ndim);
+ *   a level-(l-1) leaf holds it: prolongation, the coarse cell's value q plus,
+ *     for each axis d in order, +1/4 (upper half of the coarse cell) or -1/4
+ *     (lower half) times minmod(q - q_lo, q_hi - q), where q_lo, q_hi are the
+ *     coarse block's neighbour cells along d, read from its interior or, outside
+ *     it, by this rule without prolongation (a neighbour that would need it
+ *     makes that axis's slope zero).
+ * Otherwise copy the own block's interior cell nearest to the slot
+ * (zero-gradient). Restriction and prolongation are evaluated in double and
+ * stored in the state's precision. prim: device, [9][ncell_padded], double or
+ * float per precision; written in ghost slots only. */
 int bhac_fill_ghosts(bhac_grid *grid, void *prim, void *stream);
 
 /* The same fill restricted to the face-adjacent ghost slabs (slots with exactly
@@ -196,7 +218,10 @@ int bhac_con2prim(bhac_grid *grid, const double *cons, void *prim_inout, int8_t 
  * (BHAC_EALIAS). The halo cells of each block are read from the neighbouring
  * blocks' interiors (or the own edge cell, where bhac_fill_ghosts would copy
  * that), so the ghost slots of P_stage need not be filled; the ghost slots of
- * P_out are left unchanged. */
+ * P_out are left unchanged. Exception, block trees (amr = 1): where a block
+ * borders a coarser or finer leaf, the substep first writes those face-adjacent
+ * ghost slots of P_stage by the cross-level rule of bhac_fill_ghosts (from
+ * P_stage's interiors) and reads them; P_stage's interior is not modified. */
 int bhac_substep(bhac_grid *grid, const double *U_base, const double *U_stage, const void *P_stage,
                  double *U_out, void *P_out, double a, double b, void *stream);
 

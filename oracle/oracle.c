@@ -643,13 +643,15 @@ orc_grid *orc_grid_new(const orc_params *p, const orc_block *blocks, int64_t nb)
         g->occ[s] = (int)b;
     }
     if (p->amr) {
-        /* block tree: one block size, even along every axis in use, and no leaf
-         * inside another leaf's region (no ancestor slot occupied) */
+        /* block tree: one block size, even and at least twice the ghost depth along
+         * every axis in use (so every ghost layer lies in a leaf adjacent to the
+         * block), and no leaf inside another leaf's region (no ancestor slot
+         * occupied) */
         for (int64_t b = 0; b < nb; b++) {
             const orc_block *B = &G->blk[b];
             for (int e = 0; e < 3; e++) {
                 if (B->size[e] != G->blk[0].size[e]) goto bad;
-                if (e < p->ndim && B->size[e] % 2 != 0) goto bad;
+                if (e < p->ndim && (B->size[e] % 2 != 0 || B->size[e] < 2 * p->nghost)) goto bad;
             }
             for (int l = 0; l < B->level; l++) {
                 int64_t c[3];

@@ -46,7 +46,7 @@ struct GridDev {
 
 // Kernel families timed by the optional HIP-event timer.
 enum KernelId { K_FILL, K_FLUX0, K_FLUX1, K_FLUX2, K_UPDATE, K_PRIM2CON, K_CON2PRIM, K_SPEEDS, K_BEGIN, K_END,
-                K_BLOCK_FLUX, K_UPDATE_DIV, K_COUNT };
+                K_BLOCK_FLUX, K_UPDATE_DIV, K_FILL_XL, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Optional per-launch timing: a pre-created pool of HIP events recorded on the
@@ -100,6 +100,8 @@ struct DeviceGrid {
     WorkItem *d_wcell = nullptr, *d_wface[3] = {nullptr, nullptr, nullptr};
     MarchItem *d_wmarch[3] = {nullptr, nullptr, nullptr};
     int32_t *d_gdst = nullptr, *d_gsrc = nullptr;
+    int32_t *d_xoff = nullptr, *d_xdat = nullptr;    // cross-level recipes (block trees)
+    long long nxl = 0, nxl_face = 0;
     int32_t *d_nbr = nullptr;
     HaloAxis *d_halo = nullptr;
     void *d_flux[3] = {nullptr, nullptr, nullptr};   // face-flux scratch of the unfused path
@@ -110,6 +112,8 @@ struct DeviceGrid {
 };
 
 hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only = false);
+hipError_t launch_fill_cross(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only);
+hipError_t launch_fill_copies(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only);
 hipError_t launch_prim2con(const DeviceGrid &G, const void *P, double *U, hipStream_t s);
 hipError_t launch_con2prim(const DeviceGrid &G, const double *U, void *P, int8_t *fail, hipStream_t s);
 hipError_t launch_compute_dt(const DeviceGrid &G, const void *P, hipStream_t s);

@@ -23,6 +23,9 @@ struct DevBlock {
     int level;
     int hclamp;                  // bit 2e+side: halo of axis e on that side (0 low, 1 high) is the
                                  // block's own edge cell (zero-gradient); else a neighbour's cells
+    int hxl;                     // bit 2e+side: that halo lies in a coarser or finer leaf of a block
+                                 // tree; the kernels read the block's own ghost slots there (shift 0)
+    int pad2;
     long long ioff;              // first interior cell of the block in interior-packed arrays
     long long hshift[3][2];      // added to an own-frame padded index past the low / high end of
                                  // axis e, gives the same cell's padded index in that neighbour
@@ -80,6 +83,10 @@ struct Plan {
     int gd[3] = {0, 0, 0};               // ghost layers per axis
     std::vector<int32_t> gdst, gsrc;     // same-level ghost gather map: face-adjacent slots first,
     long long nface_slots = 0;           // then edge and corner slots
+    // block trees: cross-level ghost recipes (restriction / prolongation), slot q in
+    // xdat[xoff[q] .. xoff[q+1]), the first nxl_face of them face-adjacent
+    std::vector<int32_t> xoff, xdat;
+    long long nxl_face = 0;
     // metric tables (empty for flat space)
     long long nrec_c = 0, nrec_f0 = 0, nrec_f1 = 0;
     std::vector<double> ctab, f0tab, f1tab;

@@ -31,6 +31,77 @@ __global__ __launch_bounds__(WG) void k_fill(const int32_t *__restrict__ dst, co
 }
 
 // ---------------------------------------------------------------------------------
+// Cross-level ghost fill of block trees: one thread per recipe (built by the
+// planner), restriction or limited prolongation evaluated in double from interior
+// cells only, stored in R. Recipes: [0, dst, the 2^ndim fine cells]
+// (restriction), or [1, nchildren, coarse cell, the counts of the lower and upper
+// neighbour per axis (0 = no slope), the neighbours' cells, then (dst, upper-half
+// bits) per child] (prolongation of the ghost cells of one block that lie in one
+// coarse cell, which share its slopes).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double minmod_xl(double a, double b)
+{
+    if (a > 0.0 && b > 0.0) return a < b ? a : b;
+    if (a < 0.0 && b < 0.0) return a > b ? a : b;
+    return 0.0;
+}
+
+template <typename R>
+__device__ __forceinline__ double mean_of(const R *__restrict__ row, const int32_t *__restrict__ idx, int n)
+{
+    double sum = 0.0;
+    for (int q = 0; q < n; q++) sum += (double)row[idx[q]];
+    return n == 1 ? sum : sum * (n == 8 ? 0.125 : 0.25);
+}
+
+template <typename R>
+__global__ __launch_bounds__(WG) void k_fill_xl(const int32_t *__restrict__ xoff, const int32_t *__restrict__ xdat,
+                                                long long n, int ndim, R *__restrict__ P, long long ncp)
+{
+#pragma clang fp contract(off)
+    const long long q = (long long)blockIdx.x * WG + threadIdx.x;
+    if (q >= n) return;
+    const int32_t *r = xdat + xoff[q];
+    if (r[0] == 0) {
+        const int nc = ndim == 3 ? 8 : 4;
+#pragma unroll
+        for (int v = 0; v < NV; v++) P[v * ncp + r[1]] = (R)mean_of(P + v * ncp, r + 2, nc);
+        return;
+    }
+    const int nk = r[1];
+    const int32_t c = r[2];
+    int cnt[6], at[6];
+    int pos = 9;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        cnt[k] = r[3 + k];
+        at[k] = pos;
+        pos += cnt[k];
+    }
+    const int32_t *kids = r + pos;
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        const R *row = P + v * ncp;
+        const double qc = (double)row[c];
+        double sl[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            if (d < ndim && cnt[2 * d] > 0 && cnt[2 * d + 1] > 0) {
+                const double lo = mean_of(row, r + at[2 * d], cnt[2 * d]);
+                const double hi = mean_of(row, r + at[2 * d + 1], cnt[2 * d + 1]);
+                sl[d] = minmod_xl(qc - lo, hi - qc);
+            }
+        }
+        for (int k = 0; k < nk; k++) {
+            const int bits = kids[2 * k + 1];
+            double val = qc;
+            for (int d = 0; d < ndim; d++) val += (((bits >> d) & 1) ? 0.25 : -0.25) * sl[d];
+            P[v * ncp + kids[2 * k]] = (R)val;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // Face fluxes along D: one thread per face of a block (faces 0..s_D along D).
 // ---------------------------------------------------------------------------------
 // waves per SIMD the face kernels are compiled for: the scheduler hoists the
@@ -408,9 +479,18 @@ inline unsigned nblk(long long n) { return (unsigned)((n + WG - 1) / WG); }
 
 const char *const kKernelNames[K_COUNT] = {"fill_ghosts", "flux_x1", "flux_x2", "flux_x3", "update",
                                            "prim2con", "con2prim", "cell_speeds", "step_begin", "step_end",
-                                           "block_flux", "update_div"};
+                                           "block_flux", "update_div", "fill_cross_level"};
 
 hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only)
+{
+    // same-level copies, then the cross-level slots of block trees (whose recipes
+    // read interior cells only, so the order does not matter)
+    hipError_t e = launch_fill_copies(G, P, s, faces_only);
+    if (e != hipSuccess) return e;
+    return launch_fill_cross(G, P, s, faces_only);
+}
+
+hipError_t launch_fill_copies(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only)
 {
     // the face-adjacent slots come first in the gather map (see make_plan)
     const long long n = faces_only ? G.nface_slots : G.nghost_slots;
@@ -422,6 +502,20 @@ hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_o
         hipLaunchKernelGGL(k_fill<float>, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (float *)P, G.kp.ncp);
     else
         hipLaunchKernelGGL(k_fill<double>, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (double *)P, G.kp.ncp);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_cross(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only)
+{
+    const long long n = faces_only ? G.nxl_face : G.nxl;
+    if (n == 0) return hipSuccess;
+    TimedLaunch tl(G.timer, K_FILL_XL, s);
+    if (G.mixed)
+        hipLaunchKernelGGL(k_fill_xl<float>, dim3(nblk(n)), dim3(WG), 0, s, G.d_xoff, G.d_xdat, n, G.kp.ndim,
+                           (float *)P, G.kp.ncp);
+    else
+        hipLaunchKernelGGL(k_fill_xl<double>, dim3(nblk(n)), dim3(WG), 0, s, G.d_xoff, G.d_xdat, n, G.kp.ndim,
+                           (double *)P, G.kp.ncp);
     return hipGetLastError();
 }
 
@@ -567,6 +661,10 @@ hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *U
                           void *Po, double a, double b, hipStream_t s)
 {
     hipError_t e = begin_step(G, a == 0.0 ? 1 : 0, s);
+    if (e != hipSuccess) return e;
+    // block trees: the face ghosts bordering other levels are read from P_stage's
+    // own ghost slots, refreshed here from its interiors
+    if (G.nxl_face > 0) e = launch_fill_cross(G, const_cast<void *>(Ps), s, true);
     if (e != hipSuccess) return e;
     if (G.plan.p.fused) e = launch_fused_body(G, Ub, Us, Ps, Uo, Po, a, b, s);
     else e = G.mixed ? substep_prec<float>(G, Ub, Us, Ps, Uo, Po, a, b, s) : substep_prec<double>(G, Ub, Us, Ps, Uo, Po, a, b, s);

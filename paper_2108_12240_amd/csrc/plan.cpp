@@ -119,6 +119,7 @@ bool check_params(const bhac_params &p, std::string &err)
     if (p.flux != BHAC_FLUX_HLL && p.flux != BHAC_FLUX_TVDLF) return bad(err, "unknown flux");
     if (p.precision != BHAC_PREC_FP64 && p.precision != BHAC_PREC_MIXED) return bad(err, "unknown precision");
     if (p.fused != 0 && p.fused != 1) return bad(err, "fused must be 0 or 1");
+    if (p.amr != 0 && p.amr != 1) return bad(err, "amr must be 0 or 1");
     const int gmin = p.recon == BHAC_RECON_PPM ? 3 : 2;
     if (p.nghost < gmin || p.nghost > 8) return bad(err, "nghost must be >= 2 (MC) or >= 3 (PPM) and <= 8");
     if (!(std::fabs(p.spin) < 1.0)) return bad(err, "|spin| must be < 1");
@@ -202,6 +203,39 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         P.ioff[b + 1] = P.ncell_interior;
     }
     if (P.off[nb] >= (1ll << 31)) { err = "more than 2^31 padded cells"; return BHAC_EINVAL; }
+    // block tree: one block size, even along every axis in use, no leaf inside the
+    // region of another (no ancestor slot occupied)
+    auto leaf_at = [&](int level, const long long c[3]) -> int {
+        Key k{level, blocks[0].size[0], blocks[0].size[1], blocks[0].size[2], 0, 0, 0};
+        for (int e = 0; e < 3; e++) {
+            const long long N = e < p.ndim ? ((long long)p.ncell0[e] << level) : 1;
+            if (level < 0 || c[e] < 0 || c[e] >= N) return -1;
+        }
+        k.c0 = (int)(c[0] / blocks[0].size[0]);
+        k.c1 = (int)(c[1] / blocks[0].size[1]);
+        k.c2 = (int)(c[2] / blocks[0].size[2]);
+        auto it = lattice.find(k);
+        return it == lattice.end() ? -1 : it->second;
+    };
+    if (p.amr) {
+        if (p.fused) { err = "the block-tiled substep does not support block trees (amr = 1)"; return BHAC_EUNSUPPORTED; }
+        for (int64_t b = 0; b < nb; b++) {
+            const bhac_block_desc &B = blocks[b];
+            for (int e = 0; e < 3; e++) {
+                if (B.size[e] != blocks[0].size[e]) { err = "a block tree needs one block size"; return BHAC_EINVAL; }
+                if (e < p.ndim && (B.size[e] % 2 || B.size[e] < 2 * p.nghost)) {
+                    // even, and deep enough that every ghost layer lies in an adjacent leaf
+                    err = "a block tree needs even block sizes of at least 2 * nghost";
+                    return BHAC_EINVAL;
+                }
+            }
+            for (int l = 0; l < B.level; l++) {
+                long long c[3];
+                for (int e = 0; e < 3; e++) c[e] = e < p.ndim ? ((long long)B.origin[e] >> (B.level - l)) : 0;
+                if (leaf_at(l, c) >= 0) { err = "block tree: a leaf lies inside a coarser leaf"; return BHAC_EINVAL; }
+            }
+        }
+    }
 
     // levels
     P.levels.assign(P.maxlevel + 1, DevLevel{});
@@ -324,6 +358,111 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                 }
     }
 
+    // Block-tree helpers: the global level-L index of a block-local position after
+    // the domain's periodic wrap / outflow clamp, the padded index of a cell given by
+    // its global index, and the cross-level recipes.
+    auto wrap_axis = [&](int level, int e, long long x) -> long long {
+        if (e >= p.ndim) return 0;
+        const long long N = (long long)p.ncell0[e] << level;
+        if (x < 0 || x >= N) {
+            if (p.bc[e][x < 0 ? 0 : 1] == BHAC_BC_PERIODIC) x = ((x % N) + N) % N;
+            else x = x < 0 ? 0 : N - 1;
+        }
+        return x;
+    };
+    auto padded_global = [&](int blk, const long long g[3]) -> int32_t {
+        const DevBlock &Q = P.dblocks[blk];
+        long long li[3];
+        for (int e = 0; e < 3; e++) li[e] = g[e] - Q.o[e] + P.gd[e];
+        return (int32_t)(Q.off + (li[2] * Q.n1 + li[1]) * Q.n0 + li[0]);
+    };
+    auto padded_local = [&](int blk, const int a[3]) -> int32_t {
+        const DevBlock &Q = P.dblocks[blk];
+        return (int32_t)(Q.off + ((long long)(a[2] + P.gd[2]) * Q.n1 + (a[1] + P.gd[1])) * Q.n0 + (a[0] + P.gd[0]));
+    };
+    const int nchild = p.ndim == 3 ? 8 : 4;
+    // the 2^ndim cells of the level-(L+1) leaf fb under level-L cell Gi, z-outer
+    auto push_children = [&](int fb, const long long Gi[3], std::vector<int32_t> &out) {
+        for (int dz = 0; dz < (p.ndim == 3 ? 2 : 1); dz++)
+            for (int dy = 0; dy < 2; dy++)
+                for (int dx = 0; dx < 2; dx++) {
+                    const long long f[3] = {2 * Gi[0] + dx, 2 * Gi[1] + dy, p.ndim == 3 ? 2 * Gi[2] + dz : 0};
+                    out.push_back(padded_global(fb, f));
+                }
+    };
+    // the value of block cb at local a (inside, or one cell outside along one axis)
+    // as a list of cells to average: 1 cell, 2^ndim cells, or none where it would
+    // need prolongation
+    auto neighbour_ref = [&](int cb, const int a[3], std::vector<int32_t> &out) {
+        const DevBlock &C = P.dblocks[cb];
+        bool inside = true;
+        for (int e = 0; e < 3; e++) inside = inside && a[e] >= 0 && a[e] < C.s[e];
+        if (inside) { out.push_back(1); out.push_back(padded_local(cb, a)); return; }
+        long long Ga[3];
+        for (int e = 0; e < 3; e++) Ga[e] = wrap_axis(C.level, e, (long long)C.o[e] + a[e]);
+        int q = leaf_at(C.level, Ga);
+        if (q >= 0) { out.push_back(1); out.push_back(padded_global(q, Ga)); return; }
+        const long long f[3] = {2 * Ga[0], 2 * Ga[1], p.ndim == 3 ? 2 * Ga[2] : 0};
+        q = leaf_at(C.level + 1, f);
+        if (q >= 0) { out.push_back(nchild); push_children(q, Ga, out); return; }
+        if (C.level >= 1) {
+            const long long c[3] = {Ga[0] >> 1, Ga[1] >> 1, Ga[2] >> 1};
+            if (leaf_at(C.level - 1, c) >= 0) { out.push_back(0); return; }
+        }
+        int x[3];
+        for (int e = 0; e < 3; e++) x[e] = std::min(std::max(a[e], 0), C.s[e] - 1);
+        out.push_back(1);
+        out.push_back(padded_local(cb, x));
+    };
+    // Cross-level case of ghost position l of block b when no same-level leaf holds
+    // it. Returns 0 when no finer or coarser leaf does either (the zero-gradient copy
+    // applies); 1 for a restriction, with rec = [0, dst, 2^ndim cells]; 2 for a
+    // prolongation, with the coarse block and cell in cb, lc and the position's
+    // upper-half bits in bits. Prolongations are grouped per (block, coarse cell):
+    // the children of one coarse cell share its slopes, so a group's recipe is
+    // [1, nchildren, coarse cell, the counts of the six neighbours (lower, upper per
+    // axis; 0 = no slope), their cells, then (dst, bits) per child].
+    auto cross_case = [&](int b, const int l[3], int32_t dst, std::vector<int32_t> &rec, int &cb, int lc[3],
+                          int &bits) -> int {
+        const DevBlock &B = P.dblocks[b];
+        long long Gi[3];
+        for (int e = 0; e < 3; e++) Gi[e] = wrap_axis(B.level, e, (long long)B.o[e] + l[e]);
+        const long long f[3] = {2 * Gi[0], 2 * Gi[1], p.ndim == 3 ? 2 * Gi[2] : 0};
+        const int fb = leaf_at(B.level + 1, f);
+        if (fb >= 0) {
+            rec.push_back(0);
+            rec.push_back(dst);
+            push_children(fb, Gi, rec);
+            return 1;
+        }
+        if (B.level < 1) return 0;
+        const long long c[3] = {Gi[0] >> 1, Gi[1] >> 1, Gi[2] >> 1};
+        cb = leaf_at(B.level - 1, c);
+        if (cb < 0) return 0;
+        const DevBlock &C = P.dblocks[cb];
+        bits = 0;
+        for (int d = 0; d < p.ndim; d++) bits |= (int)(Gi[d] & 1) << d;
+        for (int e = 0; e < 3; e++) lc[e] = (int)(c[e] - C.o[e]);
+        return 2;
+    };
+    // coarse cell, the six neighbour counts (zero for unused axes), then the cells
+    auto prolong_head = [&](int cb, const int lc[3], std::vector<int32_t> &out) {
+        out.push_back(padded_local(cb, lc));
+        std::vector<int32_t> refs;
+        int32_t cnt[6] = {0, 0, 0, 0, 0, 0};
+        for (int d = 0; d < p.ndim; d++)
+            for (int sd = 0; sd < 2; sd++) {
+                int a[3] = {lc[0], lc[1], lc[2]};
+                a[d] += sd == 0 ? -1 : 1;
+                std::vector<int32_t> one;
+                neighbour_ref(cb, a, one);
+                cnt[2 * d + sd] = one[0];
+                refs.insert(refs.end(), one.begin() + 1, one.end());
+            }
+        out.insert(out.end(), cnt, cnt + 6);
+        out.insert(out.end(), refs.begin(), refs.end());
+    };
+
     // halo sides: for each block, axis and side, either the neighbour whose interior
     // continues the block (same size, so local index l maps to l +- s there) or the
     // zero-gradient clamp to the block's own edge cell. The unfused flux kernels read
@@ -332,6 +471,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     for (int64_t b = 0; b < nb; b++) {
         DevBlock &D = P.dblocks[b];
         D.hclamp = 0;
+        D.hxl = 0;
         for (int e = 0; e < 3; e++) {
             D.hshift[e][0] = D.hshift[e][1] = 0;
             if (e >= p.ndim) continue;
@@ -342,8 +482,16 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                 const HaloAxis &h = P.halo[((size_t)b * 3 + e) * P.hmax + (l + P.gd[e])];
                 const int nbk = P.nbr[(size_t)b * 27 + 13 + h.dir * pw];
                 const int cont = side == 0 ? D.s[e] - 1 : 0;    // source index of a continuation
+                std::vector<int32_t> probe;
+                const int lp[3] = {e == 0 ? l : 0, e == 1 ? l : 0, e == 2 ? l : 0};
+                int pcb, plc[3], pbits;
                 if (nbk >= 0 && h.src == cont) {
                     D.hshift[e][side] = P.off[nbk] - P.off[b] + (side == 0 ? 1 : -1) * (long long)D.s[e] * st;
+                } else if (p.amr && nbk < 0 && h.dir != 0 && cross_case((int)b, lp, 0, probe, pcb, plc, pbits)) {
+                    // a coarser or finer leaf: the kernels read the block's own ghost
+                    // slots (shift 0), which the cross-level fill refreshes
+                    D.hshift[e][side] = 0;
+                    D.hxl |= 1 << (2 * e + side);
                 } else if (nbk < 0 || (h.dir == 0 && h.src == (side == 0 ? 0 : D.s[e] - 1))) {
                     D.hclamp |= 1 << (2 * e + side);
                 } else {
@@ -360,6 +508,13 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     P.gdst.clear();
     P.gsrc.clear();
     std::vector<int32_t> edst, esrc;
+    // cross-level recipes (block trees), face slots first as for the gather map;
+    // prolongation groups keyed by (block, coarse cell), per face/edge class
+    std::vector<int32_t> xface, xedge;
+    std::vector<int32_t> xface_off, xedge_off;
+    struct PGroup { int cb; int lc[3]; std::vector<int32_t> kids; };
+    std::vector<PGroup> pgroups[2];
+    std::unordered_map<long long, size_t> pindex[2];
     for (int64_t b = 0; b < nb; b++) {
         const DevBlock &D = P.dblocks[b];
         const int n2 = D.s[2] + 2 * P.gd[2];
@@ -377,6 +532,44 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                         src[e] = h.src;
                     }
                     int sb = P.nbr[(size_t)b * 27 + (dir[0] + 1) + 3 * (dir[1] + 1) + 9 * (dir[2] + 1)];
+                    const long long to = D.off + ((long long)pk * D.n1 + pj) * D.n0 + pi;
+                    int fe = 0;                                  // axis outside (face slots)
+                    while (nout == 1 && l[fe] >= 0 && l[fe] < D.s[fe]) fe++;
+                    const int fside = nout == 1 && l[fe] >= D.s[fe] ? 1 : 0;
+                    if (sb < 0 && p.amr) {
+                        std::vector<int32_t> &xs = nout == 1 ? xface : xedge;
+                        std::vector<int32_t> &xo = nout == 1 ? xface_off : xedge_off;
+                        const size_t at = xs.size();
+                        int ccb, clc[3], cbits;
+                        const int kind = cross_case((int)b, l, (int32_t)to, xs, ccb, clc, cbits);
+                        if (kind == 1) xo.push_back((int32_t)at);
+                        if (kind == 2) {
+                            const int cls = nout == 1 ? 0 : 1;
+                            const long long key = ((long long)b << 32) | (long long)padded_local(ccb, clc);
+                            auto it = pindex[cls].find(key);
+                            if (it == pindex[cls].end()) {
+                                it = pindex[cls].emplace(key, pgroups[cls].size()).first;
+                                pgroups[cls].push_back(PGroup{ccb, {clc[0], clc[1], clc[2]}, {}});
+                            }
+                            pgroups[cls][it->second].kids.push_back((int32_t)to);
+                            pgroups[cls][it->second].kids.push_back(cbits);
+                        }
+                        if (kind) {
+                            if (nout == 1 && !(D.hxl >> (2 * fe + fside) & 1)) {
+                                err = "block tree: a block face mixes levels (block " + std::to_string(b) + ", axis " +
+                                      std::to_string(fe) + ", side " + std::to_string(fside) + ", local " +
+                                      std::to_string(l[0]) + "," + std::to_string(l[1]) + "," + std::to_string(l[2]) + ", A)";
+                                return BHAC_EINVAL;
+                            }
+                            continue;
+                        }
+                    }
+                    if (nout == 1 && (D.hxl >> (2 * fe + fside) & 1)) {
+                        err = "block tree: a block face mixes levels (block " + std::to_string(b) + ", axis " +
+                              std::to_string(fe) + ", side " + std::to_string(fside) + ", local " +
+                              std::to_string(l[0]) + "," + std::to_string(l[1]) + "," + std::to_string(l[2]) + ", B)";
+                        return BHAC_EINVAL;
+                    }
                     if (sb < 0) {
                         sb = (int)b;
                         for (int e = 0; e < 3; e++) src[e] = std::min(std::max(l[e], 0), D.s[e] - 1);
@@ -384,7 +577,6 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                     const DevBlock &S = P.dblocks[sb];
                     const long long from =
                         S.off + ((long long)(src[2] + P.gd[2]) * S.n1 + (src[1] + P.gd[1])) * S.n0 + (src[0] + P.gd[0]);
-                    const long long to = D.off + ((long long)pk * D.n1 + pj) * D.n0 + pi;
                     if (nout == 1) {
                         // the halo-side rule must name the same source cell
                         int e = 0;
@@ -408,6 +600,25 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                 }
     }
     P.nface_slots = (long long)P.gdst.size();
+    // prolongation groups after the restrictions of their class
+    for (int cls = 0; cls < 2; cls++) {
+        std::vector<int32_t> &xs = cls == 0 ? xface : xedge;
+        std::vector<int32_t> &xo = cls == 0 ? xface_off : xedge_off;
+        for (const PGroup &g : pgroups[cls]) {
+            xo.push_back((int32_t)xs.size());
+            xs.push_back(1);
+            xs.push_back((int32_t)(g.kids.size() / 2));
+            prolong_head(g.cb, g.lc, xs);
+            xs.insert(xs.end(), g.kids.begin(), g.kids.end());
+        }
+    }
+    // cross-level recipes: one stream, face recipes first, with offsets (n + 1)
+    P.xdat = xface;
+    P.xoff = xface_off;
+    P.nxl_face = (long long)xface_off.size();
+    for (int32_t o : xedge_off) P.xoff.push_back(o + (int32_t)xface.size());
+    P.xdat.insert(P.xdat.end(), xedge.begin(), xedge.end());
+    P.xoff.push_back((int32_t)P.xdat.size());
     P.gdst.insert(P.gdst.end(), edst.begin(), edst.end());
     P.gsrc.insert(P.gsrc.end(), esrc.begin(), esrc.end());
     (void)g;

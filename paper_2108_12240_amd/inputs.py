@@ -395,6 +395,8 @@ def make_case(cfg: int, **kw) -> Case:
         return case_torus(cfg, **kw)
     if cfg == 4:
         return case4(**kw)
+    if cfg == "tree":
+        return case_tree(**kw)
     raise ValueError(cfg)
 
 

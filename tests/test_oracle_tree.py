@@ -71,7 +71,7 @@ def away_from_edges(c, margin=3):
 
 @pytest.fixture(scope="module")
 def two_level():
-    return I.case_tree(n0=16, bs=4, levels=2, precision=I.PREC_FP64)
+    return I.case_tree(n0=32, bs=8, levels=2, precision=I.PREC_FP64)
 
 
 @pytest.fixture(scope="module")
@@ -104,7 +104,7 @@ def test_tree_partitions_domain_and_is_balanced(three_level):
                 assert abs(la - lb) <= 1
 
 
-@pytest.mark.parametrize("bad", ["overlap", "mixed_size", "odd_size"])
+@pytest.mark.parametrize("bad", ["overlap", "mixed_size", "odd_size", "shallow"])
 def test_tree_rejects_invalid_block_lists(two_level, bad):
     c = two_level
     blocks = c.blocks.copy()
@@ -117,10 +117,13 @@ def test_tree_rejects_invalid_block_lists(two_level, bad):
         blocks = np.vstack([blocks, extra])
     elif bad == "mixed_size":
         blocks = blocks.copy()
-        blocks[0, 1:4] = 8
+        blocks[0, 1:4] = 16
         blocks[0, 4:7] = 0
+    elif bad == "odd_size":
+        blocks = np.array([[0, 7, 7, 7, 0, 0, 0]], dtype=np.int32)
     else:
-        blocks = np.array([[0, 3, 3, 3, 0, 0, 0]], dtype=np.int32)
+        # ghost layers deeper than half a block could reach past the adjacent leaf
+        blocks = np.array([[0, 4, 4, 4, 0, 0, 0]], dtype=np.int32)
     with pytest.raises(Exception):
         O.OracleGrid(c.params, blocks)
 
@@ -251,7 +254,7 @@ def test_uniform_state_on_a_flat_tree_is_preserved_bit_for_bit():
     """Flat space, uniform dyadic state on a three-level tree: after one RK2 step the
     conserved state is unchanged bit for bit and the primitives are one uniform
     state (cross-level ghosts are exact copies of the uniform value)."""
-    t = I.case_tree(n0=16, bs=4, levels=3, precision=I.PREC_FP64)
+    t = I.case_tree(n0=32, bs=8, levels=3, precision=I.PREC_FP64)
     params = dict(t.params, metric=I.METRIC_MINKOWSKI_CART, x_lo=[0.0, 0.0, 0.0], x_hi=[1.0, 1.0, 1.0],
                   bc=[[I.BC_PERIODIC, I.BC_PERIODIC]] * 3)
     state = np.array([1.0, 0.25, -0.125, 0.5, 0.75, 0.5, 0.25, -0.25, 0.0])
