@@ -221,7 +221,10 @@ int bhac_con2prim(bhac_grid *grid, const double *cons, void *prim_inout, int8_t 
  * P_out are left unchanged. Exception, block trees (amr = 1): where a block
  * borders a coarser or finer leaf, the substep first writes those face-adjacent
  * ghost slots of P_stage by the cross-level rule of bhac_fill_ghosts (from
- * P_stage's interiors) and reads them; P_stage's interior is not modified. */
+ * P_stage's interiors) and reads them; P_stage's interior is not modified. A face
+ * whose far side lies in finer leaves uses the mean of the 2^(ndim-1) fine face
+ * fluxes covering it (flux correction), so D, S, tau and B are conserved across
+ * refinement levels. */
 int bhac_substep(bhac_grid *grid, const double *U_base, const double *U_stage, const void *P_stage,
                  double *U_out, void *P_out, double a, double b, void *stream);
 

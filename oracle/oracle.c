@@ -994,12 +994,161 @@ void orc_set_dt(orc_state *st, double dt)
  * A substep with a == 0 starts a step and latches dt from the previous substep's
  * wave speeds. P_stage ghost slots must be filled. blocks: subset (NULL = all).
  * ------------------------------------------------------------------------------- */
+/* Face fluxes of block bk along every direction (F[d]: [9][faces], x fastest);
+ * raises lam[d] to the largest |lambda| seen. */
+static void block_fluxes(const orc_grid *G, int bk, const double *Ps, double ch, double *F[3], double *lam)
+{
+    const orc_params *p = &G->p;
+    const int64_t ncp = G->off[G->nb];
+    const orc_block *B = &G->blk[bk];
+    for (int d = 0; d < p->ndim; d++) {
+        int fs[3];
+        for (int e = 0; e < 3; e++) fs[e] = B->size[e] + (e == d);
+        const int64_t nf = (int64_t)fs[0] * fs[1] * fs[2];
+        const double dx = level_dx(G, B->level, d);
+        for (int k = 0; k < fs[2]; k++)
+            for (int j = 0; j < fs[1]; j++)
+                for (int i = 0; i < fs[0]; i++) {
+                    /* face between the cell at (i,j,k) - e_d and the cell at (i,j,k) */
+                    int c[3] = { i, j, k };
+                    double qv[6], PL[NV], PR[NV];
+                    /* MC reads cells i-2..i+1, PPM reads i-3..i+2 */
+                    const int t0 = p->recon == 0 ? 1 : 0, t1 = p->recon == 0 ? 5 : 6;
+                    for (int t = 0; t < 6; t++) qv[t] = 0.0;
+                    for (int v = 0; v < NV; v++) {
+                        for (int t = t0; t < t1; t++) {
+                            int cc[3] = { c[0], c[1], c[2] };
+                            cc[d] += t - 3;
+                            qv[t] = Ps[v * ncp + pad_index(G, bk, cc[0], cc[1], cc[2])];
+                        }
+                        recon_face(p->recon, qv, &PL[v], &PR[v]);
+                    }
+                    double x1, x2;
+                    cell_center(G, bk, i, j, &x1, &x2);
+                    if (d == 0) x1 = p->x_lo[0] + (B->origin[0] + i) * dx;
+                    if (d == 1) x2 = p->x_lo[1] + (B->origin[1] + j) * dx;
+                    ometric mf;
+                    metric_at(p, x1, x2, &mf);
+                    double Ff[NV];
+                    const double l = riemann(p, &mf, d, PL, PR, ch, Ff);
+                    if (l > lam[d]) lam[d] = l;
+                    const int64_t fi = ((int64_t)k * fs[1] + j) * fs[0] + i;
+                    for (int v = 0; v < NV; v++) F[d][v * nf + fi] = Ff[v];
+                }
+    }
+}
+
+/* Flux divergence, sources, RK combine and inversion of block bk. */
+static void block_update(const orc_grid *G, int bk, double *F[3], const double *Ub, const double *Us,
+                         const double *Ps, double *Uo, double *Po, double a, double b, orc_state *st)
+{
+    const orc_params *p = &G->p;
+    const int64_t ncp = G->off[G->nb];
+    const orc_block *B = &G->blk[bk];
+    for (int k = 0; k < B->size[2]; k++)
+        for (int j = 0; j < B->size[1]; j++)
+            for (int i = 0; i < B->size[0]; i++) {
+                const int64_t c = pad_index(G, bk, i, j, k);
+                double x1, x2, Pc[NV], Uc[NV], Sv[NV], L[NV], Un[NV], Pn[NV];
+                ometric m;
+                cell_center(G, bk, i, j, &x1, &x2);
+                metric_at(p, x1, x2, &m);
+                for (int v = 0; v < NV; v++) { Pc[v] = Ps[v * ncp + c]; Uc[v] = Us[v * ncp + c]; }
+                sources_point(p, &m, Pc, Uc, st->kappa, Sv);
+                for (int v = 0; v < NV; v++) L[v] = 0.0;
+                for (int d = 0; d < p->ndim; d++) {
+                    int fs[3];
+                    for (int e = 0; e < 3; e++) fs[e] = B->size[e] + (e == d);
+                    const double dx = level_dx(G, B->level, d);
+                    const int64_t nf = (int64_t)fs[0] * fs[1] * fs[2];
+                    int hi[3] = { i, j, k };
+                    hi[d] += 1;
+                    const int64_t flo = ((int64_t)k * fs[1] + j) * fs[0] + i;
+                    const int64_t fhi = ((int64_t)hi[2] * fs[1] + hi[1]) * fs[0] + hi[0];
+                    for (int v = 0; v < NV; v++) L[v] -= (F[d][v * nf + fhi] - F[d][v * nf + flo]) / dx;
+                }
+                for (int v = 0; v < NV; v++) {
+                    L[v] += Sv[v];
+                    Un[v] = a * Ub[v * ncp + c] + b * (Uc[v] + st->dt * L[v]);
+                }
+                int nit, fl;
+                const int f = c2p_point(p, &m, Un, Pc, Pn, &nit, &fl);
+                if (f || fl) p2c_point(p, &m, Pn, Un);
+                st->c2p_fail += f;
+                st->floor_hits += (!f && fl);
+                if (nit > st->max_iter) st->max_iter = nit;
+                for (int v = 0; v < NV; v++) { Uo[v * ncp + c] = Un[v]; Po[v * ncp + c] = Pn[v]; }
+            }
+}
+
+/* Flux correction of a block tree: every face of a block whose far side lies in
+ * finer leaves takes the mean of the 2^(ndim-1) fine faces covering it (summed
+ * with the second transverse axis outer), so what leaves a coarse cell through
+ * that face is what the fine cells receive and the scheme conserves across levels. */
+static void flux_fix(const orc_grid *G, double **F)
+{
+    const orc_params *p = &G->p;
+    const int nd = p->ndim;
+    for (int64_t bk = 0; bk < G->nb; bk++) {
+        const orc_block *B = &G->blk[bk];
+        for (int d = 0; d < nd; d++) {
+            int fs[3];
+            for (int e = 0; e < 3; e++) fs[e] = B->size[e] + (e == d);
+            const int64_t nf = (int64_t)fs[0] * fs[1] * fs[2];
+            const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;   /* transverse axes */
+            for (int side = 0; side < 2; side++) {
+                const int fidx = side ? B->size[d] : 0;          /* face index along d */
+                for (int ib = 0; ib < B->size[tb]; ib++)
+                    for (int ia = 0; ia < B->size[ta]; ia++) {
+                        int l[3];
+                        l[d] = side ? B->size[d] : -1;
+                        l[ta] = ia;
+                        l[tb] = ib;
+                        int64_t Gi[3];
+                        ghost_global(G, (int)bk, l, Gi);
+                        if (leaf_at(G, B->level, Gi) >= 0) break;   /* same level: whole face */
+                        const int64_t f[3] = { 2 * Gi[0], nd > 1 ? 2 * Gi[1] : 0, nd > 2 ? 2 * Gi[2] : 0 };
+                        const int fb = leaf_at(G, B->level + 1, f);
+                        if (fb < 0) break;                             /* not a finer neighbour */
+                        const orc_block *Fb = &G->blk[fb];
+                        int ffs[3];
+                        for (int e = 0; e < 3; e++) ffs[e] = Fb->size[e] + (e == d);
+                        const int64_t fnf = (int64_t)ffs[0] * ffs[1] * ffs[2];
+                        double sum[NV];
+                        for (int v = 0; v < NV; v++) sum[v] = 0.0;
+                        const int nb_ = nd > 2 ? 2 : 1;
+                        for (int sb = 0; sb < nb_; sb++)
+                            for (int sa = 0; sa < 2; sa++) {
+                                int fl[3];
+                                /* fine face: adjacent to the coarse face on the fine side */
+                                fl[d] = side ? (int)(f[d] - Fb->origin[d]) : (int)(f[d] + 1 - Fb->origin[d]) + 1;
+                                fl[ta] = (int)(f[ta] + sa - Fb->origin[ta]);
+                                fl[tb] = nd > 2 || tb < nd ? (int)(f[tb] + sb - Fb->origin[tb]) : 0;
+                                const int64_t fi = ((int64_t)fl[2] * ffs[1] + fl[1]) * ffs[0] + fl[0];
+                                for (int v = 0; v < NV; v++) sum[v] += F[fb * 3 + d][v * fnf + fi];
+                            }
+                        const double w = nd > 2 ? 0.25 : 0.5;
+                        int cl[3];
+                        cl[d] = fidx;
+                        cl[ta] = ia;
+                        cl[tb] = ib;
+                        const int64_t ci = ((int64_t)cl[2] * fs[1] + cl[1]) * fs[0] + cl[0];
+                        for (int v = 0; v < NV; v++) F[bk * 3 + d][v * nf + ci] = sum[v] * w;
+                    }
+            }
+        }
+    }
+}
+
+/* One RK substep on the selected blocks (NULL = all): U_out = a U_base + b (U_stage +
+ * dt L), then P_out = con2prim(U_out) with P_stage as the guess; records the largest
+ * wave speeds. P_stage ghost slots must be filled. For block trees the fluxes of all
+ * blocks are formed first and corrected at level boundaries (flux_fix). */
 int orc_substep(const orc_grid *G, const double *Ub, const double *Us, const double *Ps, double *Uo,
                 double *Po, double a, double b, orc_state *st, const int64_t *blocks, int64_t nsel)
 {
     if (!st->have_dt) return -1;
     const orc_params *p = &G->p;
-    const int64_t ncp = G->off[G->nb];
     if (a == 0.0) {
         st->dt = st->dt_fixed > 0.0 ? st->dt_fixed : st->dt_next;
         double sinv = 0.0, dmin = 1e300;
@@ -1013,82 +1162,40 @@ int orc_substep(const orc_grid *G, const double *Ub, const double *Us, const dou
     }
     double lam[3] = { 0.0, 0.0, 0.0 };
     const int64_t n = blocks ? nsel : G->nb;
-    for (int64_t q = 0; q < n; q++) {
-        const int bk = (int)(blocks ? blocks[q] : q);
-        const orc_block *B = &G->blk[bk];
-        const int s0 = B->size[0], s1 = B->size[1], s2 = B->size[2];
-        const int64_t ncell = (int64_t)s0 * s1 * s2;
-        double *F[3] = { NULL, NULL, NULL };
-        int fs[3][3];
-        for (int d = 0; d < p->ndim; d++) {
-            for (int e = 0; e < 3; e++) fs[d][e] = B->size[e] + (e == d);
-            const int64_t nf = (int64_t)fs[d][0] * fs[d][1] * fs[d][2];
-            F[d] = malloc(NV * nf * sizeof(double));
-            const double dx = level_dx(G, B->level, d);
-            for (int k = 0; k < fs[d][2]; k++)
-                for (int j = 0; j < fs[d][1]; j++)
-                    for (int i = 0; i < fs[d][0]; i++) {
-                        /* face between the cell at (i,j,k) - e_d and the cell at (i,j,k) */
-                        int c[3] = { i, j, k };
-                        double qv[6], PL[NV], PR[NV];
-                        /* MC reads cells i-2..i+1, PPM reads i-3..i+2 */
-                        const int t0 = p->recon == 0 ? 1 : 0, t1 = p->recon == 0 ? 5 : 6;
-                        for (int t = 0; t < 6; t++) qv[t] = 0.0;
-                        for (int v = 0; v < NV; v++) {
-                            for (int t = t0; t < t1; t++) {
-                                int cc[3] = { c[0], c[1], c[2] };
-                                cc[d] += t - 3;
-                                qv[t] = Ps[v * ncp + pad_index(G, bk, cc[0], cc[1], cc[2])];
-                            }
-                            recon_face(p->recon, qv, &PL[v], &PR[v]);
-                        }
-                        double x1, x2;
-                        cell_center(G, bk, i, j, &x1, &x2);
-                        if (d == 0) x1 = p->x_lo[0] + (B->origin[0] + i) * dx;
-                        if (d == 1) x2 = p->x_lo[1] + (B->origin[1] + j) * dx;
-                        ometric mf;
-                        metric_at(p, x1, x2, &mf);
-                        double Ff[NV];
-                        const double l = riemann(p, &mf, d, PL, PR, st->ch, Ff);
-                        if (l > lam[d]) lam[d] = l;
-                        const int64_t fi = ((int64_t)k * fs[d][1] + j) * fs[d][0] + i;
-                        for (int v = 0; v < NV; v++) F[d][v * nf + fi] = Ff[v];
-                    }
+    if (!p->amr) {
+        for (int64_t q = 0; q < n; q++) {
+            const int bk = (int)(blocks ? blocks[q] : q);
+            const orc_block *B = &G->blk[bk];
+            double *F[3] = { NULL, NULL, NULL };
+            for (int d = 0; d < p->ndim; d++) {
+                const int64_t nf = (int64_t)(B->size[0] + (d == 0)) * (B->size[1] + (d == 1)) * (B->size[2] + (d == 2));
+                F[d] = malloc(NV * nf * sizeof(double));
+            }
+            block_fluxes(G, bk, Ps, st->ch, F, lam);
+            block_update(G, bk, F, Ub, Us, Ps, Uo, Po, a, b, st);
+            for (int d = 0; d < p->ndim; d++) free(F[d]);
         }
-        for (int k = 0; k < s2; k++)
-            for (int j = 0; j < s1; j++)
-                for (int i = 0; i < s0; i++) {
-                    const int64_t c = pad_index(G, bk, i, j, k);
-                    double x1, x2, Pc[NV], Uc[NV], Sv[NV], L[NV], Un[NV], Pn[NV];
-                    ometric m;
-                    cell_center(G, bk, i, j, &x1, &x2);
-                    metric_at(p, x1, x2, &m);
-                    for (int v = 0; v < NV; v++) { Pc[v] = Ps[v * ncp + c]; Uc[v] = Us[v * ncp + c]; }
-                    sources_point(p, &m, Pc, Uc, st->kappa, Sv);
-                    for (int v = 0; v < NV; v++) L[v] = 0.0;
-                    for (int d = 0; d < p->ndim; d++) {
-                        const double dx = level_dx(G, B->level, d);
-                        const int64_t nf = (int64_t)fs[d][0] * fs[d][1] * fs[d][2];
-                        int hi[3] = { i, j, k };
-                        hi[d] += 1;
-                        const int64_t flo = ((int64_t)k * fs[d][1] + j) * fs[d][0] + i;
-                        const int64_t fhi = ((int64_t)hi[2] * fs[d][1] + hi[1]) * fs[d][0] + hi[0];
-                        for (int v = 0; v < NV; v++) L[v] -= (F[d][v * nf + fhi] - F[d][v * nf + flo]) / dx;
-                    }
-                    for (int v = 0; v < NV; v++) {
-                        L[v] += Sv[v];
-                        Un[v] = a * Ub[v * ncp + c] + b * (Uc[v] + st->dt * L[v]);
-                    }
-                    int nit, fl;
-                    const int f = c2p_point(p, &m, Un, Pc, Pn, &nit, &fl);
-                    if (f || fl) p2c_point(p, &m, Pn, Un);
-                    st->c2p_fail += f;
-                    st->floor_hits += (!f && fl);
-                    if (nit > st->max_iter) st->max_iter = nit;
-                    for (int v = 0; v < NV; v++) { Uo[v * ncp + c] = Un[v]; Po[v * ncp + c] = Pn[v]; }
-                }
-        (void)ncell;
-        for (int d = 0; d < p->ndim; d++) free(F[d]);
+    } else {
+        /* block tree: every block's fluxes (a coarse face needs its fine neighbours'),
+         * the level-boundary correction, then the update of the selected blocks */
+        double **F = calloc(3 * G->nb, sizeof(double *));
+        for (int64_t bk = 0; bk < G->nb; bk++) {
+            const orc_block *B = &G->blk[bk];
+            double *Fb[3] = { NULL, NULL, NULL };
+            for (int d = 0; d < p->ndim; d++) {
+                const int64_t nf = (int64_t)(B->size[0] + (d == 0)) * (B->size[1] + (d == 1)) * (B->size[2] + (d == 2));
+                F[bk * 3 + d] = malloc(NV * nf * sizeof(double));
+                Fb[d] = F[bk * 3 + d];
+            }
+            block_fluxes(G, (int)bk, Ps, st->ch, Fb, lam);
+        }
+        flux_fix(G, F);
+        for (int64_t q = 0; q < n; q++) {
+            const int bk = (int)(blocks ? blocks[q] : q);
+            block_update(G, bk, &F[bk * 3], Ub, Us, Ps, Uo, Po, a, b, st);
+        }
+        for (int64_t t = 0; t < 3 * G->nb; t++) free(F[t]);
+        free(F);
     }
     for (int d = 0; d < 3; d++) st->lam[d] = lam[d];
     st->dt_next = st->dt_fixed > 0.0 ? st->dt_fixed : dt_from_lam(G, lam);

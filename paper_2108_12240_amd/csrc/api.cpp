@@ -58,7 +58,7 @@ void release(bhac::DeviceGrid &G)
     void *ptrs[] = {G.d_blocks, G.d_levels, G.d_ctab, G.d_f0tab, G.d_f1tab, G.d_ctab32, G.d_f0tab32, G.d_f1tab32,
                     G.d_state, G.d_wcell,
                     G.d_wface[0], G.d_wface[1], G.d_wface[2], G.d_wmarch[0], G.d_wmarch[1], G.d_wmarch[2],
-                    G.d_gdst, G.d_gsrc, G.d_xoff, G.d_xdat, G.d_nbr, G.d_halo,
+                    G.d_gdst, G.d_gsrc, G.d_xoff, G.d_xdat, G.d_ffix, G.d_nbr, G.d_halo,
                     G.d_flux[0], G.d_flux[1], G.d_flux[2], G.d_div};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -186,6 +186,7 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     UP(G.d_gsrc, P.gsrc);
     UP(G.d_xoff, P.xoff);
     UP(G.d_xdat, P.xdat);
+    UP(G.d_ffix, P.ffix);
     UP(G.d_nbr, P.nbr);
     UP(G.d_halo, P.halo);
 #undef UP
@@ -193,6 +194,7 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     G.nface_slots = P.nface_slots;
     G.nxl = P.xoff.empty() ? 0 : (long long)P.xoff.size() - 1;
     G.nxl_face = P.nxl_face;
+    G.nffix = (long long)P.ffix.size() / 6;
     {
         const size_t rsz = G.mixed ? sizeof(float) : sizeof(double);
         for (int d = 0; d < p.ndim && !p.fused; d++) {

@@ -46,7 +46,7 @@ struct GridDev {
 
 // Kernel families timed by the optional HIP-event timer.
 enum KernelId { K_FILL, K_FLUX0, K_FLUX1, K_FLUX2, K_UPDATE, K_PRIM2CON, K_CON2PRIM, K_SPEEDS, K_BEGIN, K_END,
-                K_BLOCK_FLUX, K_UPDATE_DIV, K_FILL_XL, K_COUNT };
+                K_BLOCK_FLUX, K_UPDATE_DIV, K_FILL_XL, K_FLUX_FIX, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Optional per-launch timing: a pre-created pool of HIP events recorded on the
@@ -102,6 +102,8 @@ struct DeviceGrid {
     int32_t *d_gdst = nullptr, *d_gsrc = nullptr;
     int32_t *d_xoff = nullptr, *d_xdat = nullptr;    // cross-level recipes (block trees)
     long long nxl = 0, nxl_face = 0;
+    int32_t *d_ffix = nullptr;                       // flux correction records (block trees)
+    long long nffix = 0;
     int32_t *d_nbr = nullptr;
     HaloAxis *d_halo = nullptr;
     void *d_flux[3] = {nullptr, nullptr, nullptr};   // face-flux scratch of the unfused path

@@ -87,6 +87,9 @@ struct Plan {
     // xdat[xoff[q] .. xoff[q+1]), the first nxl_face of them face-adjacent
     std::vector<int32_t> xoff, xdat;
     long long nxl_face = 0;
+    // block trees: flux correction records [direction, coarse face, 4 fine faces]
+    // (global indices into that direction's face array; 2 fine faces in 2-D)
+    std::vector<int32_t> ffix;
     // metric tables (empty for flat space)
     long long nrec_c = 0, nrec_f0 = 0, nrec_f1 = 0;
     std::vector<double> ctab, f0tab, f1tab;

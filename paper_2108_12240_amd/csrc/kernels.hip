@@ -102,6 +102,30 @@ __global__ __launch_bounds__(WG) void k_fill_xl(const int32_t *__restrict__ xoff
 }
 
 // ---------------------------------------------------------------------------------
+// Flux correction of block trees: one thread per coarse face on a level boundary,
+// which takes the mean of the fine faces covering it (records [direction, coarse
+// face, 4 fine faces], 2 used in 2-D), summed in double in record order.
+// ---------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(WG) void k_flux_fix(const int32_t *__restrict__ fx, long long n, int nsub,
+                                                 R *F0, R *F1, R *F2, long long nf0, long long nf1, long long nf2)
+{
+    const long long t = (long long)blockIdx.x * WG + threadIdx.x;
+    if (t >= n) return;
+    const int32_t *r = fx + 6 * t;
+    const int d = r[0];
+    R *F = d == 0 ? F0 : (d == 1 ? F1 : F2);
+    const long long nf = d == 0 ? nf0 : (d == 1 ? nf1 : nf2);
+    const double w = nsub == 4 ? 0.25 : 0.5;
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        double sum = 0.0;
+        for (int q = 0; q < nsub; q++) sum += (double)F[v * nf + r[2 + q]];
+        F[v * nf + r[1]] = (R)(sum * w);
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // Face fluxes along D: one thread per face of a block (faces 0..s_D along D).
 // ---------------------------------------------------------------------------------
 // waves per SIMD the face kernels are compiled for: the scheduler hoists the
@@ -479,7 +503,7 @@ inline unsigned nblk(long long n) { return (unsigned)((n + WG - 1) / WG); }
 
 const char *const kKernelNames[K_COUNT] = {"fill_ghosts", "flux_x1", "flux_x2", "flux_x3", "update",
                                            "prim2con", "con2prim", "cell_speeds", "step_begin", "step_end",
-                                           "block_flux", "update_div", "fill_cross_level"};
+                                           "block_flux", "update_div", "fill_cross_level", "flux_fix"};
 
 hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only)
 {
@@ -633,6 +657,13 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
     if (e == hipSuccess) e = mm & 2 ? launch_flux_march(G, 1, Ps, s) : flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, s);
     if (e == hipSuccess && G.kp.ndim == 3)
         e = mm & 4 ? launch_flux_march(G, 2, Ps, s) : flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, s);
+    if (e == hipSuccess && G.nffix > 0) {
+        TimedLaunch tl(G.timer, K_FLUX_FIX, s);
+        hipLaunchKernelGGL(k_flux_fix<R>, dim3(nblk(G.nffix)), dim3(WG), 0, s, G.d_ffix, G.nffix,
+                           G.kp.ndim == 3 ? 4 : 2, (R *)G.d_flux[0], (R *)G.d_flux[1], (R *)G.d_flux[2],
+                           G.plan.nface[0], G.plan.nface[1], G.plan.nface[2]);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = update_typed<R, KS>(G, Ub, Us, Ps, Uo, Po, a, b, s);
     return e;
 }

@@ -600,6 +600,57 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                 }
     }
     P.nface_slots = (long long)P.gdst.size();
+    // flux correction of block trees: each face of a block whose far side lies in
+    // finer leaves gets the mean of the fine faces covering it (second transverse
+    // axis outer), applied between the face kernels and the update
+    P.ffix.clear();
+    if (p.amr) {
+        for (int64_t b = 0; b < nb; b++) {
+            const DevBlock &D = P.dblocks[b];
+            for (int d = 0; d < p.ndim; d++) {
+                const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
+                const int fs0 = D.s[0] + (d == 0), fs1 = D.s[1] + (d == 1);
+                for (int side = 0; side < 2; side++) {
+                    if (!(D.hxl >> (2 * d + side) & 1)) continue;
+                    for (int ib = 0; ib < D.s[tb]; ib++)
+                        for (int ia = 0; ia < D.s[ta]; ia++) {
+                            int l[3];
+                            l[d] = side ? D.s[d] : -1;
+                            l[ta] = ia;
+                            l[tb] = ib;
+                            long long Gi[3];
+                            for (int e = 0; e < 3; e++) Gi[e] = wrap_axis(D.level, e, (long long)D.o[e] + l[e]);
+                            const long long f[3] = {2 * Gi[0], 2 * Gi[1], p.ndim == 3 ? 2 * Gi[2] : 0};
+                            const int fb = leaf_at(D.level + 1, f);
+                            if (fb < 0) break;                // a coarser neighbour: nothing to correct
+                            const DevBlock &F = P.dblocks[fb];
+                            const int ffs0 = F.s[0] + (d == 0), ffs1 = F.s[1] + (d == 1);
+                            int cl[3];
+                            cl[d] = side ? D.s[d] : 0;
+                            cl[ta] = ia;
+                            cl[tb] = ib;
+                            P.ffix.push_back(d);
+                            P.ffix.push_back((int32_t)(D.fofs[d] + ((long long)cl[2] * fs1 + cl[1]) * fs0 + cl[0]));
+                            for (int sb = 0; sb < 2; sb++)
+                                for (int sa = 0; sa < 2; sa++) {
+                                    if (p.ndim < 3 && sb > 0) { P.ffix.push_back(0); continue; }
+                                    int fl[3];
+                                    fl[d] = side ? (int)(f[d] - F.o[d]) : (int)(f[d] + 1 - F.o[d]) + 1;
+                                    fl[ta] = (int)(f[ta] + sa - F.o[ta]);
+                                    fl[tb] = tb < p.ndim ? (int)(f[tb] + sb - F.o[tb]) : 0;
+                                    if (fl[d] != (side ? 0 : F.s[d]) || fl[ta] < 0 || fl[ta] >= F.s[ta] ||
+                                        fl[tb] < 0 || fl[tb] >= F.s[tb]) {
+                                        err = "internal: fine face of a flux correction outside its block";
+                                        return BHAC_EINVAL;
+                                    }
+                                    P.ffix.push_back((int32_t)(F.fofs[d] + ((long long)fl[2] * ffs1 + fl[1]) * ffs0 + fl[0]));
+                                }
+                        }
+                }
+            }
+        }
+    }
+
     // prolongation groups after the restrictions of their class
     for (int cls = 0; cls < 2; cls++) {
         std::vector<int32_t> &xs = cls == 0 ? xface : xedge;

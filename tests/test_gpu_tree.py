@@ -6,6 +6,7 @@ import pytest
 from oracle import oracle as O
 from paper_2108_12240_amd import bhac as B
 from paper_2108_12240_amd import inputs as I
+from tests.cases import flat_tree_case, tree_volumes
 from tests.parity import rel_l1
 
 pytestmark = pytest.mark.gpu
@@ -130,3 +131,27 @@ def test_block_tiled_path_rejects_trees(torch):
     with pytest.raises(B.BhacError) as e:
         B.Grid(dict(c.params, fused=1), c.blocks)
     assert e.value.code == B.BHAC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec,tol", [(I.PREC_FP64, 1e-13), (I.PREC_MIXED, 1e-6)])
+def test_flux_correction_conserves_across_levels(torch, prec, tol):
+    """Periodic flat three-level tree, no sources: the volume-weighted totals of D,
+    S, tau and B after two RK2 steps equal the initial ones (to rounding; in mixed
+    precision each cell's flux difference is formed in float)."""
+    params, blocks, prim = flat_tree_case()
+    params = dict(params, precision=prec, fused=0)
+    banner(f"conservation prec={prec}")
+    G = B.Grid(params, blocks)
+    U, P = G.init(prim)
+    U1, P1 = G.new_state("U"), G.new_state("P")
+    vol = tree_volumes(blocks, 32)
+    U0 = U.cpu().numpy().copy()
+    for _ in range(2):
+        G.rk2_step(U, P, U1, P1)
+    torch.cuda.synchronize()
+    Un = U.cpu().numpy()
+    for q in range(8):
+        scale = np.sum(np.abs(U0[q]) * vol)
+        assert abs(np.sum(Un[q] * vol) - np.sum(U0[q] * vol)) <= tol * scale, q
+    assert G.stats()["c2p_fail"] == 0
+    G.close()
