@@ -62,6 +62,14 @@ void release(bhac::DeviceGrid &G)
                     G.d_flux[0], G.d_flux[1], G.d_flux[2], G.d_div};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (int q = 0; q < 2; q++) {
+        if (G.side[q]) (void)hipStreamDestroy(G.side[q]);
+        if (G.ev_join[q]) (void)hipEventDestroy(G.ev_join[q]);
+        G.side[q] = nullptr;
+        G.ev_join[q] = nullptr;
+    }
+    if (G.ev_fork) (void)hipEventDestroy(G.ev_fork);
+    G.ev_fork = nullptr;
 }
 
 int check_grid(bhac_grid *g)
@@ -227,6 +235,14 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     G.gd.nbr = G.d_nbr;
     G.gd.halo = G.d_halo;
     G.gd.hmax = P.hmax;
+    for (int q = 0; q < 2; q++) {
+        e = hipStreamCreateWithFlags(&G.side[q], hipStreamNonBlocking);
+        if (e != hipSuccess) goto hip_error;
+        e = hipEventCreateWithFlags(&G.ev_join[q], hipEventDisableTiming);
+        if (e != hipSuccess) goto hip_error;
+    }
+    e = hipEventCreateWithFlags(&G.ev_fork, hipEventDisableTiming);
+    if (e != hipSuccess) goto hip_error;
     if (layout) {
         layout->ncell_padded = P.off.back();
         layout->ncell_interior = P.ncell_interior;

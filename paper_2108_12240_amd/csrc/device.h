@@ -107,6 +107,11 @@ struct DeviceGrid {
     int32_t *d_nbr = nullptr;
     HaloAxis *d_halo = nullptr;
     void *d_flux[3] = {nullptr, nullptr, nullptr};   // face-flux scratch of the unfused path
+    // owned side streams (default priority) and events: the three face kernels of a
+    // substep are independent and run concurrently, forked from and joined back to
+    // the caller's stream (a captured graph records the fork and join as edges)
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
     void *d_div = nullptr;                           // flux divergence of the block-tiled path [9][interior]
     long long nghost_slots = 0;
     long long nface_slots = 0;                       // leading slots of the map with one axis outside

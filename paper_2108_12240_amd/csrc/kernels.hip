@@ -651,12 +651,29 @@ template <typename R, int RECON, int FLUX, bool KS>
 static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
                                 void *Po, double a, double b, hipStream_t s)
 {
-    // each direction by faces or by lines, as planned
+    // each direction by faces or by lines, as planned; in 3-D the x2 and x3 kernels
+    // run on the grid's side streams, concurrently with x1 on the caller's stream
     const int mm = G.plan.march_mask;
-    hipError_t e = mm & 1 ? launch_flux_march(G, 0, Ps, s) : flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, s);
-    if (e == hipSuccess) e = mm & 2 ? launch_flux_march(G, 1, Ps, s) : flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, s);
-    if (e == hipSuccess && G.kp.ndim == 3)
-        e = mm & 4 ? launch_flux_march(G, 2, Ps, s) : flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, s);
+    auto dir = [&](int d, hipStream_t st) -> hipError_t {
+        if (mm >> d & 1) return launch_flux_march(G, d, Ps, st);
+        if (d == 0) return flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, st);
+        if (d == 1) return flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, st);
+        return flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, st);
+    };
+    hipError_t e = hipSuccess;
+    if (G.kp.ndim == 3 && G.side[0] && G.side[1]) {
+        e = hipEventRecord(G.ev_fork, s);
+        for (int q = 0; q < 2 && e == hipSuccess; q++) e = hipStreamWaitEvent(G.side[q], G.ev_fork, 0);
+        if (e == hipSuccess) e = dir(1, G.side[0]);
+        if (e == hipSuccess) e = dir(2, G.side[1]);
+        if (e == hipSuccess) e = dir(0, s);
+        for (int q = 0; q < 2 && e == hipSuccess; q++) e = hipEventRecord(G.ev_join[q], G.side[q]);
+        for (int q = 0; q < 2 && e == hipSuccess; q++) e = hipStreamWaitEvent(s, G.ev_join[q], 0);
+    } else {
+        e = dir(0, s);
+        if (e == hipSuccess) e = dir(1, s);
+        if (e == hipSuccess && G.kp.ndim == 3) e = dir(2, s);
+    }
     if (e == hipSuccess && G.nffix > 0) {
         TimedLaunch tl(G.timer, K_FLUX_FIX, s);
         hipLaunchKernelGGL(k_flux_fix<R>, dim3(nblk(G.nffix)), dim3(WG), 0, s, G.d_ffix, G.nffix,
