@@ -47,6 +47,9 @@ WORKLOADS = {
     "ks_torus_192_mixed_auto": dict(cfg=3, n=192, precision=1, fused="auto"),
     "amr_like_4096_mixed_auto": dict(cfg=4, precision=1, fused="auto"),
     "ks_turb_384_mixed_auto": dict(cfg=5, n=384, precision=1, fused="auto"),
+    # one GPU's share of the 384^3 turbulent torus sharded in eight phi-slabs:
+    # 384 x 384 x 48 zones (1728 blocks of 16^3), phi ends joined periodically
+    "ks_turb_384_slab8_mixed_plain": dict(cfg="slab", n=(384, 384, 48), precision=1, fused=0),
     # 2:1 block tree of 16^3 blocks on three levels around the torus (96^3 base,
     # 972 blocks, 4.0 M zones), with restriction / prolongation between levels
     "amr_tree_96_mixed_plain": dict(cfg="tree", n0=96, bs=16, levels=3, precision=1, fused=0),

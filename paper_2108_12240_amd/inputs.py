@@ -215,13 +215,17 @@ def _finish_torus(prim, r):
     return prim
 
 
-def case_torus(cfg: int, n=128, bs: int = 16, precision=None, fused=None) -> Case:
-    """Cases 2 (128^3, FP64 plain), 3 (192^3, mixed) and 5 (384^3, mixed + turbulence)."""
+def case_torus(cfg: int, n=128, bs: int = 16, precision=None, fused=None, phi_slabs: int = 1) -> Case:
+    """Cases 2 (128^3, FP64 plain), 3 (192^3, mixed) and 5 (384^3, mixed + turbulence).
+    phi_slabs > 1: only the first of that many equal phi-slabs of the domain (one
+    GPU's share of a run sharded along phi), n giving its own cell counts; its phi
+    ends are joined periodically in place of the neighbouring slabs."""
     if isinstance(n, int):
         n = (n, n, n)
     assert all(v % bs == 0 for v in n)
     rng = np.random.default_rng(12240 + cfg)
     x_lo, x_hi = ks_domain()
+    x_hi = [x_hi[0], x_hi[1], x_lo[2] + (x_hi[2] - x_lo[2]) / phi_slabs]
     prec = {2: PREC_FP64, 3: PREC_MIXED, 5: PREC_MIXED}[cfg] if precision is None else precision
     fus = {2: 0, 3: 0, 5: 1}[cfg] if fused is None else fused
     params = base_params(x_lo=x_lo, x_hi=x_hi, ncell0=list(n), precision=prec, fused=fus)
@@ -393,6 +397,8 @@ def make_case(cfg: int, **kw) -> Case:
         return case1(**kw)
     if cfg in (2, 3, 5):
         return case_torus(cfg, **kw)
+    if cfg == "slab":
+        return case_torus(5, n=kw.get("n", (384, 384, 48)), phi_slabs=kw.get("phi_slabs", 8))
     if cfg == 4:
         return case4(**kw)
     if cfg == "tree":
