@@ -43,6 +43,7 @@ WORKLOADS = {
     "ks_turb_384_mixed_plain": dict(cfg=5, n=384, precision=1, fused=0),
     "ks_turb_384_mixed_fused": dict(cfg=5, n=384, precision=1, fused=1),
     # mixed precision, substep implementation chosen by the autotuner
+    "ks_torus_128_fp64_auto": dict(cfg=2, n=128, precision=0, fused="auto"),
     "ks_torus_128_mixed_auto": dict(cfg=2, n=128, precision=1, fused="auto"),
     "ks_torus_192_mixed_auto": dict(cfg=3, n=192, precision=1, fused="auto"),
     "amr_like_4096_mixed_auto": dict(cfg=4, precision=1, fused="auto"),
@@ -54,6 +55,8 @@ WORKLOADS = {
     # 972 blocks, 4.0 M zones), with restriction / prolongation between levels
     "amr_tree_96_mixed_plain": dict(cfg="tree", n0=96, bs=16, levels=3, precision=1, fused=0),
     "amr_tree_96_fp64_plain": dict(cfg="tree", n0=96, bs=16, levels=3, precision=0, fused=0),
+    "amr_tree_96_mixed_auto": dict(cfg="tree", n0=96, bs=16, levels=3, precision=1, fused="auto"),
+    "amr_tree_96_fp64_auto": dict(cfg="tree", n0=96, bs=16, levels=3, precision=0, fused="auto"),
 }
 
 
@@ -160,6 +163,18 @@ def run_gpu(case, steps, warmup, graph=True):
                 stats=stats, dt=ts["dt"], finite=finite, graph=graph)
 
 
+def autotune_summary(rep):
+    """The autotuner's choice and the spread of the candidates it timed."""
+    def label(ch):
+        if ch["fused"]:
+            return "block-tiled"
+        sc = ch["sched"]
+        return f"march{sc['march_mask']}/seg{sc['march_faces']}/x1stage{sc['x1_staged']}"
+    ms = [t["ms_per_step"] for t in rep["timings"] if t["ms_per_step"] is not None]
+    return dict(choice=label(rep["choice"]), cached=rep["cached"], timed=len(ms),
+                best_ms=round(min(ms), 4), worst_ms=round(max(ms), 4))
+
+
 def roofline(res, rsz, workload):
     kt = {k: v for k, v in res["ktimes"].items() if k not in ("step_begin", "step_end", "untimed")}
     dom = max(kt, key=lambda k: kt[k][1])
@@ -260,8 +275,11 @@ def main(argv=None):
             from paper_2108_12240_amd import autotune
             params, report = autotune.tune(dict(c.params, precision=w["precision"]), c.blocks, c.prim)
             w["fused"] = int(params["fused"])
+            w["sched"] = params.get("sched")
             w["autotune"] = report
         c.params = dict(c.params, precision=w["precision"], fused=w["fused"])
+        if w.get("sched"):
+            c.params["sched"] = w["sched"]
         return c, w
 
     case, w = make(args.workload)
@@ -278,7 +296,7 @@ def main(argv=None):
                            fused=bool(w["fused"]), graph=res["graph"]),
                roofline=roofline(res, rsz, args.workload))
     if "autotune" in w:
-        out["config"]["autotune"] = {str(t["choice"]["fused"]): t["ms_per_step"] for t in w["autotune"]["timings"]}
+        out["config"]["autotune"] = autotune_summary(w["autotune"])
     out["kernel_ms"] = {k: round(v[1] / max(v[0], 1), 4) for k, v in res["ktimes"].items()}
     out["c2p"] = res["stats"]
     out["finite"] = res["finite"]
@@ -291,6 +309,8 @@ def main(argv=None):
                               speedup_vs_headline=round(r2["value"] / res["value"], 3),
                               roofline=roofline(r2, rsz2, args.compare),
                               kernel_ms={k: round(v[1] / max(v[0], 1), 4) for k, v in r2["ktimes"].items()})
+        if "autotune" in w2:
+            out["compare"]["autotune"] = autotune_summary(w2["autotune"])
         del c2
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)

@@ -96,7 +96,29 @@ enum { BHAC_PREC_FP64 = 0, BHAC_PREC_MIXED = 1 };
  *                       cells come from prolongation or restriction (see
  *                       bhac_fill_ghosts). Needs fused = 0 (else
  *                       BHAC_EUNSUPPORTED).
+ *  sched                kernel schedule of the unfused substep (see bhac_schedule).
  */
+
+/* Schedule of the unfused substep (fused = 0; the block-tiled path ignores it).
+ * Every schedule computes the same face fluxes by the same per-face arithmetic
+ * (Section 2's reconstruction and Riemann solver); only the mapping of work onto
+ * waves differs, so a schedule is a tuning choice, not a change of method.
+ *  set          0: the library's defaults, the other fields are ignored.
+ *  march_mask   bit d set: the fluxes along direction d come from the line-march
+ *               kernel (one thread walks a line of cells and reconstructs each cell
+ *               once); clear: from the face kernel (one thread per face).
+ *  march_faces  longest line segment of the march kernel, in faces, 4..256; longer
+ *               lines are cut into near-equal segments, each with its own warm-up.
+ *  x1_staged    1: the x1 face kernel stages block rows with their halo in LDS where
+ *               every block's rows fit; 0: it reads cells straight from memory.
+ * Out-of-range values give BHAC_EINVAL. */
+typedef struct bhac_schedule {
+    int set;
+    int march_mask;
+    int march_faces;
+    int x1_staged;
+} bhac_schedule;
+
 typedef struct bhac_params {
     int ndim;           /* 2 or 3 */
     int nghost;         /* >= 2 for MC, >= 3 for PPM */
@@ -110,6 +132,7 @@ typedef struct bhac_params {
     double cfl, rho_floor, p_floor, w_max, glm_alpha, c2p_tol;
     int c2p_maxit;
     int amr;            /* 0 independent patches, 1 block tree */
+    bhac_schedule sched;
 } bhac_params;
 
 /* One block: refinement level, interior cells per axis, and origin in level-l
@@ -248,6 +271,10 @@ int bhac_get_timestep(bhac_grid *grid, bhac_timestep *out);
  * may be NULL. */
 int bhac_get_stats(bhac_grid *grid, int64_t *c2p_fail, int64_t *floor_hits, int *max_iter);
 int bhac_reset_stats(bhac_grid *grid, void *stream);
+
+/* The schedule the grid's unfused substep runs, defaults resolved (set = 1;
+ * x1_staged reads 1 only where the rows fit the LDS tile). Host only. */
+int bhac_get_schedule(bhac_grid *grid, bhac_schedule *out);
 
 /* One whole SSP-RK2 step as a HIP graph (the launch-bound inner loop of a run).
  * bhac_capture_rk2_step records, on a stream the grid owns, the kernels of

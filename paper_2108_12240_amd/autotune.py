@@ -1,12 +1,20 @@
-"""Choose the faster substep implementation for a workload by timing it.
+"""Choose the substep implementation and kernel schedule for a workload by timing.
 
-Candidates are the unfused kernels (``fused = 0``) and the block-tiled kernels
-(``fused = 1``, where the grid supports them). Each candidate advances a copy of
-the workload's initial state with replays of the captured RK2-step graph; the
-fastest wins. Choices are cached in a JSON file keyed by the GPU architecture and
-a signature of the workload (metric, dimensionality, reconstruction, flux,
-precision, and the histogram of block (level, size)), so later runs skip the
-timing. Everything timed runs in the library's kernels.
+Candidates are the block-tiled kernels (``fused = 1``, where the grid supports
+them) and the unfused kernels (``fused = 0``) under every schedule of the
+``bhac_schedule`` search space: which directions take the line-march kernel and
+which the face kernel, how long a march segment may be, and whether the x1 face
+kernel stages rows in LDS. The default search is staged (all march masks first,
+then segment lengths and x1 staging for the two best); an exhaustive one times
+every candidate. Schedules that resolve to the same kernels (x1 staging
+where the rows do not fit, segment lengths longer than every line) are timed once.
+Each candidate advances a copy of the workload's initial state with replays of
+the captured RK2-step graph; the fastest wins. Every schedule computes the same
+fluxes, so the choice changes speed, not results. Choices are cached in a JSON
+file keyed by the GPU architecture and a signature of the workload (metric,
+dimensionality, reconstruction, flux, precision, block tree or not, and the
+histogram of block (level, size)), so later runs skip the timing. Everything
+timed runs in the library's kernels.
 """
 from __future__ import annotations
 
@@ -19,7 +27,20 @@ import numpy as np
 from . import bhac as B
 
 CACHE_ENV = "BHAC_AUTOTUNE_CACHE"
-CANDIDATES = ({"fused": 0}, {"fused": 1})
+SEARCH_VERSION = 2
+MARCH_FACES = (9, 17, 33)
+
+
+def candidates(params: dict) -> list:
+    """The search space: the block-tiled substep, then the unfused one under every
+    schedule (march mask x x1 staging x segment length)."""
+    out = [{"fused": 1}]
+    ndim = int(params["ndim"])
+    for mask in range(1 << ndim):
+        for x1 in ((0,) if mask & 1 else (0, 1)):
+            for faces in (MARCH_FACES if mask else (MARCH_FACES[1],)):
+                out.append({"fused": 0, "sched": {"march_mask": mask, "march_faces": faces, "x1_staged": x1}})
+    return out
 
 
 def cache_path() -> str:
@@ -32,7 +53,8 @@ def signature(params: dict, blocks: np.ndarray) -> dict:
     for blk in np.asarray(blocks):
         k = f"{int(blk[0])}:{int(blk[1])}x{int(blk[2])}x{int(blk[3])}"
         hist[k] = hist.get(k, 0) + 1
-    return dict({k: int(params[k]) for k in keys}, blocks=dict(sorted(hist.items())))
+    return dict({k: int(params[k]) for k in keys}, amr=int(params.get("amr", 0)), search=SEARCH_VERSION,
+                blocks=dict(sorted(hist.items())))
 
 
 def _key(arch: str, sig: dict) -> str:
@@ -47,10 +69,25 @@ def _load(path):
         return {}
 
 
-def _time_candidate(params, blocks, prim, steps, warmup):
+def _time_candidate(params, blocks, prim, steps, warmup, seen):
+    """ms per RK2 step of one candidate, or None where the grid rejects it or its
+    resolved schedule was already timed."""
     import torch
-    G = B.Grid(params, blocks)
     try:
+        G = B.Grid(params, blocks)
+    except B.BhacError as e:
+        if e.code != B.BHAC_EUNSUPPORTED:
+            raise
+        return None, None
+    try:
+        resolved = None
+        if not params["fused"]:
+            resolved = G.schedule()
+            if not any(resolved["march_mask"] & (1 << d) for d in range(int(params["ndim"]))):
+                resolved["march_faces"] = 0          # unused when no direction marches
+            if any(resolved == r for r in seen):
+                return None, resolved
+            seen.append(resolved)
         U, P = G.init(prim)
         U1, P1 = G.new_state("U"), G.new_state("P")
         G.capture_rk2_step(U, P, U1, P1)
@@ -63,37 +100,64 @@ def _time_candidate(params, blocks, prim, steps, warmup):
             G.launch_rk2_step()
         b.record()
         torch.cuda.synchronize()
-        return a.elapsed_time(b) / steps
+        return a.elapsed_time(b) / steps, resolved
     finally:
         G.close()
 
 
+def _staged(params, blocks, prim, steps, warmup, seen, timings):
+    """Two-stage search: every march mask at the middle segment length with x1
+    staging where x1 is not marched (and the block-tiled kernels), then the other
+    segment lengths and the unstaged x1 kernel for the two fastest masks."""
+    def run(cands):
+        for cand in cands:
+            ms, _ = _time_candidate(dict(params, **cand), blocks, prim, steps, warmup, seen)
+            timings.append(dict(choice=cand, ms_per_step=ms))
+
+    def sched(mask, faces, x1):
+        return {"fused": 0, "sched": {"march_mask": mask, "march_faces": faces, "x1_staged": x1}}
+
+    mid = MARCH_FACES[len(MARCH_FACES) // 2]
+    run([{"fused": 1}] + [sched(m, mid, 0 if m & 1 else 1) for m in range(1 << int(params["ndim"]))])
+    plain = sorted((t for t in timings if t["ms_per_step"] is not None and not t["choice"]["fused"]),
+                   key=lambda t: t["ms_per_step"])
+    second = []
+    for t in plain[:2]:
+        sc = t["choice"]["sched"]
+        if sc["march_mask"]:
+            second += [sched(sc["march_mask"], f, sc["x1_staged"]) for f in MARCH_FACES if f != mid]
+        if sc["x1_staged"]:
+            second.append(sched(sc["march_mask"], mid, 0))
+    run(second)
+
+
 def tune(params: dict, blocks: np.ndarray, prim: np.ndarray, steps: int = 3, warmup: int = 1,
-         path: str | None = None, refresh: bool = False):
-    """Return (params with the chosen variant, report). The report lists each
-    candidate's ms per RK2 step (None where the grid does not support it)."""
+         path: str | None = None, refresh: bool = False, search: str = "staged"):
+    """Return (params with the chosen variant, report). ``search`` is "staged" (about
+    half the candidates, see _staged) or "exhaustive" (every candidate). The report
+    lists each timed candidate's ms per RK2 step (None where the grid does not
+    support it or an equal schedule was timed already)."""
     import torch
+    if search not in ("staged", "exhaustive"):
+        raise ValueError(f"unknown search {search!r}")
     path = path or cache_path()
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     sig = signature(params, blocks)
-    key = _key(arch, sig)
+    key = _key(arch, sig) + ":" + search
     cache = _load(path)
     if not refresh and key in cache:
         entry = cache[key]
         return dict(params, **entry["choice"]), dict(entry, cached=True)
-    timings = []
-    for cand in CANDIDATES:
-        p = dict(params, **cand)
-        try:
-            ms = _time_candidate(p, blocks, prim, steps, warmup)
-        except B.BhacError as e:
-            if e.code != B.BHAC_EUNSUPPORTED:
-                raise
-            ms = None
-        timings.append(dict(choice=cand, ms_per_step=ms))
+    timings, seen = [], []
+    if search == "staged":
+        _staged(params, blocks, prim, steps, warmup, seen, timings)
+    else:
+        for cand in candidates(params):
+            ms, _ = _time_candidate(dict(params, **cand), blocks, prim, steps, warmup, seen)
+            timings.append(dict(choice=cand, ms_per_step=ms))
     ok = [t for t in timings if t["ms_per_step"] is not None]
     best = min(ok, key=lambda t: t["ms_per_step"])
-    entry = dict(arch=arch, signature=sig, choice=best["choice"], timings=timings)
+    entry = dict(arch=arch, signature=sig, search=search, choice=best["choice"], timings=timings)
     cache[key] = entry
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -28,13 +28,17 @@ class BhacError(RuntimeError):
         self.code = code
 
 
+class bhac_schedule(C.Structure):
+    _fields_ = [("set", C.c_int), ("march_mask", C.c_int), ("march_faces", C.c_int), ("x1_staged", C.c_int)]
+
+
 class bhac_params(C.Structure):
     _fields_ = [("ndim", C.c_int), ("nghost", C.c_int), ("metric", C.c_int), ("spin", C.c_double),
                 ("gamma_ad", C.c_double), ("x_lo", C.c_double * 3), ("x_hi", C.c_double * 3),
                 ("ncell0", C.c_int * 3), ("bc", (C.c_int * 2) * 3), ("recon", C.c_int), ("flux", C.c_int),
                 ("precision", C.c_int), ("fused", C.c_int), ("cfl", C.c_double), ("rho_floor", C.c_double),
                 ("p_floor", C.c_double), ("w_max", C.c_double), ("glm_alpha", C.c_double),
-                ("c2p_tol", C.c_double), ("c2p_maxit", C.c_int), ("amr", C.c_int)]
+                ("c2p_tol", C.c_double), ("c2p_maxit", C.c_int), ("amr", C.c_int), ("sched", bhac_schedule)]
 
 
 class bhac_block_desc(C.Structure):
@@ -83,6 +87,7 @@ def lib():
             "bhac_get_timestep": [_VP, C.POINTER(bhac_timestep)],
             "bhac_get_stats": [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)],
             "bhac_reset_stats": [_VP, _VP],
+            "bhac_get_schedule": [_VP, C.POINTER(bhac_schedule)],
             "bhac_set_timing": [_VP, C.c_int],
             "bhac_capture_rk2_step": [_VP, _VP, _VP, _VP, _VP],
             "bhac_launch_rk2_step": [_VP, _VP],
@@ -111,6 +116,12 @@ def make_params(d: dict) -> bhac_params:
     for k in ("ndim", "nghost", "metric", "recon", "flux", "precision", "fused", "c2p_maxit"):
         setattr(p, k, int(d[k]))
     p.amr = int(d.get("amr", 0))
+    sched = d.get("sched")
+    if sched is not None:
+        p.sched.set = 1
+        p.sched.march_mask = int(sched["march_mask"])
+        p.sched.march_faces = int(sched["march_faces"])
+        p.sched.x1_staged = int(sched["x1_staged"])
     for k in ("spin", "gamma_ad", "cfl", "rho_floor", "p_floor", "w_max", "glm_alpha", "c2p_tol"):
         setattr(p, k, float(d[k]))
     for e in range(3):
@@ -220,6 +231,12 @@ def bhac_get_stats(h) -> dict:
     f, fl, it = C.c_int64(), C.c_int64(), C.c_int()
     _check(lib().bhac_get_stats(h, C.byref(f), C.byref(fl), C.byref(it)))
     return dict(c2p_fail=f.value, floor_hits=fl.value, max_iter=it.value)
+
+
+def bhac_get_schedule(h) -> dict:
+    o = bhac_schedule()
+    _check(lib().bhac_get_schedule(h, C.byref(o)))
+    return dict(march_mask=o.march_mask, march_faces=o.march_faces, x1_staged=o.x1_staged)
 
 
 def bhac_reset_stats(h, stream=None):
@@ -363,3 +380,6 @@ class Grid:
 
     def stats(self):
         return bhac_get_stats(self.h)
+
+    def schedule(self):
+        return bhac_get_schedule(self.h)

@@ -21,8 +21,11 @@ ARCH = "gfx950"
 
 SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "fused.hip", "march.hip"]
 
+# -ffp-contract=on: a multiply-add is fused only within one source expression, so
+# the same expression rounds the same way in every kernel that inlines it (the face
+# and line-march flux kernels then give bit-identical fluxes).
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-            "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
+            "-packed-fp32-ops", "-ffp-contract=on", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 
 
 def _hipcc() -> str:

@@ -402,6 +402,18 @@ int bhac_get_stats(bhac_grid *g, int64_t *c2p_fail, int64_t *floor_hits, int *ma
     return BHAC_OK;
 }
 
+int bhac_get_schedule(bhac_grid *g, bhac_schedule *out)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!out) return fail(BHAC_EINVAL, "null output");
+    const bhac::Plan &P = g->dg.plan;
+    out->set = 1;
+    out->march_mask = P.march_mask;
+    out->march_faces = P.march_faces;
+    out->x1_staged = P.x1_staged ? 1 : 0;
+    return BHAC_OK;
+}
+
 int bhac_capture_rk2_step(bhac_grid *g, double *U, void *P, double *U1, void *P1)
 {
     if (int rc = check_grid(g)) return rc;

@@ -99,6 +99,7 @@ struct Plan {
     std::vector<MarchItem> wmarch[3];
     int march_mask = 0;                  // bit D: direction D uses the line kernel
     bool x1_staged = false;              // x1 faces by the LDS-staged face kernel
+    int march_faces = MARCH_MAX_FACES;   // longest march segment, in faces
     long long nface[3] = {0, 0, 0};
     // fused-kernel neighbour data
     std::vector<int32_t> nbr;            // 27 per block: block id of neighbour slot (dir+1 base 3), -1 if none

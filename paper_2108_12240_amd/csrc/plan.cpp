@@ -120,6 +120,12 @@ bool check_params(const bhac_params &p, std::string &err)
     if (p.precision != BHAC_PREC_FP64 && p.precision != BHAC_PREC_MIXED) return bad(err, "unknown precision");
     if (p.fused != 0 && p.fused != 1) return bad(err, "fused must be 0 or 1");
     if (p.amr != 0 && p.amr != 1) return bad(err, "amr must be 0 or 1");
+    if (p.sched.set != 0 && p.sched.set != 1) return bad(err, "sched.set must be 0 or 1");
+    if (p.sched.set) {
+        if (p.sched.march_mask < 0 || p.sched.march_mask > 7) return bad(err, "sched.march_mask must be in [0, 7]");
+        if (p.sched.march_faces < 4 || p.sched.march_faces > 256) return bad(err, "sched.march_faces must be in [4, 256]");
+        if (p.sched.x1_staged != 0 && p.sched.x1_staged != 1) return bad(err, "sched.x1_staged must be 0 or 1");
+    }
     const int gmin = p.recon == BHAC_RECON_PPM ? 3 : 2;
     if (p.nghost < gmin || p.nghost > 8) return bad(err, "nghost must be >= 2 (MC) or >= 3 (PPM) and <= 8");
     if (!(std::fabs(p.spin) < 1.0)) return bad(err, "|spin| must be < 1");
@@ -267,6 +273,8 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     // other two lattice coordinates, then the coordinate along d), so the blocks
     // whose interiors a block's stencils reach are its neighbours in the list and,
     // after the XCD split below, mostly on the same XCD (one L2)
+    const int march_faces = p.sched.set ? p.sched.march_faces : MARCH_MAX_FACES;
+    P.march_faces = march_faces;
     for (int d = 0; d < p.ndim; d++) {
         std::vector<int> ord(nb);
         for (int64_t b = 0; b < nb; b++) ord[b] = (int)b;
@@ -284,18 +292,19 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
             // lines along d: MWG per item, faces cut into nseg near-equal segments
             const int a = d == 0 ? 1 : 0, c = d == 2 ? 1 : 2;
             const int nline = D.s[a] * D.s[c], nfd = D.s[d] + 1;
-            const int nseg = (nfd + MARCH_MAX_FACES - 1) / MARCH_MAX_FACES;
+            const int nseg = (nfd + march_faces - 1) / march_faces;
             for (int l0 = 0; l0 < nline; l0 += MWG)
                 for (int q = 0; q < nseg; q++)
                     P.wmarch[d].push_back({b, l0, (int)((long long)nfd * q / nseg), (int)((long long)nfd * (q + 1) / nseg)});
         }
     }
-    P.march_mask = (p.precision == BHAC_PREC_MIXED ? MARCH_MASK_F32 : MARCH_MASK_F64) & ((1 << p.ndim) - 1);
+    P.march_mask = (p.sched.set ? p.sched.march_mask : p.precision == BHAC_PREC_MIXED ? MARCH_MASK_F32 : MARCH_MASK_F64) &
+                   ((1 << p.ndim) - 1);
     // staged x1 faces when every block's rows fit the LDS tile: a work-group's WG
     // consecutive faces touch at most ceil(WG / (s0 + 1)) + 1 rows of s0 + 6 cells
     {
         const int cap = p.precision == BHAC_PREC_MIXED ? x1s_max_cells<float>() : x1s_max_cells<double>();
-        bool ok = !(P.march_mask & 1);
+        bool ok = !(P.march_mask & 1) && (!p.sched.set || p.sched.x1_staged);
         for (int64_t b = 0; b < nb && ok; b++) {
             const int s0 = P.dblocks[b].s[0];
             const int rows = (WG + s0) / (s0 + 1) + 1;

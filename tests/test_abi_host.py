@@ -89,3 +89,26 @@ def test_autotune_signature_is_host_logic():
     k1 = autotune._key("gfx950", sig)
     assert k1 == autotune._key("gfx950", autotune.signature(c.params, c.blocks))
     assert k1 != autotune._key("gfx942", sig)
+
+
+def test_autotune_search_space_is_valid():
+    from paper_2108_12240_amd import autotune
+    c = I.case_torus(2, n=32)
+    cands = autotune.candidates(c.params)
+    assert cands[0] == {"fused": 1}
+    scheds = [x["sched"] for x in cands[1:]]
+    assert len({tuple(sorted(x.items())) for x in scheds}) == len(scheds)
+    assert {x["march_mask"] for x in scheds} == set(range(8))
+    # each candidate passes the library's parameter check (host-only planning)
+    for x in cands[1:]:
+        B.bhac_plan_ghosts(dict(c.params, **x), c.blocks)
+
+
+@pytest.mark.parametrize("bad", [dict(march_mask=8, march_faces=17, x1_staged=0),
+                                 dict(march_mask=0, march_faces=3, x1_staged=0),
+                                 dict(march_mask=0, march_faces=17, x1_staged=2)])
+def test_out_of_range_schedule_is_rejected(bad):
+    c = I.case_torus(2, n=32)
+    with pytest.raises(B.BhacError) as e:
+        B.bhac_plan_ghosts(dict(c.params, sched=bad), c.blocks)
+    assert e.value.code == B.BHAC_EINVAL
