@@ -27,7 +27,8 @@
 #include <string.h>
 
 #define NV 9
-enum { IRHO = 0, IU1 = 1, IP = 4, IB1 = 5, IPSI = 8 };
+#define NVE 10                         /* with the entropy field */
+enum { IRHO = 0, IU1 = 1, IP = 4, IB1 = 5, IPSI = 8, IENT = 9 };
 enum { ID = 0, IS1 = 1, ITAU = 4 };
 
 /* ---------------------------------------------------------------------------------
@@ -43,7 +44,11 @@ typedef struct {
     double cfl, rho_floor, p_floor, w_max, glm_alpha, c2p_tol;
     int c2p_maxit;
     int amr;                           /* 0 independent same-level patches, 1 2:1 block tree */
+    int entropy;                       /* 1: carry the entropy field (P[9] = K, U[9] = U[0] K) */
 } orc_params;
+
+/* rows of P and U: the nine GRMHD variables, plus the entropy field if carried */
+static int nvar(const orc_params *p) { return p->entropy ? NVE : NV; }
 
 typedef struct { int level, size[3], origin[3]; } orc_block;
 
@@ -54,6 +59,7 @@ typedef struct {
     int have_dt;
     int64_t c2p_fail, floor_hits;
     int max_iter;
+    int64_t c2p_backup;                /* cells whose inversion came from the entropy backup */
 } orc_state;
 
 /* ---------------------------------------------------------------------------------
@@ -172,6 +178,7 @@ static void p2c_point(const orc_params *p, const ometric *m, const double *P, do
     U[ITAU] = m->sqrtg * s.tau;
     for (int i = 0; i < 3; i++) U[IB1 + i] = m->sqrtg * s.B[i];
     U[IPSI] = P[IPSI];
+    if (p->entropy) U[IENT] = U[ID] * P[IENT];
 }
 
 /* ---------------------------------------------------------------------------------
@@ -416,12 +423,73 @@ static double c2p_step(const c2p_sys *c, double xi)
     return xn;
 }
 
+/* ---------------------------------------------------------------------------------
+ * Entropy backup of the inversion (Section 2 names backups; reading 19). The
+ * entropy function K = p / rho^gamma is carried as its own field, so where the
+ * energy relation cannot be inverted the pressure is p = K rho^gamma instead, and
+ * with rho = D / W the enthalpy density xi = rho h W^2 becomes a function of W
+ * alone:  xi(W) = D W + gamma/(gamma-1) K D^gamma W^(2-gamma).  What is left is
+ * the momentum relation
+ *     f(W) = (xi + B^2)^2 (1 - 1/W^2) - (S.B)^2 (2 xi + B^2) / xi^2 - S^2 = 0.
+ * For gamma <= 2 every term of f grows with W and f(1) <= 0, so f has one root
+ * in [1, inf). It is found by Newton steps in W kept inside a bracket [lo, hi]
+ * (a step leaving the bracket is replaced by its midpoint; every evaluation
+ * moves one end), stopping at |dW| <= tol W.
+ * ------------------------------------------------------------------------------- */
+#define ENT_MAXIT 100
+
+static void ent_fdf(const c2p_sys *c, double K, double W, double *xi, double *f, double *df)
+{
+    const double g = c->gam, a = g / (g - 1.0);
+    const double KDg = a * K * pow(c->D, g);
+    *xi = c->D * W + KDg * pow(W, 2.0 - g);
+    const double dxi = c->D + KDg * (2.0 - g) * pow(W, 1.0 - g);
+    const double x = *xi, xb = x + c->B2, w2i = 1.0 / (W * W), sb2 = c->SB * c->SB;
+    *f = xb * xb * (1.0 - w2i) - sb2 * (2.0 * x + c->B2) / (x * x) - c->S2;
+    *df = 2.0 * xb * dxi * (1.0 - w2i) + 2.0 * xb * xb * w2i / W + sb2 * dxi * (2.0 / (x * x) + 2.0 * c->B2 / (x * x * x));
+}
+
+/* Returns 0 with the root W and xi(W), or 1 if no root was found. Wg: start value. */
+static int c2p_entropy(const c2p_sys *c, double K, double Wg, double tol, double *Wout, double *xiout)
+{
+    double xi, f, df;
+    double lo = 1.0, hi = 2.0;
+    ent_fdf(c, K, hi, &xi, &f, &df);
+    int nd = 0;
+    while (f < 0.0 && nd < 60) {
+        lo = hi;
+        hi *= 2.0;
+        ent_fdf(c, K, hi, &xi, &f, &df);
+        nd++;
+    }
+    if (!(f >= 0.0)) return 1;
+    double W = (Wg > lo && Wg < hi) ? Wg : 0.5 * (lo + hi);
+    for (int it = 0; it < ENT_MAXIT; it++) {
+        ent_fdf(c, K, W, &xi, &f, &df);
+        if (!isfinite(f) || !isfinite(df)) return 1;
+        if (f == 0.0) { *Wout = W; *xiout = xi; return 0; }
+        if (f < 0.0) lo = W; else hi = W;
+        double Wn = W - f / df;
+        if (!(Wn > lo && Wn < hi)) Wn = 0.5 * (lo + hi);
+        const int done = fabs(Wn - W) <= tol * Wn;
+        W = Wn;
+        if (done) {
+            ent_fdf(c, K, W, &xi, &f, &df);
+            *Wout = W;
+            *xiout = xi;
+            return 0;
+        }
+    }
+    return 1;
+}
+
 static int c2p_point(const orc_params *p, const ometric *m, const double *U, const double *Pg,
-                     double *Pout, int *nit, int *floored)
+                     double *Pout, int *nit, int *floored, int *backup)
 {
     const double sg = m->sqrtg;
     *nit = 0;
     *floored = 0;
+    *backup = 0;
     c2p_sys c;
     c.gam = p->gamma_ad;
     c.D = U[ID] / sg;
@@ -481,8 +549,27 @@ static int c2p_point(const orc_params *p, const ometric *m, const double *U, con
             if (!(rho > 0.0) || !(prs >= 0.0) || !isfinite(rho) || !isfinite(prs)) fail = 1;
         }
     }
+    if (fail && p->entropy) {
+        const double K = U[IENT] / U[ID];
+        if (c.D > 0.0 && K > 0.0 && isfinite(K) && isfinite(c.S2) && isfinite(c.B2)) {
+            ostate g;
+            state_from_prim(p, m, Pg, &g);
+            double Wb, xib;
+            if (c2p_entropy(&c, K, g.W, p->c2p_tol, &Wb, &xib) == 0) {
+                const double rb = c.D / Wb, pb = K * pow(rb, c.gam);
+                if (rb > 0.0 && pb >= 0.0 && isfinite(rb) && isfinite(pb) && xib > 0.0) {
+                    W = Wb;
+                    xi = xib;
+                    rho = rb;
+                    prs = pb;
+                    fail = 0;
+                    *backup = 1;
+                }
+            }
+        }
+    }
     if (fail) {
-        memcpy(Pout, Pg, NV * sizeof(double));
+        memcpy(Pout, Pg, nvar(p) * sizeof(double));
         return 1;
     }
     double vl[3];
@@ -504,6 +591,7 @@ static int c2p_point(const orc_params *p, const ometric *m, const double *U, con
     Pout[IP] = prs;
     for (int i = 0; i < 3; i++) Pout[IB1 + i] = B[i];
     Pout[IPSI] = U[IPSI];
+    if (p->entropy) Pout[IENT] = U[IENT] / U[ID];
     return 0;
 }
 
@@ -642,6 +730,8 @@ orc_grid *orc_grid_new(const orc_params *p, const orc_block *blocks, int64_t nb)
         if (g->occ[s] != -1) goto bad;   /* two blocks in one slot */
         g->occ[s] = (int)b;
     }
+    /* the entropy field: same-level patches only, gamma <= 2 (its inversion needs it) */
+    if (p->entropy && (p->entropy != 1 || p->amr || !(p->gamma_ad <= 2.0))) goto bad;
     if (p->amr) {
         /* block tree: one block size, even and at least twice the ghost depth along
          * every axis in use (so every ghost layer lies in a leaf adjacent to the
@@ -869,7 +959,7 @@ static void fill_block(const orc_grid *G, int b, double *P, int64_t ncp)
                 int sb, src[3];
                 ghost_source(G, b, l, &sb, src);
                 const int64_t from = pad_index(G, sb, src[0], src[1], src[2]);
-                for (int v = 0; v < NV; v++) P[v * ncp + dst] = P[v * ncp + from];
+                for (int v = 0; v < nvar(&G->p); v++) P[v * ncp + dst] = P[v * ncp + from];
             }
 }
 
@@ -898,14 +988,14 @@ void orc_prim2con(const orc_grid *G, const double *P, double *U, const int64_t *
         for (int k = 0; k < B->size[2]; k++)
             for (int j = 0; j < B->size[1]; j++)
                 for (int i = 0; i < B->size[0]; i++) {
-                    double x1, x2, Pc[NV], Uc[NV];
+                    double x1, x2, Pc[NVE], Uc[NVE];
                     ometric m;
                     cell_center(G, b, i, j, &x1, &x2);
                     metric_at(&G->p, x1, x2, &m);
                     const int64_t c = pad_index(G, b, i, j, k);
-                    for (int v = 0; v < NV; v++) Pc[v] = P[v * ncp + c];
+                    for (int v = 0; v < nvar(&G->p); v++) Pc[v] = P[v * ncp + c];
                     p2c_point(&G->p, &m, Pc, Uc);
-                    for (int v = 0; v < NV; v++) U[v * ncp + c] = Uc[v];
+                    for (int v = 0; v < nvar(&G->p); v++) U[v * ncp + c] = Uc[v];
                 }
     }
 }
@@ -922,18 +1012,19 @@ void orc_con2prim(const orc_grid *G, const double *U, double *P, int8_t *fail, o
         for (int k = 0; k < B->size[2]; k++)
             for (int j = 0; j < B->size[1]; j++)
                 for (int i = 0; i < B->size[0]; i++) {
-                    double x1, x2, Pg[NV], Uc[NV], Po[NV];
+                    double x1, x2, Pg[NVE], Uc[NVE], Po[NVE];
                     ometric m;
                     cell_center(G, b, i, j, &x1, &x2);
                     metric_at(&G->p, x1, x2, &m);
                     const int64_t c = pad_index(G, b, i, j, k);
-                    for (int v = 0; v < NV; v++) { Pg[v] = P[v * ncp + c]; Uc[v] = U[v * ncp + c]; }
-                    int nit, fl;
-                    const int f = c2p_point(&G->p, &m, Uc, Pg, Po, &nit, &fl);
-                    for (int v = 0; v < NV; v++) P[v * ncp + c] = Po[v];
+                    for (int v = 0; v < nvar(&G->p); v++) { Pg[v] = P[v * ncp + c]; Uc[v] = U[v * ncp + c]; }
+                    int nit, fl, bk;
+                    const int f = c2p_point(&G->p, &m, Uc, Pg, Po, &nit, &fl, &bk);
+                    for (int v = 0; v < nvar(&G->p); v++) P[v * ncp + c] = Po[v];
                     if (fail) fail[c] = (int8_t)f;
                     if (st) {
                         st->c2p_fail += f;
+                        st->c2p_backup += bk;
                         st->floor_hits += (!f && fl);
                         if (nit > st->max_iter) st->max_iter = nit;
                     }
@@ -1029,11 +1120,23 @@ static void block_fluxes(const orc_grid *G, int bk, const double *Ps, double ch,
                     if (d == 1) x2 = p->x_lo[1] + (B->origin[1] + j) * dx;
                     ometric mf;
                     metric_at(p, x1, x2, &mf);
-                    double Ff[NV];
+                    double Ff[NVE];
                     const double l = riemann(p, &mf, d, PL, PR, ch, Ff);
                     if (l > lam[d]) lam[d] = l;
+                    if (p->entropy) {
+                        /* entropy field (reading 19): reconstructed like the others and
+                         * carried by the mass flux from its upwind side */
+                        double KL, KR;
+                        for (int t = t0; t < t1; t++) {
+                            int cc[3] = { c[0], c[1], c[2] };
+                            cc[d] += t - 3;
+                            qv[t] = Ps[IENT * ncp + pad_index(G, bk, cc[0], cc[1], cc[2])];
+                        }
+                        recon_face(p->recon, qv, &KL, &KR);
+                        Ff[IENT] = Ff[ID] * (Ff[ID] >= 0.0 ? KL : KR);
+                    }
                     const int64_t fi = ((int64_t)k * fs[1] + j) * fs[0] + i;
-                    for (int v = 0; v < NV; v++) F[d][v * nf + fi] = Ff[v];
+                    for (int v = 0; v < nvar(p); v++) F[d][v * nf + fi] = Ff[v];
                 }
     }
 }
@@ -1049,13 +1152,15 @@ static void block_update(const orc_grid *G, int bk, double *F[3], const double *
         for (int j = 0; j < B->size[1]; j++)
             for (int i = 0; i < B->size[0]; i++) {
                 const int64_t c = pad_index(G, bk, i, j, k);
-                double x1, x2, Pc[NV], Uc[NV], Sv[NV], L[NV], Un[NV], Pn[NV];
+                const int nv = nvar(p);
+                double x1, x2, Pc[NVE], Uc[NVE], Sv[NVE], L[NVE], Un[NVE], Pn[NVE];
                 ometric m;
                 cell_center(G, bk, i, j, &x1, &x2);
                 metric_at(p, x1, x2, &m);
-                for (int v = 0; v < NV; v++) { Pc[v] = Ps[v * ncp + c]; Uc[v] = Us[v * ncp + c]; }
+                for (int v = 0; v < nv; v++) { Pc[v] = Ps[v * ncp + c]; Uc[v] = Us[v * ncp + c]; }
                 sources_point(p, &m, Pc, Uc, st->kappa, Sv);
-                for (int v = 0; v < NV; v++) L[v] = 0.0;
+                Sv[IENT] = 0.0;                     /* the entropy field has no source */
+                for (int v = 0; v < nv; v++) L[v] = 0.0;
                 for (int d = 0; d < p->ndim; d++) {
                     int fs[3];
                     for (int e = 0; e < 3; e++) fs[e] = B->size[e] + (e == d);
@@ -1065,19 +1170,22 @@ static void block_update(const orc_grid *G, int bk, double *F[3], const double *
                     hi[d] += 1;
                     const int64_t flo = ((int64_t)k * fs[1] + j) * fs[0] + i;
                     const int64_t fhi = ((int64_t)hi[2] * fs[1] + hi[1]) * fs[0] + hi[0];
-                    for (int v = 0; v < NV; v++) L[v] -= (F[d][v * nf + fhi] - F[d][v * nf + flo]) / dx;
+                    for (int v = 0; v < nv; v++) L[v] -= (F[d][v * nf + fhi] - F[d][v * nf + flo]) / dx;
                 }
-                for (int v = 0; v < NV; v++) {
+                for (int v = 0; v < nv; v++) {
                     L[v] += Sv[v];
                     Un[v] = a * Ub[v * ncp + c] + b * (Uc[v] + st->dt * L[v]);
                 }
-                int nit, fl;
-                const int f = c2p_point(p, &m, Un, Pc, Pn, &nit, &fl);
-                if (f || fl) p2c_point(p, &m, Pn, Un);
+                int nit, fl, bu;
+                const int f = c2p_point(p, &m, Un, Pc, Pn, &nit, &fl, &bu);
+                /* failed, floored or backed-up cells take the conserved state of
+                 * their primitives (the energy is what could not be inverted) */
+                if (f || fl || bu) p2c_point(p, &m, Pn, Un);
                 st->c2p_fail += f;
+                st->c2p_backup += bu;
                 st->floor_hits += (!f && fl);
                 if (nit > st->max_iter) st->max_iter = nit;
-                for (int v = 0; v < NV; v++) { Uo[v * ncp + c] = Un[v]; Po[v * ncp + c] = Pn[v]; }
+                for (int v = 0; v < nv; v++) { Uo[v * ncp + c] = Un[v]; Po[v * ncp + c] = Pn[v]; }
             }
 }
 
@@ -1169,7 +1277,7 @@ int orc_substep(const orc_grid *G, const double *Ub, const double *Us, const dou
             double *F[3] = { NULL, NULL, NULL };
             for (int d = 0; d < p->ndim; d++) {
                 const int64_t nf = (int64_t)(B->size[0] + (d == 0)) * (B->size[1] + (d == 1)) * (B->size[2] + (d == 2));
-                F[d] = malloc(NV * nf * sizeof(double));
+                F[d] = malloc(nvar(p) * nf * sizeof(double));
             }
             block_fluxes(G, bk, Ps, st->ch, F, lam);
             block_update(G, bk, F, Ub, Us, Ps, Uo, Po, a, b, st);
@@ -1228,16 +1336,57 @@ void orc_p2c_point(const orc_params *p, double x1, double x2, const double *P, d
     p2c_point(p, &m, P, U);
 }
 
-/* info[0] = fail, info[1] = Newton steps, info[2] = floored */
+/* info[0] = fail, info[1] = Newton steps, info[2] = floored, info[3] = entropy backup used */
 void orc_c2p_point(const orc_params *p, double x1, double x2, const double *U, const double *Pg,
                    double *Pout, int *info)
 {
     ometric m;
     metric_at(p, x1, x2, &m);
-    int nit, fl;
-    info[0] = c2p_point(p, &m, U, Pg, Pout, &nit, &fl);
+    int nit, fl, bk;
+    info[0] = c2p_point(p, &m, U, Pg, Pout, &nit, &fl, &bk);
     info[1] = nit;
     info[2] = fl;
+    info[3] = bk;
+}
+
+/* The entropy root alone (no energy inversion first): P from U (U[9] = U[0] K).
+ * Returns 0 on success. */
+int orc_c2p_entropy_point(const orc_params *p, double x1, double x2, const double *U, double Wg, double *Pout)
+{
+    ometric m;
+    metric_at(p, x1, x2, &m);
+    const double sg = m.sqrtg;
+    c2p_sys c;
+    c.gam = p->gamma_ad;
+    c.D = U[ID] / sg;
+    double Sl[3], B[3], Bl[3];
+    for (int i = 0; i < 3; i++) { Sl[i] = U[IS1 + i] / sg; B[i] = U[IB1 + i] / sg; }
+    c.Ut = 0.0;
+    c.S2 = 0.0;
+    c.B2 = 0.0;
+    c.SB = 0.0;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) c.S2 += m.gi[i][j] * Sl[i] * Sl[j];
+    for (int i = 0; i < 3; i++) {
+        Bl[i] = 0.0;
+        for (int j = 0; j < 3; j++) Bl[i] += m.g[i][j] * B[j];
+    }
+    for (int i = 0; i < 3; i++) { c.B2 += B[i] * Bl[i]; c.SB += Sl[i] * B[i]; }
+    const double K = U[IENT] / U[ID];
+    double W, xi;
+    if (c2p_entropy(&c, K, Wg, p->c2p_tol, &W, &xi)) return 1;
+    const double rho = c.D / W;
+    Pout[IRHO] = rho;
+    for (int i = 0; i < 3; i++) {
+        double vu = 0.0;
+        for (int j = 0; j < 3; j++) vu += m.gi[i][j] * (Sl[j] + c.SB * Bl[j] / xi) / (xi + c.B2);
+        Pout[IU1 + i] = W * vu;
+    }
+    Pout[IP] = K * pow(rho, c.gam);
+    for (int i = 0; i < 3; i++) Pout[IB1 + i] = B[i];
+    Pout[IPSI] = U[IPSI];
+    Pout[IENT] = K;
+    return 0;
 }
 
 void orc_phys_flux(const orc_params *p, double x1, double x2, const double *P, int d, double *U,

@@ -18,6 +18,11 @@ LIB = os.path.join(HERE, "liboracle.so")
 NV = 9
 
 
+def nvar(params: dict) -> int:
+    """Rows of P and U: nine GRMHD variables, plus the entropy field if carried."""
+    return NV + (1 if int(params.get("entropy", 0)) else 0)
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with plain IEEE FP64 semantics (no contraction, no fast-math)."""
     if force or not os.path.exists(LIB):
@@ -36,7 +41,7 @@ class Params(C.Structure):
                 ("recon", C.c_int), ("flux", C.c_int),
                 ("cfl", C.c_double), ("rho_floor", C.c_double), ("p_floor", C.c_double),
                 ("w_max", C.c_double), ("glm_alpha", C.c_double), ("c2p_tol", C.c_double),
-                ("c2p_maxit", C.c_int), ("amr", C.c_int)]
+                ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int)]
 
 
 class Block(C.Structure):
@@ -47,7 +52,7 @@ class State(C.Structure):
     _fields_ = [("dt_next", C.c_double), ("dt", C.c_double), ("ch", C.c_double),
                 ("kappa", C.c_double), ("lam", C.c_double * 3), ("dt_fixed", C.c_double),
                 ("have_dt", C.c_int), ("c2p_fail", C.c_int64), ("floor_hits", C.c_int64),
-                ("max_iter", C.c_int)]
+                ("max_iter", C.c_int), ("c2p_backup", C.c_int64)]
 
 
 _lib = None
@@ -82,6 +87,8 @@ def lib():
         L.orc_riemann.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_int, _D, _D,
                                   C.c_double, _D]
         L.orc_recon_face.argtypes = [C.c_int, _D, _D]
+        L.orc_c2p_entropy_point.restype = C.c_int
+        L.orc_c2p_entropy_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, C.c_double, _D]
         L.orc_sources.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D, C.c_double, _D]
         _lib = L
     return _lib
@@ -92,6 +99,7 @@ def make_params(d: dict) -> Params:
     for k in ("ndim", "nghost", "metric", "recon", "flux", "c2p_maxit"):
         setattr(p, k, int(d[k]))
     p.amr = int(d.get("amr", 0))
+    p.entropy = int(d.get("entropy", 0))
     for k in ("spin", "gamma_ad", "cfl", "rho_floor", "p_floor", "w_max", "glm_alpha", "c2p_tol"):
         setattr(p, k, float(d[k]))
     for e in range(3):
@@ -135,6 +143,7 @@ class OracleGrid:
             raise ValueError("oracle rejected the block list")
         self._h = C.c_void_p(h)
         self.nb = nb
+        self.nv = nvar(params)
         self.off = np.zeros(nb + 1, dtype=np.int64)
         self.ioff = np.zeros(nb + 1, dtype=np.int64)
         lib().orc_grid_layout(self._h, self.off.ctypes.data_as(_I64), self.ioff.ctypes.data_as(_I64))
@@ -168,7 +177,7 @@ class OracleGrid:
         return self._pidx
 
     def pack(self, interior: np.ndarray) -> np.ndarray:
-        out = np.zeros((NV, self.ncp), dtype=np.float64)
+        out = np.zeros((interior.shape[0], self.ncp), dtype=np.float64)
         out[:, self.interior_index()] = interior
         return out
 
@@ -210,6 +219,7 @@ class OracleGrid:
     def stats(self):
         st = self.state
         return dict(c2p_fail=int(st.c2p_fail), floor_hits=int(st.floor_hits), max_iter=int(st.max_iter),
+                    c2p_backup=int(st.c2p_backup),
                     dt=float(st.dt), dt_next=float(st.dt_next), ch=float(st.ch), kappa=float(st.kappa))
 
     # --- drivers ---------------------------------------------------------------------
@@ -254,17 +264,27 @@ def metric(params, x1, x2):
 
 
 def p2c(params, x1, x2, P):
-    U = np.zeros(NV)
-    lib().orc_p2c_point(C.byref(make_params(params)), float(x1), float(x2), _dp(_vec(P)), _dp(U))
+    n = nvar(params)
+    U = np.zeros(n)
+    lib().orc_p2c_point(C.byref(make_params(params)), float(x1), float(x2), _dp(_vec(P, n)), _dp(U))
     return U
 
 
 def c2p(params, x1, x2, U, Pguess):
-    P = np.zeros(NV)
-    info = (C.c_int * 3)()
-    lib().orc_c2p_point(C.byref(make_params(params)), float(x1), float(x2), _dp(_vec(U)),
-                        _dp(_vec(Pguess)), _dp(P), info)
-    return P, dict(fail=info[0], iters=info[1], floored=info[2])
+    n = nvar(params)
+    P = np.zeros(n)
+    info = (C.c_int * 4)()
+    lib().orc_c2p_point(C.byref(make_params(params)), float(x1), float(x2), _dp(_vec(U, n)),
+                        _dp(_vec(Pguess, n)), _dp(P), info)
+    return P, dict(fail=info[0], iters=info[1], floored=info[2], backup=info[3])
+
+
+def c2p_entropy(params, x1, x2, U, Wguess=1.0):
+    """The entropy inversion alone (U has 10 entries); returns P or None."""
+    P = np.zeros(NV + 1)
+    rc = lib().orc_c2p_entropy_point(C.byref(make_params(params)), float(x1), float(x2),
+                                     _dp(_vec(U, NV + 1)), float(Wguess), _dp(P))
+    return None if rc else P
 
 
 def phys_flux(params, x1, x2, P, d):

@@ -73,7 +73,7 @@ def base_params(**kw) -> dict:
              bc=[[BC_OUTFLOW, BC_OUTFLOW], [BC_OUTFLOW, BC_OUTFLOW], [BC_PERIODIC, BC_PERIODIC]],
              recon=RECON_PPM, flux=FLUX_HLL, precision=PREC_FP64, fused=0,
              cfl=0.4, rho_floor=RHO_ATM, p_floor=P_ATM, w_max=50.0, glm_alpha=0.1,
-             c2p_tol=1.0e-13, c2p_maxit=50, amr=0)
+             c2p_tol=1.0e-13, c2p_maxit=50, amr=0, entropy=0)
     p.update(kw)
     return p
 
@@ -390,6 +390,16 @@ def case_tree(n0: int = 64, bs: int = 16, levels: int = 3, precision=PREC_MIXED,
         prim[:, sl], rr[sl], _ = _torus_cells(params, int(blocks[b, 0]), g0, g1, g2, noise[sl])
     prim = _finish_torus(prim, rr)
     return Case(f"tree_{n0}_{bs}_{levels}", params, blocks, prim, ioff, steps=10)
+
+
+def with_entropy(case: Case) -> Case:
+    """The same case carrying the entropy field (entropy = 1): the primitives gain
+    a tenth row, the entropy function K = p / rho^gamma of the initial state."""
+    gam = float(case.params["gamma_ad"])
+    K = case.prim[PRS] / case.prim[RHO] ** gam
+    prim = np.vstack([case.prim, K[None, :]])
+    return Case(case.name + "_entropy", dict(case.params, entropy=1), case.blocks, prim, case.ioff, case.steps,
+                dict(case.meta))
 
 
 def make_case(cfg: int, **kw) -> Case:
