@@ -55,6 +55,9 @@ WORKLOADS = {
     # 972 blocks, 4.0 M zones), with restriction / prolongation between levels
     "amr_tree_96_mixed_plain": dict(cfg="tree", n0=96, bs=16, levels=3, precision=1, fused=0),
     "amr_tree_96_fp64_plain": dict(cfg="tree", n0=96, bs=16, levels=3, precision=0, fused=0),
+    # the same grid carrying the entropy field (inversion backup), FP64 and mixed
+    "ks_torus_128_fp64_entropy": dict(cfg=2, n=128, precision=0, fused=0, entropy=1),
+    "ks_torus_128_mixed_entropy": dict(cfg=2, n=128, precision=1, fused=0, entropy=1),
     "amr_tree_96_mixed_auto": dict(cfg="tree", n0=96, bs=16, levels=3, precision=1, fused="auto"),
     "amr_tree_96_fp64_auto": dict(cfg="tree", n0=96, bs=16, levels=3, precision=0, fused="auto"),
 }
@@ -84,15 +87,18 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def bytes_per_unit(kernel: str, rsz: int) -> float:
-    """Algorithmic HBM bytes per unit of work of each kernel family (unit in unit_of)."""
+def bytes_per_unit(kernel: str, rsz: int, nv: int = 9) -> float:
+    """Algorithmic HBM bytes per unit of work of each kernel family (unit in unit_of);
+    nv rows of state (10 with the entropy field)."""
     u8 = 8
-    if kernel == "fill_ghosts":            # per ghost slot: 9 values read + 9 written
-        return 18 * rsz
+    if kernel == "fill_ghosts":            # per ghost slot: nv values read + nv written
+        return 2 * nv * rsz
     if kernel.startswith("flux_x"):        # per face: one cell's 9 primitives read, 9 fluxes written
         return 18 * rsz
+    if kernel == "flux_entropy":           # per face: one cell's K and the mass flux read, 1 flux written
+        return 3 * rsz
     if kernel == "update":                 # per cell: U_stage, U_base (half the stages), P_stage,
-        return 9 * u8 * 1.5 + 9 * rsz + 3 * 9 * rsz + 9 * u8 + 9 * rsz   # 3 face fluxes, U_out, P_out
+        return nv * (u8 * 1.5 + rsz + 3 * rsz + u8 + rsz)   # 3 face fluxes, U_out, P_out
     if kernel == "update_div":             # per cell: as update, with one stored divergence instead of fluxes
         return 9 * u8 * 1.5 + 9 * rsz + 9 * 4 + 9 * u8 + 9 * rsz
     if kernel == "block_flux":             # per zone: P_stage read once, divergence written once
@@ -107,6 +113,9 @@ def units_per_launch(kernel: str, info: dict) -> float:
         return info["nface"][int(kernel[-1]) - 1]
     if kernel in ("update", "update_div", "block_flux"):
         return info["ncell"]
+    if kernel == "flux_entropy":           # one launch per direction: the mean face count
+        nf = [n for n in info["nface"] if n]
+        return sum(nf) / len(nf)
     return 0.0
 
 
@@ -115,7 +124,7 @@ def grid_info(case, G):
     off, dst, _ = B.bhac_plan_ghosts(case.params, case.blocks)
     blk = case.blocks
     nface = [int(((blk[:, 1] + (d == 0)) * (blk[:, 2] + (d == 1)) * (blk[:, 3] + (d == 2))).sum()) for d in range(3)]
-    return dict(ghost_slots=int(dst.size), nface=nface, ncell=int(G.nci))
+    return dict(ghost_slots=int(dst.size), nface=nface, ncell=int(G.nci), nvar=int(G.nvar))
 
 
 def run_gpu(case, steps, warmup, graph=True):
@@ -180,7 +189,7 @@ def roofline(res, rsz, workload):
     dom = max(kt, key=lambda k: kt[k][1])
     launches, total_ms = kt[dom]
     avg_s = total_ms / launches / 1e3
-    alg = bytes_per_unit(dom, rsz) * units_per_launch(dom, res["info"])
+    alg = bytes_per_unit(dom, rsz, res["info"]["nvar"]) * units_per_launch(dom, res["info"])
     achieved = alg / avg_s / 1e9
     measured = TRAFFIC.get((workload, dom))
     traffic = measured[0] if measured and measured[1] == source_digest() else None
@@ -271,6 +280,8 @@ def main(argv=None):
         w = dict(WORKLOADS[name])
         kw = {k: w[k] for k in ("n", "n0", "bs", "levels") if k in w}
         c = I.make_case(w["cfg"], **kw)
+        if w.get("entropy"):
+            c = I.with_entropy(c)
         if w["fused"] == "auto":
             from paper_2108_12240_amd import autotune
             params, report = autotune.tune(dict(c.params, precision=w["precision"]), c.blocks, c.prim)

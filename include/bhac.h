@@ -34,6 +34,10 @@
  *    sqrt(gamma) * (D, S_1, S_2, S_3, tau, B1, B2, B3), psi; conserved variables
  *    need no ghost cells, so each row has ncell_interior entries and block b
  *    occupies [block_interior_offset[b], block_interior_offset[b+1]), x fastest.
+ *    With the entropy field (entropy = 1) both carry a tenth row: P row 9 is the
+ *    entropy function K (p / rho^gamma where it was last consistent), U row 9 is
+ *    U row 0 times K. bhac_layout.nvar gives the row count (9 or 10); every
+ *    "[9]" below then reads "[10]".
  *  - Precision: P is double when precision == BHAC_PREC_FP64 and float when
  *    precision == BHAC_PREC_MIXED. U is always double.
  */
@@ -96,6 +100,13 @@ enum { BHAC_PREC_FP64 = 0, BHAC_PREC_MIXED = 1 };
  *                       cells come from prolongation or restriction (see
  *                       bhac_fill_ghosts). Needs fused = 0 (else
  *                       BHAC_EUNSUPPORTED).
+ *  entropy              0: nine variables. 1: also carry the entropy field K and
+ *                       use it as the backup of the inversion (Section 2 names
+ *                       backup strategies; see bhac_con2prim). K is transported
+ *                       as rho W K, its face flux the mass flux times K
+ *                       reconstructed on the upwind side, with no source. Needs
+ *                       gamma_ad <= 2 (else BHAC_EINVAL), fused = 0 and amr = 0
+ *                       (else BHAC_EUNSUPPORTED).
  *  sched                kernel schedule of the unfused substep (see bhac_schedule).
  */
 
@@ -132,6 +143,7 @@ typedef struct bhac_params {
     double cfl, rho_floor, p_floor, w_max, glm_alpha, c2p_tol;
     int c2p_maxit;
     int amr;            /* 0 independent patches, 1 block tree */
+    int entropy;        /* 0 nine variables, 1 plus the entropy field (inversion backup) */
     bhac_schedule sched;
 } bhac_params;
 
@@ -208,7 +220,8 @@ int bhac_fill_ghost_faces(bhac_grid *grid, void *prim, void *stream);
  * variables): W = sqrt(1 + gamma_ij u~^i u~^j), v^i = u~^i / W,
  * xi = rho h W^2 with h = 1 + Gamma/(Gamma-1) p/rho, D = rho W,
  * S_i = (xi + B^2) v_i - (B.v) B_i, tau = xi + B^2 - p - ((B.v)^2 + B^2/W^2)/2 - D,
- * all densitised by sqrt(gamma); psi copied. cons: device double [9][ncell_interior]. */
+ * all densitised by sqrt(gamma); psi copied; with the entropy field U row 9 =
+ * U row 0 times P row 9. cons: device double [9][ncell_interior]. */
 int bhac_prim2con(bhac_grid *grid, const void *prim, double *cons, void *stream);
 
 /* Conserved -> primitive at interior cells (Section 2: Newton-Raphson with a
@@ -216,7 +229,15 @@ int bhac_prim2con(bhac_grid *grid, const void *prim, double *cons, void *stream)
  * primitives already in prim_inout, safeguarded by halving the step towards the
  * previous iterate while xi <= 0 or v^2 >= 1; stops when |dxi| <= c2p_tol * xi,
  * then takes one more step. Then floors on rho, p and W. On failure (no
- * convergence in c2p_maxit steps, non-finite values, rho <= 0 or p < 0) the
+ * convergence in c2p_maxit steps, non-finite values, rho <= 0 or p < 0) and
+ * with the entropy field carried, the entropy backup: with K = U9 / U0, p = K
+ * rho^gamma and rho = D / W, the momentum relation
+ *   (xi + B^2)^2 (1 - 1/W^2) - (S.B)^2 (2 xi + B^2) / xi^2 = S^2,
+ *   xi = D W + Gamma/(Gamma-1) K D^Gamma W^(2-Gamma),
+ * has one root W >= 1 (its left side grows with W); it is found by Newton steps
+ * kept inside a bisection bracket, stopping at |dW| <= c2p_tol W, then floors as
+ * above; the cell counts as backed up (bhac_get_stats). P row 9 = U9 / U0 on
+ * success. If that fails too (or no entropy field is carried) the
  * cell keeps its input primitives and fail[cell] = 1, else 0. cons: device double
  * [9][ncell_interior]; fail: device int8 [ncell_interior], may be NULL. cons is not
  * modified. */
@@ -229,9 +250,10 @@ int bhac_con2prim(bhac_grid *grid, const double *cons, void *prim_inout, int8_t 
  * with F the face fluxes from reconstructed P_stage (MC or PPM), an exact solve
  * of the GLM (B~_normal, psi) subsystem and HLL or TVDLF for the rest, and S the
  * geometric sources of the stationary metric plus GLM damping -kappa psi; then
- * P_out = inversion of U_out started from P_stage (floors and backup as in
- * bhac_con2prim; cells that hit a floor or the backup get U_out rewritten from
- * P_out). SSP-RK2 is (a, b) = (0, 1) then (1/2, 1/2) with U_stage = U_base in
+ * P_out = inversion of U_out started from P_stage (floors, entropy backup and
+ * failure as in bhac_con2prim; cells that hit a floor, take the entropy backup or
+ * fail get U_out rewritten from P_out). With the entropy field, U row 9 follows
+ * the same RK combination with its own face flux and no source. SSP-RK2 is (a, b) = (0, 1) then (1/2, 1/2) with U_stage = U_base in
  * the first stage.
  * Time step: a substep with a == 0 starts a step and latches dt (and c_h, kappa)
  * from the previous substep's wave speeds; every substep records its own maximum
@@ -267,9 +289,9 @@ int bhac_get_dt(bhac_grid *grid, double *dt_host);
 int bhac_get_timestep(bhac_grid *grid, bhac_timestep *out);
 
 /* Inversion statistics accumulated since alloc or the last reset: failed cells,
- * floored cells and the largest Newton step count (synchronises). Any pointer
- * may be NULL. */
-int bhac_get_stats(bhac_grid *grid, int64_t *c2p_fail, int64_t *floor_hits, int *max_iter);
+ * floored cells, the largest Newton step count and the cells inverted by the
+ * entropy backup (synchronises). Any pointer may be NULL. */
+int bhac_get_stats(bhac_grid *grid, int64_t *c2p_fail, int64_t *floor_hits, int *max_iter, int64_t *c2p_backup);
 int bhac_reset_stats(bhac_grid *grid, void *stream);
 
 /* The schedule the grid's unfused substep runs, defaults resolved (set = 1;

@@ -38,7 +38,8 @@ class bhac_params(C.Structure):
                 ("ncell0", C.c_int * 3), ("bc", (C.c_int * 2) * 3), ("recon", C.c_int), ("flux", C.c_int),
                 ("precision", C.c_int), ("fused", C.c_int), ("cfl", C.c_double), ("rho_floor", C.c_double),
                 ("p_floor", C.c_double), ("w_max", C.c_double), ("glm_alpha", C.c_double),
-                ("c2p_tol", C.c_double), ("c2p_maxit", C.c_int), ("amr", C.c_int), ("sched", bhac_schedule)]
+                ("c2p_tol", C.c_double), ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int),
+                ("sched", bhac_schedule)]
 
 
 class bhac_block_desc(C.Structure):
@@ -85,7 +86,8 @@ def lib():
             "bhac_set_dt": [_VP, C.c_double, _VP],
             "bhac_get_dt": [_VP, C.POINTER(C.c_double)],
             "bhac_get_timestep": [_VP, C.POINTER(bhac_timestep)],
-            "bhac_get_stats": [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)],
+            "bhac_get_stats": [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int),
+                               C.POINTER(C.c_int64)],
             "bhac_reset_stats": [_VP, _VP],
             "bhac_get_schedule": [_VP, C.POINTER(bhac_schedule)],
             "bhac_set_timing": [_VP, C.c_int],
@@ -116,6 +118,7 @@ def make_params(d: dict) -> bhac_params:
     for k in ("ndim", "nghost", "metric", "recon", "flux", "precision", "fused", "c2p_maxit"):
         setattr(p, k, int(d[k]))
     p.amr = int(d.get("amr", 0))
+    p.entropy = int(d.get("entropy", 0))
     sched = d.get("sched")
     if sched is not None:
         p.sched.set = 1
@@ -228,9 +231,9 @@ def bhac_get_timestep(h) -> dict:
 
 
 def bhac_get_stats(h) -> dict:
-    f, fl, it = C.c_int64(), C.c_int64(), C.c_int()
-    _check(lib().bhac_get_stats(h, C.byref(f), C.byref(fl), C.byref(it)))
-    return dict(c2p_fail=f.value, floor_hits=fl.value, max_iter=it.value)
+    f, fl, it, bk = C.c_int64(), C.c_int64(), C.c_int(), C.c_int64()
+    _check(lib().bhac_get_stats(h, C.byref(f), C.byref(fl), C.byref(it), C.byref(bk)))
+    return dict(c2p_fail=f.value, floor_hits=fl.value, max_iter=it.value, c2p_backup=bk.value)
 
 
 def bhac_get_schedule(h) -> dict:
@@ -278,6 +281,7 @@ class Grid:
         self.nci = lay["ncell_interior"]
         self.off = lay["block_offset"]
         self.ioff = lay["block_interior_offset"]
+        self.nvar = lay["nvar"]
         self.pdtype = torch.float32 if int(params["precision"]) == 1 else torch.float64
         self._pidx = None
 
@@ -308,14 +312,14 @@ class Grid:
         return self._pidx
 
     def new_state(self, kind="P"):
-        """Primitive state [9][ncell_padded] (float or double) or conserved [9][ncell_interior]."""
+        """Primitive state [nvar][ncell_padded] (float or double) or conserved [nvar][ncell_interior]."""
         if kind == "P":
-            return self.torch.zeros((NVAR, self.ncp), dtype=self.pdtype, device=self.device)
-        return self.torch.zeros((NVAR, self.nci), dtype=self.torch.float64, device=self.device)
+            return self.torch.zeros((self.nvar, self.ncp), dtype=self.pdtype, device=self.device)
+        return self.torch.zeros((self.nvar, self.nci), dtype=self.torch.float64, device=self.device)
 
     def pack(self, prim_interior: np.ndarray):
         """Interior-packed primitives -> padded device array (ghost slots zero)."""
-        out = np.zeros((NVAR, self.ncp), dtype=np.float64)
+        out = np.zeros((self.nvar, self.ncp), dtype=np.float64)
         out[:, self.interior_index()] = prim_interior
         return self.torch.from_numpy(out).to(device=self.device, dtype=self.pdtype)
 
@@ -383,3 +387,6 @@ class Grid:
 
     def schedule(self):
         return bhac_get_schedule(self.h)
+
+    def reset_stats(self):
+        bhac_reset_stats(self.h)

@@ -161,6 +161,7 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     kp.ndim = p.ndim;
     kp.recon = p.recon;
     kp.flux = p.flux;
+    kp.nvar = bhac::NV + (p.entropy ? 1 : 0);
     for (int d = 0; d < 3; d++) kp.g[d] = P.gd[d];
     kp.ncp = P.off.back();
     kp.nci = P.ncell_interior;
@@ -206,7 +207,7 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     {
         const size_t rsz = G.mixed ? sizeof(float) : sizeof(double);
         for (int d = 0; d < p.ndim && !p.fused; d++) {
-            e = hipMalloc(&G.d_flux[d], (size_t)bhac::NV * P.nface[d] * rsz);
+            e = hipMalloc(&G.d_flux[d], (size_t)G.kp.nvar * P.nface[d] * rsz);
             if (e != hipSuccess) goto hip_error;
         }
         if (p.fused) {
@@ -246,7 +247,7 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     if (layout) {
         layout->ncell_padded = P.off.back();
         layout->ncell_interior = P.ncell_interior;
-        layout->nvar = bhac::NV;
+        layout->nvar = G.kp.nvar;
         layout->nghost = p.nghost;
         layout->block_offset = P.off.data();
         layout->block_interior_offset = P.ioff.data();
@@ -391,7 +392,7 @@ int bhac_get_timestep(bhac_grid *g, bhac_timestep *out)
     return BHAC_OK;
 }
 
-int bhac_get_stats(bhac_grid *g, int64_t *c2p_fail, int64_t *floor_hits, int *max_iter)
+int bhac_get_stats(bhac_grid *g, int64_t *c2p_fail, int64_t *floor_hits, int *max_iter, int64_t *c2p_backup)
 {
     if (int rc = check_grid(g)) return rc;
     bhac::DevState st;
@@ -399,6 +400,7 @@ int bhac_get_stats(bhac_grid *g, int64_t *c2p_fail, int64_t *floor_hits, int *ma
     if (c2p_fail) *c2p_fail = (int64_t)st.c2p_fail;
     if (floor_hits) *floor_hits = (int64_t)st.floor_hits;
     if (max_iter) *max_iter = st.max_iter;
+    if (c2p_backup) *c2p_backup = (int64_t)st.c2p_backup;
     return BHAC_OK;
 }
 

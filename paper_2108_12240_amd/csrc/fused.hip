@@ -413,7 +413,8 @@ __global__ __launch_bounds__(WG) void k_update_div(KParams kp, GridDev gd, const
             const double e = (Uc[v] - (s - bb)) + (x - bb);
             Un[v] = (BASE ? a * Ub[v * kp.nci + ic] : 0.0) + (b * s + b * e);
         }
-        fail = con_to_prim(Un, q, m, kp, Pn, nit, floored);
+        int backup;
+        fail = con_to_prim(Un, q, m, kp, Pn, nit, floored, backup);
         if (fail || floored) prim_to_cons(Pn, m, kp.gfac, Un);
         floored = fail ? 0 : floored;
 #pragma unroll

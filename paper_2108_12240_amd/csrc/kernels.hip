@@ -14,9 +14,9 @@
 namespace bhac {
 
 // ---------------------------------------------------------------------------------
-// Ghost fill: one thread per ghost slot copies the 9 rows (bit-exact copies).
+// Ghost fill: one thread per ghost slot copies the NQ rows (bit-exact copies).
 // ---------------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NQ>
 __global__ __launch_bounds__(WG) void k_fill(const int32_t *__restrict__ dst, const int32_t *__restrict__ src,
                                              long long n, T *__restrict__ P, long long ncp)
 {
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(WG) void k_fill(const int32_t *__restrict__ dst, co
     if (i >= n) return;
     const long long d = dst[i], s = src[i];
 #pragma unroll
-    for (int v = 0; v < NV; v++) P[v * ncp + d] = P[v * ncp + s];
+    for (int v = 0; v < NQ; v++) P[v * ncp + d] = P[v * ncp + s];
 }
 
 // ---------------------------------------------------------------------------------
@@ -285,28 +285,29 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
 // template parameters so that every load of a cell sits in one basic block and is
 // issued before the first wait (a uniform run-time branch per value would split
 // the loads into serial round trips).
-template <typename R, bool KS, bool ND3, bool BASE>
+template <typename R, bool KS, bool ND3, bool BASE, bool ENT>
 __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
                                                const double *Ub, const double *Us, const R *__restrict__ Ps,
                                                double *Uo, R *__restrict__ Po, const R *__restrict__ F0,
                                                const R *__restrict__ F1, const R *__restrict__ F2, long long nf0,
                                                long long nf1, long long nf2, double a, double b)
 {
+    constexpr int NQ = NV + (ENT ? 1 : 0);        // rows: GRMHD variables (+ entropy field)
     __shared__ long long redl[WG / 64];
     __shared__ int redi[WG / 64];
     const WorkItem w = work[blockIdx.x];
     if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
     const DevBlock B = gd.blocks[w.block];
     int i, j, k;
-    int fail = 0, floored = 0, nit = 0;
+    int fail = 0, floored = 0, nit = 0, backup = 0;
     if (cell_of(B, w.start + threadIdx.x, i, j, k)) {
         const long long c = pad_index(B, kp, i, j, k);
         const long long ci = B.ioff + w.start + threadIdx.x;   // interior-packed index of U
         const DevLevel &L = gd.levels[B.level];
         // flux divergence, formed per direction in R, summed in double
-        double div[3][NV];
+        double div[3][NQ];
 #pragma unroll
-        for (int v = 0; v < NV; v++) div[2][v] = 0.0;
+        for (int v = 0; v < NQ; v++) div[2][v] = 0.0;
 #pragma unroll
         for (int d = 0; d < (ND3 ? 3 : 2); d++) {
             const R *Fd = d == 0 ? F0 : (d == 1 ? F1 : F2);
@@ -316,20 +317,21 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
             const long long hi = lo + (d == 0 ? 1 : (d == 1 ? fs0 : (long long)fs0 * fs1));
             const R idx = (R)L.inv_dx[d];
 #pragma unroll
-            for (int v = 0; v < NV; v++) div[d][v] = (double)((Fd[v * nf + hi] - Fd[v * nf + lo]) * idx);
+            for (int v = 0; v < NQ; v++) div[d][v] = (double)((Fd[v * nf + hi] - Fd[v * nf + lo]) * idx);
         }
-        double q[NV], Uc[NV], S[NV];
+        double q[NQ], Uc[NQ], S[NQ];
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
+        for (int v = 0; v < NQ; v++) {
             q[v] = (double)Ps[v * kp.ncp + c];
             Uc[v] = Us[v * kp.nci + ci];
         }
         const CentM m = centre_metric<KS>(gd, B, i, j);
         const double dt = gd.st->dt, kappa = gd.st->kappa;
         geometric_sources(q, Uc, m, kappa, S);
-        double Un[NV];
+        if constexpr (ENT) S[NV] = 0.0;           // the entropy field has no source
+        double Un[NQ];
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
+        for (int v = 0; v < NQ; v++) {
             // L = -(div_1 + div_2 + div_3) + S with a Neumaier compensation
             double sum = -div[0][v], comp = 0.0;
             const double terms[3] = {-div[1][v], -div[2][v], S[v]};
@@ -346,12 +348,16 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
             two_sum(Uc[v], dt * Lv, s2, e2);
             Un[v] = (BASE ? a * Ub[v * kp.nci + ci] : 0.0) + (b * s2 + b * e2);
         }
-        double Pn[NV];
-        fail = con_to_prim(Un, q, m, kp, Pn, nit, floored);
-        if (fail || floored) prim_to_cons(Pn, m, kp.gfac, Un);
+        double Pn[NQ];
+        fail = con_to_prim<ENT>(Un, q, m, kp, Pn, nit, floored, backup);
+        // failed, floored or backed-up cells take the conserved state of their primitives
+        if (fail || floored || backup) {
+            prim_to_cons(Pn, m, kp.gfac, Un);
+            if constexpr (ENT) Un[NV] = Un[0] * Pn[NV];
+        }
         floored = fail ? 0 : floored;
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
+        for (int v = 0; v < NQ; v++) {
             Uo[v * kp.nci + ci] = Un[v];
             Po[v * kp.ncp + c] = (R)Pn[v];
         }
@@ -359,11 +365,58 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
     const long long nfail = wg_sum<WG>(fail, redl);
     const long long nfl = wg_sum<WG>(floored, redl);
     const int mit = wg_imax<WG>(nit, redi);
+    long long nbk = 0;
+    if constexpr (ENT) nbk = wg_sum<WG>(backup, redl);
     if (threadIdx.x == 0) {
         if (nfail) atomicAdd(&gd.st->c2p_fail, (unsigned long long)nfail);
         if (nfl) atomicAdd(&gd.st->floor_hits, (unsigned long long)nfl);
         if (mit) raise_max(&gd.st->max_iter, mit);
+        if (nbk) atomicAdd(&gd.st->c2p_backup, (unsigned long long)nbk);
     }
+}
+
+// ---------------------------------------------------------------------------------
+// Entropy-field face flux (grids that carry the entropy field): the field K (row
+// NV of P) is reconstructed at the face like the other variables, from the same
+// halo cells, and carried by the face's mass flux (row 0 of F, written by the
+// direction's flux kernel just before on the same stream) from the upwind side.
+// ---------------------------------------------------------------------------------
+template <typename R, int D, int RECON>
+__global__ __launch_bounds__(WG) void k_entropy_flux(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+                                                     const R *__restrict__ P, R *__restrict__ F, long long nftot)
+{
+    const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
+    const DevBlock B = gd.blocks[w.block];
+    const int fs0 = B.s[0] + (D == 0), fs1 = B.s[1] + (D == 1), fs2 = B.s[2] + (D == 2);
+    const int item = w.start + threadIdx.x;
+    if (item >= fs0 * fs1 * fs2) return;
+    const int i = item % fs0;
+    const int t = item / fs0;
+    const int j = t % fs1;
+    const int k = t / fs1;
+    const long long pc = pad_index(B, kp, i, j, k);
+    const long long st = D == 0 ? 1 : (D == 1 ? (long long)B.n0 : (long long)B.n0 * B.n1);
+    const int f = D == 0 ? i : (D == 1 ? j : k);
+    const int sD = B.s[D];
+    const bool clo = (B.hclamp >> (2 * D)) & 1, chi = (B.hclamp >> (2 * D + 1)) & 1;
+    constexpr int S0 = RECON == BHAC_RECON_PPM ? 0 : 1, S1 = RECON == BHAC_RECON_PPM ? 6 : 5;
+    const R *Kr = P + NV * kp.ncp;
+    R q[6];
+    q[0] = q[5] = R(0);
+#pragma unroll
+    for (int s = S0; s < S1; s++) {
+        const int l = f + s - 3;
+        const long long in = pc + (s - 3) * st;
+        const long long lo = clo ? pc - f * st : in + B.hshift[D][0];
+        const long long hi = chi ? pc + (sD - 1 - f) * st : in + B.hshift[D][1];
+        q[s] = Kr[l < 0 ? lo : (l >= sD ? hi : in)];
+    }
+    R KL, KR;
+    recon_face<R, RECON>(q, KL, KR);
+    R *out = F + B.fofs[D] + item;
+    const R fm = out[0];
+    out[NV * nftot] = fm * (fm >= R(0) ? KL : KR);
 }
 
 // ---------------------------------------------------------------------------------
@@ -386,9 +439,10 @@ __global__ __launch_bounds__(WG) void k_prim2con(KParams kp, GridDev gd, const W
     prim_to_cons(q, centre_metric<KS>(gd, B, i, j), kp.gfac, Uc);
 #pragma unroll
     for (int v = 0; v < NV; v++) U[v * kp.nci + ci] = Uc[v];
+    if (kp.nvar > NV) U[NV * kp.nci + ci] = Uc[0] * (double)P[NV * kp.ncp + c];
 }
 
-template <typename R, bool KS>
+template <typename R, bool KS, bool ENT>
 __global__ __launch_bounds__(WG) void k_con2prim(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
                                                  const double *__restrict__ U, R *__restrict__ P,
                                                  int8_t *__restrict__ flags)
@@ -399,29 +453,32 @@ __global__ __launch_bounds__(WG) void k_con2prim(KParams kp, GridDev gd, const W
     if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
     const DevBlock B = gd.blocks[w.block];
     int i, j, k;
-    int fail = 0, floored = 0, nit = 0;
+    constexpr int NQ = NV + (ENT ? 1 : 0);
+    int fail = 0, floored = 0, nit = 0, backup = 0;
     if (cell_of(B, w.start + threadIdx.x, i, j, k)) {
         const long long c = pad_index(B, kp, i, j, k);
         const long long ci = B.ioff + w.start + threadIdx.x;
-        double q[NV], Uc[NV], Pn[NV];
+        double q[NQ], Uc[NQ], Pn[NQ];
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
+        for (int v = 0; v < NQ; v++) {
             q[v] = (double)P[v * kp.ncp + c];
             Uc[v] = U[v * kp.nci + ci];
         }
-        fail = con_to_prim(Uc, q, centre_metric<KS>(gd, B, i, j), kp, Pn, nit, floored);
+        fail = con_to_prim<ENT>(Uc, q, centre_metric<KS>(gd, B, i, j), kp, Pn, nit, floored, backup);
         floored = fail ? 0 : floored;
 #pragma unroll
-        for (int v = 0; v < NV; v++) P[v * kp.ncp + c] = (R)Pn[v];
+        for (int v = 0; v < NQ; v++) P[v * kp.ncp + c] = (R)Pn[v];
         if (flags) flags[ci] = (int8_t)fail;
     }
     const long long nfail = wg_sum<WG>(fail, redl);
     const long long nfl = wg_sum<WG>(floored, redl);
     const int mit = wg_imax<WG>(nit, redi);
+    const long long nbk = wg_sum<WG>(backup, redl);
     if (threadIdx.x == 0) {
         if (nfail) atomicAdd(&gd.st->c2p_fail, (unsigned long long)nfail);
         if (nfl) atomicAdd(&gd.st->floor_hits, (unsigned long long)nfl);
         if (mit) raise_max(&gd.st->max_iter, mit);
+        if (nbk) atomicAdd(&gd.st->c2p_backup, (unsigned long long)nbk);
     }
 }
 
@@ -491,6 +548,7 @@ __global__ void k_reset_stats(DevState *st)
 {
     st->c2p_fail = 0ull;
     st->floor_hits = 0ull;
+    st->c2p_backup = 0ull;
     st->max_iter = 0;
 }
 
@@ -503,7 +561,8 @@ inline unsigned nblk(long long n) { return (unsigned)((n + WG - 1) / WG); }
 
 const char *const kKernelNames[K_COUNT] = {"fill_ghosts", "flux_x1", "flux_x2", "flux_x3", "update",
                                            "prim2con", "con2prim", "cell_speeds", "step_begin", "step_end",
-                                           "block_flux", "update_div", "fill_cross_level", "flux_fix"};
+                                           "block_flux", "update_div", "fill_cross_level", "flux_fix",
+                                           "flux_entropy"};
 
 hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only)
 {
@@ -522,10 +581,14 @@ hipError_t launch_fill_copies(const DeviceGrid &G, void *P, hipStream_t s, bool 
     TimedLaunch tl(G.timer, K_FILL, s);
     const unsigned nchunk = nblk(n);
     const unsigned grid = ((nchunk + NXCD - 1) / NXCD) * NXCD;
-    if (G.mixed)
-        hipLaunchKernelGGL(k_fill<float>, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (float *)P, G.kp.ncp);
-    else
-        hipLaunchKernelGGL(k_fill<double>, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (double *)P, G.kp.ncp);
+    const bool ent = G.kp.nvar > NV;
+    if (G.mixed) {
+        auto kern = ent ? k_fill<float, NV + 1> : k_fill<float, NV>;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (float *)P, G.kp.ncp);
+    } else {
+        auto kern = ent ? k_fill<double, NV + 1> : k_fill<double, NV>;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (double *)P, G.kp.ncp);
+    }
     return hipGetLastError();
 }
 
@@ -562,8 +625,8 @@ template <typename R, bool KS>
 static hipError_t c2p_typed(const DeviceGrid &G, const double *U, void *P, int8_t *f, hipStream_t s)
 {
     TimedLaunch tl(G.timer, K_CON2PRIM, s);
-    hipLaunchKernelGGL((k_con2prim<R, KS>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, U,
-                       (R *)P, f);
+    auto kern = G.kp.nvar > NV ? k_con2prim<R, KS, true> : k_con2prim<R, KS, false>;
+    hipLaunchKernelGGL(kern, dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, U, (R *)P, f);
     return hipGetLastError();
 }
 
@@ -633,14 +696,27 @@ static hipError_t flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename R, int D, int RECON>
+static hipError_t entropy_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
+{
+    const std::vector<WorkItem> &w = G.plan.wface[D];
+    TimedLaunch tl(G.timer, K_FLUX_ENT, s);
+    hipLaunchKernelGGL((k_entropy_flux<R, D, RECON>), dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D],
+                       (const R *)Ps, (R *)G.d_flux[D], G.plan.nface[D]);
+    return hipGetLastError();
+}
+
 template <typename R, bool KS>
 static hipError_t update_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
                                void *Po, double a, double b, hipStream_t s)
 {
     TimedLaunch tl(G.timer, K_UPDATE, s);
     const bool nd3 = G.kp.ndim == 3, base = a != 0.0;
-    auto kern = nd3 ? (base ? k_update<R, KS, true, true> : k_update<R, KS, true, false>)
-                    : (base ? k_update<R, KS, false, true> : k_update<R, KS, false, false>);
+    auto kern = nd3 ? (base ? k_update<R, KS, true, true, false> : k_update<R, KS, true, false, false>)
+                    : (base ? k_update<R, KS, false, true, false> : k_update<R, KS, false, false, false>);
+    if (G.kp.nvar > NV)
+        kern = nd3 ? (base ? k_update<R, KS, true, true, true> : k_update<R, KS, true, false, true>)
+                   : (base ? k_update<R, KS, false, true, true> : k_update<R, KS, false, false, true>);
     hipLaunchKernelGGL(kern, dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, Ub, Us,
                        (const R *)Ps, Uo, (R *)Po, (const R *)G.d_flux[0], (const R *)G.d_flux[1],
                        (const R *)G.d_flux[2], G.plan.nface[0], G.plan.nface[1], G.plan.nface[2], a, b);
@@ -654,11 +730,18 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
     // each direction by faces or by lines, as planned; in 3-D the x2 and x3 kernels
     // run on the grid's side streams, concurrently with x1 on the caller's stream
     const int mm = G.plan.march_mask;
-    auto dir = [&](int d, hipStream_t st) -> hipError_t {
+    auto hydro = [&](int d, hipStream_t st) -> hipError_t {
         if (mm >> d & 1) return launch_flux_march(G, d, Ps, st);
         if (d == 0) return flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, st);
         if (d == 1) return flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, st);
         return flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, st);
+    };
+    // with the entropy field, its flux follows each direction's kernel on that stream
+    auto dir = [&](int d, hipStream_t st) -> hipError_t {
+        hipError_t r = hydro(d, st);
+        if (r != hipSuccess || G.kp.nvar == NV) return r;
+        return d == 0 ? entropy_dir<R, 0, RECON>(G, Ps, st)
+                      : (d == 1 ? entropy_dir<R, 1, RECON>(G, Ps, st) : entropy_dir<R, 2, RECON>(G, Ps, st));
     };
     hipError_t e = hipSuccess;
     if (G.kp.ndim == 3 && G.side[0] && G.side[1]) {

@@ -561,12 +561,69 @@ __device__ __forceinline__ double c2p_newton_step(const C2PSys &c, double xi)
     return xn;
 }
 
+// Entropy backup of the inversion (entropy field carried, rows 9 of U and P).
+// With p = K rho^gamma and rho = D / W the enthalpy density is a function of W:
+//   xi(W) = D W + Gamma/(Gamma-1) K D^Gamma W^(2-Gamma),
+// and the momentum relation leaves the one equation
+//   f(W) = (xi + B^2)^2 (1 - W^-2) - (S.B)^2 (2 xi + B^2) / xi^2 - S^2 = 0,
+// whose left side grows with W for Gamma <= 2 (f(1) <= 0): one root on [1, inf).
+// Newton steps in W inside a bracket that every evaluation narrows; a step that
+// leaves the bracket is replaced by the bracket's midpoint.
+constexpr int ENT_MAXIT = 100;
+
+__device__ __forceinline__ void ent_eval(const C2PSys &c, double KDg, double gam, double W, double &xi, double &f,
+                                         double &df)
+{
+    const double Wp = pow(W, 1.0 - gam);            // W^(1-Gamma)
+    xi = c.D * W + KDg * (W * Wp);
+    const double dxi = c.D + KDg * (2.0 - gam) * Wp;
+    const double xb = xi + c.B2, iW = 1.0 / W, w2i = iW * iW, ixi = 1.0 / xi;
+    const double ixi2 = ixi * ixi;
+    f = xb * xb * (1.0 - w2i) - c.SB2 * (2.0 * xi + c.B2) * ixi2 - c.S2;
+    df = 2.0 * xb * dxi * (1.0 - w2i) + 2.0 * xb * xb * w2i * iW + c.SB2 * dxi * (2.0 * ixi2 + 2.0 * c.B2 * ixi2 * ixi);
+}
+
+__device__ __noinline__ bool ent_root(const C2PSys &c, double K, double gam, double gfac, double Wg, double tol,
+                                      double &W, double &xi)
+{
+    const double KDg = gfac * K * pow(c.D, gam);
+    double f, df, lo = 1.0, hi = 2.0;
+    ent_eval(c, KDg, gam, hi, xi, f, df);
+    for (int n = 0; n < 60 && f < 0.0; n++) {
+        lo = hi;
+        hi *= 2.0;
+        ent_eval(c, KDg, gam, hi, xi, f, df);
+    }
+    if (!(f >= 0.0)) return false;
+    W = (Wg > lo && Wg < hi) ? Wg : 0.5 * (lo + hi);
+    for (int it = 0; it < ENT_MAXIT; it++) {
+        ent_eval(c, KDg, gam, W, xi, f, df);
+        if (!isfinite(f) || !isfinite(df)) return false;
+        if (f == 0.0) return true;
+        if (f < 0.0) lo = W;
+        else hi = W;
+        double Wn = W - f / df;
+        if (!(Wn > lo && Wn < hi)) Wn = 0.5 * (lo + hi);
+        const bool done = fabs(Wn - W) <= tol * Wn;
+        W = Wn;
+        if (done) {
+            ent_eval(c, KDg, gam, W, xi, f, df);
+            return true;
+        }
+    }
+    return false;
+}
+
 // U: conserved (densitised); g: guess primitives; out: primitives. nit: steps taken.
+// ENT: the entropy field is carried (U[9] = U[0] K, P[9] = K); where the energy
+// inversion fails the entropy root is taken instead and `backup` is set.
+template <bool ENT = false>
 __device__ __forceinline__ int con_to_prim(const double *U, const double *g, const CentM &m, const KParams &kp,
-                                           double *out, int &nit, int &floored)
+                                           double *out, int &nit, int &floored, int &backup)
 {
     nit = 0;
     floored = 0;
+    backup = 0;
     const double isg = rcp_nr(m.sg);
     C2PSys c;
     c.gfac_inv = kp.gfac_inv;
@@ -622,8 +679,30 @@ __device__ __forceinline__ int con_to_prim(const double *U, const double *g, con
             if (!(rho > 0.0) || !(p >= 0.0) || !isfinite(rho) || !isfinite(p)) fail = true;
         }
     }
+    if constexpr (ENT) {
+        if (fail) {
+            const double K = U[9] / U[0];
+            if (c.D > 0.0 && K > 0.0 && isfinite(K) && isfinite(c.S2) && isfinite(c.B2)) {
+                const double u1 = g[1], u2 = g[2], u3 = g[3];
+                const double Wg =
+                    sqrt(1.0 + (u1 * (m.g11 * u1 + m.g13 * u3) + u2 * m.g22 * u2 + u3 * (m.g13 * u1 + m.g33 * u3)));
+                double Wb, xib;
+                if (ent_root(c, K, kp.gam, kp.gfac, Wg, kp.c2p_tol, Wb, xib)) {
+                    const double rb = c.D / Wb, pb = K * pow(rb, kp.gam);
+                    if (rb > 0.0 && pb >= 0.0 && isfinite(rb) && isfinite(pb) && xib > 0.0) {
+                        W = Wb;
+                        xi = xib;
+                        rho = rb;
+                        p = pb;
+                        fail = false;
+                        backup = 1;
+                    }
+                }
+            }
+        }
+    }
     if (fail) {
-        for (int v = 0; v < NV; v++) out[v] = g[v];
+        for (int v = 0; v < NV + (ENT ? 1 : 0); v++) out[v] = g[v];
         return 1;
     }
     const double ixb = rcp_nr(xi + c.B2), sbx = c.SB * rcp_nr(xi);
@@ -647,6 +726,7 @@ __device__ __forceinline__ int con_to_prim(const double *U, const double *g, con
     out[6] = B[1];
     out[7] = B[2];
     out[8] = U[8];
+    if constexpr (ENT) out[9] = U[9] / U[0];
     return 0;
 }
 

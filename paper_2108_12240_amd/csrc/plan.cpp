@@ -120,6 +120,8 @@ bool check_params(const bhac_params &p, std::string &err)
     if (p.precision != BHAC_PREC_FP64 && p.precision != BHAC_PREC_MIXED) return bad(err, "unknown precision");
     if (p.fused != 0 && p.fused != 1) return bad(err, "fused must be 0 or 1");
     if (p.amr != 0 && p.amr != 1) return bad(err, "amr must be 0 or 1");
+    if (p.entropy != 0 && p.entropy != 1) return bad(err, "entropy must be 0 or 1");
+    if (p.entropy && !(p.gamma_ad <= 2.0)) return bad(err, "the entropy backup needs gamma_ad <= 2");
     if (p.sched.set != 0 && p.sched.set != 1) return bad(err, "sched.set must be 0 or 1");
     if (p.sched.set) {
         if (p.sched.march_mask < 0 || p.sched.march_mask > 7) return bad(err, "sched.march_mask must be in [0, 7]");
@@ -223,6 +225,10 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         auto it = lattice.find(k);
         return it == lattice.end() ? -1 : it->second;
     };
+    if (p.entropy && (p.fused || p.amr)) {
+        err = "the entropy field needs the unfused substep (fused = 0) on independent patches (amr = 0)";
+        return BHAC_EUNSUPPORTED;
+    }
     if (p.amr) {
         if (p.fused) { err = "the block-tiled substep does not support block trees (amr = 1)"; return BHAC_EUNSUPPORTED; }
         for (int64_t b = 0; b < nb; b++) {

@@ -112,3 +112,21 @@ def test_out_of_range_schedule_is_rejected(bad):
     with pytest.raises(B.BhacError) as e:
         B.bhac_plan_ghosts(dict(c.params, sched=bad), c.blocks)
     assert e.value.code == B.BHAC_EINVAL
+
+
+def test_entropy_parameter_checks():
+    c = I.with_entropy(I.case_torus(2, n=32))
+    B.bhac_plan_ghosts(c.params, c.blocks)
+    with pytest.raises(B.BhacError) as e:
+        B.bhac_plan_ghosts(dict(c.params, gamma_ad=2.5), c.blocks)
+    assert e.value.code == B.BHAC_EINVAL
+    with pytest.raises(B.BhacError) as e:
+        B.bhac_plan_ghosts(dict(c.params, entropy=2), c.blocks)
+    assert e.value.code == B.BHAC_EINVAL
+    with pytest.raises(B.BhacError) as e:
+        B.bhac_plan_ghosts(dict(c.params, fused=1), c.blocks)
+    assert e.value.code == B.BHAC_EUNSUPPORTED
+    t = I.case_tree(n0=32, bs=8, levels=2)
+    with pytest.raises(B.BhacError) as e:
+        B.bhac_plan_ghosts(dict(t.params, entropy=1), t.blocks)
+    assert e.value.code == B.BHAC_EUNSUPPORTED
