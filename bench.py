@@ -70,9 +70,9 @@ WORKLOADS = {
 # on; with any other sources the field is reported as null.
 TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
-    ("ks_torus_128_fp64_plain", "update"): (1265119648, "e2c7d7dc5e63a76a"),
-    ("ks_torus_128_mixed_plain", "update"): (838038170, "e2c7d7dc5e63a76a"),
-    ("ks_torus_128_mixed_auto", "update"): (838038170, "e2c7d7dc5e63a76a"),
+    ("ks_torus_128_fp64_plain", "update"): (1265614325, "6442f2d0598db647"),
+    ("ks_torus_128_mixed_plain", "update"): (838002213, "6442f2d0598db647"),
+    ("ks_torus_128_mixed_auto", "update"): (838002213, "6442f2d0598db647"),
 }
 
 
