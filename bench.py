@@ -70,9 +70,9 @@ WORKLOADS = {
 # on; with any other sources the field is reported as null.
 TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
-    ("ks_torus_128_fp64_plain", "update"): (1265614325, "6442f2d0598db647"),
-    ("ks_torus_128_mixed_plain", "update"): (838002213, "6442f2d0598db647"),
-    ("ks_torus_128_mixed_auto", "update"): (838002213, "6442f2d0598db647"),
+    ("ks_torus_128_fp64_plain", "update"): (1165876507, "cf5d25e2b6d78454"),
+    ("ks_torus_128_mixed_plain", "update"): (838002731, "cf5d25e2b6d78454"),
+    ("ks_torus_128_mixed_auto", "update"): (838002731, "cf5d25e2b6d78454"),
 }
 
 

@@ -29,8 +29,17 @@
  *    u~2, u~3 (Lorentz factor times Eulerian 3-velocity, contravariant), p, B1,
  *    B2, B3 (Eulerian magnetic field), psi (GLM scalar); each row has
  *    ncell_padded entries and block b occupies [block_offset[b],
- *    block_offset[b+1]): its (size+2g)-padded box, x fastest, then y, then z (for
- *    ndim = 2 the z extent is 1 with no ghosts). Conserved U: rows
+ *    block_offset[b+1]): its padded box, x fastest, then y, then z. Along y and
+ *    z the box is size + 2g cells (g ghost layers each side; for ndim = 2 the z
+ *    extent is 1 with no ghosts). Along x each row holds
+ *    n0 = roundup(x_offset + size + g, x_align) slots with the interior starting
+ *    at slot x_offset = roundup(g, x_align); x_align is 16 for a double state
+ *    (with a 128-byte aligned state pointer every row and every block's interior
+ *    rows then start on a 128-byte line, so a 16-cell interior row is one whole
+ *    line) and 1 for a float state (rows of size + 2g). bhac_layout reports
+ *    both. The g slots on either side of the interior are the x ghost layers;
+ *    the rest of a row is padding
+ *    that no call reads or writes. Conserved U: rows
  *    sqrt(gamma) * (D, S_1, S_2, S_3, tau, B1, B2, B3), psi; conserved variables
  *    need no ghost cells, so each row has ncell_interior entries and block b
  *    occupies [block_interior_offset[b], block_interior_offset[b+1]), x fastest.
@@ -164,6 +173,8 @@ typedef struct bhac_layout {
     int64_t ncell_interior;
     int nvar;
     int nghost;
+    int x_offset;       /* slot of the first interior cell in a padded x row */
+    int x_align;        /* padded x rows: pitch and x_offset are multiples of this */
     const int64_t *block_offset;
     const int64_t *block_interior_offset;
 } bhac_layout;
@@ -317,7 +328,10 @@ int bhac_launch_rk2_step(bhac_grid *grid, void *stream);
  * kernel family into out[0..max_entries) (name, launches, total milliseconds;
  * names are static strings), writes the number of families with launches to
  * *n_entries, and restarts the accumulation. Launches beyond the pool are not
- * timed (their count is returned as a family named "untimed"). */
+ * timed (their count is returned as a family named "untimed"). While timing is
+ * enabled the face kernels of a 3-D substep run one after another on the
+ * caller's stream instead of concurrently on the grid's side streams, so each
+ * measured duration is the kernel's own (results are the same either way). */
 typedef struct bhac_kernel_time {
     const char *name;
     int64_t launches;

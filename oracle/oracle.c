@@ -45,6 +45,8 @@ typedef struct {
     int c2p_maxit;
     int amr;                           /* 0 independent same-level patches, 1 2:1 block tree */
     int entropy;                       /* 1: carry the entropy field (P[9] = K, U[9] = U[0] K) */
+    int precision;                     /* 0 double, 1 float state: sets only the x alignment of the
+                                          padded layout (the oracle computes in double) */
 } orc_params;
 
 /* rows of P and U: the nine GRMHD variables, plus the entropy field if carried */
@@ -618,8 +620,25 @@ typedef struct {
     int maxlevel;
 } orc_grid;
 
+/* Padded box of a block (data contract shared with the library): g ghost layers
+ * per side along y and z; along x the interior starts at slot xo = roundup(g, A)
+ * and a row holds roundup(xo + size + g, A) slots, A = 16 for a double state
+ * (128-byte rows) and 1 for a float state (rows of size + 2g); slots further than
+ * g from the interior are padding. */
+static int xalign(const orc_grid *G) { return G->p.precision == 1 ? 1 : 16; }
+
+static int x_offset(const orc_grid *G)
+{
+    const int a = xalign(G);
+    return (G->gd[0] + a - 1) / a * a;
+}
+
 static int64_t ncell_axis(const orc_grid *G, int b, int e)
 {
+    if (e == 0) {
+        const int a = xalign(G);
+        return (x_offset(G) + G->blk[b].size[0] + G->gd[0] + a - 1) / a * a;
+    }
     return G->blk[b].size[e] + 2 * G->gd[e];
 }
 
@@ -627,7 +646,7 @@ static int64_t pad_index(const orc_grid *G, int b, int i, int j, int k)
 {
     /* i, j, k: local indices, interior is [0, size) */
     const int64_t n0 = ncell_axis(G, b, 0), n1 = ncell_axis(G, b, 1);
-    return G->off[b] + ((int64_t)(k + G->gd[2]) * n1 + (j + G->gd[1])) * n0 + (i + G->gd[0]);
+    return G->off[b] + ((int64_t)(k + G->gd[2]) * n1 + (j + G->gd[1])) * n0 + (i + x_offset(G));
 }
 
 static double level_dx(const orc_grid *G, int level, int e)

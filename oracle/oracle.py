@@ -18,6 +18,15 @@ LIB = os.path.join(HERE, "liboracle.so")
 NV = 9
 
 
+def padded_x(params: dict):
+    """(x alignment, x offset of the interior) of the padded layout: 16 for a double
+    state (128-byte rows), 1 for a float state; the offset is the ghost depth
+    rounded up to it."""
+    xa = 1 if int(params.get("precision", 0)) == 1 else 16
+    g = int(params["nghost"])
+    return xa, -(-g // xa) * xa
+
+
 def nvar(params: dict) -> int:
     """Rows of P and U: nine GRMHD variables, plus the entropy field if carried."""
     return NV + (1 if int(params.get("entropy", 0)) else 0)
@@ -41,7 +50,7 @@ class Params(C.Structure):
                 ("recon", C.c_int), ("flux", C.c_int),
                 ("cfl", C.c_double), ("rho_floor", C.c_double), ("p_floor", C.c_double),
                 ("w_max", C.c_double), ("glm_alpha", C.c_double), ("c2p_tol", C.c_double),
-                ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int)]
+                ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int), ("precision", C.c_int)]
 
 
 class Block(C.Structure):
@@ -100,6 +109,7 @@ def make_params(d: dict) -> Params:
         setattr(p, k, int(d[k]))
     p.amr = int(d.get("amr", 0))
     p.entropy = int(d.get("entropy", 0))
+    p.precision = int(d.get("precision", 0))
     for k in ("spin", "gamma_ad", "cfl", "rho_floor", "p_floor", "w_max", "glm_alpha", "c2p_tol"):
         setattr(p, k, float(d[k]))
     for e in range(3):
@@ -166,13 +176,14 @@ class OracleGrid:
         if self._pidx is None:
             g = int(self.params["nghost"])
             nd = int(self.params["ndim"])
+            xa, xo = padded_x(self.params)
             parts = []
             for b in range(self.nb):
                 s = self.blocks[b, 1:4]
                 gd = [g if e < nd else 0 for e in range(3)]
-                n0, n1 = s[0] + 2 * gd[0], s[1] + 2 * gd[1]
+                n0, n1 = -(-(xo + s[0] + gd[0]) // xa) * xa, s[1] + 2 * gd[1]
                 k, j, i = np.meshgrid(np.arange(s[2]), np.arange(s[1]), np.arange(s[0]), indexing="ij")
-                parts.append(self.off[b] + ((k + gd[2]) * n1 + (j + gd[1])) * n0 + (i + gd[0]))
+                parts.append(self.off[b] + ((k + gd[2]) * n1 + (j + gd[1])) * n0 + (i + xo))
             self._pidx = np.concatenate([p.ravel() for p in parts]).astype(np.int64)
         return self._pidx
 

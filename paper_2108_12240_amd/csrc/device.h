@@ -20,6 +20,7 @@ struct KParams {
     int g[3];
     int recon, flux;
     int nvar;                        // rows of P and U: NV, or NV + 1 with the entropy field
+    int xo;                          // x offset of the interior in a block's padded box
 };
 
 // Time-step state and counters, resident on the device.

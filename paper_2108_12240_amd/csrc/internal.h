@@ -72,6 +72,8 @@ constexpr int MARCH_MAX_FACES = 17;
 struct HaloAxis { signed char dir; signed char pad; short src; };
 
 struct Plan {
+    int xo = 0;                          // x offset of a block's interior in its padded box
+    int xalign = 8;                      // padded x rows: pitch and interior start in elements
     bhac_params p{};
     std::vector<bhac_block_desc> blocks;
     std::vector<int64_t> off;            // padded offsets, nb + 1

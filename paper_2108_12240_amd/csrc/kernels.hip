@@ -729,6 +729,8 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
 {
     // each direction by faces or by lines, as planned; in 3-D the x2 and x3 kernels
     // run on the grid's side streams, concurrently with x1 on the caller's stream
+    // (while kernel timing is on they run one after another on the caller's
+    // stream, so that each kernel's measured duration is its own)
     const int mm = G.plan.march_mask;
     auto hydro = [&](int d, hipStream_t st) -> hipError_t {
         if (mm >> d & 1) return launch_flux_march(G, d, Ps, st);
@@ -744,7 +746,7 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
                       : (d == 1 ? entropy_dir<R, 1, RECON>(G, Ps, st) : entropy_dir<R, 2, RECON>(G, Ps, st));
     };
     hipError_t e = hipSuccess;
-    if (G.kp.ndim == 3 && G.side[0] && G.side[1]) {
+    if (G.kp.ndim == 3 && G.side[0] && G.side[1] && !G.timer.on) {
         e = hipEventRecord(G.ev_fork, s);
         for (int q = 0; q < 2 && e == hipSuccess; q++) e = hipStreamWaitEvent(G.side[q], G.ev_fork, 0);
         if (e == hipSuccess) e = dir(1, G.side[0]);

@@ -164,6 +164,13 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     P.p = p;
     P.blocks.assign(blocks, blocks + nb);
     for (int e = 0; e < 3; e++) P.gd[e] = e < p.ndim ? p.nghost : 0;
+    // x rows of the padded box, double state: the interior starts and every row
+    // begins on a 128-byte line (16 doubles), so a 16-cell interior row is one
+    // whole line, read and written without partial lines. A float state keeps
+    // rows of size + 2g: a 16-cell float row is half a line, and aligning it only
+    // adds lines to the reads (measured slower)
+    P.xalign = p.precision == BHAC_PREC_MIXED ? 1 : 16;
+    P.xo = (P.gd[0] + P.xalign - 1) / P.xalign * P.xalign;
 
     // blocks, lattice occupancy, layout
     std::unordered_map<Key, int, KeyHash> lattice;
@@ -200,7 +207,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
             D.o[e] = B.origin[e];
             if (B.size[e] > P.smax[e]) P.smax[e] = B.size[e];
         }
-        D.n0 = B.size[0] + 2 * P.gd[0];
+        D.n0 = (P.xo + B.size[0] + P.gd[0] + P.xalign - 1) / P.xalign * P.xalign;
         D.n1 = B.size[1] + 2 * P.gd[1];
         D.level = B.level;
         D.off = P.off[b];
@@ -388,12 +395,12 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     auto padded_global = [&](int blk, const long long g[3]) -> int32_t {
         const DevBlock &Q = P.dblocks[blk];
         long long li[3];
-        for (int e = 0; e < 3; e++) li[e] = g[e] - Q.o[e] + P.gd[e];
+        for (int e = 0; e < 3; e++) li[e] = g[e] - Q.o[e] + (e == 0 ? P.xo : P.gd[e]);
         return (int32_t)(Q.off + (li[2] * Q.n1 + li[1]) * Q.n0 + li[0]);
     };
     auto padded_local = [&](int blk, const int a[3]) -> int32_t {
         const DevBlock &Q = P.dblocks[blk];
-        return (int32_t)(Q.off + ((long long)(a[2] + P.gd[2]) * Q.n1 + (a[1] + P.gd[1])) * Q.n0 + (a[0] + P.gd[0]));
+        return (int32_t)(Q.off + ((long long)(a[2] + P.gd[2]) * Q.n1 + (a[1] + P.gd[1])) * Q.n0 + (a[0] + P.xo));
     };
     const int nchild = p.ndim == 3 ? 8 : 4;
     // the 2^ndim cells of the level-(L+1) leaf fb under level-L cell Gi, z-outer
@@ -535,8 +542,8 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         const int n2 = D.s[2] + 2 * P.gd[2];
         for (int pk = 0; pk < n2; pk++)
             for (int pj = 0; pj < D.n1; pj++)
-                for (int pi = 0; pi < D.n0; pi++) {
-                    const int l[3] = {pi - P.gd[0], pj - P.gd[1], pk - P.gd[2]};
+                for (int pi = P.xo - P.gd[0]; pi < P.xo + D.s[0] + P.gd[0]; pi++) {
+                    const int l[3] = {pi - P.xo, pj - P.gd[1], pk - P.gd[2]};
                     int nout = 0;
                     for (int e = 0; e < 3; e++) nout += (l[e] < 0 || l[e] >= D.s[e]);
                     if (nout == 0) continue;
@@ -591,7 +598,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                     }
                     const DevBlock &S = P.dblocks[sb];
                     const long long from =
-                        S.off + ((long long)(src[2] + P.gd[2]) * S.n1 + (src[1] + P.gd[1])) * S.n0 + (src[0] + P.gd[0]);
+                        S.off + ((long long)(src[2] + P.gd[2]) * S.n1 + (src[1] + P.gd[1])) * S.n0 + (src[0] + P.xo);
                     if (nout == 1) {
                         // the halo-side rule must name the same source cell
                         int e = 0;

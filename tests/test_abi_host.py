@@ -76,7 +76,10 @@ def test_ghost_plan_matches_oracle_fill_bitwise(name, make):
     # every ghost slot appears exactly once and reads an interior cell
     interior = np.zeros(G.ncp, bool)
     interior[G.interior_index()] = True
-    assert len(np.unique(dst)) == len(dst) == G.ncp - G.nci
+    g, nd = int(c.params["nghost"]), int(c.params["ndim"])
+    nghost_slots = sum(int(np.prod([b[1 + e] + (2 * g if e < nd else 0) for e in range(3)])) - int(np.prod(b[1:4]))
+                       for b in np.asarray(c.blocks, dtype=np.int64))
+    assert len(np.unique(dst)) == len(dst) == nghost_slots
     assert interior[src].all() and not interior[dst].any()
 
 

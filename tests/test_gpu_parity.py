@@ -5,6 +5,7 @@ import pytest
 from oracle import oracle as O
 from paper_2108_12240_amd import bhac as B
 from paper_2108_12240_amd import inputs as I
+from tests import layout as L
 from tests.parity import rel_l1, linf
 
 pytestmark = pytest.mark.gpu
@@ -182,17 +183,16 @@ def test_substep_rejects_aliasing_and_uninitialised_dt(torch):
 
 
 def outside_count(c, G):
-    """For every padded cell: how many of its coordinates lie outside its block."""
-    g = c.params["nghost"]
-    nd = c.params["ndim"]
+    """For every padded cell: how many of its coordinates lie outside its block
+    (-1 for the padding slots of the x rows)."""
+    params = dict(c.params, precision=1 if G.pdtype == G.torch.float32 else 0)
     nout = np.zeros(G.ncp, dtype=np.int64)
     for b, blk in enumerate(c.blocks):
         s = blk[1:4]
-        n = np.array([s[e] + (2 * g if e < nd else 0) for e in range(3)])
-        k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
-        cnt = sum(((x - (g if e < nd else 0)) < 0) | ((x - (g if e < nd else 0)) >= s[e])
-                  for e, x in enumerate((i, j, k)))
-        nout[G.off[b]:G.off[b + 1]] = cnt.ravel()
+        x, y, z, pad = L.box_locals(params, s)
+        cnt = sum(((v < 0) | (v >= s[e])).astype(np.int64) for e, v in enumerate((x, y, z)))
+        cnt[pad] = -1
+        nout[G.off[b]:G.off[b + 1]] = cnt
     return nout
 
 
@@ -252,4 +252,5 @@ def test_fill_ghost_faces_fills_exactly_the_face_slabs(torch):
         assert np.array_equal(got[:, face], ref[:, face])
         assert np.array_equal(got[:, nout >= 2], ids[:, nout >= 2])
         assert np.array_equal(got[:, nout == 0], ids[:, nout == 0])
+        assert np.array_equal(got[:, nout < 0], ids[:, nout < 0])
         G.close()

@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from tests import layout as L
 from paper_2108_12240_amd import inputs as I
 
 
@@ -61,9 +62,7 @@ def ghost_expectations(G, blocks, params):
                             break
                     if owner is None:
                         tgt = [o[e] + min(max(loc[e], 0), s[e] - 1) for e in range(3)]
-                    pad = [loc[e] + gd[e] for e in range(3)]
-                    n0, n1 = s[0] + 2 * gd[0], s[1] + 2 * gd[1]
-                    idx = G.off[b] + (pad[2] * n1 + pad[1]) * n0 + pad[0]
+                    idx = L.pad_index(params, G.off[b], s, loc[0], loc[1], loc[2])
                     gid = (tgt[2] * N[1] + tgt[1]) * N[0] + tgt[0] + 1e7 * l
                     out.append((idx, gid))
     return out
@@ -108,7 +107,9 @@ def test_periodic_wrap_closed_form_single_block():
     ids = np.arange(512, dtype=np.float64)
     P = G.pack(np.stack([ids] * 9))
     G.fill_ghosts(P)
-    cube = P[0].reshape(14, 14, 14)
+    n0 = L.box(p, (8, 8, 8))[0]
+    xo = L.origin(p)[0]
+    cube = P[0].reshape(14, 14, n0)[:, :, xo - 3:xo + 11]
     w = (np.arange(14) - 3) % 8
     K, J, Ii = np.meshgrid(w, w, w, indexing="ij")
     assert np.array_equal(cube, (K * 64 + J * 8 + Ii).astype(np.float64))

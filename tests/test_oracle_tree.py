@@ -17,22 +17,23 @@ import pytest
 
 from oracle import oracle as O
 from paper_2108_12240_amd import inputs as I
+from tests import layout as L
 from tests.cases import flat_tree_case, tree_volumes
 
 
 def ghost_positions(c, G):
-    """Per padded cell: (block, level, global level-l index per axis, is_ghost)."""
-    g = c.params["nghost"]
+    """Per padded cell: (block, level, global level-l index per axis, is_ghost);
+    padding slots of the x rows count as neither interior nor ghost."""
     rows = []
     for b, blk in enumerate(c.blocks):
         lev, s = int(blk[0]), blk[1:4]
         org = blk[4:7]
-        n = s + 2 * g
-        k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
-        loc = [i.ravel() - g, j.ravel() - g, k.ravel() - g]
+        x, y, z, pad = L.box_locals(c.params, s)
+        loc = [x, y, z]
         ghost = np.zeros(loc[0].size, bool)
         for e in range(3):
             ghost |= (loc[e] < 0) | (loc[e] >= s[e])
+        ghost &= ~pad
         glob = [org[e] + loc[e] for e in range(3)]
         rows.append((b, lev, glob, ghost))
     return rows
@@ -56,14 +57,12 @@ def away_from_edges(c, margin=3):
     their level) inside the domain on every axis (no wrap, no clamp involved)."""
     n0 = c.params["ncell0"]
     masks = []
-    g = c.params["nghost"]
     for blk in c.blocks:
         lev, s, org = int(blk[0]), blk[1:4], blk[4:7]
-        n = s + 2 * g
-        k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
-        ok = np.ones(k.size, bool)
-        for e, v in enumerate((i.ravel(), j.ravel(), k.ravel())):
-            glob = org[e] + v - g
+        x, y, z, pad = L.box_locals(c.params, s)
+        ok = ~pad
+        for e, v in enumerate((x, y, z)):
+            glob = org[e] + v
             N = n0[e] * 2 ** lev
             ok &= (glob >= margin) & (glob < N - margin)
         masks.append(ok)
@@ -208,8 +207,7 @@ def test_prolongation_children_average_to_the_coarse_cell(two_level):
         full += 1
         cb = idx[tuple(v // s for v in cc)]
         loc = [cc[e] - int(c.blocks[cb, 4 + e]) for e in range(3)]
-        n = int(c.blocks[cb, 1]) + 2 * g
-        qc = Pin[:, int(G.off[cb]) + ((loc[2] + g) * n + loc[1] + g) * n + loc[0] + g]
+        qc = Pin[:, L.pad_index(c.params, G.off[cb], c.blocks[cb, 1:4], *loc)]
         assert np.allclose(P[:, slots].mean(axis=1), qc, rtol=0, atol=1e-14)
     assert full > 50
 
@@ -232,12 +230,11 @@ def test_prolongation_is_limited(two_level):
     for (cc, b), slots in fine_ghosts_by_coarse_cell(c, G).items():
         cb = idx[tuple(v // s for v in cc)]
         loc = [cc[e] - int(c.blocks[cb, 4 + e]) for e in range(3)]
-        n = int(c.blocks[cb, 1]) + 2 * g
 
         def at(a):
-            return P[:, int(G.off[cb]) + ((a[2] + g) * n + a[1] + g) * n + a[0] + g]
+            return P[:, L.pad_index(c.params, G.off[cb], c.blocks[cb, 1:4], *a)]
 
-        vals = [Pin[:, int(G.off[cb]) + ((loc[2] + g) * n + loc[1] + g) * n + loc[0] + g]]
+        vals = [Pin[:, L.pad_index(c.params, G.off[cb], c.blocks[cb, 1:4], *loc)]]
         for d in range(3):
             for sgn in (-1, 1):
                 a = list(loc)
