@@ -61,9 +61,11 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
 @pytest.mark.parametrize("name,make", CASES)
-def test_ghost_plan_matches_oracle_fill_bitwise(name, make):
+def test_ghost_plan_matches_oracle_fill_bitwise(name, make, prec):
     c = make()
+    c.params = dict(c.params, precision=prec)
     G = O.OracleGrid(c.params, c.blocks)
     off, dst, src = B.bhac_plan_ghosts(c.params, c.blocks)
     assert np.array_equal(off, G.off)
@@ -133,3 +135,26 @@ def test_entropy_parameter_checks():
     with pytest.raises(B.BhacError) as e:
         B.bhac_plan_ghosts(dict(t.params, entropy=1), t.blocks)
     assert e.value.code == B.BHAC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
+def test_padded_layout_follows_the_rule(prec):
+    """Block offsets from the planner are the running sum of the padded boxes the
+    layout rule gives (128-byte double rows, float rows of size + 2g), and in a
+    double state every interior row starts on a 16-element boundary."""
+    from tests import layout as L
+    c = I.case4(nblocks=48, n0=48)
+    params = dict(c.params, precision=prec, fused=0)
+    off, dst, src = B.bhac_plan_ghosts(params, c.blocks)
+    sizes = [int(np.prod(L.box(params, b[1:4]))) for b in c.blocks]
+    assert np.array_equal(off, np.concatenate([[0], np.cumsum(sizes)]))
+    xa, xo = L.x_layout(params)
+    assert (xa, xo) == ((16, 16) if prec == I.PREC_FP64 else (1, 3))
+    for b, blk in enumerate(c.blocks):
+        start = L.pad_index(params, off[b], blk[1:4], 0, np.arange(blk[2]), 0)
+        assert (start % xa == 0).all()
+    # no ghost-map entry touches a padding slot
+    pad = np.zeros(off[-1], bool)
+    for b, blk in enumerate(c.blocks):
+        pad[off[b]:off[b + 1]] = L.box_locals(params, blk[1:4])[3]
+    assert not pad[dst].any() and not pad[src].any()
