@@ -75,6 +75,24 @@ TRAFFIC = {
     ("ks_torus_128_mixed_auto", "update"): (838002731, "cf5d25e2b6d78454"),
 }
 
+# Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
+# launches of two RK2 steps) of the compute-bound kernels, with the digest of the
+# sources they were counted on. With the HIP-event duration of the same kernel
+# they give its VALU issue rate against the chip's 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 39.3e12 lane-instructions/s (one wave64 instruction takes 4 cycles of
+# a 16-lane SIMD; FP64 and unpacked FP32 issue at the same rate).
+VALU = {
+    ("ks_torus_128_fp64_plain", "flux_x1"): (49151468, "cf5d25e2b6d78454"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27173533, "cf5d25e2b6d78454"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24585234, "cf5d25e2b6d78454"),
+    ("ks_torus_128_fp64_plain", "update"): (43317308, "cf5d25e2b6d78454"),
+    ("ks_torus_128_mixed_plain", "flux_x1"): (38483002, "cf5d25e2b6d78454"),
+    ("ks_torus_128_mixed_plain", "flux_x2"): (38671083, "cf5d25e2b6d78454"),
+    ("ks_torus_128_mixed_plain", "flux_x3"): (20349205, "cf5d25e2b6d78454"),
+    ("ks_torus_128_mixed_plain", "update"): (44890194, "cf5d25e2b6d78454"),
+}
+VALU_PEAK = 39.3e12      # lane-instructions/s
+
 
 def source_digest() -> str:
     import hashlib
@@ -170,6 +188,20 @@ def run_gpu(case, steps, warmup, graph=True):
     zu = info["ncell"] * 2 * steps
     return dict(ms_total=ms, ms_per_step=ms / steps, value=zu / (ms / 1e3), ktimes=ktimes, info=info,
                 stats=stats, dt=ts["dt"], finite=finite, graph=graph)
+
+
+def valu_rates(res, workload):
+    """VALU issue rate of each kernel family with a stored instruction count."""
+    out = {}
+    dig = source_digest()
+    for fam, (launches, total_ms) in res["ktimes"].items():
+        m = VALU.get((workload, fam))
+        if not m or m[1] != dig or not launches:
+            continue
+        rate = m[0] * 64 / (total_ms / launches / 1e3)
+        out[fam] = dict(bound="alu", achieved=round(rate / 1e12, 2), peak=VALU_PEAK / 1e12,
+                        unit="Tlane-instr/s", frac=round(rate / VALU_PEAK, 3))
+    return out
 
 
 def autotune_summary(rep):
@@ -309,6 +341,7 @@ def main(argv=None):
     if "autotune" in w:
         out["config"]["autotune"] = autotune_summary(w["autotune"])
     out["kernel_ms"] = {k: round(v[1] / max(v[0], 1), 4) for k, v in res["ktimes"].items()}
+    out["valu"] = valu_rates(res, args.workload)
     out["c2p"] = res["stats"]
     out["finite"] = res["finite"]
     if args.compare:
@@ -320,6 +353,7 @@ def main(argv=None):
                               speedup_vs_headline=round(r2["value"] / res["value"], 3),
                               roofline=roofline(r2, rsz2, args.compare),
                               kernel_ms={k: round(v[1] / max(v[0], 1), 4) for k, v in r2["ktimes"].items()})
+        out["compare"]["valu"] = valu_rates(r2, args.compare)
         if "autotune" in w2:
             out["compare"]["autotune"] = autotune_summary(w2["autotune"])
         del c2
