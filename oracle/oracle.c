@@ -620,12 +620,16 @@ typedef struct {
     int maxlevel;
 } orc_grid;
 
-/* Padded box of a block (data contract shared with the library): g ghost layers
- * per side along y and z; along x the interior starts at slot xo = roundup(g, A)
- * and a row holds roundup(xo + size + g, A) slots, A = 16 for a double state
- * (128-byte rows) and 1 for a float state (rows of size + 2g); slots further than
- * g from the interior are padding. */
-static int xalign(const orc_grid *G) { return G->p.precision == 1 ? 1 : 16; }
+/* Where a block's cells and ghost slots sit in P (data contract shared with the
+ * library). Independent patches: interior first -- the block's interior cells (x
+ * fastest), then the ghost slots of its (size + 2g) box in box order with the
+ * interior skipped, the region rounded up to 32 slots. Block trees: the padded
+ * box -- g ghost layers per side along y and z; along x the interior starts at
+ * slot xo = roundup(g, A) and a row holds roundup(xo + size + g, A) slots, A = 16
+ * for a double state and 1 for a float state. Unnamed slots are padding. */
+static int interior_first(const orc_grid *G) { return !G->p.amr; }
+
+static int xalign(const orc_grid *G) { return interior_first(G) || G->p.precision == 1 ? 1 : 16; }
 
 static int x_offset(const orc_grid *G)
 {
@@ -642,11 +646,39 @@ static int64_t ncell_axis(const orc_grid *G, int b, int e)
     return G->blk[b].size[e] + 2 * G->gd[e];
 }
 
+/* slots of block b's region */
+static int64_t region_size(const orc_grid *G, int b)
+{
+    const int64_t box = ncell_axis(G, b, 0) * ncell_axis(G, b, 1) * ncell_axis(G, b, 2);
+    return interior_first(G) ? (box + 31) / 32 * 32 : box;
+}
+
 static int64_t pad_index(const orc_grid *G, int b, int i, int j, int k)
 {
     /* i, j, k: local indices, interior is [0, size) */
-    const int64_t n0 = ncell_axis(G, b, 0), n1 = ncell_axis(G, b, 1);
-    return G->off[b] + ((int64_t)(k + G->gd[2]) * n1 + (j + G->gd[1])) * n0 + (i + x_offset(G));
+    const orc_block *B = &G->blk[b];
+    if (!interior_first(G)) {
+        const int64_t n0 = ncell_axis(G, b, 0), n1 = ncell_axis(G, b, 1);
+        return G->off[b] + ((int64_t)(k + G->gd[2]) * n1 + (j + G->gd[1])) * n0 + (i + x_offset(G));
+    }
+    const int s0 = B->size[0], s1 = B->size[1], s2 = B->size[2];
+    if (i >= 0 && i < s0 && j >= 0 && j < s1 && k >= 0 && k < s2)
+        return G->off[b] + ((int64_t)k * s1 + j) * s0 + i;
+    /* a ghost slot: count the ghost slots that come before it in box order (whole
+     * planes, then whole rows of its plane, then slots of its row) */
+    const int g0 = G->gd[0], g1 = G->gd[1], g2 = G->gd[2];
+    const int64_t w0 = s0 + 2 * g0, w1 = s1 + 2 * g1;
+    const int64_t bx = i + g0, by = j + g1, bz = k + g2;
+    const int64_t zin = bz - g2 < 0 ? 0 : (bz - g2 > s2 ? s2 : bz - g2);     /* interior planes before */
+    int64_t before = bz * w0 * w1 - zin * s0 * s1;
+    if (bz < g2 || bz >= s2 + g2) {
+        before += by * w0 + bx;
+    } else {
+        const int64_t yin = by - g1 < 0 ? 0 : (by - g1 > s1 ? s1 : by - g1);  /* interior rows before */
+        before += by * w0 - yin * s0;
+        before += (by < g1 || by >= s1 + g1 || bx < g0) ? bx : bx - s0;
+    }
+    return G->off[b] + (int64_t)s0 * s1 * s2 + before;
 }
 
 static double level_dx(const orc_grid *G, int level, int e)
@@ -715,7 +747,7 @@ orc_grid *orc_grid_new(const orc_params *p, const orc_block *blocks, int64_t nb)
             if (B->size[e] < p->nghost || B->origin[e] < 0 || B->origin[e] % B->size[e] != 0) goto bad;
             if (B->origin[e] + B->size[e] > N || N % B->size[e] != 0) goto bad;
         }
-        G->off[b + 1] = G->off[b] + ncell_axis(G, b, 0) * ncell_axis(G, b, 1) * ncell_axis(G, b, 2);
+        G->off[b + 1] = G->off[b] + region_size(G, (int)b);
         G->ioff[b + 1] = G->ioff[b] + (int64_t)B->size[0] * B->size[1] * B->size[2];
     }
     /* same (level, size) lattices with their occupancy */

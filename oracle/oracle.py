@@ -18,11 +18,17 @@ LIB = os.path.join(HERE, "liboracle.so")
 NV = 9
 
 
+def interior_first(params: dict) -> bool:
+    """Independent patches store each block's interior cells first, block trees
+    store padded boxes."""
+    return not int(params.get("amr", 0))
+
+
 def padded_x(params: dict):
-    """(x alignment, x offset of the interior) of the padded layout: 16 for a double
+    """Padded boxes: (x alignment, x offset of the interior): 16 for a double
     state (128-byte rows), 1 for a float state; the offset is the ghost depth
     rounded up to it."""
-    xa = 1 if int(params.get("precision", 0)) == 1 else 16
+    xa = 1 if interior_first(params) or int(params.get("precision", 0)) == 1 else 16
     g = int(params["nghost"])
     return xa, -(-g // xa) * xa
 
@@ -180,6 +186,9 @@ class OracleGrid:
             parts = []
             for b in range(self.nb):
                 s = self.blocks[b, 1:4]
+                if interior_first(self.params):
+                    parts.append(self.off[b] + np.arange(int(np.prod(s)), dtype=np.int64))
+                    continue
                 gd = [g if e < nd else 0 for e in range(3)]
                 n0, n1 = -(-(xo + s[0] + gd[0]) // xa) * xa, s[1] + 2 * gd[1]
                 k, j, i = np.meshgrid(np.arange(s[2]), np.arange(s[1]), np.arange(s[0]), indexing="ij")

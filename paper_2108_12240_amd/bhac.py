@@ -48,7 +48,8 @@ class bhac_block_desc(C.Structure):
 
 class bhac_layout(C.Structure):
     _fields_ = [("ncell_padded", C.c_int64), ("ncell_interior", C.c_int64), ("nvar", C.c_int),
-                ("nghost", C.c_int), ("x_offset", C.c_int), ("x_align", C.c_int),
+                ("nghost", C.c_int), ("interior_first", C.c_int), ("x_offset", C.c_int),
+                ("x_align", C.c_int),
                 ("block_offset", C.POINTER(C.c_int64)),
                 ("block_interior_offset", C.POINTER(C.c_int64))]
 
@@ -172,7 +173,8 @@ def bhac_alloc_blocks(params: dict, blocks: np.ndarray):
     off = np.ctypeslib.as_array(lay.block_offset, shape=(len(arr) + 1,)).copy()
     ioff = np.ctypeslib.as_array(lay.block_interior_offset, shape=(len(arr) + 1,)).copy()
     return h, dict(ncell_padded=int(lay.ncell_padded), ncell_interior=int(lay.ncell_interior),
-                   nvar=int(lay.nvar), nghost=int(lay.nghost), x_offset=int(lay.x_offset),
+                   nvar=int(lay.nvar), nghost=int(lay.nghost), interior_first=int(lay.interior_first),
+                   x_offset=int(lay.x_offset),
                    x_align=int(lay.x_align), block_offset=off, block_interior_offset=ioff)
 
 
@@ -284,6 +286,7 @@ class Grid:
         self.off = lay["block_offset"]
         self.ioff = lay["block_interior_offset"]
         self.nvar = lay["nvar"]
+        self.interior_first = bool(lay["interior_first"])
         self.x_offset = lay["x_offset"]
         self.x_align = lay["x_align"]
         self.pdtype = torch.float32 if int(params["precision"]) == 1 else torch.float64
@@ -309,6 +312,9 @@ class Grid:
             xo, xa = self.x_offset, self.x_align
             for b, blk in enumerate(self.blocks):
                 s = blk[1:4]
+                if self.interior_first:
+                    parts.append(self.off[b] + np.arange(int(s[0]) * int(s[1]) * int(s[2]), dtype=np.int64))
+                    continue
                 gd = [g if e < nd else 0 for e in range(3)]
                 n0, n1 = -(-(xo + s[0] + gd[0]) // xa) * xa, s[1] + 2 * gd[1]
                 k, j, i = np.meshgrid(np.arange(s[2]), np.arange(s[1]), np.arange(s[0]), indexing="ij")

@@ -20,7 +20,7 @@ struct KParams {
     int g[3];
     int recon, flux;
     int nvar;                        // rows of P and U: NV, or NV + 1 with the entropy field
-    int xo;                          // x offset of the interior in a block's padded box
+    int po[3];                       // linear-index offsets of a block's local (0, 0, 0) per axis
 };
 
 // Time-step state and counters, resident on the device.

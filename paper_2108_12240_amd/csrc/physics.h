@@ -134,7 +134,7 @@ __device__ __forceinline__ bool cell_of(const DevBlock &B, int item, int &i, int
 
 __device__ __forceinline__ long long pad_index(const DevBlock &B, const KParams &kp, int i, int j, int k)
 {
-    return B.off + ((long long)(k + kp.g[2]) * B.n1 + (j + kp.g[1])) * B.n0 + (i + kp.xo);
+    return B.off + ((long long)(k + kp.po[2]) * B.n1 + (j + kp.po[1])) * B.n0 + (i + kp.po[0]);
 }
 
 template <bool KS>

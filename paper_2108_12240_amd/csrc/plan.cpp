@@ -110,6 +110,36 @@ bool bad(std::string &err, const std::string &msg)
     return false;
 }
 
+// Index of local position l of block D by the linear rule the kernels use
+// (strides 1, n0, n0 n1 from the padded origin): the position's slot when it lies
+// inside the block (in the box layout: anywhere in the box), and the base of the
+// halo shifts otherwise.
+long long linear_index(const Plan &P, const DevBlock &D, const int l[3])
+{
+    return D.off + ((long long)(l[2] + P.po[2]) * D.n1 + (l[1] + P.po[1])) * D.n0 + (l[0] + P.po[0]);
+}
+
+// Slot of local position l (interior cell or ghost slot) in block D's region of P.
+// Interior-first layout: the interior cells (x fastest), then the ghost slots of
+// the (size + 2g) box in box order (x fastest) with the interior skipped.
+long long slot_index(const Plan &P, const DevBlock &D, const int l[3])
+{
+    bool in = true;
+    for (int e = 0; e < 3; e++) in = in && l[e] >= 0 && l[e] < D.s[e];
+    if (!P.ifirst || in) return linear_index(P, D, l);
+    const int g0 = P.gd[0], g1 = P.gd[1], g2 = P.gd[2];
+    const long long n0 = D.s[0] + 2 * g0, n1 = D.s[1] + 2 * g1;
+    const int pi = l[0] + g0, pj = l[1] + g1, pk = l[2] + g2;
+    long long r = pk * n0 * n1 - (long long)D.s[0] * D.s[1] * std::clamp(pk - g2, 0, D.s[2]);
+    if (pk < g2 || pk >= D.s[2] + g2) {
+        r += pj * n0 + pi;
+    } else {
+        r += pj * n0 - (long long)D.s[0] * std::clamp(pj - g1, 0, D.s[1]);
+        r += (pj < g1 || pj >= D.s[1] + g1) ? pi : (pi < g0 ? pi : pi - D.s[0]);
+    }
+    return D.off + (long long)D.s[0] * D.s[1] * D.s[2] + r;
+}
+
 bool check_params(const bhac_params &p, std::string &err)
 {
     if (p.ndim != 2 && p.ndim != 3) return bad(err, "ndim must be 2 or 3");
@@ -164,13 +194,21 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     P.p = p;
     P.blocks.assign(blocks, blocks + nb);
     for (int e = 0; e < 3; e++) P.gd[e] = e < p.ndim ? p.nghost : 0;
-    // x rows of the padded box, double state: the interior starts and every row
-    // begins on a 128-byte line (16 doubles), so a 16-cell interior row is one
-    // whole line, read and written without partial lines. A float state keeps
-    // rows of size + 2g: a 16-cell float row is half a line, and aligning it only
-    // adds lines to the reads (measured slower)
-    P.xalign = p.precision == BHAC_PREC_MIXED ? 1 : 16;
-    P.xo = (P.gd[0] + P.xalign - 1) / P.xalign * P.xalign;
+    // State layout of a block's region of P. Independent patches (amr = 0): the
+    // interior cells first, contiguous and x fastest like U (every interior row of
+    // 16 cells then shares whole 128-byte lines with its neighbours, read and
+    // written without partial lines), then the ghost slots; the region is rounded
+    // to 32 elements so that every block starts on a line. Block trees keep the
+    // padded box, whose linear index extends to the ghost slots the cross-level
+    // halo reads: x rows of a double state are 128-byte lines (interior at slot 16),
+    // a float state keeps rows of size + 2g (a 16-cell float row is half a line
+    // either way; aligned float rows measured slower).
+    P.ifirst = !p.amr;
+    P.xalign = P.ifirst || p.precision == BHAC_PREC_MIXED ? 1 : 16;
+    P.xo = P.ifirst ? 0 : (P.gd[0] + P.xalign - 1) / P.xalign * P.xalign;
+    P.po[0] = P.xo;
+    P.po[1] = P.ifirst ? 0 : P.gd[1];
+    P.po[2] = P.ifirst ? 0 : P.gd[2];
 
     // blocks, lattice occupancy, layout
     std::unordered_map<Key, int, KeyHash> lattice;
@@ -207,12 +245,21 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
             D.o[e] = B.origin[e];
             if (B.size[e] > P.smax[e]) P.smax[e] = B.size[e];
         }
-        D.n0 = (P.xo + B.size[0] + P.gd[0] + P.xalign - 1) / P.xalign * P.xalign;
-        D.n1 = B.size[1] + 2 * P.gd[1];
+        long long ncell;
+        if (P.ifirst) {
+            D.n0 = B.size[0];
+            D.n1 = B.size[1];
+            const long long box =
+                (long long)(B.size[0] + 2 * P.gd[0]) * (B.size[1] + 2 * P.gd[1]) * (B.size[2] + 2 * P.gd[2]);
+            ncell = (box + 31) / 32 * 32;
+        } else {
+            D.n0 = (P.xo + B.size[0] + P.gd[0] + P.xalign - 1) / P.xalign * P.xalign;
+            D.n1 = B.size[1] + 2 * P.gd[1];
+            ncell = (long long)D.n0 * D.n1 * (B.size[2] + 2 * P.gd[2]);
+        }
         D.level = B.level;
         D.off = P.off[b];
         D.ioff = P.ncell_interior;
-        const long long ncell = (long long)D.n0 * D.n1 * (B.size[2] + 2 * P.gd[2]);
         P.off[b + 1] = P.off[b] + ncell;
         P.ncell_interior += (long long)B.size[0] * B.size[1] * B.size[2];
         P.ioff[b + 1] = P.ncell_interior;
@@ -394,13 +441,12 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     };
     auto padded_global = [&](int blk, const long long g[3]) -> int32_t {
         const DevBlock &Q = P.dblocks[blk];
-        long long li[3];
-        for (int e = 0; e < 3; e++) li[e] = g[e] - Q.o[e] + (e == 0 ? P.xo : P.gd[e]);
-        return (int32_t)(Q.off + (li[2] * Q.n1 + li[1]) * Q.n0 + li[0]);
+        int li[3];
+        for (int e = 0; e < 3; e++) li[e] = (int)(g[e] - Q.o[e]);
+        return (int32_t)slot_index(P, Q, li);
     };
     auto padded_local = [&](int blk, const int a[3]) -> int32_t {
-        const DevBlock &Q = P.dblocks[blk];
-        return (int32_t)(Q.off + ((long long)(a[2] + P.gd[2]) * Q.n1 + (a[1] + P.gd[1])) * Q.n0 + (a[0] + P.xo));
+        return (int32_t)slot_index(P, P.dblocks[blk], a);
     };
     const int nchild = p.ndim == 3 ? 8 : 4;
     // the 2^ndim cells of the level-(L+1) leaf fb under level-L cell Gi, z-outer
@@ -539,11 +585,10 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     std::unordered_map<long long, size_t> pindex[2];
     for (int64_t b = 0; b < nb; b++) {
         const DevBlock &D = P.dblocks[b];
-        const int n2 = D.s[2] + 2 * P.gd[2];
-        for (int pk = 0; pk < n2; pk++)
-            for (int pj = 0; pj < D.n1; pj++)
-                for (int pi = P.xo - P.gd[0]; pi < P.xo + D.s[0] + P.gd[0]; pi++) {
-                    const int l[3] = {pi - P.xo, pj - P.gd[1], pk - P.gd[2]};
+        for (int lk = -P.gd[2]; lk < D.s[2] + P.gd[2]; lk++)
+            for (int lj = -P.gd[1]; lj < D.s[1] + P.gd[1]; lj++)
+                for (int li = -P.gd[0]; li < D.s[0] + P.gd[0]; li++) {
+                    const int l[3] = {li, lj, lk};
                     int nout = 0;
                     for (int e = 0; e < 3; e++) nout += (l[e] < 0 || l[e] >= D.s[e]);
                     if (nout == 0) continue;
@@ -554,7 +599,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                         src[e] = h.src;
                     }
                     int sb = P.nbr[(size_t)b * 27 + (dir[0] + 1) + 3 * (dir[1] + 1) + 9 * (dir[2] + 1)];
-                    const long long to = D.off + ((long long)pk * D.n1 + pj) * D.n0 + pi;
+                    const long long to = slot_index(P, D, l);
                     int fe = 0;                                  // axis outside (face slots)
                     while (nout == 1 && l[fe] >= 0 && l[fe] < D.s[fe]) fe++;
                     const int fside = nout == 1 && l[fe] >= D.s[fe] ? 1 : 0;
@@ -597,19 +642,20 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
                         for (int e = 0; e < 3; e++) src[e] = std::min(std::max(l[e], 0), D.s[e] - 1);
                     }
                     const DevBlock &S = P.dblocks[sb];
-                    const long long from =
-                        S.off + ((long long)(src[2] + P.gd[2]) * S.n1 + (src[1] + P.gd[1])) * S.n0 + (src[0] + P.xo);
+                    const long long from = slot_index(P, S, src);
                     if (nout == 1) {
                         // the halo-side rule must name the same source cell
                         int e = 0;
                         while (l[e] >= 0 && l[e] < D.s[e]) e++;
                         const int side = l[e] < 0 ? 0 : 1;
                         const long long st = e == 0 ? 1 : (e == 1 ? (long long)D.n0 : (long long)D.n0 * D.n1);
+                        // the kernels address the halo from the linear index of l
+                        const long long lin = linear_index(P, D, l);
                         long long expect;
                         if (D.hclamp >> (2 * e + side) & 1)
-                            expect = to + (long long)((side == 0 ? 0 : D.s[e] - 1) - l[e]) * st;
+                            expect = lin + (long long)((side == 0 ? 0 : D.s[e] - 1) - l[e]) * st;
                         else
-                            expect = to + D.hshift[e][side];
+                            expect = lin + D.hshift[e][side];
                         if (expect != from) {
                             err = "internal: halo-side rule disagrees with the ghost gather map";
                             return BHAC_EINVAL;

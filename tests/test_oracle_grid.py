@@ -107,9 +107,8 @@ def test_periodic_wrap_closed_form_single_block():
     ids = np.arange(512, dtype=np.float64)
     P = G.pack(np.stack([ids] * 9))
     G.fill_ghosts(P)
-    n0 = L.box(p, (8, 8, 8))[0]
-    xo = L.origin(p)[0]
-    cube = P[0].reshape(14, 14, n0)[:, :, xo - 3:xo + 11]
+    K3, J3, I3 = np.meshgrid(np.arange(-3, 11), np.arange(-3, 11), np.arange(-3, 11), indexing="ij")
+    cube = P[0][L.pad_index(p, G.off[0], (8, 8, 8), I3, J3, K3)]
     w = (np.arange(14) - 3) % 8
     K, J, Ii = np.meshgrid(w, w, w, indexing="ij")
     assert np.array_equal(cube, (K * 64 + J * 8 + Ii).astype(np.float64))

@@ -135,11 +135,20 @@ def test_single_level_tree_equals_same_level_rule():
     rng = np.random.default_rng(5)
     G0 = O.OracleGrid(p0, c.blocks)
     G1 = O.OracleGrid(p1, c.blocks)
-    P = rng.standard_normal((9, G0.ncp))
-    A, B = P.copy(), P.copy()
+    # the two grids lay their blocks out differently: map every slot of the first
+    # layout to the same block-local position in the second
+    i0, i1 = [], []
+    for b, blk in enumerate(c.blocks):
+        x, y, z, pad = L.box_locals(p0, blk[1:4])
+        i0.append(G0.off[b] + np.nonzero(~pad)[0])
+        i1.append(L.pad_index(p1, G1.off[b], blk[1:4], x[~pad], y[~pad], z[~pad]))
+    i0, i1 = np.concatenate(i0), np.concatenate(i1)
+    A = rng.standard_normal((9, G0.ncp))
+    B = np.zeros((9, G1.ncp))
+    B[:, i1] = A[:, i0]
     G0.fill_ghosts(A)
     G1.fill_ghosts(B)
-    assert np.array_equal(A, B)
+    assert np.array_equal(A[:, i0], B[:, i1])
 
 
 @pytest.mark.parametrize("coef", [(0.7, 0.3, -0.2, 0.05), (-1.0, 0.0, 1.25, 0.5)])
