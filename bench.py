@@ -70,9 +70,9 @@ WORKLOADS = {
 # on; with any other sources the field is reported as null.
 TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
-    ("ks_torus_128_fp64_plain", "update"): (1165876507, "cf5d25e2b6d78454"),
-    ("ks_torus_128_mixed_plain", "update"): (838002731, "cf5d25e2b6d78454"),
-    ("ks_torus_128_mixed_auto", "update"): (838002731, "cf5d25e2b6d78454"),
+    ("ks_torus_128_fp64_plain", "update"): (1165920912, "653678c8ba11c8f1"),
+    ("ks_torus_128_mixed_plain", "update"): (773983520, "653678c8ba11c8f1"),
+    ("ks_torus_128_mixed_auto", "update"): (773983520, "653678c8ba11c8f1"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
@@ -82,14 +82,14 @@ TRAFFIC = {
 # 2.4 GHz = 39.3e12 lane-instructions/s (one wave64 instruction takes 4 cycles of
 # a 16-lane SIMD; FP64 and unpacked FP32 issue at the same rate).
 VALU = {
-    ("ks_torus_128_fp64_plain", "flux_x1"): (49151468, "cf5d25e2b6d78454"),
-    ("ks_torus_128_fp64_plain", "flux_x2"): (27173533, "cf5d25e2b6d78454"),
-    ("ks_torus_128_fp64_plain", "flux_x3"): (24585234, "cf5d25e2b6d78454"),
-    ("ks_torus_128_fp64_plain", "update"): (43317308, "cf5d25e2b6d78454"),
-    ("ks_torus_128_mixed_plain", "flux_x1"): (38483002, "cf5d25e2b6d78454"),
-    ("ks_torus_128_mixed_plain", "flux_x2"): (38671083, "cf5d25e2b6d78454"),
-    ("ks_torus_128_mixed_plain", "flux_x3"): (20349205, "cf5d25e2b6d78454"),
-    ("ks_torus_128_mixed_plain", "update"): (44890194, "cf5d25e2b6d78454"),
+    ("ks_torus_128_fp64_plain", "flux_x1"): (49151494, "653678c8ba11c8f1"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27173282, "653678c8ba11c8f1"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24585222, "653678c8ba11c8f1"),
+    ("ks_torus_128_fp64_plain", "update"): (43317340, "653678c8ba11c8f1"),
+    ("ks_torus_128_mixed_plain", "flux_x1"): (38483604, "653678c8ba11c8f1"),
+    ("ks_torus_128_mixed_plain", "flux_x2"): (38671206, "653678c8ba11c8f1"),
+    ("ks_torus_128_mixed_plain", "flux_x3"): (20349241, "653678c8ba11c8f1"),
+    ("ks_torus_128_mixed_plain", "update"): (44890166, "653678c8ba11c8f1"),
 }
 VALU_PEAK = 39.3e12      # lane-instructions/s
 
