@@ -241,6 +241,24 @@ def case_torus(cfg: int, n=128, bs: int = 16, precision=None, fused=None, phi_sl
     return Case(f"case{cfg}_ks_torus_{n[0]}x{n[1]}x{n[2]}", params, blocks, prim, ioff, steps)
 
 
+def case_torus_2d(n=(64, 64), bs: int = 16, precision=PREC_FP64, seed: int = 12250) -> Case:
+    """The synthetic torus on an axisymmetric (ln r, theta) grid: ndim = 2 in the
+    Kerr-Schild metric, n[0] x n[1] cells in blocks of bs x bs (phi is not resolved)."""
+    assert n[0] % bs == 0 and n[1] % bs == 0
+    rng = np.random.default_rng(seed)
+    x_lo, x_hi = ks_domain()
+    params = base_params(ndim=2, x_lo=x_lo, x_hi=x_hi, ncell0=[n[0], n[1], 1], precision=precision,
+                         bc=[[BC_OUTFLOW, BC_OUTFLOW], [BC_OUTFLOW, BC_OUTFLOW], [BC_PERIODIC, BC_PERIODIC]])
+    blocks = np.array([[0, bs, bs, 1, b0 * bs, b1 * bs, 0] for b0 in range(n[0] // bs)
+                       for b1 in range(n[1] // bs)], dtype=np.int32)
+    ioff = _ioff(blocks)
+    noise = rng.uniform(size=int(ioff[-1]))
+    g = [np.concatenate(v) for v in zip(*(_block_cells(b) for b in blocks))]
+    prim, r, th = _torus_cells(params, 0, g[0], g[1], g[2], noise)
+    prim = _finish_torus(prim, r)
+    return Case(f"ks_torus_2d_{n[0]}x{n[1]}", params, blocks, prim, ioff, steps=10)
+
+
 def _add_turbulence(params, prim, r, th, g, n, rng):
     """Seeded velocity field at Mach 0.3 of the Newtonian sound speed, torus cells only."""
     nm = 32

@@ -74,3 +74,4 @@ def test_second_order_convergence_on_advected_wave(recon, order):
         errs.append(np.abs(rho - exact).mean())
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(rates) >= order, (errs, rates)
+
