@@ -15,10 +15,14 @@ namespace bhac {
 
 // ---------------------------------------------------------------------------------
 // Ghost fill: one thread per ghost slot copies the NQ rows (bit-exact copies).
+// Pin and Pout are the same state: the kernel reads interior cells and writes ghost
+// slots only, so the two views never meet and every row's load can be issued
+// before the first store.
 // ---------------------------------------------------------------------------------
 template <typename T, int NQ>
 __global__ __launch_bounds__(WG) void k_fill(const int32_t *__restrict__ dst, const int32_t *__restrict__ src,
-                                             long long n, T *__restrict__ P, long long ncp)
+                                             long long n, const T *__restrict__ Pin, T *__restrict__ Pout,
+                                             long long ncp)
 {
     // XCD-ordered chunks: XCD x copies the contiguous slot range of chunks [x per, (x+1) per)
     const unsigned per = (gridDim.x + NXCD - 1) / NXCD;
@@ -27,7 +31,7 @@ __global__ __launch_bounds__(WG) void k_fill(const int32_t *__restrict__ dst, co
     if (i >= n) return;
     const long long d = dst[i], s = src[i];
 #pragma unroll
-    for (int v = 0; v < NQ; v++) P[v * ncp + d] = P[v * ncp + s];
+    for (int v = 0; v < NQ; v++) Pout[v * ncp + d] = Pin[v * ncp + s];
 }
 
 // ---------------------------------------------------------------------------------
@@ -37,7 +41,8 @@ __global__ __launch_bounds__(WG) void k_fill(const int32_t *__restrict__ dst, co
 // (restriction), or [1, nchildren, coarse cell, the counts of the lower and upper
 // neighbour per axis (0 = no slope), the neighbours' cells, then (dst, upper-half
 // bits) per child] (prolongation of the ghost cells of one block that lie in one
-// coarse cell, which share its slopes).
+// coarse cell, which share its slopes). Pin and Pout are the same state, read at
+// interior cells and written at ghost slots only.
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ double minmod_xl(double a, double b)
 {
@@ -46,26 +51,35 @@ __device__ __forceinline__ double minmod_xl(double a, double b)
     return 0.0;
 }
 
-template <typename R>
-__device__ __forceinline__ double mean_of(const R *__restrict__ row, const int32_t *__restrict__ idx, int n)
+// mean of the NC cells listed at idx (restriction of 2^ndim fine cells), summed in
+// double in list order; the count is a compile-time constant, so all the loads of
+// a variable (and, the views being disjoint, of all variables) are issued at once
+template <int NC, typename R>
+__device__ __forceinline__ double mean_n(const R *__restrict__ row, const int32_t *__restrict__ idx)
 {
     double sum = 0.0;
-    for (int q = 0; q < n; q++) sum += (double)row[idx[q]];
-    return n == 1 ? sum : sum * (n == 8 ? 0.125 : 0.25);
+#pragma unroll
+    for (int q = 0; q < NC; q++) sum += (double)row[idx[q]];
+    return sum * (NC == 8 ? 0.125 : 0.25);
 }
 
-template <typename R>
+template <typename R, int ND>
 __global__ __launch_bounds__(WG) void k_fill_xl(const int32_t *__restrict__ xoff, const int32_t *__restrict__ xdat,
-                                                long long n, int ndim, R *__restrict__ P, long long ncp)
+                                                long long n, const R *__restrict__ Pin, R *__restrict__ Pout,
+                                                long long ncp)
 {
 #pragma clang fp contract(off)
+    constexpr int NC = ND == 3 ? 8 : 4;           // fine cells per coarse cell
     const long long q = (long long)blockIdx.x * WG + threadIdx.x;
     if (q >= n) return;
     const int32_t *r = xdat + xoff[q];
     if (r[0] == 0) {
-        const int nc = ndim == 3 ? 8 : 4;
+        int32_t idx[NC];
 #pragma unroll
-        for (int v = 0; v < NV; v++) P[v * ncp + r[1]] = (R)mean_of(P + v * ncp, r + 2, nc);
+        for (int k = 0; k < NC; k++) idx[k] = r[2 + k];
+        const int32_t dst = r[1];
+#pragma unroll
+        for (int v = 0; v < NV; v++) Pout[v * ncp + dst] = (R)mean_n<NC>(Pin + v * ncp, idx);
         return;
     }
     const int nk = r[1];
@@ -79,24 +93,30 @@ __global__ __launch_bounds__(WG) void k_fill_xl(const int32_t *__restrict__ xoff
         pos += cnt[k];
     }
     const int32_t *kids = r + pos;
+    // a neighbour of the coarse cell is one cell (count 1) or the restriction of
+    // NC fine cells (count NC); count 0 means no slope along that axis
+    auto neighbour = [&](const R *__restrict__ row, int k) -> double {
+        return cnt[k] == 1 ? (double)row[r[at[k]]] : mean_n<NC>(row, r + at[k]);
+    };
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-        const R *row = P + v * ncp;
+        const R *row = Pin + v * ncp;
         const double qc = (double)row[c];
         double sl[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int d = 0; d < 3; d++) {
-            if (d < ndim && cnt[2 * d] > 0 && cnt[2 * d + 1] > 0) {
-                const double lo = mean_of(row, r + at[2 * d], cnt[2 * d]);
-                const double hi = mean_of(row, r + at[2 * d + 1], cnt[2 * d + 1]);
+        for (int d = 0; d < ND; d++) {
+            if (cnt[2 * d] > 0 && cnt[2 * d + 1] > 0) {
+                const double lo = neighbour(row, 2 * d);
+                const double hi = neighbour(row, 2 * d + 1);
                 sl[d] = minmod_xl(qc - lo, hi - qc);
             }
         }
         for (int k = 0; k < nk; k++) {
             const int bits = kids[2 * k + 1];
             double val = qc;
-            for (int d = 0; d < ndim; d++) val += (((bits >> d) & 1) ? 0.25 : -0.25) * sl[d];
-            P[v * ncp + kids[2 * k]] = (R)val;
+#pragma unroll
+            for (int d = 0; d < ND; d++) val += (((bits >> d) & 1) ? 0.25 : -0.25) * sl[d];
+            Pout[v * ncp + kids[2 * k]] = (R)val;
         }
     }
 }
@@ -106,22 +126,31 @@ __global__ __launch_bounds__(WG) void k_fill_xl(const int32_t *__restrict__ xoff
 // which takes the mean of the fine faces covering it (records [direction, coarse
 // face, 4 fine faces], 2 used in 2-D), summed in double in record order.
 // ---------------------------------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(WG) void k_flux_fix(const int32_t *__restrict__ fx, long long n, int nsub,
-                                                 R *F0, R *F1, R *F2, long long nf0, long long nf1, long long nf2)
+template <typename R, int NSUB>
+__global__ __launch_bounds__(WG) void k_flux_fix(const int32_t *__restrict__ fx, long long n,
+                                                 const R *__restrict__ F0i, const R *__restrict__ F1i,
+                                                 const R *__restrict__ F2i, R *__restrict__ F0o, R *__restrict__ F1o,
+                                                 R *__restrict__ F2o, long long nf0, long long nf1, long long nf2)
 {
     const long long t = (long long)blockIdx.x * WG + threadIdx.x;
     if (t >= n) return;
     const int32_t *r = fx + 6 * t;
     const int d = r[0];
-    R *F = d == 0 ? F0 : (d == 1 ? F1 : F2);
+    // a face is written by at most one record and never read by another (its far
+    // side is either finer or coarser), so the input and output views never meet
+    const R *Fi = d == 0 ? F0i : (d == 1 ? F1i : F2i);
+    R *Fo = d == 0 ? F0o : (d == 1 ? F1o : F2o);
     const long long nf = d == 0 ? nf0 : (d == 1 ? nf1 : nf2);
-    const double w = nsub == 4 ? 0.25 : 0.5;
+    constexpr double w = NSUB == 4 ? 0.25 : 0.5;
+    int32_t fine[NSUB];
+#pragma unroll
+    for (int q = 0; q < NSUB; q++) fine[q] = r[2 + q];
 #pragma unroll
     for (int v = 0; v < NV; v++) {
         double sum = 0.0;
-        for (int q = 0; q < nsub; q++) sum += (double)F[v * nf + r[2 + q]];
-        F[v * nf + r[1]] = (R)(sum * w);
+#pragma unroll
+        for (int q = 0; q < NSUB; q++) sum += (double)Fi[v * nf + fine[q]];
+        Fo[v * nf + r[1]] = (R)(sum * w);
     }
 }
 
@@ -584,10 +613,12 @@ hipError_t launch_fill_copies(const DeviceGrid &G, void *P, hipStream_t s, bool 
     const bool ent = G.kp.nvar > NV;
     if (G.mixed) {
         auto kern = ent ? k_fill<float, NV + 1> : k_fill<float, NV>;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (float *)P, G.kp.ncp);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (const float *)P, (float *)P,
+                           G.kp.ncp);
     } else {
         auto kern = ent ? k_fill<double, NV + 1> : k_fill<double, NV>;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (double *)P, G.kp.ncp);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, s, G.d_gdst, G.d_gsrc, n, (const double *)P, (double *)P,
+                           G.kp.ncp);
     }
     return hipGetLastError();
 }
@@ -597,12 +628,16 @@ hipError_t launch_fill_cross(const DeviceGrid &G, void *P, hipStream_t s, bool f
     const long long n = faces_only ? G.nxl_face : G.nxl;
     if (n == 0) return hipSuccess;
     TimedLaunch tl(G.timer, K_FILL_XL, s);
-    if (G.mixed)
-        hipLaunchKernelGGL(k_fill_xl<float>, dim3(nblk(n)), dim3(WG), 0, s, G.d_xoff, G.d_xdat, n, G.kp.ndim,
-                           (float *)P, G.kp.ncp);
-    else
-        hipLaunchKernelGGL(k_fill_xl<double>, dim3(nblk(n)), dim3(WG), 0, s, G.d_xoff, G.d_xdat, n, G.kp.ndim,
+    const bool nd3 = G.kp.ndim == 3;
+    if (G.mixed) {
+        auto kern = nd3 ? k_fill_xl<float, 3> : k_fill_xl<float, 2>;
+        hipLaunchKernelGGL(kern, dim3(nblk(n)), dim3(WG), 0, s, G.d_xoff, G.d_xdat, n, (const float *)P, (float *)P,
+                           G.kp.ncp);
+    } else {
+        auto kern = nd3 ? k_fill_xl<double, 3> : k_fill_xl<double, 2>;
+        hipLaunchKernelGGL(kern, dim3(nblk(n)), dim3(WG), 0, s, G.d_xoff, G.d_xdat, n, (const double *)P,
                            (double *)P, G.kp.ncp);
+    }
     return hipGetLastError();
 }
 
@@ -761,8 +796,10 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
     }
     if (e == hipSuccess && G.nffix > 0) {
         TimedLaunch tl(G.timer, K_FLUX_FIX, s);
-        hipLaunchKernelGGL(k_flux_fix<R>, dim3(nblk(G.nffix)), dim3(WG), 0, s, G.d_ffix, G.nffix,
-                           G.kp.ndim == 3 ? 4 : 2, (R *)G.d_flux[0], (R *)G.d_flux[1], (R *)G.d_flux[2],
+        auto kern = G.kp.ndim == 3 ? k_flux_fix<R, 4> : k_flux_fix<R, 2>;
+        hipLaunchKernelGGL(kern, dim3(nblk(G.nffix)), dim3(WG), 0, s, G.d_ffix, G.nffix,
+                           (const R *)G.d_flux[0], (const R *)G.d_flux[1],
+                           (const R *)G.d_flux[2], (R *)G.d_flux[0], (R *)G.d_flux[1], (R *)G.d_flux[2],
                            G.plan.nface[0], G.plan.nface[1], G.plan.nface[2]);
         e = hipGetLastError();
     }
