@@ -29,20 +29,13 @@
  *    u~2, u~3 (Lorentz factor times Eulerian 3-velocity, contravariant), p, B1,
  *    B2, B3 (Eulerian magnetic field), psi (GLM scalar); each row has
  *    ncell_padded entries and block b occupies [block_offset[b],
- *    block_offset[b+1]). Its cells and ghost slots: the (size + 2g) box around the
- *    block, g ghost layers on each side of every axis in use (for ndim = 2 the z
- *    extent is 1 with no ghosts). Two arrangements (bhac_layout.interior_first):
- *    independent patches (amr = 0): interior first — the block's interior cells,
- *    x fastest, then y, then z (as in U), followed by its ghost slots in box order
- *    (x fastest, the interior skipped), the region rounded up to a multiple of 32
- *    slots; with a 128-byte aligned state pointer every block then starts on a
- *    128-byte line and consecutive interior rows fill whole lines. Block trees
- *    (amr = 1): the padded box, x fastest, then y, then z; along y and z it is
- *    size + 2g, along x each row holds n0 = roundup(x_offset + size + g, x_align)
- *    slots with the interior starting at slot x_offset = roundup(g, x_align);
- *    x_align is 16 for a double state (rows of 128-byte lines) and 1 for a float
- *    state (rows of size + 2g). The g slots on either side of the interior are
- *    the x ghost layers; the rest of a row, and of a rounded region, is padding
+ *    block_offset[b+1]): first its interior cells, x fastest, then y, then z
+ *    (as in U), then the ghost slots of its (size + 2g) box (g ghost layers on
+ *    each side of every axis in use; for ndim = 2 the z extent is 1 with no
+ *    ghosts) in box order, x fastest, the interior skipped; the region is
+ *    rounded up to a multiple of 32 slots. With a 128-byte aligned state
+ *    pointer every block starts on a 128-byte line and consecutive interior
+ *    rows fill whole lines. The slots after a block's ghost slots are padding
  *    that no call reads or writes. Conserved U: rows
  *    sqrt(gamma) * (D, S_1, S_2, S_3, tau, B1, B2, B3), psi; conserved variables
  *    need no ghost cells, so each row has ncell_interior entries and block b
@@ -177,9 +170,6 @@ typedef struct bhac_layout {
     int64_t ncell_interior;
     int nvar;
     int nghost;
-    int interior_first; /* 1: interior-first block regions, 0: padded boxes (see above) */
-    int x_offset;       /* padded boxes: slot of the first interior cell in an x row */
-    int x_align;        /* padded boxes: x rows' pitch and x_offset are multiples of this */
     const int64_t *block_offset;
     const int64_t *block_interior_offset;
 } bhac_layout;

@@ -45,8 +45,6 @@ typedef struct {
     int c2p_maxit;
     int amr;                           /* 0 independent same-level patches, 1 2:1 block tree */
     int entropy;                       /* 1: carry the entropy field (P[9] = K, U[9] = U[0] K) */
-    int precision;                     /* 0 double, 1 float state: sets only the x alignment of the
-                                          padded layout (the oracle computes in double) */
 } orc_params;
 
 /* rows of P and U: the nine GRMHD variables, plus the entropy field if carried */
@@ -621,28 +619,11 @@ typedef struct {
 } orc_grid;
 
 /* Where a block's cells and ghost slots sit in P (data contract shared with the
- * library). Independent patches: interior first -- the block's interior cells (x
- * fastest), then the ghost slots of its (size + 2g) box in box order with the
- * interior skipped, the region rounded up to 32 slots. Block trees: the padded
- * box -- g ghost layers per side along y and z; along x the interior starts at
- * slot xo = roundup(g, A) and a row holds roundup(xo + size + g, A) slots, A = 16
- * for a double state and 1 for a float state. Unnamed slots are padding. */
-static int interior_first(const orc_grid *G) { return !G->p.amr; }
-
-static int xalign(const orc_grid *G) { return interior_first(G) || G->p.precision == 1 ? 1 : 16; }
-
-static int x_offset(const orc_grid *G)
-{
-    const int a = xalign(G);
-    return (G->gd[0] + a - 1) / a * a;
-}
-
+ * library): the block's interior cells first (x fastest), then the ghost slots of
+ * its (size + 2g) box in box order with the interior skipped, the region rounded
+ * up to 32 slots (the rest is padding). */
 static int64_t ncell_axis(const orc_grid *G, int b, int e)
 {
-    if (e == 0) {
-        const int a = xalign(G);
-        return (x_offset(G) + G->blk[b].size[0] + G->gd[0] + a - 1) / a * a;
-    }
     return G->blk[b].size[e] + 2 * G->gd[e];
 }
 
@@ -650,17 +631,13 @@ static int64_t ncell_axis(const orc_grid *G, int b, int e)
 static int64_t region_size(const orc_grid *G, int b)
 {
     const int64_t box = ncell_axis(G, b, 0) * ncell_axis(G, b, 1) * ncell_axis(G, b, 2);
-    return interior_first(G) ? (box + 31) / 32 * 32 : box;
+    return (box + 31) / 32 * 32;
 }
 
 static int64_t pad_index(const orc_grid *G, int b, int i, int j, int k)
 {
     /* i, j, k: local indices, interior is [0, size) */
     const orc_block *B = &G->blk[b];
-    if (!interior_first(G)) {
-        const int64_t n0 = ncell_axis(G, b, 0), n1 = ncell_axis(G, b, 1);
-        return G->off[b] + ((int64_t)(k + G->gd[2]) * n1 + (j + G->gd[1])) * n0 + (i + x_offset(G));
-    }
     const int s0 = B->size[0], s1 = B->size[1], s2 = B->size[2];
     if (i >= 0 && i < s0 && j >= 0 && j < s1 && k >= 0 && k < s2)
         return G->off[b] + ((int64_t)k * s1 + j) * s0 + i;

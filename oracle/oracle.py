@@ -18,21 +18,6 @@ LIB = os.path.join(HERE, "liboracle.so")
 NV = 9
 
 
-def interior_first(params: dict) -> bool:
-    """Independent patches store each block's interior cells first, block trees
-    store padded boxes."""
-    return not int(params.get("amr", 0))
-
-
-def padded_x(params: dict):
-    """Padded boxes: (x alignment, x offset of the interior): 16 for a double
-    state (128-byte rows), 1 for a float state; the offset is the ghost depth
-    rounded up to it."""
-    xa = 1 if interior_first(params) or int(params.get("precision", 0)) == 1 else 16
-    g = int(params["nghost"])
-    return xa, -(-g // xa) * xa
-
-
 def nvar(params: dict) -> int:
     """Rows of P and U: nine GRMHD variables, plus the entropy field if carried."""
     return NV + (1 if int(params.get("entropy", 0)) else 0)
@@ -56,7 +41,7 @@ class Params(C.Structure):
                 ("recon", C.c_int), ("flux", C.c_int),
                 ("cfl", C.c_double), ("rho_floor", C.c_double), ("p_floor", C.c_double),
                 ("w_max", C.c_double), ("glm_alpha", C.c_double), ("c2p_tol", C.c_double),
-                ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int), ("precision", C.c_int)]
+                ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int)]
 
 
 class Block(C.Structure):
@@ -115,7 +100,6 @@ def make_params(d: dict) -> Params:
         setattr(p, k, int(d[k]))
     p.amr = int(d.get("amr", 0))
     p.entropy = int(d.get("entropy", 0))
-    p.precision = int(d.get("precision", 0))
     for k in ("spin", "gamma_ad", "cfl", "rho_floor", "p_floor", "w_max", "glm_alpha", "c2p_tol"):
         setattr(p, k, float(d[k]))
     for e in range(3):
@@ -178,22 +162,12 @@ class OracleGrid:
 
     # --- data marshalling ------------------------------------------------------------
     def interior_index(self) -> np.ndarray:
-        """Padded-cell index of every interior cell, in interior-packed order."""
+        """Index in P of every interior cell, in interior-packed order (each block's
+        interior cells lead its region, x fastest)."""
         if self._pidx is None:
-            g = int(self.params["nghost"])
-            nd = int(self.params["ndim"])
-            xa, xo = padded_x(self.params)
-            parts = []
-            for b in range(self.nb):
-                s = self.blocks[b, 1:4]
-                if interior_first(self.params):
-                    parts.append(self.off[b] + np.arange(int(np.prod(s)), dtype=np.int64))
-                    continue
-                gd = [g if e < nd else 0 for e in range(3)]
-                n0, n1 = -(-(xo + s[0] + gd[0]) // xa) * xa, s[1] + 2 * gd[1]
-                k, j, i = np.meshgrid(np.arange(s[2]), np.arange(s[1]), np.arange(s[0]), indexing="ij")
-                parts.append(self.off[b] + ((k + gd[2]) * n1 + (j + gd[1])) * n0 + (i + xo))
-            self._pidx = np.concatenate([p.ravel() for p in parts]).astype(np.int64)
+            parts = [self.off[b] + np.arange(int(np.prod(self.blocks[b, 1:4])), dtype=np.int64)
+                     for b in range(self.nb)]
+            self._pidx = np.concatenate(parts).astype(np.int64)
         return self._pidx
 
     def pack(self, interior: np.ndarray) -> np.ndarray:

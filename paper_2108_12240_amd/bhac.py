@@ -48,9 +48,7 @@ class bhac_block_desc(C.Structure):
 
 class bhac_layout(C.Structure):
     _fields_ = [("ncell_padded", C.c_int64), ("ncell_interior", C.c_int64), ("nvar", C.c_int),
-                ("nghost", C.c_int), ("interior_first", C.c_int), ("x_offset", C.c_int),
-                ("x_align", C.c_int),
-                ("block_offset", C.POINTER(C.c_int64)),
+                ("nghost", C.c_int), ("block_offset", C.POINTER(C.c_int64)),
                 ("block_interior_offset", C.POINTER(C.c_int64))]
 
 
@@ -173,9 +171,7 @@ def bhac_alloc_blocks(params: dict, blocks: np.ndarray):
     off = np.ctypeslib.as_array(lay.block_offset, shape=(len(arr) + 1,)).copy()
     ioff = np.ctypeslib.as_array(lay.block_interior_offset, shape=(len(arr) + 1,)).copy()
     return h, dict(ncell_padded=int(lay.ncell_padded), ncell_interior=int(lay.ncell_interior),
-                   nvar=int(lay.nvar), nghost=int(lay.nghost), interior_first=int(lay.interior_first),
-                   x_offset=int(lay.x_offset),
-                   x_align=int(lay.x_align), block_offset=off, block_interior_offset=ioff)
+                   nvar=int(lay.nvar), nghost=int(lay.nghost), block_offset=off, block_interior_offset=ioff)
 
 
 def bhac_free_blocks(h):
@@ -286,9 +282,6 @@ class Grid:
         self.off = lay["block_offset"]
         self.ioff = lay["block_interior_offset"]
         self.nvar = lay["nvar"]
-        self.interior_first = bool(lay["interior_first"])
-        self.x_offset = lay["x_offset"]
-        self.x_align = lay["x_align"]
         self.pdtype = torch.float32 if int(params["precision"]) == 1 else torch.float64
         self._pidx = None
 
@@ -304,21 +297,11 @@ class Grid:
             pass
 
     def interior_index(self) -> np.ndarray:
-        """Padded index of every interior cell, interior-packed order (block-major, x fastest)."""
+        """Index in P of every interior cell, interior-packed order (block-major, x
+        fastest): each block's interior cells lead its region of P."""
         if self._pidx is None:
-            g = int(self.params["nghost"])
-            nd = int(self.params["ndim"])
-            parts = []
-            xo, xa = self.x_offset, self.x_align
-            for b, blk in enumerate(self.blocks):
-                s = blk[1:4]
-                if self.interior_first:
-                    parts.append(self.off[b] + np.arange(int(s[0]) * int(s[1]) * int(s[2]), dtype=np.int64))
-                    continue
-                gd = [g if e < nd else 0 for e in range(3)]
-                n0, n1 = -(-(xo + s[0] + gd[0]) // xa) * xa, s[1] + 2 * gd[1]
-                k, j, i = np.meshgrid(np.arange(s[2]), np.arange(s[1]), np.arange(s[0]), indexing="ij")
-                parts.append((self.off[b] + ((k + gd[2]) * n1 + (j + gd[1])) * n0 + (i + xo)).ravel())
+            parts = [self.off[b] + np.arange(int(np.prod(blk[1:4])), dtype=np.int64)
+                     for b, blk in enumerate(self.blocks)]
             self._pidx = np.concatenate(parts).astype(np.int64)
         return self._pidx
 

@@ -163,7 +163,6 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     kp.flux = p.flux;
     kp.nvar = bhac::NV + (p.entropy ? 1 : 0);
     for (int d = 0; d < 3; d++) kp.g[d] = P.gd[d];
-    for (int d = 0; d < 3; d++) kp.po[d] = P.po[d];
     kp.ncp = P.off.back();
     kp.nci = P.ncell_interior;
     const bhac::DevLevel &fine = P.levels[P.maxlevel];
@@ -250,9 +249,6 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
         layout->ncell_interior = P.ncell_interior;
         layout->nvar = G.kp.nvar;
         layout->nghost = p.nghost;
-        layout->interior_first = P.ifirst ? 1 : 0;
-        layout->x_offset = P.xo;
-        layout->x_align = P.xalign;
         layout->block_offset = P.off.data();
         layout->block_interior_offset = P.ioff.data();
     }

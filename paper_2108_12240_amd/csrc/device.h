@@ -20,7 +20,6 @@ struct KParams {
     int g[3];
     int recon, flux;
     int nvar;                        // rows of P and U: NV, or NV + 1 with the entropy field
-    int po[3];                       // linear-index offsets of a block's local (0, 0, 0) per axis
 };
 
 // Time-step state and counters, resident on the device.

@@ -68,7 +68,7 @@ __device__ __forceinline__ long long gather_index(const GridDev &gd, const KPara
         sj = clampi(lj, 0, B.s[1] - 1);
         sk = clampi(lk, 0, B.s[2] - 1);
     }
-    return off + ((long long)(sk + kp.po[2]) * B.n1 + (sj + kp.po[1])) * B.n0 + (si + kp.po[0]);
+    return off + ((long long)sk * B.n1 + sj) * B.n0 + si;
 }
 
 __device__ __forceinline__ void load_cell(const float *__restrict__ P, long long ncp, long long c, float *q)
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(FWG, 2) void k_block_flux(KParams kp, GridDev gd, i
         for (int m = 0; m < 6; m++) {
             const int lk = m - 3;
             const long long c = (lk >= 0 && lk < s2)
-                                    ? B.off + ((long long)(lk + kp.po[2]) * B.n1 + (j + kp.po[1])) * B.n0 + (i + kp.po[0])
+                                    ? B.off + ((long long)lk * B.n1 + j) * B.n0 + i
                                     : gather_index(gd, kp, b, B, i, j, lk);
             load_cell(P, ncp, c, w[m]);
         }
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(FWG, 2) void k_block_flux(KParams kp, GridDev gd, i
         }
     }
     auto own_index = [&](int lk) -> long long {
-        return (lk >= 0 && lk < s2) ? B.off + ((long long)(lk + kp.po[2]) * B.n1 + (j + kp.po[1])) * B.n0 + (i + kp.po[0])
+        return (lk >= 0 && lk < s2) ? B.off + ((long long)lk * B.n1 + j) * B.n0 + i
                                     : gather_index(gd, kp, b, B, i, j, lk);
     };
     // loads for plane 0 (prefetched one plane ahead from here on)

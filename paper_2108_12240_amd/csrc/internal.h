@@ -72,10 +72,6 @@ constexpr int MARCH_MAX_FACES = 17;
 struct HaloAxis { signed char dir; signed char pad; short src; };
 
 struct Plan {
-    bool ifirst = true;                  // interior-first block regions (else padded boxes)
-    int xo = 0;                          // padded box: x offset of a block's interior
-    int xalign = 1;                      // padded box: x rows' pitch and interior start in elements
-    int po[3] = {0, 0, 0};               // linear-index offsets of local (0, 0, 0) per axis
     bhac_params p{};
     std::vector<bhac_block_desc> blocks;
     std::vector<int64_t> off;            // padded offsets, nb + 1

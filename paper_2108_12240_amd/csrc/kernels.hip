@@ -172,7 +172,9 @@ constexpr int flux_occupancy()
     return sizeof(R) == 4 ? BHAC_FLUX_OCC_F32 : (RECON == BHAC_RECON_MC ? BHAC_FLUX_OCC_F64 - 1 : BHAC_FLUX_OCC_F64);
 }
 
-template <typename R, int D, int RECON, int FLUX, bool KS>
+// XL (block trees): a halo side marked cross-level is read from the block's own
+// ghost slots (which the substep refreshes first), reached by the slot rule.
+template <typename R, int D, int RECON, int FLUX, bool KS, bool XL>
 __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
                                              const R *__restrict__ P, R *__restrict__ F, long long nftot)
 {
@@ -205,6 +207,13 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KPara
             const long long lo = clo ? pc - f * st : in + B.hshift[D][0];
             const long long hi = chi ? pc + (sD - 1 - f) * st : in + B.hshift[D][1];
             cell[s] = l < 0 ? lo : (l >= sD ? hi : in);
+            if constexpr (XL) {
+                if ((l < 0 && ((B.hxl >> (2 * D)) & 1)) || (l >= sD && ((B.hxl >> (2 * D + 1)) & 1))) {
+                    int q[3] = {i, j, k};
+                    q[D] = l;
+                    cell[s] = ghost_slot(B, kp, q[0], q[1], q[2]);
+                }
+            }
         }
         // In float the reconstruction is branch-free and every stencil load of the
         // face is written first, so all of them are in flight before the first wait.
@@ -249,7 +258,7 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KPara
 // Along x1 a face's stencil lies in one padded row, so without staging every
 // load instruction of a wave touches several rows and the neighbours' halo lines.
 // ---------------------------------------------------------------------------------
-template <typename R, int RECON, int FLUX, bool KS>
+template <typename R, int RECON, int FLUX, bool KS, bool XL>
 __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(KParams kp, GridDev gd,
                                                                             const WorkItem *__restrict__ work,
                                                                             const R *__restrict__ P,
@@ -272,6 +281,10 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(K
         long long c = base + l;
         if (l < 0) c = clo ? base : c + B.hshift[0][0];
         else if (l >= s0) c = chi ? base + s0 - 1 : c + B.hshift[0][1];
+        if constexpr (XL) {
+            if ((l < 0 && (B.hxl & 1)) || (l >= s0 && ((B.hxl >> 1) & 1)))
+                c = ghost_slot(B, kp, l, row % B.s[1], row / B.s[1]);
+        }
 #pragma unroll
         for (int v = 0; v < NV; v++) tile[v][t] = P[v * kp.ncp + c];
     }
@@ -721,13 +734,16 @@ static hipError_t flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
 {
     const std::vector<WorkItem> &w = G.plan.wface[D];
     TimedLaunch tl(G.timer, K_FLUX0 + D, s);
+    const bool xl = G.plan.p.amr != 0;
     if (D == 0 && G.plan.x1_staged) {
-        hipLaunchKernelGGL((k_flux_x1s<R, RECON, FLUX, KS>), dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd,
-                           G.d_wface[0], (const R *)Ps, (R *)G.d_flux[0], G.plan.nface[0]);
+        auto kern = xl ? k_flux_x1s<R, RECON, FLUX, KS, true> : k_flux_x1s<R, RECON, FLUX, KS, false>;
+        hipLaunchKernelGGL(kern, dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[0], (const R *)Ps,
+                           (R *)G.d_flux[0], G.plan.nface[0]);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_flux<R, D, RECON, FLUX, KS>), dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D],
-                       (const R *)Ps, (R *)G.d_flux[D], G.plan.nface[D]);
+    auto kern = xl ? k_flux<R, D, RECON, FLUX, KS, true> : k_flux<R, D, RECON, FLUX, KS, false>;
+    hipLaunchKernelGGL(kern, dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D], (const R *)Ps,
+                       (R *)G.d_flux[D], G.plan.nface[D]);
     return hipGetLastError();
 }
 

@@ -18,7 +18,9 @@
 
 namespace bhac {
 
-template <typename R, int D, int RECON, int FLUX, bool KS>
+// XL (block trees): a halo side marked cross-level is read from the block's own
+// ghost slots (which the substep refreshes first), reached by the slot rule.
+template <typename R, int D, int RECON, int FLUX, bool KS, bool XL>
 __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KParams kp, GridDev gd, const MarchItem *__restrict__ work,
                                                     const R *__restrict__ P, R *__restrict__ F, long long nftot)
 {
@@ -46,6 +48,13 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
         // padded index of cell l of the line (l in [-3, sD + 2])
         auto cell = [&](int l) -> long long {
             const long long in = base + l * st;
+            if constexpr (XL) {
+                if ((l < 0 && ((B.hxl >> (2 * D)) & 1)) || (l >= sD && ((B.hxl >> (2 * D + 1)) & 1))) {
+                    int q[3] = {ix[0], ix[1], ix[2]};
+                    q[D] = l;
+                    return ghost_slot(B, kp, q[0], q[1], q[2]);
+                }
+            }
             if (l < 0) return clo ? base : in + sh_lo;
             if (l >= sD) return chi ? base + (sD - 1) * st : in + sh_hi;
             return in;
@@ -191,8 +200,9 @@ hipError_t launch_flux_march_typed(const DeviceGrid &G, const void *Ps, hipStrea
 {
     const std::vector<MarchItem> &w = G.plan.wmarch[D];
     TimedLaunch tl(G.timer, K_FLUX0 + D, s);
-    hipLaunchKernelGGL((k_flux_march<R, D, RECON, FLUX, KS>), dim3(w.size()), dim3(MWG), 0, s, G.kp, G.gd,
-                       G.d_wmarch[D], (const R *)Ps, (R *)G.d_flux[D], G.plan.nface[D]);
+    auto kern = G.plan.p.amr ? k_flux_march<R, D, RECON, FLUX, KS, true> : k_flux_march<R, D, RECON, FLUX, KS, false>;
+    hipLaunchKernelGGL(kern, dim3(w.size()), dim3(MWG), 0, s, G.kp, G.gd, G.d_wmarch[D], (const R *)Ps,
+                       (R *)G.d_flux[D], G.plan.nface[D]);
     return hipGetLastError();
 }
 

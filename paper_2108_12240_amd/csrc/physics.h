@@ -134,7 +134,28 @@ __device__ __forceinline__ bool cell_of(const DevBlock &B, int item, int &i, int
 
 __device__ __forceinline__ long long pad_index(const DevBlock &B, const KParams &kp, int i, int j, int k)
 {
-    return B.off + ((long long)(k + kp.po[2]) * B.n1 + (j + kp.po[1])) * B.n0 + (i + kp.po[0]);
+    return B.off + ((long long)k * B.n1 + j) * B.n0 + i;
+}
+
+// Slot of block B's ghost position (l0, l1, l2) (at least one coordinate outside the
+// block): a block's ghost slots follow its interior cells, in the order of its
+// (size + 2g) box with x fastest and the interior skipped.
+__device__ __forceinline__ long long ghost_slot(const DevBlock &B, const KParams &kp, int l0, int l1, int l2)
+{
+    const int g0 = kp.g[0], g1 = kp.g[1], g2 = kp.g[2];
+    const int s0 = B.s[0], s1 = B.s[1], s2 = B.s[2];
+    const long long w0 = s0 + 2 * g0, w1 = s1 + 2 * g1;
+    const long long bx = l0 + g0, by = l1 + g1, bz = l2 + g2;
+    const long long zin = min(max(l2, 0), s2);                 // interior planes before
+    long long r = bz * w0 * w1 - zin * s0 * s1;
+    if (l2 < 0 || l2 >= s2) {
+        r += by * w0 + bx;
+    } else {
+        const long long yin = min(max(l1, 0), s1);              // interior rows before
+        r += by * w0 - yin * s0;
+        r += (l1 < 0 || l1 >= s1 || l0 < 0) ? bx : bx - s0;
+    }
+    return B.off + (long long)s0 * s1 * s2 + r;
 }
 
 template <bool KS>

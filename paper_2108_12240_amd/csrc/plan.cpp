@@ -111,22 +111,21 @@ bool bad(std::string &err, const std::string &msg)
 }
 
 // Index of local position l of block D by the linear rule the kernels use
-// (strides 1, n0, n0 n1 from the padded origin): the position's slot when it lies
-// inside the block (in the box layout: anywhere in the box), and the base of the
-// halo shifts otherwise.
-long long linear_index(const Plan &P, const DevBlock &D, const int l[3])
+// (strides 1, s0, s0 s1 from the block's first interior cell): the position's slot
+// when it lies inside the block, and the base of the halo shifts otherwise.
+long long linear_index(const Plan &, const DevBlock &D, const int l[3])
 {
-    return D.off + ((long long)(l[2] + P.po[2]) * D.n1 + (l[1] + P.po[1])) * D.n0 + (l[0] + P.po[0]);
+    return D.off + ((long long)l[2] * D.n1 + l[1]) * D.n0 + l[0];
 }
 
-// Slot of local position l (interior cell or ghost slot) in block D's region of P.
-// Interior-first layout: the interior cells (x fastest), then the ghost slots of
-// the (size + 2g) box in box order (x fastest) with the interior skipped.
+// Slot of local position l (interior cell or ghost slot) in block D's region of P:
+// the interior cells (x fastest), then the ghost slots of the (size + 2g) box in
+// box order (x fastest) with the interior skipped.
 long long slot_index(const Plan &P, const DevBlock &D, const int l[3])
 {
     bool in = true;
     for (int e = 0; e < 3; e++) in = in && l[e] >= 0 && l[e] < D.s[e];
-    if (!P.ifirst || in) return linear_index(P, D, l);
+    if (in) return linear_index(P, D, l);
     const int g0 = P.gd[0], g1 = P.gd[1], g2 = P.gd[2];
     const long long n0 = D.s[0] + 2 * g0, n1 = D.s[1] + 2 * g1;
     const int pi = l[0] + g0, pj = l[1] + g1, pk = l[2] + g2;
@@ -194,21 +193,13 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     P.p = p;
     P.blocks.assign(blocks, blocks + nb);
     for (int e = 0; e < 3; e++) P.gd[e] = e < p.ndim ? p.nghost : 0;
-    // State layout of a block's region of P. Independent patches (amr = 0): the
-    // interior cells first, contiguous and x fastest like U (every interior row of
-    // 16 cells then shares whole 128-byte lines with its neighbours, read and
-    // written without partial lines), then the ghost slots; the region is rounded
-    // to 32 elements so that every block starts on a line. Block trees keep the
-    // padded box, whose linear index extends to the ghost slots the cross-level
-    // halo reads: x rows of a double state are 128-byte lines (interior at slot 16),
-    // a float state keeps rows of size + 2g (a 16-cell float row is half a line
-    // either way; aligned float rows measured slower).
-    P.ifirst = !p.amr;
-    P.xalign = P.ifirst || p.precision == BHAC_PREC_MIXED ? 1 : 16;
-    P.xo = P.ifirst ? 0 : (P.gd[0] + P.xalign - 1) / P.xalign * P.xalign;
-    P.po[0] = P.xo;
-    P.po[1] = P.ifirst ? 0 : P.gd[1];
-    P.po[2] = P.ifirst ? 0 : P.gd[2];
+    // State layout of a block's region of P: the interior cells first, contiguous
+    // and x fastest like U (consecutive 16-cell interior rows fill whole 128-byte
+    // lines, read and written without partial lines), then the ghost slots in box
+    // order; the region is rounded to 32 elements so that every block starts on a
+    // line. The kernels index interior cells linearly (strides 1, s0, s0 s1) and
+    // reach the few ghost slots they read (cross-level halos of block trees) by
+    // the slot rule.
 
     // blocks, lattice occupancy, layout
     std::unordered_map<Key, int, KeyHash> lattice;
@@ -245,18 +236,11 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
             D.o[e] = B.origin[e];
             if (B.size[e] > P.smax[e]) P.smax[e] = B.size[e];
         }
-        long long ncell;
-        if (P.ifirst) {
-            D.n0 = B.size[0];
-            D.n1 = B.size[1];
-            const long long box =
-                (long long)(B.size[0] + 2 * P.gd[0]) * (B.size[1] + 2 * P.gd[1]) * (B.size[2] + 2 * P.gd[2]);
-            ncell = (box + 31) / 32 * 32;
-        } else {
-            D.n0 = (P.xo + B.size[0] + P.gd[0] + P.xalign - 1) / P.xalign * P.xalign;
-            D.n1 = B.size[1] + 2 * P.gd[1];
-            ncell = (long long)D.n0 * D.n1 * (B.size[2] + 2 * P.gd[2]);
-        }
+        D.n0 = B.size[0];
+        D.n1 = B.size[1];
+        const long long box =
+            (long long)(B.size[0] + 2 * P.gd[0]) * (B.size[1] + 2 * P.gd[1]) * (B.size[2] + 2 * P.gd[2]);
+        const long long ncell = (box + 31) / 32 * 32;
         D.level = B.level;
         D.off = P.off[b];
         D.ioff = P.ncell_interior;

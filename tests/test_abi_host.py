@@ -137,33 +137,27 @@ def test_entropy_parameter_checks():
     assert e.value.code == B.BHAC_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
 @pytest.mark.parametrize("tree", [False, True])
-def test_padded_layout_follows_the_rule(prec, tree):
+def test_padded_layout_follows_the_rule(tree):
     """Block offsets from the planner are the running sum of the block regions the
-    layout rule gives; independent patches store each block's interior first and
-    contiguous, starting on a 32-slot boundary; block trees store padded boxes
-    whose double rows start on 16-element boundaries. No ghost-map entry touches
-    a padding slot."""
+    layout rule gives; each block's interior leads its region, contiguous, and
+    every region starts on a 32-slot boundary; no ghost-map entry touches a
+    padding slot, and every cross-level recipe of a tree writes a ghost slot."""
     from tests import layout as L
     c = I.case_tree(n0=32, bs=8, levels=2) if tree else I.case4(nblocks=48, n0=48)
-    params = dict(c.params, precision=prec, fused=0)
+    params = dict(c.params, fused=0)
     off, dst, src = B.bhac_plan_ghosts(params, c.blocks)
     sizes = [L.region_size(params, b[1:4]) for b in c.blocks]
     assert np.array_equal(off, np.concatenate([[0], np.cumsum(sizes)]))
+    pad = np.zeros(off[-1], bool)
+    interior = np.zeros(off[-1], bool)
     for b, blk in enumerate(c.blocks):
         s = [int(v) for v in blk[1:4]]
-        if not tree:
-            assert off[b] % 32 == 0
-            k, j, i = np.meshgrid(np.arange(s[2]), np.arange(s[1]), np.arange(s[0]), indexing="ij")
-            assert np.array_equal(L.pad_index(params, off[b], s, i.ravel(), j.ravel(), k.ravel()),
-                                  off[b] + np.arange(np.prod(s)))
-        else:
-            xa = L.x_layout(params)[0]
-            assert xa == (16 if prec == I.PREC_FP64 else 1)
-            start = L.pad_index(params, off[b], s, 0, np.arange(s[1]), 0)
-            assert (start % xa == 0).all()
-    pad = np.zeros(off[-1], bool)
-    for b, blk in enumerate(c.blocks):
-        pad[off[b]:off[b + 1]] = L.box_locals(params, blk[1:4])[3]
+        assert off[b] % 32 == 0
+        k, j, i = np.meshgrid(np.arange(s[2]), np.arange(s[1]), np.arange(s[0]), indexing="ij")
+        assert np.array_equal(L.pad_index(params, off[b], s, i.ravel(), j.ravel(), k.ravel()),
+                              off[b] + np.arange(np.prod(s)))
+        pad[off[b]:off[b + 1]] = L.box_locals(params, s)[3]
+        interior[off[b]:off[b] + np.prod(s)] = True
     assert not pad[dst].any() and not pad[src].any()
+    assert not interior[dst].any() and interior[src].all()
