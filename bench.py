@@ -70,9 +70,9 @@ WORKLOADS = {
 # on; with any other sources the field is reported as null.
 TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
-    ("ks_torus_128_fp64_plain", "update"): (1165920912, "653678c8ba11c8f1"),
-    ("ks_torus_128_mixed_plain", "update"): (773983520, "653678c8ba11c8f1"),
-    ("ks_torus_128_mixed_auto", "update"): (773983520, "653678c8ba11c8f1"),
+    ("ks_torus_128_fp64_plain", "update"): (1165901024, "7d943f0967fee5d1"),
+    ("ks_torus_128_mixed_plain", "update"): (774000517, "7d943f0967fee5d1"),
+    ("ks_torus_128_mixed_auto", "update"): (774000517, "7d943f0967fee5d1"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
@@ -82,14 +82,14 @@ TRAFFIC = {
 # 2.4 GHz = 39.3e12 lane-instructions/s (one wave64 instruction takes 4 cycles of
 # a 16-lane SIMD; FP64 and unpacked FP32 issue at the same rate).
 VALU = {
-    ("ks_torus_128_fp64_plain", "flux_x1"): (49151494, "653678c8ba11c8f1"),
-    ("ks_torus_128_fp64_plain", "flux_x2"): (27173282, "653678c8ba11c8f1"),
-    ("ks_torus_128_fp64_plain", "flux_x3"): (24585222, "653678c8ba11c8f1"),
-    ("ks_torus_128_fp64_plain", "update"): (43317340, "653678c8ba11c8f1"),
-    ("ks_torus_128_mixed_plain", "flux_x1"): (38483604, "653678c8ba11c8f1"),
-    ("ks_torus_128_mixed_plain", "flux_x2"): (38671206, "653678c8ba11c8f1"),
-    ("ks_torus_128_mixed_plain", "flux_x3"): (20349241, "653678c8ba11c8f1"),
-    ("ks_torus_128_mixed_plain", "update"): (44890166, "653678c8ba11c8f1"),
+    ("ks_torus_128_fp64_plain", "flux_x1"): (49047031, "7d943f0967fee5d1"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27163087, "7d943f0967fee5d1"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24566785, "7d943f0967fee5d1"),
+    ("ks_torus_128_fp64_plain", "update"): (43153489, "7d943f0967fee5d1"),
+    ("ks_torus_128_mixed_plain", "flux_x1"): (38379106, "7d943f0967fee5d1"),
+    ("ks_torus_128_mixed_plain", "flux_x2"): (38566304, "7d943f0967fee5d1"),
+    ("ks_torus_128_mixed_plain", "flux_x3"): (20330777, "7d943f0967fee5d1"),
+    ("ks_torus_128_mixed_plain", "update"): (44726294, "7d943f0967fee5d1"),
 }
 VALU_PEAK = 39.3e12      # lane-instructions/s
 
