@@ -322,13 +322,14 @@ def case4(nblocks: int = 4096, n0: int = 96, levels: int = 3, precision=PREC_MIX
 
 
 def _tree_leaves(params, bs, levels, thresholds):
-    """Leaves (level, i, j, k) of a 2:1-balanced tree of bs^3 blocks over the level-0
+    """Leaves (level, i, j, k) of a 2:1-balanced tree of bs^ndim blocks over the level-0
     lattice: a block is refined while the synthetic torus density sampled at its
     cells exceeds the threshold of its level, then coarse leaves next to leaves two
     levels finer (across faces, edges or corners) are refined until none is."""
     n0 = params["ncell0"]
+    nd = int(params["ndim"])
     per = [params["bc"][d][0] == BC_PERIODIC for d in range(3)]
-    nsl0 = [n0[d] // bs for d in range(3)]
+    nsl0 = [n0[d] // bs if d < nd else 1 for d in range(3)]
     leaves = {(0, i, j, k) for i in range(nsl0[0]) for j in range(nsl0[1]) for k in range(nsl0[2])}
 
     def rho_max(lf):
@@ -346,8 +347,8 @@ def _tree_leaves(params, bs, levels, thresholds):
         leaves.remove(lf)
         for a in range(2):
             for b in range(2):
-                for c in range(2):
-                    leaves.add((l + 1, 2 * i + a, 2 * j + b, 2 * k + c))
+                for c in range(2 if nd == 3 else 1):
+                    leaves.add((l + 1, 2 * i + a, 2 * j + b, (2 * k + c) if nd == 3 else 0))
 
     def covering(l, idx):
         for m in range(l, -1, -1):
@@ -366,10 +367,10 @@ def _tree_leaves(params, bs, levels, thresholds):
                 l = lf[0]
                 for di in (-1, 0, 1):
                     for dj in (-1, 0, 1):
-                        for dk in (-1, 0, 1):
+                        for dk in ((-1, 0, 1) if nd == 3 else (0,)):
                             idx = [lf[1] + di, lf[2] + dj, lf[3] + dk]
                             ok = True
-                            for d in range(3):
+                            for d in range(nd):
                                 n = nsl0[d] << l
                                 if per[d]:
                                     idx[d] %= n
@@ -386,6 +387,27 @@ def _tree_leaves(params, bs, levels, thresholds):
                 refine(lf)
         balance()
     return sorted(leaves)
+
+
+def case_tree_2d(n0: int = 64, bs: int = 16, levels: int = 3, precision=PREC_MIXED, seed: int = 12247) -> Case:
+    """The block tree on the axisymmetric (ln r, theta) grid: ndim = 2, bs x bs
+    blocks refined around the torus as in case_tree."""
+    rng = np.random.default_rng(seed)
+    x_lo, x_hi = ks_domain()
+    params = base_params(ndim=2, x_lo=x_lo, x_hi=x_hi, ncell0=[n0, n0, 1], precision=precision, fused=0, amr=1,
+                         bc=[[BC_OUTFLOW, BC_OUTFLOW], [BC_OUTFLOW, BC_OUTFLOW], [BC_PERIODIC, BC_PERIODIC]])
+    leaves = _tree_leaves(params, bs, levels, thresholds=[0.0, 0.3] + [0.6] * max(0, levels - 3))
+    blocks = np.array([[l, bs, bs, 1, i * bs, j * bs, 0] for (l, i, j, k) in leaves], dtype=np.int32)
+    ioff = _ioff(blocks)
+    noise = rng.uniform(size=int(ioff[-1]))
+    prim = np.zeros((NVAR, int(ioff[-1])))
+    rr = np.zeros(int(ioff[-1]))
+    for b in range(len(blocks)):
+        g0, g1, g2 = _block_cells(blocks[b])
+        sl = slice(int(ioff[b]), int(ioff[b + 1]))
+        prim[:, sl], rr[sl], _ = _torus_cells(params, int(blocks[b, 0]), g0, g1, g2, noise[sl])
+    prim = _finish_torus(prim, rr)
+    return Case(f"tree2d_{n0}_{bs}_{levels}", params, blocks, prim, ioff, steps=10)
 
 
 def case_tree(n0: int = 64, bs: int = 16, levels: int = 3, precision=PREC_MIXED, seed: int = 12246) -> Case:

@@ -26,17 +26,21 @@ def torch():
     return T
 
 
-def tree(prec, n0=32, bs=8, levels=3):
-    c = I.case_tree(n0=n0, bs=bs, levels=levels, precision=prec)
+def tree(prec, ndim=3, levels=3):
+    if ndim == 3:
+        c = I.case_tree(n0=32, bs=8, levels=levels, precision=prec)
+    else:
+        c = I.case_tree_2d(n0=64, bs=8, levels=levels, precision=prec)
     c.params = dict(c.params, precision=prec, fused=0)
     return c
 
 
+@pytest.mark.parametrize("ndim", [3, 2])
 @pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
-def test_fill_matches_oracle_bitwise(torch, prec):
+def test_fill_matches_oracle_bitwise(torch, prec, ndim):
     """Every ghost slot (same-level copies, restrictions, prolongations, clamps)
     equals the oracle's value, rounded to the state's precision."""
-    c = tree(prec)
+    c = tree(prec, ndim)
     banner(f"fill {c.name} prec={prec}")
     G = B.Grid(c.params, c.blocks)
     Og = O.OracleGrid(c.params, c.blocks)
@@ -57,12 +61,13 @@ def test_fill_matches_oracle_bitwise(torch, prec):
     G.close()
 
 
+@pytest.mark.parametrize("ndim", [3, 2])
 @pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
-def test_substep_reads_only_cross_level_ghosts_it_writes(torch, prec):
+def test_substep_reads_only_cross_level_ghosts_it_writes(torch, prec, ndim):
     """With every ghost slot of P_stage poisoned, a substep gives bit-identical
     results: same-level halos come from neighbours, cross-level ones are rebuilt
     from interiors before use."""
-    c = tree(prec)
+    c = tree(prec, ndim)
     banner(f"halo {c.name} prec={prec}")
     G = B.Grid(c.params, c.blocks)
     U, P = G.init(c.prim)
@@ -86,9 +91,10 @@ def test_substep_reads_only_cross_level_ghosts_it_writes(torch, prec):
     G.close()
 
 
+@pytest.mark.parametrize("ndim", [3, 2])
 @pytest.mark.parametrize("prec,tol", [(I.PREC_FP64, FP64_TOL), (I.PREC_MIXED, MIXED_TOL)])
-def test_ten_steps_match_oracle(torch, prec, tol):
-    c = tree(prec)
+def test_ten_steps_match_oracle(torch, prec, tol, ndim):
+    c = tree(prec, ndim)
     banner(f"10 steps {c.name} prec={prec}")
     Og = O.OracleGrid(c.params, c.blocks)
     Uo, Po = Og.run(c.prim, 10)
@@ -133,18 +139,20 @@ def test_block_tiled_path_rejects_trees(torch):
     assert e.value.code == B.BHAC_EUNSUPPORTED
 
 
+@pytest.mark.parametrize("ndim", [3, 2])
 @pytest.mark.parametrize("prec,tol", [(I.PREC_FP64, 1e-13), (I.PREC_MIXED, 1e-6)])
-def test_flux_correction_conserves_across_levels(torch, prec, tol):
-    """Periodic flat three-level tree, no sources: the volume-weighted totals of D,
-    S, tau and B after two RK2 steps equal the initial ones (to rounding; in mixed
-    precision each cell's flux difference is formed in float)."""
-    params, blocks, prim = flat_tree_case()
+def test_flux_correction_conserves_across_levels(torch, prec, tol, ndim):
+    """Periodic flat three-level tree (square in 2-D), no sources: the
+    volume-weighted totals of D, S, tau and B after two RK2 steps equal the
+    initial ones (to rounding; in mixed precision each cell's flux difference is
+    formed in float)."""
+    params, blocks, prim = flat_tree_case(ndim=ndim)
     params = dict(params, precision=prec, fused=0)
-    banner(f"conservation prec={prec}")
+    banner(f"conservation ndim={ndim} prec={prec}")
     G = B.Grid(params, blocks)
     U, P = G.init(prim)
     U1, P1 = G.new_state("U"), G.new_state("P")
-    vol = tree_volumes(blocks, 32)
+    vol = tree_volumes(blocks, int(params["ncell0"][0]), ndim)
     U0 = U.cpu().numpy().copy()
     for _ in range(2):
         G.rk2_step(U, P, U1, P1)

@@ -275,15 +275,16 @@ def test_uniform_state_on_a_flat_tree_is_preserved_bit_for_bit():
     assert np.allclose(Pi[:, 0], state, rtol=1e-13, atol=1e-15)
 
 
-def test_flux_correction_conserves_across_levels():
+@pytest.mark.parametrize("ndim", [3, 2])
+def test_flux_correction_conserves_across_levels(ndim):
     """With the coarse faces on level boundaries set to the mean of the fine faces,
     the volume-weighted totals of D, S, tau and B are conserved to rounding on a
     periodic flat three-level tree (no sources); without that correction they
     drift at the 1e-4 level."""
-    params, blocks, prim = flat_tree_case()
+    params, blocks, prim = flat_tree_case(ndim=ndim)
     G = O.OracleGrid(params, blocks)
     U, P = G.init(prim)
-    vol = tree_volumes(blocks, 32)
+    vol = tree_volumes(blocks, int(params["ncell0"][0]), ndim)
     idx = G.interior_index()
 
     def totals(U):
@@ -297,3 +298,34 @@ def test_flux_correction_conserves_across_levels():
     st = G.stats()
     assert st["c2p_fail"] == 0
     assert (np.abs(t1 - t0) <= 1e-13 * np.maximum(scale, 1e-300)).all(), (t1 - t0) / scale
+
+
+def test_two_d_tree_partitions_the_domain():
+    """The 2-D tree's leaves cover the (ln r, theta) domain exactly once, levels
+    differ by at most one across faces, edges and corners, and a uniform flat
+    state is preserved bit for bit."""
+    c = I.case_tree_2d(n0=64, bs=8, levels=3)
+    assert set(np.unique(c.blocks[:, 0])) == {0, 1, 2}
+    # rasterise each leaf onto the finest level: every fine cell is covered once
+    fine = 64 * 4
+    cover = np.zeros((fine, fine), np.int32)
+    lev = np.full((fine, fine), -1, np.int32)
+    for l, s0, s1, s2, o0, o1, o2 in c.blocks:
+        f = 4 >> int(l)
+        assert s2 == 1 and o2 == 0
+        cover[o0 * f:(o0 + s0) * f, o1 * f:(o1 + s1) * f] += 1
+        lev[o0 * f:(o0 + s0) * f, o1 * f:(o1 + s1) * f] = l
+    assert (cover == 1).all()
+    # 2:1 balance across faces, edges and corners
+    for d0, d1 in [(1, 0), (0, 1), (1, 1), (1, -1)]:
+        a = lev[max(d0, 0):fine + min(d0, 0), max(d1, 0):fine + min(d1, 0)]
+        b = lev[max(-d0, 0):fine + min(-d0, 0), max(-d1, 0):fine + min(-d1, 0)]
+        assert np.abs(a - b).max() <= 1
+    params = dict(c.params, metric=I.METRIC_MINKOWSKI_CART, x_lo=[0.0, 0.0, 0.0], x_hi=[1.0, 1.0, 1.0],
+                  bc=[[I.BC_PERIODIC, I.BC_PERIODIC]] * 3)
+    state = np.array([1.0, 0.25, -0.125, 0.5, 0.75, 0.5, 0.25, -0.25, 0.0])
+    prim = np.repeat(state[:, None], int(c.ioff[-1]), axis=1)
+    G = O.OracleGrid(params, c.blocks)
+    U0, P0 = G.init(prim)
+    U, P = G.rk2_step(U0.copy(), P0.copy())
+    assert np.array_equal(U, U0)
