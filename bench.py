@@ -111,10 +111,8 @@ def bytes_per_unit(kernel: str, rsz: int, nv: int = 9) -> float:
     u8 = 8
     if kernel == "fill_ghosts":            # per ghost slot: nv values read + nv written
         return 2 * nv * rsz
-    if kernel.startswith("flux_x"):        # per face: one cell's 9 primitives read, 9 fluxes written
-        return 18 * rsz
-    if kernel == "flux_entropy":           # per face: one cell's K and the mass flux read, 1 flux written
-        return 3 * rsz
+    if kernel.startswith("flux_x"):        # per face: one cell's nv primitives read, nv fluxes written
+        return 2 * nv * rsz
     if kernel == "update":                 # per cell: U_stage, U_base (half the stages), P_stage,
         return nv * (u8 * 1.5 + rsz + 3 * rsz + u8 + rsz)   # 3 face fluxes, U_out, P_out
     if kernel == "update_div":             # per cell: as update, with one stored divergence instead of fluxes
@@ -131,9 +129,6 @@ def units_per_launch(kernel: str, info: dict) -> float:
         return info["nface"][int(kernel[-1]) - 1]
     if kernel in ("update", "update_div", "block_flux"):
         return info["ncell"]
-    if kernel == "flux_entropy":           # one launch per direction: the mean face count
-        nf = [n for n in info["nface"] if n]
-        return sum(nf) / len(nf)
     return 0.0
 
 

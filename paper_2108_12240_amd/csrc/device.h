@@ -48,7 +48,7 @@ struct GridDev {
 
 // Kernel families timed by the optional HIP-event timer.
 enum KernelId { K_FILL, K_FLUX0, K_FLUX1, K_FLUX2, K_UPDATE, K_PRIM2CON, K_CON2PRIM, K_SPEEDS, K_BEGIN, K_END,
-                K_BLOCK_FLUX, K_UPDATE_DIV, K_FILL_XL, K_FLUX_FIX, K_FLUX_ENT, K_COUNT };
+                K_BLOCK_FLUX, K_UPDATE_DIV, K_FILL_XL, K_FLUX_FIX, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Optional per-launch timing: a pre-created pool of HIP events recorded on the

@@ -174,7 +174,10 @@ constexpr int flux_occupancy()
 
 // XL (block trees): a halo side marked cross-level is read from the block's own
 // ghost slots (which the substep refreshes first), reached by the slot rule.
-template <typename R, int D, int RECON, int FLUX, bool KS, bool XL>
+// ENT (entropy field): the entropy function K (row NV of P) is reconstructed at the
+// face like the other variables, from the same stencil cells, and carried by the
+// face's mass flux from the side that flux comes from (row NV of F).
+template <typename R, int D, int RECON, int FLUX, bool KS, bool XL, bool ENT>
 __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
                                              const R *__restrict__ P, R *__restrict__ F, long long nftot)
 {
@@ -239,6 +242,14 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KPara
                 recon_face<R, RECON>(q[v], qL[v], qR[v]);
             }
         }
+        R KL = R(0), KR = R(0);
+        if constexpr (ENT) {
+            R qk[6];
+            qk[0] = qk[5] = R(0);
+#pragma unroll
+            for (int s = S0; s < S1; s++) qk[s] = P[NV * kp.ncp + cell[s]];
+            recon_face<R, RECON>(qk, KL, KR);
+        }
         const FaceM<R> m = face_metric<R, D, KS>(gd, B, i, j);
         const R ch = (R)gd.st->ch;
         R Ff[NV];
@@ -246,6 +257,7 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KPara
         R *out = F + B.fofs[D] + item;
 #pragma unroll
         for (int v = 0; v < NV; v++) out[v * nftot] = Ff[v];
+        if constexpr (ENT) out[NV * nftot] = Ff[0] * (Ff[0] >= R(0) ? KL : KR);
     }
     const double m = wg_max<WG>(lam, red);
     if (threadIdx.x == 0) raise_max(&gd.st->lam_acc[D], m);
@@ -258,13 +270,14 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KPara
 // Along x1 a face's stencil lies in one padded row, so without staging every
 // load instruction of a wave touches several rows and the neighbours' halo lines.
 // ---------------------------------------------------------------------------------
-template <typename R, int RECON, int FLUX, bool KS, bool XL>
+template <typename R, int RECON, int FLUX, bool KS, bool XL, bool ENT>
 __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(KParams kp, GridDev gd,
                                                                             const WorkItem *__restrict__ work,
                                                                             const R *__restrict__ P,
                                                                             R *__restrict__ F, long long nftot)
 {
-    __shared__ R tile[NV][x1s_max_cells<R>()];
+    constexpr int NS = NV + (ENT ? 1 : 0);        // staged rows of P (the entropy function last)
+    __shared__ R tile[NS][x1s_max_cells<R>()];
     __shared__ double red[WG / 64];
     const WorkItem w = work[blockIdx.x];
     if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
@@ -286,7 +299,7 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(K
                 c = ghost_slot(B, kp, l, row % B.s[1], row / B.s[1]);
         }
 #pragma unroll
-        for (int v = 0; v < NV; v++) tile[v][t] = P[v * kp.ncp + c];
+        for (int v = 0; v < NS; v++) tile[v][t] = P[v * kp.ncp + c];
     }
     __syncthreads();
     const int item = w.start + threadIdx.x;
@@ -302,12 +315,20 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(K
             for (int s = 0; s < 6; s++) q[s] = tile[v][t0 + s];
             recon_face<R, RECON>(q, qL[v], qR[v]);
         }
+        R KL = R(0), KR = R(0);
+        if constexpr (ENT) {
+            R q[6];
+#pragma unroll
+            for (int s = 0; s < 6; s++) q[s] = tile[NV][t0 + s];
+            recon_face<R, RECON>(q, KL, KR);
+        }
         const FaceM<R> m = face_metric<R, 0, KS>(gd, B, i, row % B.s[1]);
         R Ff[NV];
         lam = (double)face_flux<R, 0, FLUX>(qL, qR, m, (R)gd.st->ch, (R)kp.gam, (R)kp.gfac, Ff);
         R *out = F + B.fofs[0] + item;
 #pragma unroll
         for (int v = 0; v < NV; v++) out[v * nftot] = Ff[v];
+        if constexpr (ENT) out[NV * nftot] = Ff[0] * (Ff[0] >= R(0) ? KL : KR);
     }
     const double mx = wg_max<WG>(lam, red);
     if (threadIdx.x == 0) raise_max(&gd.st->lam_acc[0], mx);
@@ -415,50 +436,6 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
         if (mit) raise_max(&gd.st->max_iter, mit);
         if (nbk) atomicAdd(&gd.st->c2p_backup, (unsigned long long)nbk);
     }
-}
-
-// ---------------------------------------------------------------------------------
-// Entropy-field face flux (grids that carry the entropy field): the field K (row
-// NV of P) is reconstructed at the face like the other variables, from the same
-// halo cells, and carried by the face's mass flux (row 0 of F, written by the
-// direction's flux kernel just before on the same stream) from the upwind side.
-// ---------------------------------------------------------------------------------
-template <typename R, int D, int RECON>
-__global__ __launch_bounds__(WG) void k_entropy_flux(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
-                                                     const R *__restrict__ P, R *__restrict__ F, long long nftot)
-{
-    const WorkItem w = work[blockIdx.x];
-    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
-    const DevBlock B = gd.blocks[w.block];
-    const int fs0 = B.s[0] + (D == 0), fs1 = B.s[1] + (D == 1), fs2 = B.s[2] + (D == 2);
-    const int item = w.start + threadIdx.x;
-    if (item >= fs0 * fs1 * fs2) return;
-    const int i = item % fs0;
-    const int t = item / fs0;
-    const int j = t % fs1;
-    const int k = t / fs1;
-    const long long pc = pad_index(B, kp, i, j, k);
-    const long long st = D == 0 ? 1 : (D == 1 ? (long long)B.n0 : (long long)B.n0 * B.n1);
-    const int f = D == 0 ? i : (D == 1 ? j : k);
-    const int sD = B.s[D];
-    const bool clo = (B.hclamp >> (2 * D)) & 1, chi = (B.hclamp >> (2 * D + 1)) & 1;
-    constexpr int S0 = RECON == BHAC_RECON_PPM ? 0 : 1, S1 = RECON == BHAC_RECON_PPM ? 6 : 5;
-    const R *Kr = P + NV * kp.ncp;
-    R q[6];
-    q[0] = q[5] = R(0);
-#pragma unroll
-    for (int s = S0; s < S1; s++) {
-        const int l = f + s - 3;
-        const long long in = pc + (s - 3) * st;
-        const long long lo = clo ? pc - f * st : in + B.hshift[D][0];
-        const long long hi = chi ? pc + (sD - 1 - f) * st : in + B.hshift[D][1];
-        q[s] = Kr[l < 0 ? lo : (l >= sD ? hi : in)];
-    }
-    R KL, KR;
-    recon_face<R, RECON>(q, KL, KR);
-    R *out = F + B.fofs[D] + item;
-    const R fm = out[0];
-    out[NV * nftot] = fm * (fm >= R(0) ? KL : KR);
 }
 
 // ---------------------------------------------------------------------------------
@@ -603,8 +580,7 @@ inline unsigned nblk(long long n) { return (unsigned)((n + WG - 1) / WG); }
 
 const char *const kKernelNames[K_COUNT] = {"fill_ghosts", "flux_x1", "flux_x2", "flux_x3", "update",
                                            "prim2con", "con2prim", "cell_speeds", "step_begin", "step_end",
-                                           "block_flux", "update_div", "fill_cross_level", "flux_fix",
-                                           "flux_entropy"};
+                                           "block_flux", "update_div", "fill_cross_level", "flux_fix"};
 
 hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only)
 {
@@ -729,31 +705,25 @@ hipError_t launch_reset_stats(const DeviceGrid &G, hipStream_t s)
     return hipGetLastError();
 }
 
+// block trees (XL) and the entropy field (ENT) never come together (the planner
+// rejects that combination), so three variants per direction are launched
 template <typename R, int D, int RECON, int FLUX, bool KS>
 static hipError_t flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
 {
     const std::vector<WorkItem> &w = G.plan.wface[D];
     TimedLaunch tl(G.timer, K_FLUX0 + D, s);
-    const bool xl = G.plan.p.amr != 0;
+    const bool xl = G.plan.p.amr != 0, ent = G.kp.nvar > NV;
     if (D == 0 && G.plan.x1_staged) {
-        auto kern = xl ? k_flux_x1s<R, RECON, FLUX, KS, true> : k_flux_x1s<R, RECON, FLUX, KS, false>;
+        auto kern = xl ? k_flux_x1s<R, RECON, FLUX, KS, true, false>
+                       : (ent ? k_flux_x1s<R, RECON, FLUX, KS, false, true> : k_flux_x1s<R, RECON, FLUX, KS, false, false>);
         hipLaunchKernelGGL(kern, dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[0], (const R *)Ps,
                            (R *)G.d_flux[0], G.plan.nface[0]);
         return hipGetLastError();
     }
-    auto kern = xl ? k_flux<R, D, RECON, FLUX, KS, true> : k_flux<R, D, RECON, FLUX, KS, false>;
+    auto kern = xl ? k_flux<R, D, RECON, FLUX, KS, true, false>
+                   : (ent ? k_flux<R, D, RECON, FLUX, KS, false, true> : k_flux<R, D, RECON, FLUX, KS, false, false>);
     hipLaunchKernelGGL(kern, dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D], (const R *)Ps,
                        (R *)G.d_flux[D], G.plan.nface[D]);
-    return hipGetLastError();
-}
-
-template <typename R, int D, int RECON>
-static hipError_t entropy_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
-{
-    const std::vector<WorkItem> &w = G.plan.wface[D];
-    TimedLaunch tl(G.timer, K_FLUX_ENT, s);
-    hipLaunchKernelGGL((k_entropy_flux<R, D, RECON>), dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D],
-                       (const R *)Ps, (R *)G.d_flux[D], G.plan.nface[D]);
     return hipGetLastError();
 }
 
@@ -783,18 +753,11 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
     // (while kernel timing is on they run one after another on the caller's
     // stream, so that each kernel's measured duration is its own)
     const int mm = G.plan.march_mask;
-    auto hydro = [&](int d, hipStream_t st) -> hipError_t {
+    auto dir = [&](int d, hipStream_t st) -> hipError_t {
         if (mm >> d & 1) return launch_flux_march(G, d, Ps, st);
         if (d == 0) return flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, st);
         if (d == 1) return flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, st);
         return flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, st);
-    };
-    // with the entropy field, its flux follows each direction's kernel on that stream
-    auto dir = [&](int d, hipStream_t st) -> hipError_t {
-        hipError_t r = hydro(d, st);
-        if (r != hipSuccess || G.kp.nvar == NV) return r;
-        return d == 0 ? entropy_dir<R, 0, RECON>(G, Ps, st)
-                      : (d == 1 ? entropy_dir<R, 1, RECON>(G, Ps, st) : entropy_dir<R, 2, RECON>(G, Ps, st));
     };
     hipError_t e = hipSuccess;
     if (G.kp.ndim == 3 && G.side[0] && G.side[1] && !G.timer.on) {

@@ -20,13 +20,17 @@ namespace bhac {
 
 // XL (block trees): a halo side marked cross-level is read from the block's own
 // ghost slots (which the substep refreshes first), reached by the slot rule.
-template <typename R, int D, int RECON, int FLUX, bool KS, bool XL>
+// ENT (entropy field): the entropy function K (row NV of P) marches with the other
+// variables and is carried by each face's mass flux from the side that flux comes
+// from (row NV of F).
+template <typename R, int D, int RECON, int FLUX, bool KS, bool XL, bool ENT>
 __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KParams kp, GridDev gd, const MarchItem *__restrict__ work,
                                                     const R *__restrict__ P, R *__restrict__ F, long long nftot)
 {
     __shared__ double red[MWG / 64];
+    constexpr int NM = NV + (ENT ? 1 : 0);        // marched variables
     constexpr bool LST = sizeof(R) == 8;          // march state in LDS (double)
-    __shared__ R lst[LST ? 3 : 1][NV][LST ? MWG : 1];
+    __shared__ R lst[LST ? 3 : 1][NM][LST ? MWG : 1];
     const MarchItem w = work[blockIdx.x];
     if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
     const DevBlock B = gd.blocks[w.block];
@@ -62,7 +66,7 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
         auto load = [&](int l, R *q) {
             const long long c = cell(l);
 #pragma unroll
-            for (int v = 0; v < NV; v++) q[v] = P[v * ncp + c];
+            for (int v = 0; v < NM; v++) q[v] = P[v * ncp + c];
         };
         // index of face f of the line in the direction-D face array
         const int fs0 = B.s[0] + (D == 0), fs1 = B.s[1] + (D == 1);
@@ -97,6 +101,7 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
             R *out = F + face0 + f * fA;
 #pragma unroll
             for (int v = 0; v < NV; v++) out[v * nftot] = Ff[v];
+            if constexpr (ENT) out[NV * nftot] = Ff[0] * (Ff[0] >= R(0) ? qL[NV] : qR[NV]);
         };
 
         if constexpr (RECON == BHAC_RECON_PPM) {
@@ -105,8 +110,8 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
             // limited upper value qp_{c-1} of cell c-1 (registers in float; in
             // double they live in this lane's LDS slots, which keeps the kernel
             // within the register budget of two waves per SIMD)
-            R qc[NV], qn[NV], q2[NV];
-            R sreg[LST ? 1 : 3][NV];
+            R qc[NM], qn[NM], q2[NM];
+            R sreg[LST ? 1 : 3][NM];
             auto get = [&](int a, int v) -> R {
                 if constexpr (LST) return lst[a][v][threadIdx.x];
                 else return sreg[a][v];
@@ -116,14 +121,14 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
                 else sreg[a][v] = x;
             };
             {
-                R qa[NV], qb[NV];
+                R qa[NM], qb[NM];
                 load(w.f0 - 3, qa);
                 load(w.f0 - 2, qb);
                 load(w.f0 - 1, qc);
                 load(w.f0, qn);
                 if constexpr (!LST) load(w.f0 + 1, q2);
 #pragma unroll
-                for (int v = 0; v < NV; v++) {
+                for (int v = 0; v < NM; v++) {
                     const R sb = mc_slope(qa[v], qb[v], qc[v]);
                     const R s0 = mc_slope(qb[v], qc[v], qn[v]);
                     put(0, v, s0);
@@ -134,12 +139,12 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
             for (int c = w.f0 - 1; c < w.f1; c++) {
                 // float: q_{c+3} is fetched one cell ahead; double loads q_{c+2} here
                 // (no room for a second set; the other wave on the SIMD hides it)
-                R q3[LST ? 1 : NV];
+                R q3[LST ? 1 : NM];
                 if constexpr (LST) load(c + 2, q2);
                 else if (c + 1 < w.f1) load(c + 3, q3);
-                R qm[NV], qL[NV];
+                R qm[NM], qL[NM];
 #pragma unroll
-                for (int v = 0; v < NV; v++) {
+                for (int v = 0; v < NM; v++) {
                     const R sn = mc_slope(qc[v], qn[v], q2[v]);
                     const R ap = ppm_iface(qc[v], qn[v], get(0, v), sn);
                     R qp;
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
                 }
                 if (c >= w.f0) solve(c, qL, qm);           // face c: cell c-1 | cell c
 #pragma unroll
-                for (int v = 0; v < NV; v++) {
+                for (int v = 0; v < NM; v++) {
                     qc[v] = qn[v];
                     qn[v] = q2[v];
                     if constexpr (!LST) q2[v] = q3[v];
@@ -159,22 +164,22 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
             }
         } else {
             // MC: state before face c: q_{c-1}, q_c, q_{c+1}, slope s_{c-1}
-            R qa[NV], qc[NV], qn[NV], sa[NV];
+            R qa[NM], qc[NM], qn[NM], sa[NM];
             {
-                R qb[NV];
+                R qb[NM];
                 load(w.f0 - 2, qb);
                 load(w.f0 - 1, qa);
                 load(w.f0, qc);
                 load(w.f0 + 1, qn);
 #pragma unroll
-                for (int v = 0; v < NV; v++) sa[v] = mc_slope(qb[v], qa[v], qc[v]);
+                for (int v = 0; v < NM; v++) sa[v] = mc_slope(qb[v], qa[v], qc[v]);
             }
             for (int c = w.f0; c < w.f1; c++) {
-                R q2[NV];
+                R q2[NM];
                 if (c + 1 < w.f1) load(c + 2, q2);
-                R qL[NV], qR[NV];
+                R qL[NM], qR[NM];
 #pragma unroll
-                for (int v = 0; v < NV; v++) {
+                for (int v = 0; v < NM; v++) {
                     const R s = mc_slope(qa[v], qc[v], qn[v]);
                     qL[v] = qa[v] + R(0.5) * sa[v];
                     qR[v] = qc[v] - R(0.5) * s;
@@ -182,7 +187,7 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
                 }
                 solve(c, qL, qR);
 #pragma unroll
-                for (int v = 0; v < NV; v++) {
+                for (int v = 0; v < NM; v++) {
                     qa[v] = qc[v];
                     qc[v] = qn[v];
                     qn[v] = q2[v];
@@ -200,7 +205,9 @@ hipError_t launch_flux_march_typed(const DeviceGrid &G, const void *Ps, hipStrea
 {
     const std::vector<MarchItem> &w = G.plan.wmarch[D];
     TimedLaunch tl(G.timer, K_FLUX0 + D, s);
-    auto kern = G.plan.p.amr ? k_flux_march<R, D, RECON, FLUX, KS, true> : k_flux_march<R, D, RECON, FLUX, KS, false>;
+    auto kern = G.plan.p.amr ? k_flux_march<R, D, RECON, FLUX, KS, true, false>
+                             : (G.kp.nvar > NV ? k_flux_march<R, D, RECON, FLUX, KS, false, true>
+                                               : k_flux_march<R, D, RECON, FLUX, KS, false, false>);
     hipLaunchKernelGGL(kern, dim3(w.size()), dim3(MWG), 0, s, G.kp, G.gd, G.d_wmarch[D], (const R *)Ps,
                        (R *)G.d_flux[D], G.plan.nface[D]);
     return hipGetLastError();

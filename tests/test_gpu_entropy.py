@@ -171,3 +171,34 @@ def test_entropy_needs_the_unfused_path_on_patches(torch):
     with pytest.raises(B.BhacError) as e:
         B.Grid(dict(t.params, entropy=1, fused=0), t.blocks)
     assert e.value.code == B.BHAC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
+def test_every_schedule_gives_identical_entropy_results(torch, prec):
+    """The entropy flux comes out of whichever face kernel a direction uses (face per
+    thread, LDS-staged x1 rows, line march); two RK2 steps under each of them give
+    bit-identical states, the entropy rows included."""
+    from paper_2108_12240_amd import autotune
+    c = case(prec)
+    banner(f"schedules {c.name} prec={prec}")
+    ref, seen = None, []
+    for cand in autotune.candidates(c.params)[1:]:
+        if cand["sched"]["march_faces"] != 17:
+            continue
+        G = B.Grid(dict(c.params, **cand), c.blocks)
+        sch = G.schedule()
+        if sch in seen:
+            G.close()
+            continue
+        seen.append(sch)
+        U, P = G.run(c.prim, 2)
+        torch.cuda.synchronize()
+        got = (U.cpu().numpy(), G.unpack(P))
+        G.close()
+        assert got[0].shape[0] == 10
+        if ref is None:
+            ref = got
+            continue
+        assert np.array_equal(ref[0], got[0]), sch
+        assert np.array_equal(ref[1], got[1]), sch
+    assert len(seen) >= 8
