@@ -70,9 +70,9 @@ WORKLOADS = {
 # on; with any other sources the field is reported as null.
 TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
-    ("ks_torus_128_fp64_plain", "update"): (1165901024, "7d943f0967fee5d1"),
-    ("ks_torus_128_mixed_plain", "update"): (774000517, "7d943f0967fee5d1"),
-    ("ks_torus_128_mixed_auto", "update"): (774000517, "7d943f0967fee5d1"),
+    ("ks_torus_128_fp64_plain", "update"): (1165908736, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_mixed_plain", "update"): (773974981, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_mixed_auto", "update"): (773974981, "01df6c6dc4b1eedc"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
@@ -82,14 +82,14 @@ TRAFFIC = {
 # 2.4 GHz = 39.3e12 lane-instructions/s (one wave64 instruction takes 4 cycles of
 # a 16-lane SIMD; FP64 and unpacked FP32 issue at the same rate).
 VALU = {
-    ("ks_torus_128_fp64_plain", "flux_x1"): (49047031, "7d943f0967fee5d1"),
-    ("ks_torus_128_fp64_plain", "flux_x2"): (27163087, "7d943f0967fee5d1"),
-    ("ks_torus_128_fp64_plain", "flux_x3"): (24566785, "7d943f0967fee5d1"),
-    ("ks_torus_128_fp64_plain", "update"): (43153489, "7d943f0967fee5d1"),
-    ("ks_torus_128_mixed_plain", "flux_x1"): (38379106, "7d943f0967fee5d1"),
-    ("ks_torus_128_mixed_plain", "flux_x2"): (38566304, "7d943f0967fee5d1"),
-    ("ks_torus_128_mixed_plain", "flux_x3"): (20330777, "7d943f0967fee5d1"),
-    ("ks_torus_128_mixed_plain", "update"): (44726294, "7d943f0967fee5d1"),
+    ("ks_torus_128_fp64_plain", "flux_x1"): (49047121, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27163052, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24566772, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_fp64_plain", "update"): (43153461, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_mixed_plain", "flux_x1"): (38378960, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_mixed_plain", "flux_x2"): (38566816, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_mixed_plain", "flux_x3"): (20330925, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_mixed_plain", "update"): (44726299, "01df6c6dc4b1eedc"),
 }
 VALU_PEAK = 39.3e12      # lane-instructions/s
 
