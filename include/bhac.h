@@ -126,8 +126,12 @@ enum { BHAC_PREC_FP64 = 0, BHAC_PREC_MIXED = 1 };
  *               once); clear: from the face kernel (one thread per face).
  *  march_faces  longest line segment of the march kernel, in faces, 4..256; longer
  *               lines are cut into near-equal segments, each with its own warm-up.
- *  x1_staged    1: the x1 face kernel stages block rows with their halo in LDS where
- *               every block's rows fit; 0: it reads cells straight from memory.
+ *  x1_staged    how the x1 faces are computed where x1 is not marched. 0: the face
+ *               kernel reads cells straight from memory; 1: it stages block rows
+ *               with their halo in LDS where every block's rows fit; 2: the update
+ *               kernel stages the rows and computes the x1 faces itself, so no x1
+ *               flux array is written or read (independent patches without the
+ *               entropy field, rows fitting the LDS tile; otherwise as 1).
  * Out-of-range values give BHAC_EINVAL. */
 typedef struct bhac_schedule {
     int set;
@@ -301,7 +305,8 @@ int bhac_get_stats(bhac_grid *grid, int64_t *c2p_fail, int64_t *floor_hits, int 
 int bhac_reset_stats(bhac_grid *grid, void *stream);
 
 /* The schedule the grid's unfused substep runs, defaults resolved (set = 1;
- * x1_staged reads 1 only where the rows fit the LDS tile). Host only. */
+ * x1_staged reads the mode actually used: 2 or 1 only where the grid allows it).
+ * Host only. */
 int bhac_get_schedule(bhac_grid *grid, bhac_schedule *out);
 
 /* One whole SSP-RK2 step as a HIP graph (the launch-bound inner loop of a run).

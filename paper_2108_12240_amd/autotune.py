@@ -3,11 +3,13 @@
 Candidates are the block-tiled kernels (``fused = 1``, where the grid supports
 them) and the unfused kernels (``fused = 0``) under every schedule of the
 ``bhac_schedule`` search space: which directions take the line-march kernel and
-which the face kernel, how long a march segment may be, and whether the x1 face
-kernel stages rows in LDS. The default search is staged (all march masks first,
-then segment lengths and x1 staging for the two best); an exhaustive one times
-every candidate. Schedules that resolve to the same kernels (x1 staging
-where the rows do not fit, segment lengths longer than every line) are timed once.
+which the face kernel, how long a march segment may be, and how the x1 faces are
+computed where x1 is not marched (a face kernel reading memory, a face kernel
+staging rows in LDS, or the update kernel itself). The default search is staged
+(all march masks first, then segment lengths and the other x1 modes for the two
+best); an exhaustive one times every candidate. Schedules that resolve to the
+same kernels (an x1 mode the grid does not support, segment lengths longer than
+every line) are timed once.
 Each candidate advances a copy of the workload's initial state with replays of
 the captured RK2-step graph; the fastest wins. Every schedule computes the same
 fluxes, so the choice changes speed, not results. Choices are cached in a JSON
@@ -27,17 +29,17 @@ import numpy as np
 from . import bhac as B
 
 CACHE_ENV = "BHAC_AUTOTUNE_CACHE"
-SEARCH_VERSION = 2
+SEARCH_VERSION = 3
 MARCH_FACES = (9, 17, 33)
 
 
 def candidates(params: dict) -> list:
     """The search space: the block-tiled substep, then the unfused one under every
-    schedule (march mask x x1 staging x segment length)."""
+    schedule (march mask x x1 mode x segment length)."""
     out = [{"fused": 1}]
     ndim = int(params["ndim"])
     for mask in range(1 << ndim):
-        for x1 in ((0,) if mask & 1 else (0, 1)):
+        for x1 in ((0,) if mask & 1 else (0, 1, 2)):
             for faces in (MARCH_FACES if mask else (MARCH_FACES[1],)):
                 out.append({"fused": 0, "sched": {"march_mask": mask, "march_faces": faces, "x1_staged": x1}})
     return out
@@ -106,9 +108,10 @@ def _time_candidate(params, blocks, prim, steps, warmup, seen):
 
 
 def _staged(params, blocks, prim, steps, warmup, seen, timings):
-    """Two-stage search: every march mask at the middle segment length with x1
-    staging where x1 is not marched (and the block-tiled kernels), then the other
-    segment lengths and the unstaged x1 kernel for the two fastest masks."""
+    """Two-stage search: every march mask at the middle segment length with the
+    staged x1 face kernel where x1 is not marched (and the block-tiled kernels),
+    then the other segment lengths and the other two x1 modes for the two fastest
+    masks."""
     def run(cands):
         for cand in cands:
             ms, _ = _time_candidate(dict(params, **cand), blocks, prim, steps, warmup, seen)
@@ -126,8 +129,8 @@ def _staged(params, blocks, prim, steps, warmup, seen, timings):
         sc = t["choice"]["sched"]
         if sc["march_mask"]:
             second += [sched(sc["march_mask"], f, sc["x1_staged"]) for f in MARCH_FACES if f != mid]
-        if sc["x1_staged"]:
-            second.append(sched(sc["march_mask"], mid, 0))
+        if not sc["march_mask"] & 1:
+            second += [sched(sc["march_mask"], mid, x) for x in (0, 1, 2) if x != sc["x1_staged"]]
     run(second)
 
 

@@ -57,7 +57,7 @@ void release(bhac::DeviceGrid &G)
     release_timer(G);
     void *ptrs[] = {G.d_blocks, G.d_levels, G.d_ctab, G.d_f0tab, G.d_f1tab, G.d_ctab32, G.d_f0tab32, G.d_f1tab32,
                     G.d_state, G.d_wcell,
-                    G.d_wface[0], G.d_wface[1], G.d_wface[2], G.d_wmarch[0], G.d_wmarch[1], G.d_wmarch[2],
+                    G.d_wface[0], G.d_wface[1], G.d_wface[2], G.d_wupd1, G.d_wmarch[0], G.d_wmarch[1], G.d_wmarch[2],
                     G.d_gdst, G.d_gsrc, G.d_xoff, G.d_xdat, G.d_ffix, G.d_nbr, G.d_halo,
                     G.d_flux[0], G.d_flux[1], G.d_flux[2], G.d_div};
     for (void *p : ptrs)
@@ -190,6 +190,7 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     UP(G.d_f1tab32, P.f1tab32);
     UP(G.d_wcell, P.wcell);
     for (int d = 0; d < 3; d++) UP(G.d_wface[d], P.wface[d]);
+    UP(G.d_wupd1, P.wupd1);
     for (int d = 0; d < 3; d++) UP(G.d_wmarch[d], P.wmarch[d]);
     UP(G.d_gdst, P.gdst);
     UP(G.d_gsrc, P.gsrc);
@@ -412,7 +413,7 @@ int bhac_get_schedule(bhac_grid *g, bhac_schedule *out)
     out->set = 1;
     out->march_mask = P.march_mask;
     out->march_faces = P.march_faces;
-    out->x1_staged = P.x1_staged ? 1 : 0;
+    out->x1_staged = P.x1_in_update ? 2 : (P.x1_staged ? 1 : 0);
     return BHAC_OK;
 }
 

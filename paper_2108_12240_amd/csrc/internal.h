@@ -62,8 +62,15 @@ struct MarchItem { int block; int line0; int f0; int f1; };
 // touches times the padded row length), per precision
 template <typename R>
 constexpr int x1s_max_cells() { return sizeof(R) == 4 ? 600 : 400; }
+// rows of s0 cells one work-group of the update with in-place x1 faces takes: one
+// thread per x1 face of the rows (s0 + 1 per row)
+constexpr int x1u_rows(int s0) { return WG / (s0 + 1); }
 constexpr int MARCH_MASK_F32 = 4;
 constexpr int MARCH_MASK_F64 = 6;
+// the x1 faces are computed inside the update kernel (sched.x1_staged = 2) only when
+// a schedule asks for it: it pays at 128^3 in FP64 (-4 % per step) but costs 8 % on
+// the 384^3 grid in mixed precision, so it is left to the autotuner
+constexpr int X1_IN_UPDATE_DEFAULT = 0;
 constexpr int MARCH_MAX_FACES = 17;
 
 // Fused-kernel halo addressing: for each block and axis, the source of every
@@ -99,6 +106,8 @@ struct Plan {
     std::vector<MarchItem> wmarch[3];
     int march_mask = 0;                  // bit D: direction D uses the line kernel
     bool x1_staged = false;              // x1 faces by the LDS-staged face kernel
+    bool x1_in_update = false;           // x1 faces computed inside the update kernel
+    std::vector<WorkItem> wupd1;         // its work: x1u_rows(s0) whole rows per item (start = first row)
     int march_faces = MARCH_MAX_FACES;   // longest march segment, in faces
     long long nface[3] = {0, 0, 0};
     // fused-kernel neighbour data

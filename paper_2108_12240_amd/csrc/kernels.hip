@@ -439,6 +439,147 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
 }
 
 // ---------------------------------------------------------------------------------
+// Update with the x1 faces computed in place (independent patches, no entropy
+// field). A work item is x1u_rows(s0) whole rows of one block. The rows' cells with
+// their x1 halo (from the neighbours as in the face kernels) are staged in LDS;
+// each thread computes one x1 face flux exactly as the staged x1 face kernel does
+// and leaves it in LDS; after a barrier each thread updates one cell of the rows
+// exactly as k_update does, taking its x1 faces and its stage primitives from LDS
+// and its x2/x3 faces from the face arrays. The x1 fluxes never reach HBM, P_stage
+// is read once, and the Riemann arithmetic of one work-group overlaps the memory
+// traffic of the others on the CU.
+// ---------------------------------------------------------------------------------
+template <typename R, int RECON, int FLUX, bool KS, bool ND3, bool BASE>
+__global__ __launch_bounds__(WG, 3) void k_update_x1(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+                                                  const double *Ub, const double *Us, const R *__restrict__ Ps,
+                                                  double *Uo, R *__restrict__ Po, const R *__restrict__ F1,
+                                                  const R *__restrict__ F2, long long nf1, long long nf2, double a,
+                                                  double b)
+{
+    __shared__ R tile[NV][x1s_max_cells<R>()];
+    __shared__ R fx[NV][WG];
+    __shared__ double red[WG / 64];
+    __shared__ long long redl[WG / 64];
+    __shared__ int redi[WG / 64];
+    const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
+    const DevBlock B = gd.blocks[w.block];
+    const int s0 = B.s[0], fs0 = s0 + 1, r0 = w.start;
+    const int nr = min(x1u_rows(s0), B.s[1] * B.s[2] - r0);
+    const int rowlen = s0 + 6;                    // cells -3 .. s0+2 of a row
+    const int ncell = nr * rowlen;
+    const bool clo = B.hclamp & 1, chi = (B.hclamp >> 1) & 1;
+    for (int t = threadIdx.x; t < ncell; t += WG) {
+        const int row = r0 + t / rowlen, l = t % rowlen - 3;
+        const long long base = pad_index(B, kp, 0, row % B.s[1], row / B.s[1]);
+        long long c = base + l;
+        if (l < 0) c = clo ? base : c + B.hshift[0][0];
+        else if (l >= s0) c = chi ? base + s0 - 1 : c + B.hshift[0][1];
+#pragma unroll
+        for (int v = 0; v < NV; v++) tile[v][t] = Ps[v * kp.ncp + c];
+    }
+    __syncthreads();
+    // x1 face t of the item (faces 0 .. s0 of each row, row-major)
+    double lam = 0.0;
+    if (threadIdx.x < nr * fs0) {
+        const int frow = threadIdx.x / fs0, fi = threadIdx.x % fs0;
+        const int t0 = frow * rowlen + fi;        // tile slot of cell fi - 3
+        R qL[NV], qR[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            R q[6];
+#pragma unroll
+            for (int s = 0; s < 6; s++) q[s] = tile[v][t0 + s];
+            recon_face<R, RECON>(q, qL[v], qR[v]);
+        }
+        const FaceM<R> m = face_metric<R, 0, KS>(gd, B, fi, (r0 + frow) % B.s[1]);
+        R Ff[NV];
+        lam = (double)face_flux<R, 0, FLUX>(qL, qR, m, (R)gd.st->ch, (R)kp.gam, (R)kp.gfac, Ff);
+#pragma unroll
+        for (int v = 0; v < NV; v++) fx[v][threadIdx.x] = Ff[v];
+    }
+    const double mx = wg_max<WG>(lam, red);       // (its barrier also publishes fx)
+    if (threadIdx.x == 0) raise_max(&gd.st->lam_acc[0], mx);
+    // cell t of the item (cells 0 .. s0-1 of each row, row-major = interior order)
+    int fail = 0, floored = 0, nit = 0, backup = 0;
+    if (threadIdx.x < nr * s0) {
+        const int crow = threadIdx.x / s0, i = threadIdx.x % s0;
+        const int row = r0 + crow, j = row % B.s[1], k = row / B.s[1];
+        const long long cl = (long long)row * s0 + i;           // interior index within the block
+        const long long c = B.off + cl;
+        const long long ci = B.ioff + cl;
+        const DevLevel &L = gd.levels[B.level];
+        double div[3][NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) div[2][v] = 0.0;
+        {
+            const int lo = crow * fs0 + i;
+            const R idx = (R)L.inv_dx[0];
+#pragma unroll
+            for (int v = 0; v < NV; v++) div[0][v] = (double)((fx[v][lo + 1] - fx[v][lo]) * idx);
+        }
+#pragma unroll
+        for (int d = 1; d < (ND3 ? 3 : 2); d++) {
+            const R *Fd = d == 1 ? F1 : F2;
+            const long long nf = d == 1 ? nf1 : nf2;
+            const int fs1 = B.s[1] + (d == 1);
+            const long long lo = B.fofs[d] + ((long long)k * fs1 + j) * s0 + i;
+            const long long hi = lo + (d == 1 ? s0 : (long long)s0 * fs1);
+            const R idx = (R)L.inv_dx[d];
+#pragma unroll
+            for (int v = 0; v < NV; v++) div[d][v] = (double)((Fd[v * nf + hi] - Fd[v * nf + lo]) * idx);
+        }
+        // from here on the same statements as k_update, in the same order (kept
+        // inline: as a shared function the compiler split the cell's loads into
+        // more serial batches and the update ran 12 % slower)
+        double q[NV], Uc[NV], S[NV];
+        const int ts = crow * rowlen + i + 3;     // tile slot of the cell
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            q[v] = (double)tile[v][ts];
+            Uc[v] = Us[v * kp.nci + ci];
+        }
+        const CentM m = centre_metric<KS>(gd, B, i, j);
+        const double dt = gd.st->dt, kappa = gd.st->kappa;
+        geometric_sources(q, Uc, m, kappa, S);
+        double Un[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            double sum = -div[0][v], comp = 0.0;
+            const double terms[3] = {-div[1][v], -div[2][v], S[v]};
+#pragma unroll
+            for (int q2 = 0; q2 < 3; q2++) {
+                const double x = terms[q2];
+                const double t = sum + x;
+                comp += fabs(sum) >= fabs(x) ? (sum - t) + x : (x - t) + sum;
+                sum = t;
+            }
+            const double Lv = sum + comp;
+            double s2, e2;
+            two_sum(Uc[v], dt * Lv, s2, e2);
+            Un[v] = (BASE ? a * Ub[v * kp.nci + ci] : 0.0) + (b * s2 + b * e2);
+        }
+        double Pn[NV];
+        fail = con_to_prim<false>(Un, q, m, kp, Pn, nit, floored, backup);
+        if (fail || floored) prim_to_cons(Pn, m, kp.gfac, Un);
+        floored = fail ? 0 : floored;
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            Uo[v * kp.nci + ci] = Un[v];
+            Po[v * kp.ncp + c] = (R)Pn[v];
+        }
+    }
+    const long long nfail = wg_sum<WG>(fail, redl);
+    const long long nfl = wg_sum<WG>(floored, redl);
+    const int mit = wg_imax<WG>(nit, redi);
+    if (threadIdx.x == 0) {
+        if (nfail) atomicAdd(&gd.st->c2p_fail, (unsigned long long)nfail);
+        if (nfl) atomicAdd(&gd.st->floor_hits, (unsigned long long)nfl);
+        if (mit) raise_max(&gd.st->max_iter, mit);
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // Pointwise kernels.
 // ---------------------------------------------------------------------------------
 template <typename R, bool KS>
@@ -580,7 +721,8 @@ inline unsigned nblk(long long n) { return (unsigned)((n + WG - 1) / WG); }
 
 const char *const kKernelNames[K_COUNT] = {"fill_ghosts", "flux_x1", "flux_x2", "flux_x3", "update",
                                            "prim2con", "con2prim", "cell_speeds", "step_begin", "step_end",
-                                           "block_flux", "update_div", "fill_cross_level", "flux_fix"};
+                                           "block_flux", "update_div", "fill_cross_level", "flux_fix",
+                                           "update_x1"};
 
 hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only)
 {
@@ -745,6 +887,20 @@ static hipError_t update_typed(const DeviceGrid &G, const double *Ub, const doub
 }
 
 template <typename R, int RECON, int FLUX, bool KS>
+static hipError_t update_x1_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps,
+                                  double *Uo, void *Po, double a, double b, hipStream_t s)
+{
+    TimedLaunch tl(G.timer, K_UPDATE_X1, s);
+    const bool nd3 = G.kp.ndim == 3, base = a != 0.0;
+    auto kern = nd3 ? (base ? k_update_x1<R, RECON, FLUX, KS, true, true> : k_update_x1<R, RECON, FLUX, KS, true, false>)
+                    : (base ? k_update_x1<R, RECON, FLUX, KS, false, true> : k_update_x1<R, RECON, FLUX, KS, false, false>);
+    hipLaunchKernelGGL(kern, dim3(G.plan.wupd1.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wupd1, Ub, Us,
+                       (const R *)Ps, Uo, (R *)Po, (const R *)G.d_flux[1], (const R *)G.d_flux[2],
+                       G.plan.nface[1], G.plan.nface[2], a, b);
+    return hipGetLastError();
+}
+
+template <typename R, int RECON, int FLUX, bool KS>
 static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
                                 void *Po, double a, double b, hipStream_t s)
 {
@@ -760,6 +916,23 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
         return flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, st);
     };
     hipError_t e = hipSuccess;
+    if (G.plan.x1_in_update) {
+        // x2 (and x3 on a side stream, concurrently) by face kernels, then the update,
+        // which computes the x1 faces itself
+        if (G.kp.ndim == 3 && !G.timer.on) {
+            e = hipEventRecord(G.ev_fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(G.side[0], G.ev_fork, 0);
+            if (e == hipSuccess) e = dir(2, G.side[0]);
+            if (e == hipSuccess) e = dir(1, s);
+            if (e == hipSuccess) e = hipEventRecord(G.ev_join[0], G.side[0]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, G.ev_join[0], 0);
+        } else {
+            e = dir(1, s);
+            if (e == hipSuccess && G.kp.ndim == 3) e = dir(2, s);
+        }
+        if (e == hipSuccess) e = update_x1_typed<R, RECON, FLUX, KS>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+        return e;
+    }
     if (G.kp.ndim == 3 && G.side[0] && G.side[1] && !G.timer.on) {
         e = hipEventRecord(G.ev_fork, s);
         for (int q = 0; q < 2 && e == hipSuccess; q++) e = hipStreamWaitEvent(G.side[q], G.ev_fork, 0);

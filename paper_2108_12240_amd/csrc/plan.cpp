@@ -155,7 +155,7 @@ bool check_params(const bhac_params &p, std::string &err)
     if (p.sched.set) {
         if (p.sched.march_mask < 0 || p.sched.march_mask > 7) return bad(err, "sched.march_mask must be in [0, 7]");
         if (p.sched.march_faces < 4 || p.sched.march_faces > 256) return bad(err, "sched.march_faces must be in [4, 256]");
-        if (p.sched.x1_staged != 0 && p.sched.x1_staged != 1) return bad(err, "sched.x1_staged must be 0 or 1");
+        if (p.sched.x1_staged < 0 || p.sched.x1_staged > 2) return bad(err, "sched.x1_staged must be 0, 1 or 2");
     }
     const int gmin = p.recon == BHAC_RECON_PPM ? 3 : 2;
     if (p.nghost < gmin || p.nghost > 8) return bad(err, "nghost must be >= 2 (MC) or >= 3 (PPM) and <= 8");
@@ -356,6 +356,27 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         }
         P.x1_staged = ok;
     }
+    // x1 faces inside the update: independent patches without the entropy field,
+    // x1 not marched, every block's rows fit the LDS tile
+    {
+        const int cap = p.precision == BHAC_PREC_MIXED ? x1s_max_cells<float>() : x1s_max_cells<double>();
+        const int want = p.sched.set ? p.sched.x1_staged : X1_IN_UPDATE_DEFAULT;
+        bool ok = want == 2 && !p.amr && !p.entropy && !p.fused && !(P.march_mask & 1);
+        for (int64_t b = 0; b < nb && ok; b++) {
+            const int s0 = P.dblocks[b].s[0];
+            ok = s0 >= 3 && x1u_rows(s0) >= 1 && x1u_rows(s0) * (s0 + 6) <= cap;
+        }
+        P.x1_in_update = ok;
+        P.wupd1.clear();
+        if (ok) {
+            P.x1_staged = false;
+            for (int64_t b = 0; b < nb; b++) {
+                const DevBlock &D = P.dblocks[b];
+                const int rpw = x1u_rows(D.s[0]), nrow = D.s[1] * D.s[2];
+                for (int r = 0; r < nrow; r += rpw) P.wupd1.push_back({(int)b, r});
+            }
+        }
+    }
 
     // XCD-aware order: work-group p runs on XCD p % NXCD, so item q is placed at
     // p = (q % per) * NXCD + q / per. Each XCD then walks a contiguous range of items
@@ -367,6 +388,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         w.swap(out);
     };
     xcd_order(P.wcell, WorkItem{-1, 0});
+    xcd_order(P.wupd1, WorkItem{-1, 0});
     for (int d = 0; d < p.ndim; d++) {
         xcd_order(P.wface[d], WorkItem{-1, 0});
         xcd_order(P.wmarch[d], MarchItem{-1, 0, 0, 0});

@@ -111,7 +111,7 @@ def test_autotune_search_space_is_valid():
 
 @pytest.mark.parametrize("bad", [dict(march_mask=8, march_faces=17, x1_staged=0),
                                  dict(march_mask=0, march_faces=3, x1_staged=0),
-                                 dict(march_mask=0, march_faces=17, x1_staged=2)])
+                                 dict(march_mask=0, march_faces=17, x1_staged=3)])
 def test_out_of_range_schedule_is_rejected(bad):
     c = I.case_torus(2, n=32)
     with pytest.raises(B.BhacError) as e:

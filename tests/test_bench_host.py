@@ -90,3 +90,25 @@ def test_cpu_baseline_runs_the_oracle_on_a_bounded_sample():
     out = bench.cpu_baseline(c, 0.5)
     assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "zone-updates/s"
     assert out["value"] > 0 and "blocks" in out["sample"]
+
+
+def test_bound_follows_the_larger_floor(monkeypatch):
+    """With a stored VALU count whose issue time exceeds the HBM time of the
+    kernel's algorithmic bytes, the roofline is taken against the VALU peak."""
+    dig = bench.source_digest()
+    hbm_floor = 540 * 2 ** 21 / 8e12                       # s per launch at 8 TB/s
+    small = int(0.5 * hbm_floor * bench.VALU_PEAK / 64)     # issue time half the HBM floor
+    monkeypatch.setitem(bench.VALU, ("fake_workload", "update"), (small, dig))
+    assert bench.roofline(fake_result(), 8, "fake_workload")["bound"] == "hbm"
+    big = int(2.0 * hbm_floor * bench.VALU_PEAK / 64)
+    monkeypatch.setitem(bench.VALU, ("fake_workload", "update"), (big, dig))
+    r = bench.roofline(fake_result(), 8, "fake_workload")
+    assert r["bound"] == "alu" and r["unit"] == "Tlane-instr/s"
+    assert r["frac"] == pytest.approx(big * 64 / 0.25e-3 / bench.VALU_PEAK, abs=1e-4)
+    assert r["hbm_frac"] == pytest.approx(540 * 2 ** 21 / 0.25e-3 / 8e12, abs=1e-4)
+
+
+def test_bytes_of_the_update_with_x1_faces_in_place():
+    # as the update, without the x1 face fluxes: 9 (1.5 * 8 + R + 2R + 8 + R)
+    assert bench.bytes_per_unit("update_x1", 8) == 468
+    assert bench.bytes_per_unit("update_x1", 4) == 324

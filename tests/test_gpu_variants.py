@@ -1,6 +1,7 @@
 """GPU parity beyond the benchmark configurations: the 2-D Kerr-Schild grid, and
 the 3-D torus with every reconstruction / Riemann-solver pair under the face-kernel
-and the line-march schedules, in both precisions."""
+and the line-march schedules (and with the x1 faces inside the update), in both
+precisions."""
 import numpy as np
 import pytest
 
@@ -53,7 +54,8 @@ def test_kerr_schild_2d(prec, recon, flux):
 
 
 SCHEDULES = {"faces": dict(march_mask=0, march_faces=17, x1_staged=1),
-             "lines": dict(march_mask=7, march_faces=9, x1_staged=0)}
+             "lines": dict(march_mask=7, march_faces=9, x1_staged=0),
+             "x1_in_update": dict(march_mask=6, march_faces=17, x1_staged=2)}
 
 
 @pytest.mark.parametrize("sched", sorted(SCHEDULES))
@@ -64,3 +66,20 @@ def test_kerr_schild_3d_solver_pairs(prec, recon, flux, sched):
     params = dict(c.params, precision=prec, recon=recon, flux=flux, fused=0, sched=SCHEDULES[sched])
     banner(f"{c.name} prec={prec} recon={recon} flux={flux} schedule={sched}")
     check(c, params, ("3d", recon, flux))
+
+
+@pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
+def test_x1_faces_in_the_update_on_mixed_block_sizes(prec):
+    """The update kernel computing the x1 faces itself, on the AMR-like list (blocks
+    of 8, 12 and 16 cells, so work items of 28, 19 and 15 rows) and on the 2-D grid."""
+    sched = dict(march_mask=6, march_faces=17, x1_staged=2)
+    c = I.case4(nblocks=64, n0=48)
+    params = dict(c.params, precision=prec, fused=0, sched=sched)
+    banner(f"{c.name} prec={prec} x1 in update")
+    G = B.Grid(params, c.blocks)
+    assert G.schedule()["x1_staged"] == 2
+    G.close()
+    check(c, params, ("amr_like",))
+    c2 = I.case_torus_2d(n=(64, 64), bs=16)
+    params2 = dict(c2.params, precision=prec, fused=0, sched=dict(sched, march_mask=2))
+    check(c2, params2, ("2d", c2.params["recon"], c2.params["flux"]))
