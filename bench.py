@@ -74,9 +74,9 @@ WORKLOADS = {
 # on; with any other sources the field is reported as null.
 TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
-    ("ks_torus_128_fp64_plain", "update"): (1165908736, "01df6c6dc4b1eedc"),
-    ("ks_torus_128_mixed_plain", "update"): (773974981, "01df6c6dc4b1eedc"),
-    ("ks_torus_128_mixed_auto", "update"): (773974981, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_fp64_plain", "update"): (1165892683, "f8649014c8c73b4c"),
+    ("ks_torus_128_mixed_plain", "update"): (774002373, "f8649014c8c73b4c"),
+    ("ks_torus_128_mixed_auto", "update"): (774002373, "f8649014c8c73b4c"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
@@ -86,14 +86,20 @@ TRAFFIC = {
 # 2.4 GHz = 39.3e12 lane-instructions/s (one wave64 instruction takes 4 cycles of
 # a 16-lane SIMD; FP64 and unpacked FP32 issue at the same rate).
 VALU = {
-    ("ks_torus_128_fp64_plain", "flux_x1"): (49047121, "01df6c6dc4b1eedc"),
-    ("ks_torus_128_fp64_plain", "flux_x2"): (27163052, "01df6c6dc4b1eedc"),
-    ("ks_torus_128_fp64_plain", "flux_x3"): (24566772, "01df6c6dc4b1eedc"),
-    ("ks_torus_128_fp64_plain", "update"): (43153461, "01df6c6dc4b1eedc"),
-    ("ks_torus_128_mixed_plain", "flux_x1"): (38378960, "01df6c6dc4b1eedc"),
-    ("ks_torus_128_mixed_plain", "flux_x2"): (38566816, "01df6c6dc4b1eedc"),
-    ("ks_torus_128_mixed_plain", "flux_x3"): (20330925, "01df6c6dc4b1eedc"),
-    ("ks_torus_128_mixed_plain", "update"): (44726299, "01df6c6dc4b1eedc"),
+    ("ks_torus_128_fp64_x1u", "flux_x2"): (27163080, "f8649014c8c73b4c"),
+    ("ks_torus_128_fp64_x1u", "flux_x3"): (24566769, "f8649014c8c73b4c"),
+    ("ks_torus_128_fp64_x1u", "update_x1"): (94183136, "f8649014c8c73b4c"),
+    ("ks_torus_128_mixed_x1u", "flux_x2"): (38566273, "f8649014c8c73b4c"),
+    ("ks_torus_128_mixed_x1u", "flux_x3"): (20330754, "f8649014c8c73b4c"),
+    ("ks_torus_128_mixed_x1u", "update_x1"): (85035998, "f8649014c8c73b4c"),
+    ("ks_torus_128_fp64_plain", "flux_x1"): (49046916, "f8649014c8c73b4c"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27163026, "f8649014c8c73b4c"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24566760, "f8649014c8c73b4c"),
+    ("ks_torus_128_fp64_plain", "update"): (43153485, "f8649014c8c73b4c"),
+    ("ks_torus_128_mixed_plain", "flux_x1"): (38379222, "f8649014c8c73b4c"),
+    ("ks_torus_128_mixed_plain", "flux_x2"): (38566281, "f8649014c8c73b4c"),
+    ("ks_torus_128_mixed_plain", "flux_x3"): (20330863, "f8649014c8c73b4c"),
+    ("ks_torus_128_mixed_plain", "update"): (44726337, "f8649014c8c73b4c"),
 }
 VALU_PEAK = 39.3e12      # lane-instructions/s
 
