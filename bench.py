@@ -269,14 +269,20 @@ def cpu_baseline(case, seconds_hint: float):
     nsel = int(max(1, min(nb, seconds_hint / 2.0 / max(per_block, 1e-9))))
     sel = list(range(nsel))
     cells = int(Og.ioff[nsel])
+    # whole RK2 steps on the sample until about the time hint (the whole grid may
+    # take less than that for one step)
+    steps, el = 0, 0.0
     t0 = time.perf_counter()
-    Og.fill_ghosts(P, sel)
-    Og.substep(U, U, P, U1, P1, 0.0, 1.0, sel)
-    Og.fill_ghosts(P1, sel)
-    Og.substep(U, U1, P1, U1, P, 0.5, 0.5, sel)
-    el = time.perf_counter() - t0
-    return dict(value=round(cells * 2 / el, 1), unit="zone-updates/s", cores=1, kind="oracle",
-                sample=f"one RK2 step (2 substeps with ghost fills) on {nsel} of {nb} blocks "
+    while steps == 0 or (el < 0.8 * seconds_hint and steps < 8):
+        Og.fill_ghosts(P, sel)
+        Og.substep(U, U, P, U1, P1, 0.0, 1.0, sel)
+        Og.fill_ghosts(P1, sel)
+        Og.substep(U, U1, P1, U1, P, 0.5, 0.5, sel)
+        U, U1 = U1, U                             # the step's result is the next step's state
+        steps += 1
+        el = time.perf_counter() - t0
+    return dict(value=round(cells * 2 * steps / el, 1), unit="zone-updates/s", cores=1, kind="oracle",
+                sample=f"{steps} RK2 step(s) (2 substeps with ghost fills each) on {nsel} of {nb} blocks "
                        f"({cells} zones), single thread, {el:.1f} s")
 
 

@@ -71,3 +71,24 @@ def test_exhaustive_search_times_every_distinct_schedule(tmp_path):
     best = [t for t in rep["timings"] if t["choice"] == rep["choice"]]
     assert len(best) == 1 and best[0]["ms_per_step"] == min(ms)
     assert chosen["fused"] == rep["choice"]["fused"] and chosen.get("sched") == rep["choice"].get("sched")
+
+
+def test_x1_in_update_falls_back_where_the_grid_cannot_use_it():
+    """x1_staged = 2 resolves to the staged face kernel on grids with the entropy
+    field or a block tree, and to no x1 face mode at all where x1 is marched."""
+    sched = dict(march_mask=6, march_faces=17, x1_staged=2)
+    c = I.case_torus(2, n=32)
+    G = B.Grid(dict(c.params, fused=0, sched=sched), c.blocks)
+    assert G.schedule()["x1_staged"] == 2
+    G.close()
+    e = I.with_entropy(I.case_torus(2, n=32))
+    G = B.Grid(dict(e.params, fused=0, sched=sched), e.blocks)
+    assert G.schedule()["x1_staged"] == 1
+    G.close()
+    t = I.case_tree(n0=32, bs=8, levels=2)
+    G = B.Grid(dict(t.params, fused=0, sched=sched), t.blocks)
+    assert G.schedule()["x1_staged"] == 1
+    G.close()
+    G = B.Grid(dict(c.params, fused=0, sched=dict(sched, march_mask=7)), c.blocks)
+    assert G.schedule()["x1_staged"] == 0
+    G.close()
