@@ -161,3 +161,32 @@ def test_padded_layout_follows_the_rule(tree):
         interior[off[b]:off[b] + np.prod(s)] = True
     assert not pad[dst].any() and not pad[src].any()
     assert not interior[dst].any() and interior[src].all()
+
+
+@pytest.mark.parametrize("desc,blocks", [
+    ("no blocks", np.zeros((0, 7), np.int32)),
+    ("smaller than the ghost depth", np.array([[0, 2, 2, 2, 0, 0, 0]], np.int32)),
+    ("two blocks in one slot", np.array([[0, 8, 8, 8, 0, 0, 0], [0, 8, 8, 8, 0, 0, 0]], np.int32)),
+    ("off its size lattice", np.array([[0, 8, 8, 8, 4, 0, 0]], np.int32)),
+    ("outside the domain", np.array([[0, 8, 8, 8, 48, 0, 0]], np.int32)),
+    ("negative origin", np.array([[0, 8, 8, 8, -8, 0, 0]], np.int32)),
+    ("level out of range", np.array([[30, 8, 8, 8, 0, 0, 0]], np.int32)),
+])
+def test_invalid_block_lists_are_rejected(desc, blocks):
+    c = I.case4(nblocks=16, n0=48)
+    with pytest.raises(B.BhacError) as e:
+        B.bhac_plan_ghosts(c.params, blocks)
+    assert e.value.code == B.BHAC_EINVAL, desc
+
+
+def test_blocks_as_small_as_the_ghost_depth_are_planned():
+    """3-cell blocks with PPM (3 ghost layers): every halo spans the neighbour's
+    whole interior, and the plan still reproduces the oracle's fill bit for bit."""
+    c = I.case_torus(2, n=(24, 12, 12), bs=3)
+    G = O.OracleGrid(c.params, c.blocks)
+    off, dst, src = B.bhac_plan_ghosts(c.params, c.blocks)
+    P = unique_ids(G)
+    ref = P.copy()
+    G.fill_ghosts(ref)
+    P[:, dst] = P[:, src]
+    assert np.array_equal(P, ref)

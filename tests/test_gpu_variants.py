@@ -83,3 +83,14 @@ def test_x1_faces_in_the_update_on_mixed_block_sizes(prec):
     c2 = I.case_torus_2d(n=(64, 64), bs=16)
     params2 = dict(c2.params, precision=prec, fused=0, sched=dict(sched, march_mask=2))
     check(c2, params2, ("2d", c2.params["recon"], c2.params["flux"]))
+
+
+@pytest.mark.parametrize("x1", [1, 2])
+@pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
+def test_blocks_as_small_as_the_ghost_depth(prec, x1):
+    """3³ blocks with PPM: halos reach across the neighbour's whole interior; the LDS
+    row tiles are at their largest (where they do not fit, the x1 mode falls back)."""
+    c = I.case_torus(2, n=(24, 12, 12), bs=3)
+    params = dict(c.params, precision=prec, fused=0, sched=dict(march_mask=6, march_faces=17, x1_staged=x1))
+    banner(f"{c.name} prec={prec} x1_staged={x1}")
+    check(c, params, ("bs3",))
