@@ -59,7 +59,11 @@ CASES = [
     ("case4_4096_mixed_fused", lambda: I.case4(), I.PREC_MIXED, 1, 1e-5),
     ("case4_4096_mixed_plain", lambda: I.case4(), I.PREC_MIXED, 0, 1e-5),
     ("case5_384_mixed_plain", lambda: I.case_torus(5, n=384), I.PREC_MIXED, 0, 1e-5),
+    # the update computing the x1 faces itself (the autotuner's pick for the FP64 torus)
+    ("case2_128_fp64_x1u", lambda: I.case_torus(2, n=128), I.PREC_FP64, "x1u", 1e-12),
+    ("case2_128_mixed_x1u", lambda: I.case_torus(2, n=128), I.PREC_MIXED, "x1u", 1e-5),
 ]
+X1U = dict(march_mask=6, march_faces=17, x1_staged=2)
 
 
 @pytest.mark.parametrize("name,make,prec,fused,tol", CASES)
@@ -67,7 +71,9 @@ def test_one_step_sampled_blocks(name, make, prec, fused, tol):
     import torch
     print(f"\n[fullsize] {name}", flush=True)
     c = make()
-    c.params = dict(c.params, precision=prec, fused=fused)
+    c.params = dict(c.params, precision=prec, fused=0 if fused == "x1u" else fused)
+    if fused == "x1u":
+        c.params["sched"] = X1U
     sel = sample_blocks(c)
     n1 = neighbourhood(c.blocks, c.params, sel)
     n2 = neighbourhood(c.blocks, c.params, n1)
@@ -79,6 +85,8 @@ def test_one_step_sampled_blocks(name, make, prec, fused, tol):
 
     # HIP path on the whole grid
     G = B.Grid(c.params, c.blocks)
+    if fused == "x1u":
+        assert G.schedule()["x1_staged"] == 2
     U, P = G.init(c.prim)
     G.set_dt(dt)
     U1, P1 = G.new_state("U"), G.new_state("P")
@@ -146,6 +154,8 @@ def test_block_tree_full_grid_one_step(prec, tol):
     print(f"\n[fullsize] {c.name} prec={prec}", flush=True)
     dt = 1e-3
     G = B.Grid(c.params, c.blocks)
+    if fused == "x1u":
+        assert G.schedule()["x1_staged"] == 2
     U, P = G.init(c.prim)
     G.set_dt(dt)
     U1, P1 = G.new_state("U"), G.new_state("P")
