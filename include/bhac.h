@@ -62,7 +62,7 @@ enum {
     BHAC_ENOMEM = -2,       /* device or host allocation failed */
     BHAC_EDEVICE = -3,      /* no usable GPU, or a HIP runtime error */
     BHAC_EALIAS = -4,       /* an output aliases an input it must not alias */
-    BHAC_EUNSUPPORTED = -5  /* a valid combination this build does not implement */
+    BHAC_EUNSUPPORTED = -5  /* a valid combination the library does not implement */
 };
 enum { BHAC_METRIC_MINKOWSKI_CART = 0, BHAC_METRIC_KS_SPH_LOGR = 1 };
 enum { BHAC_BC_PERIODIC = 0, BHAC_BC_OUTFLOW = 1 };

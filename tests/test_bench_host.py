@@ -112,3 +112,10 @@ def test_bytes_of_the_update_with_x1_faces_in_place():
     # as the update, without the x1 face fluxes: 9 (1.5 * 8 + R + 2R + 8 + R)
     assert bench.bytes_per_unit("update_x1", 8) == 468
     assert bench.bytes_per_unit("update_x1", 4) == 324
+
+
+def test_source_digest_ignores_comments_only():
+    src = 'int f(int a) { // a comment\n  /* another\n  one */ return a + 1; } const char *s = "//x";'
+    assert bench._strip_comments(src) == bench._strip_comments(src.replace("a comment", "reworded"))
+    assert bench._strip_comments(src) != bench._strip_comments(src.replace("a + 1", "a + 2"))
+    assert '"//x"' in bench._strip_comments(src)
