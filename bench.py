@@ -63,7 +63,7 @@ WORKLOADS = {
     "ks_torus_128_fp64_x1u": dict(cfg=2, n=128, precision=0, fused=0,
                                   sched=dict(march_mask=6, march_faces=17, x1_staged=2)),
     "ks_torus_128_mixed_x1u": dict(cfg=2, n=128, precision=1, fused=0,
-                                   sched=dict(march_mask=4, march_faces=17, x1_staged=2)),
+                                   sched=dict(march_mask=6, march_faces=17, x1_staged=2)),
 }
 
 

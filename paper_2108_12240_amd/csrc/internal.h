@@ -65,7 +65,7 @@ constexpr int x1s_max_cells() { return sizeof(R) == 4 ? 600 : 400; }
 // rows of s0 cells one work-group of the update with in-place x1 faces takes: one
 // thread per x1 face of the rows (s0 + 1 per row)
 constexpr int x1u_rows(int s0) { return WG / (s0 + 1); }
-constexpr int MARCH_MASK_F32 = 4;
+constexpr int MARCH_MASK_F32 = 6;
 constexpr int MARCH_MASK_F64 = 6;
 // the x1 faces are computed inside the update kernel (sched.x1_staged = 2) only when
 // a schedule asks for it: it pays at 128^3 in FP64 (-4 % per step) but costs 8 % on
