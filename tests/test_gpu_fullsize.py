@@ -154,8 +154,6 @@ def test_block_tree_full_grid_one_step(prec, tol):
     print(f"\n[fullsize] {c.name} prec={prec}", flush=True)
     dt = 1e-3
     G = B.Grid(c.params, c.blocks)
-    if fused == "x1u":
-        assert G.schedule()["x1_staged"] == 2
     U, P = G.init(c.prim)
     G.set_dt(dt)
     U1, P1 = G.new_state("U"), G.new_state("P")
