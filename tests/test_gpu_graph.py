@@ -12,12 +12,17 @@ pytestmark = pytest.mark.gpu
     ("torus32_fp64_plain", lambda: I.case_torus(2, n=32), I.PREC_FP64, 0),
     ("torus48x32x32_mixed_fused", lambda: I.case_torus(2, n=(48, 32, 32)), I.PREC_MIXED, 1),
     ("case1_mixed_plain", lambda: I.case1(), I.PREC_MIXED, 0),
+    # the update computing the x1 faces itself (one side stream for x3)
+    ("torus32_fp64_x1u", lambda: I.case_torus(2, n=32), I.PREC_FP64, "x1u"),
+    ("torus48x32x32_mixed_x1u", lambda: I.case_torus(2, n=(48, 32, 32)), I.PREC_MIXED, "x1u"),
 ])
 def test_graph_replays_match_eager(name, make, prec, fused):
     import torch
     print(f"\n[graph] {name}", flush=True)
     c = make()
-    c.params = dict(c.params, precision=prec, fused=fused)
+    c.params = dict(c.params, precision=prec, fused=0 if fused == "x1u" else fused)
+    if fused == "x1u":
+        c.params["sched"] = dict(march_mask=6, march_faces=17, x1_staged=2)
     # eager reference after 1, 2, 3 steps
     G = B.Grid(c.params, c.blocks)
     U, P = G.init(c.prim)
