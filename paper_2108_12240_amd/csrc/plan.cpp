@@ -317,7 +317,8 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     // other two lattice coordinates, then the coordinate along d), so the blocks
     // whose interiors a block's stencils reach are its neighbours in the list and,
     // after the XCD split below, mostly on the same XCD (one L2)
-    const int march_faces = p.sched.set ? p.sched.march_faces : MARCH_MAX_FACES;
+    const int march_faces = p.sched.set ? p.sched.march_faces
+                                        : (p.precision == BHAC_PREC_MIXED ? MARCH_FACES_F32 : MARCH_FACES_F64);
     P.march_faces = march_faces;
     for (int d = 0; d < p.ndim; d++) {
         std::vector<int> ord(nb);
