@@ -74,9 +74,9 @@ WORKLOADS = {
 # on; with any other sources the field is reported as null.
 TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
-    ("ks_torus_128_fp64_plain", "update"): (1165752368, "b6b7905c1aa83502"),
-    ("ks_torus_128_mixed_plain", "update"): (774013701, "b6b7905c1aa83502"),
-    ("ks_torus_128_mixed_auto", "update"): (774013701, "b6b7905c1aa83502"),
+    ("ks_torus_128_fp64_plain", "update"): (1165887115, "bf50faf62767a30b"),
+    ("ks_torus_128_mixed_plain", "update"): (773995659, "bf50faf62767a30b"),
+    ("ks_torus_128_mixed_auto", "update"): (773995659, "bf50faf62767a30b"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
@@ -86,20 +86,20 @@ TRAFFIC = {
 # 2.4 GHz = 39.3e12 lane-instructions/s (one wave64 instruction takes 4 cycles of
 # a 16-lane SIMD; FP64 and unpacked FP32 issue at the same rate).
 VALU = {
-    ("ks_torus_128_fp64_x1u", "flux_x2"): (27163052, "b6b7905c1aa83502"),
-    ("ks_torus_128_fp64_x1u", "flux_x3"): (24566758, "b6b7905c1aa83502"),
-    ("ks_torus_128_fp64_x1u", "update_x1"): (94183008, "b6b7905c1aa83502"),
-    ("ks_torus_128_mixed_x1u", "flux_x2"): (23059716, "b6b7905c1aa83502"),
-    ("ks_torus_128_mixed_x1u", "flux_x3"): (20330853, "b6b7905c1aa83502"),
-    ("ks_torus_128_mixed_x1u", "update_x1"): (85036049, "b6b7905c1aa83502"),
-    ("ks_torus_128_fp64_plain", "flux_x1"): (49046823, "b6b7905c1aa83502"),
-    ("ks_torus_128_fp64_plain", "flux_x2"): (27162976, "b6b7905c1aa83502"),
-    ("ks_torus_128_fp64_plain", "flux_x3"): (24566772, "b6b7905c1aa83502"),
-    ("ks_torus_128_fp64_plain", "update"): (43153491, "b6b7905c1aa83502"),
-    ("ks_torus_128_mixed_plain", "flux_x1"): (38379246, "b6b7905c1aa83502"),
-    ("ks_torus_128_mixed_plain", "flux_x2"): (23059653, "b6b7905c1aa83502"),
-    ("ks_torus_128_mixed_plain", "flux_x3"): (20330946, "b6b7905c1aa83502"),
-    ("ks_torus_128_mixed_plain", "update"): (44726319, "b6b7905c1aa83502"),
+    ("ks_torus_128_fp64_x1u", "flux_x2"): (27163123, "bf50faf62767a30b"),
+    ("ks_torus_128_fp64_x1u", "flux_x3"): (24566791, "bf50faf62767a30b"),
+    ("ks_torus_128_fp64_x1u", "update_x1"): (94183020, "bf50faf62767a30b"),
+    ("ks_torus_128_mixed_x1u", "flux_x2"): (23059687, "bf50faf62767a30b"),
+    ("ks_torus_128_mixed_x1u", "flux_x3"): (20330794, "bf50faf62767a30b"),
+    ("ks_torus_128_mixed_x1u", "update_x1"): (85035948, "bf50faf62767a30b"),
+    ("ks_torus_128_fp64_plain", "flux_x1"): (49046930, "bf50faf62767a30b"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27163084, "bf50faf62767a30b"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24566778, "bf50faf62767a30b"),
+    ("ks_torus_128_fp64_plain", "update"): (43153478, "bf50faf62767a30b"),
+    ("ks_torus_128_mixed_plain", "flux_x1"): (38379255, "bf50faf62767a30b"),
+    ("ks_torus_128_mixed_plain", "flux_x2"): (23059859, "bf50faf62767a30b"),
+    ("ks_torus_128_mixed_plain", "flux_x3"): (20330799, "bf50faf62767a30b"),
+    ("ks_torus_128_mixed_plain", "update"): (44726327, "bf50faf62767a30b"),
 }
 VALU_PEAK = 39.3e12      # lane-instructions/s
 
