@@ -104,6 +104,10 @@ def test_autotune_search_space_is_valid():
     scheds = [x["sched"] for x in cands[1:]]
     assert len({tuple(sorted(x.items())) for x in scheds}) == len(scheds)
     assert {x["march_mask"] for x in scheds} == set(range(8))
+    # every x1 mode where x1 is not marched, none where it is
+    assert {x["x1_staged"] for x in scheds if not x["march_mask"] & 1} == {0, 1, 2}
+    assert {x["x1_staged"] for x in scheds if x["march_mask"] & 1} == {0}
+    assert len(cands) == 1 + 3 + 3 * 9 + 4 * 3
     # each candidate passes the library's parameter check (host-only planning)
     for x in cands[1:]:
         B.bhac_plan_ghosts(dict(c.params, **x), c.blocks)
