@@ -25,6 +25,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define NV 9
 #define NVE 10                         /* with the entropy field */
@@ -61,6 +62,27 @@ typedef struct {
     int max_iter;
     int64_t c2p_backup;                /* cells whose inversion came from the entropy backup */
 } orc_state;
+
+/* Inversion counters of one block (merged into orc_state after the block). */
+typedef struct { int64_t fail, floors, backup; int max_iter; } ocount;
+
+static void ocount_merge(orc_state *st, const ocount *c)
+{
+    st->c2p_fail += c->fail;
+    st->floor_hits += c->floors;
+    st->c2p_backup += c->backup;
+    if (c->max_iter > st->max_iter) st->max_iter = c->max_iter;
+}
+
+/* Threads of the block loops (default 1: the oracle runs single-threaded unless a
+ * caller asks for more). Blocks are independent within every call, each block's
+ * arithmetic is the same whichever thread runs it, and the only cross-block
+ * results are exact (integer counts and maxima), so any thread count gives
+ * bit-identical results. */
+static int g_threads = 1;
+
+void orc_set_threads(int n) { g_threads = n > 0 ? n : 1; }
+int orc_get_threads(void) { return g_threads; }
 
 /* ---------------------------------------------------------------------------------
  * Spacetime metric (reading: stationary Kerr-Schild in spherical coordinates with
@@ -996,6 +1018,8 @@ void orc_fill_ghosts(const orc_grid *G, double *P, const int64_t *blocks, int64_
 {
     const int64_t ncp = G->off[G->nb];
     const int64_t n = blocks ? nsel : G->nb;
+    /* each block writes its own ghost slots from interior cells only */
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads)
     for (int64_t q = 0; q < n; q++) fill_block(G, (int)(blocks ? blocks[q] : q), P, ncp);
 }
 
@@ -1010,6 +1034,7 @@ void orc_prim2con(const orc_grid *G, const double *P, double *U, const int64_t *
 {
     const int64_t ncp = G->off[G->nb];
     const int64_t n = blocks ? nsel : G->nb;
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads)
     for (int64_t q = 0; q < n; q++) {
         const int b = (int)(blocks ? blocks[q] : q);
         const orc_block *B = &G->blk[b];
@@ -1034,9 +1059,11 @@ void orc_con2prim(const orc_grid *G, const double *U, double *P, int8_t *fail, o
 {
     const int64_t ncp = G->off[G->nb];
     const int64_t n = blocks ? nsel : G->nb;
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads)
     for (int64_t q = 0; q < n; q++) {
         const int b = (int)(blocks ? blocks[q] : q);
         const orc_block *B = &G->blk[b];
+        ocount cnt = { 0, 0, 0, 0 };
         for (int k = 0; k < B->size[2]; k++)
             for (int j = 0; j < B->size[1]; j++)
                 for (int i = 0; i < B->size[0]; i++) {
@@ -1050,13 +1077,15 @@ void orc_con2prim(const orc_grid *G, const double *U, double *P, int8_t *fail, o
                     const int f = c2p_point(&G->p, &m, Uc, Pg, Po, &nit, &fl, &bk);
                     for (int v = 0; v < nvar(&G->p); v++) P[v * ncp + c] = Po[v];
                     if (fail) fail[c] = (int8_t)f;
-                    if (st) {
-                        st->c2p_fail += f;
-                        st->c2p_backup += bk;
-                        st->floor_hits += (!f && fl);
-                        if (nit > st->max_iter) st->max_iter = nit;
-                    }
+                    cnt.fail += f;
+                    cnt.backup += bk;
+                    cnt.floors += (!f && fl);
+                    if (nit > cnt.max_iter) cnt.max_iter = nit;
                 }
+        if (st) {
+#pragma omp critical(oracle_counts)
+            ocount_merge(st, &cnt);
+        }
     }
 }
 
@@ -1076,6 +1105,8 @@ void orc_compute_dt(const orc_grid *G, const double *P, orc_state *st)
 {
     const int64_t ncp = G->off[G->nb];
     double lam[3] = { 0.0, 0.0, 0.0 };
+    /* maxima are exact, so the order in which blocks are visited does not matter */
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads) reduction(max : lam[:3])
     for (int64_t b = 0; b < G->nb; b++) {
         const orc_block *B = &G->blk[b];
         for (int k = 0; k < B->size[2]; k++)
@@ -1171,7 +1202,8 @@ static void block_fluxes(const orc_grid *G, int bk, const double *Ps, double ch,
 
 /* Flux divergence, sources, RK combine and inversion of block bk. */
 static void block_update(const orc_grid *G, int bk, double *F[3], const double *Ub, const double *Us,
-                         const double *Ps, double *Uo, double *Po, double a, double b, orc_state *st)
+                         const double *Ps, double *Uo, double *Po, double a, double b, const orc_state *st,
+                         ocount *cnt)
 {
     const orc_params *p = &G->p;
     const int64_t ncp = G->off[G->nb];
@@ -1209,10 +1241,10 @@ static void block_update(const orc_grid *G, int bk, double *F[3], const double *
                 /* failed, floored or backed-up cells take the conserved state of
                  * their primitives (the energy is what could not be inverted) */
                 if (f || fl || bu) p2c_point(p, &m, Pn, Un);
-                st->c2p_fail += f;
-                st->c2p_backup += bu;
-                st->floor_hits += (!f && fl);
-                if (nit > st->max_iter) st->max_iter = nit;
+                cnt->fail += f;
+                cnt->backup += bu;
+                cnt->floors += (!f && fl);
+                if (nit > cnt->max_iter) cnt->max_iter = nit;
                 for (int v = 0; v < nv; v++) { Uo[v * ncp + c] = Un[v]; Po[v * ncp + c] = Pn[v]; }
             }
 }
@@ -1299,6 +1331,9 @@ int orc_substep(const orc_grid *G, const double *Ub, const double *Us, const dou
     double lam[3] = { 0.0, 0.0, 0.0 };
     const int64_t n = blocks ? nsel : G->nb;
     if (!p->amr) {
+        /* blocks are independent: each reads P_stage and U and writes only its own
+         * cells of U_out and P_out (which alias no input read by another block) */
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads) reduction(max : lam[:3])
         for (int64_t q = 0; q < n; q++) {
             const int bk = (int)(blocks ? blocks[q] : q);
             const orc_block *B = &G->blk[bk];
@@ -1307,14 +1342,18 @@ int orc_substep(const orc_grid *G, const double *Ub, const double *Us, const dou
                 const int64_t nf = (int64_t)(B->size[0] + (d == 0)) * (B->size[1] + (d == 1)) * (B->size[2] + (d == 2));
                 F[d] = malloc(nvar(p) * nf * sizeof(double));
             }
+            ocount cnt = { 0, 0, 0, 0 };
             block_fluxes(G, bk, Ps, st->ch, F, lam);
-            block_update(G, bk, F, Ub, Us, Ps, Uo, Po, a, b, st);
+            block_update(G, bk, F, Ub, Us, Ps, Uo, Po, a, b, st, &cnt);
+#pragma omp critical(oracle_counts)
+            ocount_merge(st, &cnt);
             for (int d = 0; d < p->ndim; d++) free(F[d]);
         }
     } else {
         /* block tree: every block's fluxes (a coarse face needs its fine neighbours'),
          * the level-boundary correction, then the update of the selected blocks */
         double **F = calloc(3 * G->nb, sizeof(double *));
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads) reduction(max : lam[:3])
         for (int64_t bk = 0; bk < G->nb; bk++) {
             const orc_block *B = &G->blk[bk];
             double *Fb[3] = { NULL, NULL, NULL };
@@ -1326,9 +1365,13 @@ int orc_substep(const orc_grid *G, const double *Ub, const double *Us, const dou
             block_fluxes(G, (int)bk, Ps, st->ch, Fb, lam);
         }
         flux_fix(G, F);
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads)
         for (int64_t q = 0; q < n; q++) {
             const int bk = (int)(blocks ? blocks[q] : q);
-            block_update(G, bk, &F[bk * 3], Ub, Us, Ps, Uo, Po, a, b, st);
+            ocount cnt = { 0, 0, 0, 0 };
+            block_update(G, bk, &F[bk * 3], Ub, Us, Ps, Uo, Po, a, b, st, &cnt);
+#pragma omp critical(oracle_counts)
+            ocount_merge(st, &cnt);
         }
         for (int64_t t = 0; t < 3 * G->nb; t++) free(F[t]);
         free(F);

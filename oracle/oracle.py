@@ -2,7 +2,9 @@
 
 Only tests/, the smoke check and the benchmark's CPU-baseline leg may import this
 module. It loads ``oracle/liboracle.so`` (built from ``oracle/oracle.c`` with gcc,
-``-O2 -ffp-contract=off``) and shares nothing with the HIP library or its binding.
+``-O2 -ffp-contract=off``, OpenMP over blocks, one thread unless ``set_threads``
+asks for more, with bit-identical results) and shares nothing with the HIP library
+or its binding.
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with plain IEEE FP64 semantics (no contraction, no fast-math)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp",
                                "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -90,8 +92,19 @@ def lib():
         L.orc_c2p_entropy_point.restype = C.c_int
         L.orc_c2p_entropy_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, C.c_double, _D]
         L.orc_sources.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D, C.c_double, _D]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's block loops (1 = single-threaded, the default)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def make_params(d: dict) -> Params:

@@ -14,8 +14,9 @@ Each candidate advances a copy of the workload's initial state with replays of
 the captured RK2-step graph; the fastest wins. Every schedule computes the same
 fluxes, so the choice changes speed, not results. Choices are cached in a JSON
 file keyed by the GPU architecture and a signature of the workload (metric,
-dimensionality, reconstruction, flux, precision, block tree or not, and the
-histogram of block (level, size)), so later runs skip the timing. Everything
+dimensionality, reconstruction, flux, precision, block tree or not, entropy field
+or not, and the histogram of block (level, size)) and of the library's sources,
+so later runs skip the timing and a change of the kernels invalidates the choice. Everything
 timed runs in the library's kernels.
 """
 from __future__ import annotations
@@ -49,13 +50,30 @@ def cache_path() -> str:
     return os.environ.get(CACHE_ENV) or os.path.join(os.path.expanduser("~"), ".cache", "bhac_autotune.json")
 
 
+def source_digest() -> str:
+    """Digest of the library's kernel and interface sources (C/C++ comments
+    excluded), so that a choice timed on other kernels is not reused."""
+    import re
+    pat = re.compile(r'"(?:\\.|[^"\\])*"|//[^\n]*|/\*.*?\*/', re.S)
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha1()
+    for d in (os.path.join(here, "csrc"), os.path.join(os.path.dirname(here), "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".h", ".cpp")):
+                with open(os.path.join(d, f), encoding="utf-8") as fh:
+                    src = pat.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", fh.read())
+                h.update(f.encode() + b"\0" + src.encode())
+    return h.hexdigest()[:16]
+
+
 def signature(params: dict, blocks: np.ndarray) -> dict:
     keys = ("metric", "ndim", "recon", "flux", "precision", "nghost")
     hist = {}
     for blk in np.asarray(blocks):
         k = f"{int(blk[0])}:{int(blk[1])}x{int(blk[2])}x{int(blk[3])}"
         hist[k] = hist.get(k, 0) + 1
-    return dict({k: int(params[k]) for k in keys}, amr=int(params.get("amr", 0)), search=SEARCH_VERSION,
+    return dict({k: int(params[k]) for k in keys}, amr=int(params.get("amr", 0)),
+                entropy=int(params.get("entropy", 0)), search=SEARCH_VERSION, sources=source_digest(),
                 blocks=dict(sorted(hist.items())))
 
 

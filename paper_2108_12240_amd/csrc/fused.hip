@@ -18,6 +18,7 @@
 // those rows.
 #include <hip/hip_runtime.h>
 
+#include "compensated.h"
 #include "physics.h"
 
 namespace bhac {
@@ -407,11 +408,7 @@ __global__ __launch_bounds__(WG) void k_update_div(KParams kp, GridDev gd, const
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             const double L = S[v] - (double)dU[v * nci + ic];
-            const double x = dt * L;
-            const double s = Uc[v] + x;
-            const double bb = s - Uc[v];
-            const double e = (Uc[v] - (s - bb)) + (x - bb);
-            Un[v] = (BASE ? a * Ub[v * kp.nci + ic] : 0.0) + (b * s + b * e);
+            Un[v] = rk_combine<BASE>(a, BASE ? Ub[v * kp.nci + ic] : 0.0, b, Uc[v], dt, L);
         }
         int backup;
         fail = con_to_prim(Un, q, m, kp, Pn, nit, floored, backup);

@@ -9,6 +9,7 @@
 // along x inside a block.
 #include <hip/hip_runtime.h>
 
+#include "compensated.h"
 #include "physics.h"
 
 namespace bhac {
@@ -337,13 +338,6 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(K
 // ---------------------------------------------------------------------------------
 // Update: divergence (in R), sources, RK combine (double), inversion (double).
 // ---------------------------------------------------------------------------------
-__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
-{
-    s = a + b;
-    const double bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
 // ND3: three dimensions (else two); BASE: a != 0, so U_base is read. Both are
 // template parameters so that every load of a cell sits in one basic block and is
 // issued before the first wait (a uniform run-time branch per value would split
@@ -395,21 +389,10 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
         double Un[NQ];
 #pragma unroll
         for (int v = 0; v < NQ; v++) {
-            // L = -(div_1 + div_2 + div_3) + S with a Neumaier compensation
-            double sum = -div[0][v], comp = 0.0;
-            const double terms[3] = {-div[1][v], -div[2][v], S[v]};
-#pragma unroll
-            for (int q2 = 0; q2 < 3; q2++) {
-                const double x = terms[q2];
-                const double t = sum + x;
-                comp += fabs(sum) >= fabs(x) ? (sum - t) + x : (x - t) + sum;
-                sum = t;
-            }
-            const double Lv = sum + comp;
-            // U_out = a U_base + b (U_stage + dt L): the stage sum as an exact pair
-            double s2, e2;
-            two_sum(Uc[v], dt * Lv, s2, e2);
-            Un[v] = (BASE ? a * Ub[v * kp.nci + ci] : 0.0) + (b * s2 + b * e2);
+            // L = -(div_1 + div_2 + div_3) + S with a Neumaier compensation, then
+            // U_out = a U_base + b (U_stage + dt L) rounded once
+            const double Lv = neumaier4(-div[0][v], -div[1][v], -div[2][v], S[v]);
+            Un[v] = rk_combine<BASE>(a, BASE ? Ub[v * kp.nci + ci] : 0.0, b, Uc[v], dt, Lv);
         }
         double Pn[NQ];
         fail = con_to_prim<ENT>(Un, q, m, kp, Pn, nit, floored, backup);
@@ -545,19 +528,8 @@ __global__ __launch_bounds__(WG, 3) void k_update_x1(KParams kp, GridDev gd, con
         double Un[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) {
-            double sum = -div[0][v], comp = 0.0;
-            const double terms[3] = {-div[1][v], -div[2][v], S[v]};
-#pragma unroll
-            for (int q2 = 0; q2 < 3; q2++) {
-                const double x = terms[q2];
-                const double t = sum + x;
-                comp += fabs(sum) >= fabs(x) ? (sum - t) + x : (x - t) + sum;
-                sum = t;
-            }
-            const double Lv = sum + comp;
-            double s2, e2;
-            two_sum(Uc[v], dt * Lv, s2, e2);
-            Un[v] = (BASE ? a * Ub[v * kp.nci + ci] : 0.0) + (b * s2 + b * e2);
+            const double Lv = neumaier4(-div[0][v], -div[1][v], -div[2][v], S[v]);
+            Un[v] = rk_combine<BASE>(a, BASE ? Ub[v * kp.nci + ci] : 0.0, b, Uc[v], dt, Lv);
         }
         double Pn[NV];
         fail = con_to_prim<false>(Un, q, m, kp, Pn, nit, floored, backup);

@@ -94,6 +94,11 @@ def test_autotune_signature_is_host_logic():
     k1 = autotune._key("gfx950", sig)
     assert k1 == autotune._key("gfx950", autotune.signature(c.params, c.blocks))
     assert k1 != autotune._key("gfx942", sig)
+    # the entropy field and the library's sources are part of the key
+    sig_e = autotune.signature(dict(c.params, entropy=1), c.blocks)
+    assert sig_e["entropy"] == 1 and autotune._key("gfx950", sig_e) != k1
+    assert sig["sources"] == autotune.source_digest() and len(sig["sources"]) == 16
+    assert autotune._key("gfx950", dict(sig, sources="0" * 16)) != k1
 
 
 def test_autotune_search_space_is_valid():
