@@ -3,14 +3,19 @@
 
 Metric: zone-updates per second, counting interior cells times RK substeps (the
 paper's "cellupdates", Section 4.2). One benchmark step is one SSP-RK2 step = two
-substeps, each a full pass of the hot path (ghost fill, reconstruction, face
-fluxes, divergence, sources, RK combine, inversion, wave-speed reduction) over the
-whole grid. Inputs are synthetic and already resident in HBM when timing starts.
+substeps, each a full pass of the hot path (halo reads, reconstruction, face fluxes,
+divergence, sources, RK combine, inversion, wave-speed reduction) over the whole
+grid, with the CFL time step from the wave-speed reduction. Inputs are synthetic and
+already resident in HBM when timing starts.
 
-Prints ONE JSON line. Besides the headline path it reports the dominant kernel's
-roofline (algorithmic bytes per launch over its HIP-event-timed average duration),
-the other precision on the same grid, and the CPU oracle timed on a bounded
-sample of the same workload.
+Headline: the 384^3 turbulent Kerr-Schild torus (13824 blocks of 16^3), mixed
+precision, run for W warmup steps and then R timed segments of K steps each, one
+continuous CFL-stepped run (W + R K steps; 105 with the defaults and with the
+driver's K = 20); value = the median segment, with the best beside it. Beside it:
+the plain FP64 path on the same grid (same protocol) and its speed-up, the 128^3
+FP64 and 192^3 mixed torus grids, rooflines (HBM on the state bytes of the method,
+VALU on its algorithmic flops) and the CPU oracle timed on the host's cores.
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -25,7 +30,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP_PEAK_TFLOPS = 78.6     # MI355X vector FP64 (and unpacked FP32), FMA = 2 flops
 METRIC = "zone-updates/s per RK substep (FP64 vs mixed, 1 GPU) + % HBM roofline"
+
+# Algorithmic HBM bytes per zone-substep: the state minimum of SSP-RK2 with the five
+# hydrodynamic primitives stored (stage 1 reads U and P and writes them; stage 2 also
+# reads U_base): 260 B with P in double, 220 B with P in float.
+STATE_BYTES = {8: 260.0, 4: 220.0}
+
+# Algorithmic flops per zone-substep (additions, multiplications, divisions, square
+# roots, transcendental calls) of the method on each workload: the oracle's op
+# counter (oracle/opcount.py: python -m oracle.opcount <name>, 32 evenly spaced
+# blocks) with every part counted once per unit of the method (one MC slope, PPM
+# interface and limiter per cell, direction and variable; two face states and one
+# Riemann combination per face; sources, inversion with the Newton steps the
+# workload takes, divergence and RK combine per cell; metric excluded). A test
+# recomputes the 128^3 entry.
+OPCOUNT = {
+    "ks_torus_128": dict(algorithmic=3020.506254906748, computed=4091.952346801758),
+    "ks_torus_192": dict(algorithmic=3012.2640030804805, computed=4084.5058059692383),
+    "ks_turb_384": dict(algorithmic=3004.655625287224, computed=4091.6902465820312),
+}
+WORKLOAD_OPS = {"ks_torus_128_fp64_plain": "ks_torus_128", "ks_torus_128_mixed_plain": "ks_torus_128",
+                "ks_torus_192_mixed_plain": "ks_torus_192", "ks_turb_384_mixed_plain": "ks_turb_384",
+                "ks_turb_384_fp64_plain": "ks_turb_384"}
 
 # Workloads: name -> (case builder kwargs, precision, fused)
 WORKLOADS = {
@@ -41,6 +69,7 @@ WORKLOADS = {
     "amr_like_4096_mixed_fused": dict(cfg=4, precision=1, fused=1),
     # 384^3 torus with seeded turbulence, 13824 blocks of 16^3, mixed precision
     "ks_turb_384_mixed_plain": dict(cfg=5, n=384, precision=1, fused=0),
+    "ks_turb_384_fp64_plain": dict(cfg=5, n=384, precision=0, fused=0),
     "ks_turb_384_mixed_fused": dict(cfg=5, n=384, precision=1, fused=1),
     # mixed precision, substep implementation chosen by the autotuner
     "ks_torus_128_fp64_auto": dict(cfg=2, n=128, precision=0, fused="auto"),
@@ -161,10 +190,12 @@ def grid_info(case, G):
     return dict(ghost_slots=int(dst.size), nface=nface, ncell=int(G.nci), nvar=int(G.nvar))
 
 
-def run_gpu(case, steps, warmup, graph=True):
-    """Time `steps` RK2 steps. With graph=True the timed loop replays the captured step
-    graph; per-kernel durations then come from a second, eager pass of the same number
-    of steps with HIP events around every launch (same kernels, same stream)."""
+def run_gpu(case, steps, warmup, repeats=1, graph=True, timing_steps=None):
+    """One continuous CFL-stepped run: `warmup` untimed RK2 steps, then `repeats`
+    timed segments of `steps` steps each (HIP events on the launch stream around each
+    segment). With graph=True the timed loop replays the captured step graph; the
+    per-kernel durations then come from an eager pass of `timing_steps` further steps
+    with HIP events around every launch (same kernels, same stream)."""
     import torch
     from paper_2108_12240_amd import bhac as B
 
@@ -181,17 +212,19 @@ def run_gpu(case, steps, warmup, graph=True):
     B.bhac_get_timing(G.h)
     if not graph:
         B.bhac_set_timing(G.h, True)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(steps):
-        step()
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
+    seg = []
+    for _ in range(repeats):
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(steps):
+            step()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        seg.append(start.elapsed_time(stop))
     if graph:
         B.bhac_set_timing(G.h, True)
-        for _ in range(steps):
+        for _ in range(timing_steps or steps):
             G.rk2_step(U, P, U1, P1)
         torch.cuda.synchronize()
     B.bhac_set_timing(G.h, False)
@@ -201,9 +234,15 @@ def run_gpu(case, steps, warmup, graph=True):
     ts = G.timestep()
     finite = bool(torch.isfinite(P).all().item())
     G.close()
+    del U, P, U1, P1
+    torch.cuda.empty_cache()
+    med = sorted(seg)[len(seg) // 2] if len(seg) % 2 else 0.5 * sum(sorted(seg)[len(seg) // 2 - 1:len(seg) // 2 + 1])
+    best = min(seg)
     zu = info["ncell"] * 2 * steps
-    return dict(ms_total=ms, ms_per_step=ms / steps, value=zu / (ms / 1e3), ktimes=ktimes, info=info,
-                stats=stats, dt=ts["dt"], finite=finite, graph=graph)
+    return dict(ms_total=sum(seg), ms_per_step=med / steps, ms_per_step_best=best / steps,
+                segments_ms=[round(x, 4) for x in seg], value=zu / (med / 1e3), value_best=zu / (best / 1e3),
+                ktimes=ktimes, info=info, stats=stats, dt=ts["dt"], finite=finite, graph=graph,
+                steps_run=warmup + repeats * steps + (timing_steps or steps if graph else 0))
 
 
 def valu_rates(res, workload):
@@ -232,16 +271,26 @@ def autotune_summary(rep):
                 best_ms=round(min(ms), 4), worst_ms=round(max(ms), 4))
 
 
+UPDATE_FAMILIES = ("update", "update_x1", "update_div")
+
+
 def roofline(res, rsz, workload):
-    """Roofline of the dominant kernel. Its bound is HBM unless a VALU instruction
-    count is stored for it (on the current sources) whose issue time at the chip's
-    peak exceeds the time its algorithmic bytes take at 8 TB/s (the update kernel
-    that computes the x1 faces itself); then it is reported against the VALU peak."""
+    """Roofline of the dominant kernel (largest share of the timed kernels).
+
+    The per-cell update is the kernel that moves the method's state (U_stage, U_base,
+    P_stage in, U_out, P_out out); its algorithmic bytes per launch are the state
+    bytes of one zone-substep (260 B FP64, 220 B mixed) times the zones. Its own
+    traffic (which also reads the face fluxes, and B and psi from P as well as U) is
+    reported beside it as kernel_bytes. Any other dominant kernel is measured on its
+    own bytes. Where a VALU instruction count is stored for the dominant kernel (on
+    the current sources) whose issue time at the chip's peak exceeds the HBM time of
+    its bytes, the bound is the VALU peak instead."""
     kt = {k: v for k, v in res["ktimes"].items() if k not in ("step_begin", "step_end", "untimed")}
     dom = max(kt, key=lambda k: kt[k][1])
     launches, total_ms = kt[dom]
     avg_s = total_ms / launches / 1e3
-    alg = bytes_per_unit(dom, rsz, res["info"]["nvar"]) * units_per_launch(dom, res["info"])
+    own = bytes_per_unit(dom, rsz, res["info"]["nvar"]) * units_per_launch(dom, res["info"])
+    alg = STATE_BYTES[rsz] * res["info"]["ncell"] if dom in UPDATE_FAMILIES else own
     achieved = alg / avg_s / 1e9
     dig = source_digest()
     measured = TRAFFIC.get((workload, dom))
@@ -250,6 +299,9 @@ def roofline(res, rsz, workload):
                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                traffic_over_algorithmic=round(traffic / alg, 3) if traffic else None,
                avg_launch_ms=round(total_ms / launches, 4), bytes_per_launch=alg,
+               bytes_basis="state bytes per zone-substep x zones" if dom in UPDATE_FAMILIES else "kernel's own bytes",
+               kernel_bytes_per_launch=own, kernel_bytes_frac=round(own / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+               traffic_over_kernel_bytes=round(traffic / own, 3) if traffic else None,
                share_of_step=round(total_ms / sum(v[1] for v in kt.values()), 3))
     counted = VALU.get((workload, dom))
     if counted and counted[1] == dig and counted[0] * 64 / VALU_PEAK > alg / (HBM_PEAK_GBS * 1e9):
@@ -259,51 +311,112 @@ def roofline(res, rsz, workload):
     return out
 
 
-def cpu_baseline(case, seconds_hint: float):
-    """The oracle as it stands, single-threaded, on a bounded sample of the same workload."""
+def substep_roofline(res, rsz, workload):
+    """The whole substep against both ceilings: the state bytes at 8 TB/s and the
+    method's algorithmic flops (oracle op counter) at the vector peak."""
+    zones = res["info"]["ncell"]
+    t = res["ms_per_step"] / 2 / 1e3
+    hbm = STATE_BYTES[rsz] * zones / t
+    out = dict(ms=round(t * 1e3, 4), state_bytes_per_zone=STATE_BYTES[rsz],
+               hbm_achieved_GBs=round(hbm / 1e9, 1), hbm_frac=round(hbm / (HBM_PEAK_GBS * 1e9), 4),
+               hbm_floor_ms=round(STATE_BYTES[rsz] * zones / (HBM_PEAK_GBS * 1e9) * 1e3, 4))
+    ops = OPCOUNT.get(WORKLOAD_OPS.get(workload, ""))
+    if ops:
+        fl = ops["algorithmic"] * zones
+        out.update(flops_per_zone=round(ops["algorithmic"], 1), alu_achieved_TFLOPs=round(fl / t / 1e12, 2),
+                   alu_peak_TFLOPs=FP_PEAK_TFLOPS, alu_frac=round(fl / t / (FP_PEAK_TFLOPS * 1e12), 4),
+                   alu_floor_ms=round(fl / (FP_PEAK_TFLOPS * 1e12) * 1e3, 4))
+    return out
+
+
+def host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return dict(cpu_model=model, logical_cpus=os.cpu_count(), usable_cpus=usable,
+                threads_allowed=min(usable, omp) if omp > 0 else usable)
+
+
+def _sample_case(case, nblk):
+    """The nblk blocks nearest (in level-0 cell units) to the block holding the densest
+    cell, as a grid of their own: the same cells, scheme and state; where a sampled
+    block's neighbour is not sampled, its halo follows the zero-gradient rule."""
+    import numpy as np
+    blk = np.asarray(case.blocks)
+    scale = 2.0 ** blk[:, 0:1]
+    centre = (blk[:, 4:7] + 0.5 * blk[:, 1:4]) / scale
+    dens = np.array([case.prim[0, case.ioff[b]:case.ioff[b + 1]].max() for b in range(len(blk))])
+    d = np.linalg.norm(centre - centre[int(dens.argmax())], axis=1)
+    sel = np.sort(np.argsort(d, kind="stable")[:max(1, min(nblk, len(blk)))])
+    prim = np.concatenate([case.prim[:, case.ioff[b]:case.ioff[b + 1]] for b in sel], axis=1)
+    return blk[sel], prim
+
+
+def cpu_baseline(case, seconds_hint: float, threads: int = 1):
+    """The oracle as it stands on a bounded sample of the same workload (whole RK2 steps
+    of a block sample, its ghost fills included), on `threads` host threads (the
+    oracle's block loops; results are bit-identical to one thread)."""
     import numpy as np
     from oracle import oracle as O
 
-    Og = O.OracleGrid(case.params, case.blocks)
-    U, P = Og.init(case.prim)
-    U1, P1 = np.zeros_like(U), np.zeros_like(P)
-    nb = Og.nb
-    # pick a block sample sized to the time hint from a short probe
-    probe = list(range(min(nb, 8)))
-    t0 = time.perf_counter()
-    Og.fill_ghosts(P, probe)
-    Og.substep(U, U, P, U1, P1, 0.0, 1.0, probe)
-    t_probe = time.perf_counter() - t0
-    per_block = t_probe / len(probe)
-    nsel = int(max(1, min(nb, seconds_hint / 2.0 / max(per_block, 1e-9))))
-    sel = list(range(nsel))
-    cells = int(Og.ioff[nsel])
-    # whole RK2 steps on the sample until about the time hint (the whole grid may
-    # take less than that for one step)
-    steps, el = 0, 0.0
-    t0 = time.perf_counter()
-    while steps == 0 or (el < 0.8 * seconds_hint and steps < 8):
-        Og.fill_ghosts(P, sel)
-        Og.substep(U, U, P, U1, P1, 0.0, 1.0, sel)
-        Og.fill_ghosts(P1, sel)
-        Og.substep(U, U1, P1, U1, P, 0.5, 0.5, sel)
-        U, U1 = U1, U                             # the step's result is the next step's state
-        steps += 1
-        el = time.perf_counter() - t0
-    return dict(value=round(cells * 2 * steps / el, 1), unit="zone-updates/s", cores=1, kind="oracle",
-                sample=f"{steps} RK2 step(s) (2 substeps with ghost fills each) on {nsel} of {nb} blocks "
-                       f"({cells} zones), single thread, {el:.1f} s")
+    O.set_threads(threads)
+    try:
+        def steps_on(nblk, budget, max_steps):
+            blocks, prim = _sample_case(case, nblk)
+            Og = O.OracleGrid(case.params, blocks)
+            U, P = Og.init(prim)
+            U1, P1 = np.zeros_like(U), np.zeros_like(P)
+            steps, el = 0, 0.0
+            t0 = time.perf_counter()
+            while steps == 0 or (el < budget and steps < max_steps):
+                Og.rk2_step(U, P, U1, P1)
+                steps += 1
+                el = time.perf_counter() - t0
+            return int(Og.nci), steps, el, len(blocks)
+
+        nb = case.nblocks
+        # probe: one step of a few blocks per thread gives the time per zone-update
+        cells, steps, el, _ = steps_on(min(nb, 2 * threads), 0.0, 1)
+        per_zu = el / (cells * 2 * steps)
+        bs = case.ioff[-1] / nb
+        nblk = int(max(1, min(nb, seconds_hint / 2.0 / (per_zu * 2 * bs))))
+        cells, steps, el, nsel = steps_on(nblk, 0.8 * seconds_hint, 8)
+    finally:
+        O.set_threads(1)
+    return dict(value=round(cells * 2 * steps / el, 1), unit="zone-updates/s", cores=threads, kind="oracle",
+                sample=f"{steps} RK2 step(s) (2 substeps with ghost fills each) of {nsel} of the {nb} blocks "
+                       f"({cells} zones; the blocks nearest the densest torus cell, as a grid of their own), "
+                       f"{threads} thread(s), {el:.1f} s")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10, help="timed SSP-RK2 steps (2 substeps each)")
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="ks_torus_128_fp64_plain", choices=sorted(WORKLOADS))
-    ap.add_argument("--compare", default="ks_torus_128_mixed_auto",
+    ap.add_argument("--steps", type=int, default=20, help="SSP-RK2 steps (2 substeps each) per timed segment")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--repeats", type=int, default=5, help="timed segments of one continuous run")
+    ap.add_argument("--workload", default="ks_turb_384_mixed_plain", choices=sorted(WORKLOADS))
+    ap.add_argument("--compare", default="ks_turb_384_fp64_plain",
                     help="second path on the same grid reported beside the headline ('' to skip)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--extra", default="ks_torus_128_fp64_plain,ks_torus_192_mixed_plain",
+                    help="further workloads timed with --extra-steps per segment ('' to skip)")
+    ap.add_argument("--extra-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of each oracle sample")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of the captured step graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -340,13 +453,18 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     torch.cuda.set_device(0)
+    cases = {}
 
     def make(name):
         w = dict(WORKLOADS[name])
         kw = {k: w[k] for k in ("n", "n0", "bs", "levels") if k in w}
-        c = I.make_case(w["cfg"], **kw)
-        if w.get("entropy"):
-            c = I.with_entropy(c)
+        key = (str(w["cfg"]), str(kw), bool(w.get("entropy")))
+        if key not in cases:
+            log(f"inputs of {name}")
+            c0 = I.make_case(w["cfg"], **kw)
+            cases[key] = I.with_entropy(c0) if w.get("entropy") else c0
+        c0 = cases[key]
+        c = I.Case(c0.name, dict(c0.params), c0.blocks, c0.prim, c0.ioff, c0.steps)
         if w["fused"] == "auto":
             from paper_2108_12240_amd import autotune
             params, report = autotune.tune(dict(c.params, precision=w["precision"]), c.blocks, c.prim)
@@ -358,40 +476,57 @@ def main(argv=None):
             c.params["sched"] = w["sched"]
         return c, w
 
-    case, w = make(args.workload)
-    res = run_gpu(case, args.steps, args.warmup, graph=not args.eager)
+    def measure(name, steps):
+        c, w = make(name)
+        log(f"timing {name}: {args.warmup} warmup + {args.repeats} x {steps} RK2 steps")
+        r = run_gpu(c, steps, args.warmup, repeats=args.repeats, graph=not args.eager,
+                    timing_steps=min(steps, 4))
+        rsz = 4 if w["precision"] == 1 else 8
+        summary = dict(workload=name, value=round(r["value"], 1), value_best=round(r["value_best"], 1),
+                       ms_per_step=round(r["ms_per_step"], 4), ms_per_step_best=round(r["ms_per_step_best"], 4),
+                       segments_ms=r["segments_ms"], steps_per_segment=steps, dtype="f64" if rsz == 8 else "f32+f64",
+                       zones=r["info"]["ncell"], roofline=roofline(r, rsz, name),
+                       substep=substep_roofline(r, rsz, name),
+                       kernel_ms={k: round(v[1] / max(v[0], 1), 4) for k, v in r["ktimes"].items()},
+                       valu=valu_rates(r, name), c2p=r["stats"], finite=r["finite"], dt_last=r["dt"])
+        if "autotune" in w:
+            summary["autotune"] = autotune_summary(w["autotune"])
+        return c, w, r, summary
+
+    case, w, res, head = measure(args.workload, args.steps)
     rsz = 4 if w["precision"] == 1 else 8
-    out = dict(metric=METRIC, value=round(res["value"], 1), unit="zone-updates/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=round(res["ms_per_step"], 4), higher_is_better=True,
-               scaling="weak", vs_baseline=None, dtype="f64" if rsz == 8 else "f32+f64",
+    out = dict(metric=METRIC, value=head["value"], unit="zone-updates/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=head["ms_per_step"], higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype=head["dtype"],
                data="synthetic (seeded Kerr-Schild torus, no dataset)",
                config=dict(workload=args.workload, zones=res["info"]["ncell"], blocks=int(case.nblocks),
                            block_sizes=sorted(set(int(v) for v in case.blocks[:, 1])),
                            levels=sorted(set(int(v) for v in case.blocks[:, 0])), substeps_per_step=2,
-                           recon="PPM", flux="HLL",
-                           fused=bool(w["fused"]), graph=res["graph"]),
-               roofline=roofline(res, rsz, args.workload))
+                           recon="PPM", flux="HLL", time_step="CFL (lagged wave-speed reduction)",
+                           fused=bool(w["fused"]), graph=res["graph"], repeats=args.repeats,
+                           steps_run=res["steps_run"]),
+               value_best=head["value_best"], ms_per_step_best=head["ms_per_step_best"],
+               segments_ms=head["segments_ms"], roofline=head["roofline"], substep=head["substep"],
+               kernel_ms=head["kernel_ms"], valu=head["valu"], c2p=head["c2p"], finite=head["finite"])
     if "autotune" in w:
-        out["config"]["autotune"] = autotune_summary(w["autotune"])
-    out["kernel_ms"] = {k: round(v[1] / max(v[0], 1), 4) for k, v in res["ktimes"].items()}
-    out["valu"] = valu_rates(res, args.workload)
-    out["c2p"] = res["stats"]
-    out["finite"] = res["finite"]
+        out["config"]["autotune"] = head["autotune"]
     if args.compare:
-        c2, w2 = make(args.compare)
-        r2 = run_gpu(c2, args.steps, args.warmup, graph=not args.eager)
-        rsz2 = 4 if w2["precision"] == 1 else 8
-        out["compare"] = dict(workload=args.compare, fused=bool(w2["fused"]), value=round(r2["value"], 1),
-                              ms_per_step=round(r2["ms_per_step"], 4), dtype="f64" if rsz2 == 8 else "f32+f64",
-                              speedup_vs_headline=round(r2["value"] / res["value"], 3),
-                              roofline=roofline(r2, rsz2, args.compare),
-                              kernel_ms={k: round(v[1] / max(v[0], 1), 4) for k, v in r2["ktimes"].items()})
-        out["compare"]["valu"] = valu_rates(r2, args.compare)
-        if "autotune" in w2:
-            out["compare"]["autotune"] = autotune_summary(w2["autotune"])
-        del c2
+        _, _, r2, cmp_ = measure(args.compare, args.steps)
+        cmp_["headline_speedup_over_this"] = round(res["value"] / r2["value"], 3)
+        out["compare"] = cmp_
+    if args.extra:
+        out["configs"] = {}
+        for name in [x for x in args.extra.split(",") if x]:
+            _, _, _, ex = measure(name, args.extra_steps)
+            out["configs"][name] = ex
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+        host = host_info()
+        log(f"oracle on the host: {host}")
+        base = cpu_baseline(case, args.cpu_seconds, threads=1)
+        base["host"] = host
+        if host["threads_allowed"] > 1:
+            base["all_cores"] = cpu_baseline(case, args.cpu_seconds, threads=host["threads_allowed"])
+        out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
     return 0
 

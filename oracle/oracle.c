@@ -29,6 +29,15 @@
 
 #define NV 9
 #define NVE 10                         /* with the entropy field */
+
+/* Op-count regions. The plain build leaves OC_SCOPE empty. The op-count build
+ * (opcount.cpp) compiles this file with a counting arithmetic type and defines
+ * OC_SCOPE to attribute the arithmetic of the enclosing block to a region, so that
+ * the algorithmic operations per zone and substep can be read per part of the
+ * method. */
+#ifndef OC_SCOPE
+#define OC_SCOPE(region)
+#endif
 enum { IRHO = 0, IU1 = 1, IP = 4, IB1 = 5, IPSI = 8, IENT = 9 };
 enum { ID = 0, IS1 = 1, ITAU = 4 };
 
@@ -98,6 +107,7 @@ typedef struct {
 
 static void metric_at(const orc_params *p, double x1, double x2, ometric *m)
 {
+    OC_SCOPE(OC_METRIC);
     memset(m, 0, sizeof *m);
     if (p->metric == 0) {
         m->alpha = 1.0;
@@ -193,6 +203,7 @@ static void state_from_prim(const orc_params *p, const ometric *m, const double 
 
 static void p2c_point(const orc_params *p, const ometric *m, const double *P, double *U)
 {
+    OC_SCOPE(OC_P2C);
     ostate s;
     state_from_prim(p, m, P, &s);
     U[ID] = m->sqrtg * s.D;
@@ -211,6 +222,7 @@ static void p2c_point(const orc_params *p, const ometric *m, const double *P, do
 static void phys_flux(const orc_params *p, const ometric *m, const double *P, int d,
                       double *U, double *F, double *lminus, double *lplus)
 {
+    OC_SCOPE(OC_FACE_STATE);
     const double gam = p->gamma_ad;
     ostate s;
     state_from_prim(p, m, P, &s);
@@ -260,6 +272,7 @@ static void phys_flux(const orc_params *p, const ometric *m, const double *P, in
 static double riemann(const orc_params *p, const ometric *mf, int d, const double *PL,
                       const double *PR, double ch, double *F)
 {
+    OC_SCOPE(OC_RIEMANN);
     const double sg = mf->sqrtg;
     const double btl = sg * PL[IB1 + d], btr = sg * PR[IB1 + d];
     const double psl = PL[IPSI], psr = PR[IPSI];
@@ -307,6 +320,7 @@ static double riemann(const orc_params *p, const ometric *mf, int d, const doubl
  * ------------------------------------------------------------------------------- */
 static double mc_slope(double qm, double q0, double qp)
 {
+    OC_SCOPE(OC_SLOPE);
     const double dm = q0 - qm, dp = qp - q0;
     if (dm * dp <= 0.0) return 0.0;
     double s = 2.0 * fabs(dm);
@@ -321,8 +335,13 @@ static void ppm_cell(const double *q, double *qminus, double *qplus)
     const double sm = mc_slope(q[0], q[1], q[2]);
     const double s0 = mc_slope(q[1], q[2], q[3]);
     const double sp = mc_slope(q[2], q[3], q[4]);
-    double ql = 0.5 * (q[1] + q[2]) - (s0 - sm) / 6.0;
-    double qr = 0.5 * (q[2] + q[3]) - (sp - s0) / 6.0;
+    double ql, qr;
+    {
+        OC_SCOPE(OC_PPM_IFACE);
+        ql = 0.5 * (q[1] + q[2]) - (s0 - sm) / 6.0;
+        qr = 0.5 * (q[2] + q[3]) - (sp - s0) / 6.0;
+    }
+    OC_SCOPE(OC_PPM_LIMIT);
     const double qi = q[2];
     if ((qr - qi) * (qi - ql) <= 0.0) {
         ql = qi;
@@ -340,8 +359,10 @@ static void ppm_cell(const double *q, double *qminus, double *qplus)
 static void recon_face(int method, const double *q, double *qL, double *qR)
 {
     if (method == 0) {
-        *qL = q[2] + 0.5 * mc_slope(q[1], q[2], q[3]);
-        *qR = q[3] - 0.5 * mc_slope(q[2], q[3], q[4]);
+        const double sl = mc_slope(q[1], q[2], q[3]), sr = mc_slope(q[2], q[3], q[4]);
+        OC_SCOPE(OC_MC_FACE);
+        *qL = q[2] + 0.5 * sl;
+        *qR = q[3] - 0.5 * sr;
     } else {
         double a, b;
         ppm_cell(q + 0, &a, qL);      /* cell i-1 uses i-3..i+1 */
@@ -357,6 +378,7 @@ static void recon_face(int method, const double *q, double *qL, double *qR)
 static void sources_point(const orc_params *p, const ometric *m, const double *P, const double *U,
                           double kappa, double *S)
 {
+    OC_SCOPE(OC_SOURCES);
     ostate s;
     state_from_prim(p, m, P, &s);
     const double sg = m->sqrtg;
@@ -508,6 +530,7 @@ static int c2p_entropy(const c2p_sys *c, double K, double Wg, double tol, double
 static int c2p_point(const orc_params *p, const ometric *m, const double *U, const double *Pg,
                      double *Pout, int *nit, int *floored, int *backup)
 {
+    OC_SCOPE(OC_C2P);
     const double sg = m->sqrtg;
     *nit = 0;
     *floored = 0;
@@ -682,6 +705,7 @@ static int64_t pad_index(const orc_grid *G, int b, int i, int j, int k)
 
 static double level_dx(const orc_grid *G, int level, int e)
 {
+    OC_SCOPE(OC_OTHER);
     return (G->p.x_hi[e] - G->p.x_lo[e]) / ((double)G->p.ncell0[e] * (double)(1 << level));
 }
 
@@ -1025,6 +1049,7 @@ void orc_fill_ghosts(const orc_grid *G, double *P, const int64_t *blocks, int64_
 
 static void cell_center(const orc_grid *G, int b, int i, int j, double *x1, double *x2)
 {
+    OC_SCOPE(OC_OTHER);
     const orc_block *B = &G->blk[b];
     *x1 = G->p.x_lo[0] + (B->origin[0] + i + 0.5) * level_dx(G, B->level, 0);
     *x2 = G->p.x_lo[1] + (B->origin[1] + j + 0.5) * level_dx(G, B->level, 1);
@@ -1211,6 +1236,7 @@ static void block_update(const orc_grid *G, int bk, double *F[3], const double *
     for (int k = 0; k < B->size[2]; k++)
         for (int j = 0; j < B->size[1]; j++)
             for (int i = 0; i < B->size[0]; i++) {
+                OC_SCOPE(OC_UPDATE);
                 const int64_t c = pad_index(G, bk, i, j, k);
                 const int nv = nvar(p);
                 double x1, x2, Pc[NVE], Uc[NVE], Sv[NVE], L[NVE], Un[NVE], Pn[NVE];

@@ -67,35 +67,41 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
-        L.orc_grid_new.restype = C.c_void_p
-        L.orc_grid_new.argtypes = [C.POINTER(Params), C.POINTER(Block), C.c_int64]
-        L.orc_grid_free.argtypes = [C.c_void_p]
-        L.orc_grid_layout.argtypes = [C.c_void_p, _I64, _I64]
-        L.orc_fill_ghosts.argtypes = [C.c_void_p, _D, _I64, C.c_int64]
-        L.orc_prim2con.argtypes = [C.c_void_p, _D, _D, _I64, C.c_int64]
-        L.orc_con2prim.argtypes = [C.c_void_p, _D, _D, C.POINTER(C.c_int8), C.POINTER(State), _I64, C.c_int64]
-        L.orc_compute_dt.argtypes = [C.c_void_p, _D, C.POINTER(State)]
-        L.orc_set_dt.argtypes = [C.POINTER(State), C.c_double]
-        L.orc_substep.restype = C.c_int
-        L.orc_substep.argtypes = [C.c_void_p, _D, _D, _D, _D, _D, C.c_double, C.c_double,
-                                  C.POINTER(State), _I64, C.c_int64]
-        L.orc_metric.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D]
-        L.orc_p2c_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D]
-        L.orc_c2p_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D, _D,
-                                    C.POINTER(C.c_int)]
-        L.orc_phys_flux.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, C.c_int, _D, _D, _D]
-        L.orc_riemann.restype = C.c_double
-        L.orc_riemann.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_int, _D, _D,
-                                  C.c_double, _D]
-        L.orc_recon_face.argtypes = [C.c_int, _D, _D]
-        L.orc_c2p_entropy_point.restype = C.c_int
-        L.orc_c2p_entropy_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, C.c_double, _D]
-        L.orc_sources.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D, C.c_double, _D]
-        L.orc_set_threads.argtypes = [C.c_int]
-        L.orc_get_threads.restype = C.c_int
-        _lib = L
+        _lib = load(LIB)
     return _lib
+
+
+def load(path: str):
+    """Load an oracle build (the plain one, or the op-count build of opcount.py, which
+    exports the same entry points) and declare its signatures."""
+    L = C.CDLL(path)
+    L.orc_grid_new.restype = C.c_void_p
+    L.orc_grid_new.argtypes = [C.POINTER(Params), C.POINTER(Block), C.c_int64]
+    L.orc_grid_free.argtypes = [C.c_void_p]
+    L.orc_grid_layout.argtypes = [C.c_void_p, _I64, _I64]
+    L.orc_fill_ghosts.argtypes = [C.c_void_p, _D, _I64, C.c_int64]
+    L.orc_prim2con.argtypes = [C.c_void_p, _D, _D, _I64, C.c_int64]
+    L.orc_con2prim.argtypes = [C.c_void_p, _D, _D, C.POINTER(C.c_int8), C.POINTER(State), _I64, C.c_int64]
+    L.orc_compute_dt.argtypes = [C.c_void_p, _D, C.POINTER(State)]
+    L.orc_set_dt.argtypes = [C.POINTER(State), C.c_double]
+    L.orc_substep.restype = C.c_int
+    L.orc_substep.argtypes = [C.c_void_p, _D, _D, _D, _D, _D, C.c_double, C.c_double,
+                              C.POINTER(State), _I64, C.c_int64]
+    L.orc_metric.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D]
+    L.orc_p2c_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D]
+    L.orc_c2p_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D, _D,
+                                C.POINTER(C.c_int)]
+    L.orc_phys_flux.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, C.c_int, _D, _D, _D]
+    L.orc_riemann.restype = C.c_double
+    L.orc_riemann.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_int, _D, _D,
+                              C.c_double, _D]
+    L.orc_recon_face.argtypes = [C.c_int, _D, _D]
+    L.orc_c2p_entropy_point.restype = C.c_int
+    L.orc_c2p_entropy_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, C.c_double, _D]
+    L.orc_sources.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D, C.c_double, _D]
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_get_threads.restype = C.c_int
+    return L
 
 
 def set_threads(n: int) -> None:

@@ -51,11 +51,35 @@ def fake_result(update_ms=0.25, launches=20):
 def test_roofline_of_the_dominant_kernel():
     r = bench.roofline(fake_result(), 8, "no_such_workload")
     assert r["kernel"] == "update" and r["bound"] == "hbm" and r["unit"] == "GB/s"
-    alg = 540 * 2 ** 21
+    # the update moves the method's state: 260 B per zone-substep in FP64
+    alg = 260 * 2 ** 21
     assert r["bytes_per_launch"] == alg
     assert r["achieved"] == pytest.approx(alg / 0.25e-3 / 1e9, rel=1e-6)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, abs=1e-4)
+    # its own bytes (face fluxes, B and psi in P as well) beside it
+    assert r["kernel_bytes_per_launch"] == 540 * 2 ** 21
+    assert r["kernel_bytes_frac"] == pytest.approx(540 * 2 ** 21 / 0.25e-3 / 8e12, abs=1e-4)
     assert r["traffic"] is None                      # nothing stored for this workload
+    assert bench.roofline(fake_result(), 4, "no_such_workload")["bytes_per_launch"] == 220 * 2 ** 21
+
+
+def test_whole_substep_roofline():
+    res = dict(fake_result(), ms_per_step=1.0)
+    res["info"]["ncell"] = 2 ** 21
+    s = bench.substep_roofline(res, 4, "ks_torus_128_mixed_plain")
+    t = 0.5e-3
+    assert s["hbm_frac"] == pytest.approx(220 * 2 ** 21 / t / 8e12, abs=1e-4)
+    fl = bench.OPCOUNT["ks_torus_128"]["algorithmic"] * 2 ** 21
+    assert s["alu_frac"] == pytest.approx(fl / t / 78.6e12, abs=1e-4)
+    assert s["alu_floor_ms"] == pytest.approx(fl / 78.6e12 * 1e3, rel=1e-3)
+    assert s["hbm_floor_ms"] == pytest.approx(220 * 2 ** 21 / 8e12 * 1e3, rel=1e-3)
+    assert "alu_frac" not in bench.substep_roofline(res, 4, "no_such_workload")
+
+
+def test_host_description():
+    h = bench.host_info()
+    assert h["logical_cpus"] >= 1 and 1 <= h["usable_cpus"] <= h["logical_cpus"]
+    assert 1 <= h["threads_allowed"] <= h["usable_cpus"] and isinstance(h["cpu_model"], str)
 
 
 def test_stored_traffic_is_used_only_with_matching_sources(monkeypatch):
@@ -63,7 +87,8 @@ def test_stored_traffic_is_used_only_with_matching_sources(monkeypatch):
     monkeypatch.setitem(bench.TRAFFIC, key, (1.2e9, bench.source_digest()))
     r = bench.roofline(fake_result(), 8, "fake_workload")
     assert r["traffic"] == 1.2e9
-    assert r["traffic_over_algorithmic"] == pytest.approx(1.2e9 / (540 * 2 ** 21), abs=1e-3)
+    assert r["traffic_over_algorithmic"] == pytest.approx(1.2e9 / (260 * 2 ** 21), abs=1e-3)
+    assert r["traffic_over_kernel_bytes"] == pytest.approx(1.2e9 / (540 * 2 ** 21), abs=1e-3)
     monkeypatch.setitem(bench.TRAFFIC, key, (1.2e9, "0000000000000000"))
     assert bench.roofline(fake_result(), 8, "fake_workload")["traffic"] is None
 
@@ -90,13 +115,24 @@ def test_cpu_baseline_runs_the_oracle_on_a_bounded_sample():
     out = bench.cpu_baseline(c, 0.5)
     assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "zone-updates/s"
     assert out["value"] > 0 and "blocks" in out["sample"]
+    two = bench.cpu_baseline(c, 0.5, threads=2)
+    assert two["cores"] == 2 and "2 thread(s)" in two["sample"]
+
+
+def test_oracle_sample_is_the_neighbourhood_of_the_densest_block():
+    c = I.case_torus(2, n=64)
+    blocks, prim = bench._sample_case(c, 5)
+    assert len(blocks) == 5 and prim.shape == (9, 5 * 16 ** 3)
+    dens = [c.prim[0, c.ioff[b]:c.ioff[b + 1]].max() for b in range(c.nblocks)]
+    densest = c.blocks[int(max(range(c.nblocks), key=lambda b: dens[b]))]
+    assert any((b == densest).all() for b in blocks)
 
 
 def test_bound_follows_the_larger_floor(monkeypatch):
     """With a stored VALU count whose issue time exceeds the HBM time of the
     kernel's algorithmic bytes, the roofline is taken against the VALU peak."""
     dig = bench.source_digest()
-    hbm_floor = 540 * 2 ** 21 / 8e12                       # s per launch at 8 TB/s
+    hbm_floor = 260 * 2 ** 21 / 8e12                       # s per launch at 8 TB/s
     small = int(0.5 * hbm_floor * bench.VALU_PEAK / 64)     # issue time half the HBM floor
     monkeypatch.setitem(bench.VALU, ("fake_workload", "update"), (small, dig))
     assert bench.roofline(fake_result(), 8, "fake_workload")["bound"] == "hbm"
@@ -105,7 +141,7 @@ def test_bound_follows_the_larger_floor(monkeypatch):
     r = bench.roofline(fake_result(), 8, "fake_workload")
     assert r["bound"] == "alu" and r["unit"] == "Tlane-instr/s"
     assert r["frac"] == pytest.approx(big * 64 / 0.25e-3 / bench.VALU_PEAK, abs=1e-4)
-    assert r["hbm_frac"] == pytest.approx(540 * 2 ** 21 / 0.25e-3 / 8e12, abs=1e-4)
+    assert r["hbm_frac"] == pytest.approx(260 * 2 ** 21 / 0.25e-3 / 8e12, abs=1e-4)
 
 
 def test_bytes_of_the_update_with_x1_faces_in_place():

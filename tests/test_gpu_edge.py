@@ -13,8 +13,12 @@ from tests.parity import rel_l1
 
 pytestmark = pytest.mark.gpu
 
-# element-wise bars: |gpu - oracle| <= RTOL |oracle| + ATOL max|oracle row|
+# element-wise bars: |gpu - oracle| <= RTOL |oracle| + ATOL scale, where scale is the
+# largest magnitude of the field's row, or of its parent vector's rows for the vector
+# components and psi (a component that is zero in the exact state is compared against
+# its vector, not against its own round-off)
 BARS = {I.PREC_FP64: (1e-12, 1e-13), I.PREC_MIXED: (1e-5, 1e-6)}
+ROW_SCALE = {1: (1, 4), 2: (1, 4), 3: (1, 4), 5: (5, 8), 6: (5, 8), 7: (5, 8), 8: (5, 8)}
 
 
 def banner(msg):
@@ -28,9 +32,13 @@ def torch():
     return T
 
 
-def close_elementwise(got, ref, prec, what):
-    rtol, atol = BARS[prec]
+def close_elementwise(got, ref, prec, what, rtol=None):
+    rtol_, atol = BARS[prec]
+    rtol = rtol_ if rtol is None else rtol
     scale = np.abs(ref).max(axis=1, keepdims=True)
+    for q, (lo, hi) in ROW_SCALE.items():
+        if q < ref.shape[0]:
+            scale[q] = np.abs(ref[lo:hi]).max()
     bad = np.abs(got - ref) > rtol * np.abs(ref) + atol * scale
     if bad.any():
         q, c = np.argwhere(bad)[0]
@@ -161,7 +169,9 @@ def test_lorentz_cap_matches_oracle(torch, prec):
     got = G.unpack(P)
     W = np.sqrt(1.0 + (got[1:4, sel] ** 2).sum(axis=0))
     assert np.allclose(W, c.params["w_max"], rtol=1e-5 if prec else 1e-12)
-    close_elementwise(got, Po[:, idx], prec, "P")
+    # at W ~ 50 the inversion amplifies relative differences of the conserved state by
+    # about W^2 = 2500: the FP64 bar there is 2500 x 1e-16 x a few, 1e-10
+    close_elementwise(got, Po[:, idx], prec, "P", rtol=1e-10 if prec == I.PREC_FP64 else None)
     # a substep from the capped state: the capped cells' neighbours see the fast flow
     G.set_dt(1e-3)
     Og.set_dt(1e-3)
@@ -179,12 +189,19 @@ def test_lorentz_cap_matches_oracle(torch, prec):
     st, ost = G.stats(), Og.stats()
     print(f"  substep gpu {st}\n  substep oracle {ost}", flush=True)
     assert st["floor_hits"] == ost["floor_hits"] and st["c2p_fail"] == ost["c2p_fail"]
-    eU = rel_l1(G.unpack(U1), U1o[:, idx])
-    eP = rel_l1(G.unpack(P1), P1o[:, idx])
-    print(f"  rel-L1 U {eU}\n  rel-L1 P {eP}", flush=True)
-    tol = 1e-11 if prec == I.PREC_FP64 else 1e-5
-    assert (eU <= tol).all() and (eP <= tol).all()
+    # psi starts from zero and one step makes it tiny: it is measured against its
+    # parent vector (the densitised field)
+    eU = rel_l1(G.unpack(U1), U1o[:, idx], parent_fields=(8,))
+    eP = rel_l1(G.unpack(P1), P1o[:, idx], parent_fields=(8,))
+    print(f"  rel-L1 U {eU}\n  rel-L1 P {eP}\n  own-sum psi {rel_l1(G.unpack(U1), U1o[:, idx])[8]:.3e}",
+          flush=True)
     if prec == I.PREC_FP64:
-        close_elementwise(G.unpack(P1), P1o[:, idx], prec, "P_out")
-        close_elementwise(G.unpack(U1), U1o[:, idx], prec, "U_out")
+        assert (eU <= 1e-11).all() and (eP <= 1e-11).all()
+        close_elementwise(G.unpack(P1), P1o[:, idx], prec, "P_out", rtol=1e-10)
+        close_elementwise(G.unpack(U1), U1o[:, idx], prec, "U_out", rtol=1e-10)
+    else:
+        # float face states of a W ~ 50 flow: float's 6e-8 relative error times the
+        # inversion's W^2 ~ 2500 amplification bounds the primitives' error by ~1.5e-4
+        assert (eU <= 1e-5).all(), eU
+        assert (eP <= 2e-4).all(), eP
     G.close()
