@@ -55,6 +55,7 @@ typedef struct {
     int c2p_maxit;
     int amr;                           /* 0 independent same-level patches, 1 2:1 block tree */
     int entropy;                       /* 1: carry the entropy field (P[9] = K, U[9] = U[0] K) */
+    int c2p_2d;                        /* 1: a failed inversion tries the two-unknown Newton backup */
 } orc_params;
 
 /* rows of P and U: the nine GRMHD variables, plus the entropy field if carried */
@@ -468,6 +469,77 @@ static double c2p_step(const c2p_sys *c, double xi)
 }
 
 /* ---------------------------------------------------------------------------------
+ * Two-unknown Newton backup (Section 2 lists multi-dimensional Newton solvers among
+ * the inversion's strategies). Reading: unknowns xi = rho h W^2 and q = W^2 - 1 (so
+ * v^2 = q / (1 + q) and the iteration never meets the wall v^2 = 1), with the
+ * momentum relation (the v^2(xi) identity multiplied out)
+ *   F1 = (xi + B^2)^2 q / (1 + q) - (S.B)^2 (2 xi + B^2) / xi^2 - S^2 = 0
+ * and the energy relation
+ *   F2 = xi - p + B^2 - (B^2 / (1 + q) + (S.B)^2 / xi^2) / 2 - (tau + D) = 0,
+ *   p = (Gamma - 1) / Gamma (xi / (1 + q) - D / sqrt(1 + q)),
+ * solved together: Newton steps with the analytic Jacobian, each step halved while
+ * it would leave xi > 0, q >= 0; stop when |dxi| <= tol xi and |dq| <= tol (1 + q),
+ * then one more step; at most maxit steps.
+ * ------------------------------------------------------------------------------- */
+static void c2p2_fj(const c2p_sys *c, double xi, double q, double F[2], double J[2][2])
+{
+    const double gi = (c->gam - 1.0) / c->gam;
+    const double sb2 = c->SB * c->SB, xb = xi + c->B2, w2inv = 1.0 / (1.0 + q), iw = sqrt(w2inv);
+    const double p = gi * (xi * w2inv - c->D * iw);
+    F[0] = xb * xb * q * w2inv - sb2 * (2.0 * xi + c->B2) / (xi * xi) - c->S2;
+    F[1] = xi - p + c->B2 - 0.5 * (c->B2 * w2inv + sb2 / (xi * xi)) - c->Ut;
+    const double dw2inv = -w2inv * w2inv;                 /* d(1/(1+q))/dq */
+    const double dp_dxi = gi * w2inv;
+    const double dp_dq = gi * (xi * dw2inv + 0.5 * c->D * iw * w2inv);
+    J[0][0] = 2.0 * xb * q * w2inv + 2.0 * sb2 * xb / (xi * xi * xi);
+    J[0][1] = xb * xb * w2inv * w2inv;
+    J[1][0] = 1.0 - dp_dxi + sb2 / (xi * xi * xi);
+    J[1][1] = -dp_dq - 0.5 * c->B2 * dw2inv;
+}
+
+/* one safeguarded Newton step of the pair; returns 1 where it cannot be taken */
+static int c2p2_step(const c2p_sys *c, double *xi, double *q, double tol, int *small)
+{
+    double F[2], J[2][2];
+    c2p2_fj(c, *xi, *q, F, J);
+    const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    if (!isfinite(det) || det == 0.0 || !isfinite(F[0]) || !isfinite(F[1])) return 1;
+    double dxi = -(J[1][1] * F[0] - J[0][1] * F[1]) / det;
+    double dq = -(J[0][0] * F[1] - J[1][0] * F[0]) / det;
+    int nh = 0;
+    while ((*xi + dxi <= 0.0 || *q + dq < 0.0) && nh < 64) {
+        dxi *= 0.5;
+        dq *= 0.5;
+        nh++;
+    }
+    if (*xi + dxi <= 0.0 || *q + dq < 0.0) return 1;
+    *xi += dxi;
+    *q += dq;
+    *small = fabs(dxi) <= tol * *xi && fabs(dq) <= tol * (1.0 + *q);
+    return 0;
+}
+
+/* from (xi, q) to a root (xi, q); returns 0 on convergence */
+static int c2p_newton2(const c2p_sys *c, double xi, double q, double tol, int maxit, double *xi_out, double *q_out,
+                       int *nit)
+{
+    int it = 0, conv = 0, small = 0;
+    while (it < maxit) {
+        if (c2p2_step(c, &xi, &q, tol, &small)) { *nit = it; return 1; }
+        it++;
+        if (small) { conv = 1; break; }
+    }
+    if (conv) {
+        if (c2p2_step(c, &xi, &q, tol, &small)) conv = 0;     /* one more step after the stopping test */
+        it++;
+    }
+    *nit = it;
+    *xi_out = xi;
+    *q_out = q;
+    return conv && isfinite(xi) && isfinite(q) ? 0 : 1;
+}
+
+/* ---------------------------------------------------------------------------------
  * Entropy backup of the inversion (Section 2 names backups; reading 19). The
  * entropy function K = p / rho^gamma is carried as its own field, so where the
  * energy relation cannot be inverted the pressure is p = K rho^gamma instead, and
@@ -592,6 +664,26 @@ static int c2p_point(const orc_params *p, const ometric *m, const double *U, con
             rho = c.D / W;
             prs = (c.gam - 1.0) / c.gam * (xi / (W * W) - rho);
             if (!(rho > 0.0) || !(prs >= 0.0) || !isfinite(rho) || !isfinite(prs)) fail = 1;
+        }
+    }
+    if (fail && p->c2p_2d && c.D > 0.0 && isfinite(c.Ut) && isfinite(c.S2) && isfinite(c.B2)) {
+        ostate g;
+        state_from_prim(p, m, Pg, &g);
+        const double xi0 = g.xi > 0.0 && isfinite(g.xi) ? g.xi : (c.Ut > c.D ? c.Ut : c.D);
+        const double q0 = isfinite(g.W) ? g.W * g.W - 1.0 : 0.0;
+        double xb, qb;
+        int n2;
+        if (c2p_newton2(&c, xi0, q0 > 0.0 ? q0 : 0.0, p->c2p_tol, p->c2p_maxit, &xb, &qb, &n2) == 0) {
+            const double Wb = sqrt(1.0 + qb), rb = c.D / Wb;
+            const double pb = (c.gam - 1.0) / c.gam * (xb / (Wb * Wb) - rb);
+            if (rb > 0.0 && pb >= 0.0 && isfinite(rb) && isfinite(pb)) {
+                W = Wb;
+                xi = xb;
+                rho = rb;
+                prs = pb;
+                fail = 0;
+                *backup = 1;
+            }
         }
     }
     if (fail && p->entropy) {
@@ -1444,6 +1536,73 @@ void orc_c2p_point(const orc_params *p, double x1, double x2, const double *U, c
     info[1] = nit;
     info[2] = fl;
     info[3] = bk;
+}
+
+/* The two-unknown Newton iteration alone, from the guess primitives Pg (no 1-D
+ * iteration first, no floors): P from U. Returns 0 on convergence to a physical state
+ * (rho > 0, p >= 0); *nit = steps taken. */
+static void c2p_system(const orc_params *p, const ometric *m, const double *U, c2p_sys *c, double Sl[3],
+                       double B[3], double Bl[3])
+{
+    const double sg = m->sqrtg;
+    c->gam = p->gamma_ad;
+    c->D = U[ID] / sg;
+    for (int i = 0; i < 3; i++) { Sl[i] = U[IS1 + i] / sg; B[i] = U[IB1 + i] / sg; }
+    c->Ut = U[ITAU] / sg + c->D;
+    c->S2 = 0.0;
+    c->B2 = 0.0;
+    c->SB = 0.0;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) c->S2 += m->gi[i][j] * Sl[i] * Sl[j];
+    for (int i = 0; i < 3; i++) {
+        Bl[i] = 0.0;
+        for (int j = 0; j < 3; j++) Bl[i] += m->g[i][j] * B[j];
+    }
+    for (int i = 0; i < 3; i++) { c->B2 += B[i] * Bl[i]; c->SB += Sl[i] * B[i]; }
+}
+
+int orc_c2p_2d_point(const orc_params *p, double x1, double x2, const double *U, const double *Pg, double *Pout,
+                     int *nit)
+{
+    ometric m;
+    metric_at(p, x1, x2, &m);
+    c2p_sys c;
+    double Sl[3], B[3], Bl[3];
+    c2p_system(p, &m, U, &c, Sl, B, Bl);
+    ostate g;
+    state_from_prim(p, &m, Pg, &g);
+    double xi, q;
+    if (c2p_newton2(&c, g.xi, g.W * g.W - 1.0, p->c2p_tol, p->c2p_maxit, &xi, &q, nit)) return 1;
+    const double W = sqrt(1.0 + q), rho = c.D / W;
+    const double prs = (c.gam - 1.0) / c.gam * (xi / (W * W) - rho);
+    if (!(rho > 0.0) || !(prs >= 0.0)) return 1;
+    Pout[IRHO] = rho;
+    for (int i = 0; i < 3; i++) {
+        double vu = 0.0;
+        for (int j = 0; j < 3; j++) vu += m.gi[i][j] * (Sl[j] + c.SB * Bl[j] / xi) / (xi + c.B2);
+        Pout[IU1 + i] = W * vu;
+    }
+    Pout[IP] = prs;
+    for (int i = 0; i < 3; i++) Pout[IB1 + i] = B[i];
+    Pout[IPSI] = U[IPSI];
+    return 0;
+}
+
+/* Residuals (F1, F2) and Jacobian (row-major) of the two-unknown system at (xi, q). */
+void orc_c2p_2d_residual(const orc_params *p, double x1, double x2, const double *U, double xi, double q, double *F,
+                         double *J)
+{
+    ometric m;
+    metric_at(p, x1, x2, &m);
+    c2p_sys c;
+    double Sl[3], B[3], Bl[3];
+    c2p_system(p, &m, U, &c, Sl, B, Bl);
+    double Jm[2][2];
+    c2p2_fj(&c, xi, q, F, Jm);
+    J[0] = Jm[0][0];
+    J[1] = Jm[0][1];
+    J[2] = Jm[1][0];
+    J[3] = Jm[1][1];
 }
 
 /* The entropy root alone (no energy inversion first): P from U (U[9] = U[0] K).

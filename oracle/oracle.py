@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("recon", C.c_int), ("flux", C.c_int),
                 ("cfl", C.c_double), ("rho_floor", C.c_double), ("p_floor", C.c_double),
                 ("w_max", C.c_double), ("glm_alpha", C.c_double), ("c2p_tol", C.c_double),
-                ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int)]
+                ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int), ("c2p_2d", C.c_int)]
 
 
 class Block(C.Structure):
@@ -99,6 +99,10 @@ def load(path: str):
     L.orc_c2p_entropy_point.restype = C.c_int
     L.orc_c2p_entropy_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, C.c_double, _D]
     L.orc_sources.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D, C.c_double, _D]
+    L.orc_c2p_2d_point.restype = C.c_int
+    L.orc_c2p_2d_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D, _D, C.POINTER(C.c_int)]
+    L.orc_c2p_2d_residual.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, C.c_double, C.c_double,
+                                      _D, _D]
     L.orc_set_threads.argtypes = [C.c_int]
     L.orc_get_threads.restype = C.c_int
     return L
@@ -119,6 +123,7 @@ def make_params(d: dict) -> Params:
         setattr(p, k, int(d[k]))
     p.amr = int(d.get("amr", 0))
     p.entropy = int(d.get("entropy", 0))
+    p.c2p_2d = int(d.get("c2p_2d", 0))
     for k in ("spin", "gamma_ad", "cfl", "rho_floor", "p_floor", "w_max", "glm_alpha", "c2p_tol"):
         setattr(p, k, float(d[k]))
     for e in range(3):
@@ -298,6 +303,22 @@ def c2p_entropy(params, x1, x2, U, Wguess=1.0):
     rc = lib().orc_c2p_entropy_point(C.byref(make_params(params)), float(x1), float(x2),
                                      _dp(_vec(U, NV + 1)), float(Wguess), _dp(P))
     return None if rc else P
+
+
+def c2p_2d(params, x1, x2, U, Pguess):
+    """The two-unknown Newton iteration alone: (P or None, steps)."""
+    P = np.zeros(NV)
+    nit = C.c_int()
+    rc = lib().orc_c2p_2d_point(C.byref(make_params(params)), float(x1), float(x2), _dp(_vec(U)),
+                                _dp(_vec(Pguess)), _dp(P), C.byref(nit))
+    return (None if rc else P), nit.value
+
+
+def c2p_2d_residual(params, x1, x2, U, xi, z):
+    F, J = np.zeros(2), np.zeros(4)
+    lib().orc_c2p_2d_residual(C.byref(make_params(params)), float(x1), float(x2), _dp(_vec(U)), float(xi),
+                              float(z), _dp(F), _dp(J))
+    return F, J.reshape(2, 2)
 
 
 def phys_flux(params, x1, x2, P, d):

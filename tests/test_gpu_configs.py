@@ -51,7 +51,7 @@ def report(tag, names, got, ref):
     inf = rel_linf(got, ref)
     print(f"  {tag}: field, rel-L1 (parity measure), own-sum rel-L1, rel-Linf", flush=True)
     for q, n in enumerate(names):
-        note = " (parent-normalised)" if q in PARENT and bar[q] != own[q] else ""
+        note = " (parent-normalised)" if q in PARENT and abs(bar[q] - own[q]) > 1e-6 * own[q] else ""
         print(f"    {n:>4s} {bar[q]:.3e} {own[q]:.3e} {inf[q]:.3e}{note}", flush=True)
     return bar
 
