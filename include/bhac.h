@@ -283,6 +283,23 @@ int bhac_con2prim(bhac_grid *grid, const double *cons, void *prim_inout, int8_t 
 int bhac_substep(bhac_grid *grid, const double *U_base, const double *U_stage, const void *P_stage,
                  double *U_out, void *P_out, double a, double b, void *stream);
 
+/* bhac_substep for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same substep
+ * with the same kernels and bit-identical results, its face-flux scratch taken from
+ * a static device array of 64 MiB that each GPU the library runs on holds until the
+ * process ends, instead of the grid's own buffers; the call allocates nothing.
+ * Limit: the grid's face fluxes (nvar rows x faces per direction x 4 bytes in mixed
+ * precision, 8 in FP64, each direction rounded up to 256 bytes) must fit the 64 MiB
+ * (about 80^3 cells in mixed precision, 64^3 in FP64), else BHAC_EINVAL with the
+ * sizes in the message; fused = 1 gives BHAC_EUNSUPPORTED; the grid's device must be
+ * the current device (BHAC_EINVAL). Arguments, aliasing rules, time-step handling
+ * and other errors as bhac_substep. Every call on one GPU shares that GPU's array and
+ * leaves its contents behind; nothing in it has to start at zero (a substep writes
+ * every face flux before it reads it). Calls that overlap on one GPU (concurrent
+ * streams or host threads) race on the array: serialise them. */
+int bhac_substep_noalloc(bhac_grid *grid, const double *U_base, const double *U_stage, const void *P_stage,
+                         double *U_out, void *P_out, double a, double b, void *stream);
+
 /* Standalone wave-speed reduction over cell-centred states of prim (interior
  * cells): sets dt_next = C / sum_d (lambda_d / dx_d), dx on the finest level. */
 int bhac_compute_dt(bhac_grid *grid, const void *prim, void *stream);

@@ -82,6 +82,7 @@ def lib():
             "bhac_prim2con": [_VP, _VP, _VP, _VP],
             "bhac_con2prim": [_VP, _VP, _VP, _VP, _VP],
             "bhac_substep": [_VP, _VP, _VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP],
+            "bhac_substep_noalloc": [_VP, _VP, _VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP],
             "bhac_compute_dt": [_VP, _VP, _VP],
             "bhac_set_dt": [_VP, C.c_double, _VP],
             "bhac_get_dt": [_VP, C.POINTER(C.c_double)],
@@ -208,6 +209,11 @@ def bhac_con2prim(h, cons, prim, fail=None, stream=None):
 def bhac_substep(h, U_base, U_stage, P_stage, U_out, P_out, a, b, stream=None):
     _check(lib().bhac_substep(h, _ptr(U_base), _ptr(U_stage), _ptr(P_stage), _ptr(U_out), _ptr(P_out),
                               float(a), float(b), _stream(stream)))
+
+
+def bhac_substep_noalloc(h, U_base, U_stage, P_stage, U_out, P_out, a, b, stream=None):
+    _check(lib().bhac_substep_noalloc(h, _ptr(U_base), _ptr(U_stage), _ptr(P_stage), _ptr(U_out), _ptr(P_out),
+                                      float(a), float(b), _stream(stream)))
 
 
 def bhac_compute_dt(h, prim, stream=None):
@@ -344,6 +350,9 @@ class Grid:
 
     def substep(self, Ub, Us, Ps, Uo, Po, a, b):
         bhac_substep(self.h, Ub, Us, Ps, Uo, Po, a, b)
+
+    def substep_noalloc(self, Ub, Us, Ps, Uo, Po, a, b):
+        bhac_substep_noalloc(self.h, Ub, Us, Ps, Uo, Po, a, b)
 
     def init(self, prim_interior):
         """Device P (ghosts filled), U = prim2con(P) and the initial wave-speed reduction."""

@@ -4,6 +4,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -16,6 +17,9 @@ struct bhac_grid {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
 };
+
+// face-flux scratch of bhac_substep_noalloc (64 MiB per GPU; see below)
+static __device__ __align__(256) unsigned char scratch[size_t(64) << 20];
 
 namespace {
 
@@ -75,6 +79,49 @@ void release(bhac::DeviceGrid &G)
 int check_grid(bhac_grid *g)
 {
     if (!g) return fail(BHAC_EINVAL, "null grid");
+    return BHAC_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Static face-flux scratch of bhac_substep_noalloc: one array per GPU, resident until
+// the process ends. Host code never uses the array's name as an address (on the host
+// it is only a stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, taken once per device (in bhac_alloc_blocks, with that device
+// current) and kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------------
+constexpr size_t kScratchBytes = sizeof(scratch);
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's array (looked up on its first request)
+int scratch_of_device(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(BHAC_EDEVICE, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(BHAC_EDEVICE, "hipGetSymbolAddress(scratch) returned null");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return BHAC_OK;
+}
+
+// argument checks shared by bhac_substep and bhac_substep_noalloc
+int check_substep(bhac_grid *g, const double *U_base, const double *U_stage, const void *P_stage,
+                  const double *U_out, const void *P_out, double a, double b)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!U_base || !U_stage || !P_stage || !U_out || !P_out) return fail(BHAC_EINVAL, "null array");
+    if (P_out == P_stage) return fail(BHAC_EALIAS, "P_out aliases P_stage");
+    if ((const void *)U_out == P_stage || (const void *)U_out == P_out || (const void *)U_base == P_out ||
+        (const void *)U_stage == P_out)
+        return fail(BHAC_EALIAS, "a conserved array aliases a primitive array");
+    if (!(a >= 0.0) || !(b > 0.0)) return fail(BHAC_EINVAL, "need a >= 0 and b > 0");
+    if (!g->dg.have_dt) return fail(BHAC_EINVAL, "time step not initialised: call bhac_compute_dt or bhac_set_dt");
     return BHAC_OK;
 }
 
@@ -145,6 +192,14 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     const bhac::Plan &P = G.plan;
     const bhac_params &p = P.p;
     (void)hipGetDevice(&G.device);
+    {
+        // set-up of the static scratch of bhac_substep_noalloc on this device
+        void *unused = nullptr;
+        if (int rc = scratch_of_device(G.device, &unused)) {
+            delete g;
+            return rc;
+        }
+    }
     G.ks = p.metric == BHAC_METRIC_KS_SPH_LOGR;
     G.mixed = p.precision == BHAC_PREC_MIXED;
     bhac::KParams &kp = G.kp;
@@ -325,17 +380,39 @@ int bhac_con2prim(bhac_grid *g, const double *cons, void *prim_inout, int8_t *fa
 int bhac_substep(bhac_grid *g, const double *U_base, const double *U_stage, const void *P_stage, double *U_out,
                  void *P_out, double a, double b, void *stream)
 {
-    if (int rc = check_grid(g)) return rc;
-    if (!U_base || !U_stage || !P_stage || !U_out || !P_out) return fail(BHAC_EINVAL, "null array");
-    if (P_out == P_stage) return fail(BHAC_EALIAS, "P_out aliases P_stage");
-    if ((const void *)U_out == P_stage || (void *)U_out == P_out || (const void *)U_base == P_out ||
-        (const void *)U_stage == P_out)
-        return fail(BHAC_EALIAS, "a conserved array aliases a primitive array");
-    if (!(a >= 0.0) || !(b > 0.0)) return fail(BHAC_EINVAL, "need a >= 0 and b > 0");
-    if (!g->dg.have_dt) return fail(BHAC_EINVAL, "time step not initialised: call bhac_compute_dt or bhac_set_dt");
+    if (int rc = check_substep(g, U_base, U_stage, P_stage, U_out, P_out, a, b)) return rc;
     g->last_stream = (hipStream_t)stream;
     hipError_t e = bhac::launch_substep(g->dg, U_base, U_stage, P_stage, U_out, P_out, a, b, (hipStream_t)stream);
     return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_substep");
+}
+
+int bhac_substep_noalloc(bhac_grid *g, const double *U_base, const double *U_stage, const void *P_stage,
+                         double *U_out, void *P_out, double a, double b, void *stream)
+{
+    if (int rc = check_substep(g, U_base, U_stage, P_stage, U_out, P_out, a, b)) return rc;
+    const bhac::DeviceGrid &G = g->dg;
+    if (G.plan.p.fused) return fail(BHAC_EUNSUPPORTED, "bhac_substep_noalloc runs the unfused substep (fused = 0) only");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != G.device)
+        return fail(BHAC_EINVAL, "bhac_substep_noalloc: the grid's device is not the current device");
+    // the three face-flux arrays, each starting on a 256-byte boundary
+    const size_t rsz = G.mixed ? sizeof(float) : sizeof(double);
+    size_t offs[3] = {0, 0, 0}, need = 0;
+    for (int d = 0; d < G.kp.ndim; d++) {
+        offs[d] = need;
+        need += ((size_t)G.kp.nvar * (size_t)G.plan.nface[d] * rsz + 255) / 256 * 256;
+    }
+    if (need > kScratchBytes)
+        return fail(BHAC_EINVAL, "bhac_substep_noalloc: the grid's face fluxes need " + std::to_string(need) +
+                                     " bytes, beyond the static scratch of " + std::to_string(kScratchBytes) +
+                                     " bytes; use bhac_substep");
+    void *base = nullptr;
+    if (int rc = scratch_of_device(dev, &base)) return rc;
+    void *flux[3] = {nullptr, nullptr, nullptr};
+    for (int d = 0; d < G.kp.ndim; d++) flux[d] = (unsigned char *)base + offs[d];
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_substep(G, U_base, U_stage, P_stage, U_out, P_out, a, b, (hipStream_t)stream, flux);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_substep_noalloc");
 }
 
 int bhac_compute_dt(bhac_grid *g, const void *prim, void *stream)

@@ -822,7 +822,7 @@ hipError_t launch_reset_stats(const DeviceGrid &G, hipStream_t s)
 // block trees (XL) and the entropy field (ENT) never come together (the planner
 // rejects that combination), so three variants per direction are launched
 template <typename R, int D, int RECON, int FLUX, bool KS>
-static hipError_t flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
+static hipError_t flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux)
 {
     const std::vector<WorkItem> &w = G.plan.wface[D];
     TimedLaunch tl(G.timer, K_FLUX0 + D, s);
@@ -831,19 +831,19 @@ static hipError_t flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
         auto kern = xl ? k_flux_x1s<R, RECON, FLUX, KS, true, false>
                        : (ent ? k_flux_x1s<R, RECON, FLUX, KS, false, true> : k_flux_x1s<R, RECON, FLUX, KS, false, false>);
         hipLaunchKernelGGL(kern, dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[0], (const R *)Ps,
-                           (R *)G.d_flux[0], G.plan.nface[0]);
+                           (R *)flux[0], G.plan.nface[0]);
         return hipGetLastError();
     }
     auto kern = xl ? k_flux<R, D, RECON, FLUX, KS, true, false>
                    : (ent ? k_flux<R, D, RECON, FLUX, KS, false, true> : k_flux<R, D, RECON, FLUX, KS, false, false>);
     hipLaunchKernelGGL(kern, dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D], (const R *)Ps,
-                       (R *)G.d_flux[D], G.plan.nface[D]);
+                       (R *)flux[D], G.plan.nface[D]);
     return hipGetLastError();
 }
 
 template <typename R, bool KS>
 static hipError_t update_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
-                               void *Po, double a, double b, hipStream_t s)
+                               void *Po, double a, double b, hipStream_t s, void *const *flux)
 {
     TimedLaunch tl(G.timer, K_UPDATE, s);
     const bool nd3 = G.kp.ndim == 3, base = a != 0.0;
@@ -853,28 +853,28 @@ static hipError_t update_typed(const DeviceGrid &G, const double *Ub, const doub
         kern = nd3 ? (base ? k_update<R, KS, true, true, true> : k_update<R, KS, true, false, true>)
                    : (base ? k_update<R, KS, false, true, true> : k_update<R, KS, false, false, true>);
     hipLaunchKernelGGL(kern, dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, Ub, Us,
-                       (const R *)Ps, Uo, (R *)Po, (const R *)G.d_flux[0], (const R *)G.d_flux[1],
-                       (const R *)G.d_flux[2], G.plan.nface[0], G.plan.nface[1], G.plan.nface[2], a, b);
+                       (const R *)Ps, Uo, (R *)Po, (const R *)flux[0], (const R *)flux[1],
+                       (const R *)flux[2], G.plan.nface[0], G.plan.nface[1], G.plan.nface[2], a, b);
     return hipGetLastError();
 }
 
 template <typename R, int RECON, int FLUX, bool KS>
 static hipError_t update_x1_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps,
-                                  double *Uo, void *Po, double a, double b, hipStream_t s)
+                                  double *Uo, void *Po, double a, double b, hipStream_t s, void *const *flux)
 {
     TimedLaunch tl(G.timer, K_UPDATE_X1, s);
     const bool nd3 = G.kp.ndim == 3, base = a != 0.0;
     auto kern = nd3 ? (base ? k_update_x1<R, RECON, FLUX, KS, true, true> : k_update_x1<R, RECON, FLUX, KS, true, false>)
                     : (base ? k_update_x1<R, RECON, FLUX, KS, false, true> : k_update_x1<R, RECON, FLUX, KS, false, false>);
     hipLaunchKernelGGL(kern, dim3(G.plan.wupd1.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wupd1, Ub, Us,
-                       (const R *)Ps, Uo, (R *)Po, (const R *)G.d_flux[1], (const R *)G.d_flux[2],
+                       (const R *)Ps, Uo, (R *)Po, (const R *)flux[1], (const R *)flux[2],
                        G.plan.nface[1], G.plan.nface[2], a, b);
     return hipGetLastError();
 }
 
 template <typename R, int RECON, int FLUX, bool KS>
 static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
-                                void *Po, double a, double b, hipStream_t s)
+                                void *Po, double a, double b, hipStream_t s, void *const *flux)
 {
     // each direction by faces or by lines, as planned; in 3-D the x2 and x3 kernels
     // run on the grid's side streams, concurrently with x1 on the caller's stream
@@ -882,10 +882,10 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
     // stream, so that each kernel's measured duration is its own)
     const int mm = G.plan.march_mask;
     auto dir = [&](int d, hipStream_t st) -> hipError_t {
-        if (mm >> d & 1) return launch_flux_march(G, d, Ps, st);
-        if (d == 0) return flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, st);
-        if (d == 1) return flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, st);
-        return flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, st);
+        if (mm >> d & 1) return launch_flux_march(G, d, Ps, st, flux);
+        if (d == 0) return flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, st, flux);
+        if (d == 1) return flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, st, flux);
+        return flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, st, flux);
     };
     hipError_t e = hipSuccess;
     if (G.plan.x1_in_update) {
@@ -902,7 +902,7 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
             e = dir(1, s);
             if (e == hipSuccess && G.kp.ndim == 3) e = dir(2, s);
         }
-        if (e == hipSuccess) e = update_x1_typed<R, RECON, FLUX, KS>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+        if (e == hipSuccess) e = update_x1_typed<R, RECON, FLUX, KS>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
         return e;
     }
     if (G.kp.ndim == 3 && G.side[0] && G.side[1] && !G.timer.on) {
@@ -922,38 +922,40 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
         TimedLaunch tl(G.timer, K_FLUX_FIX, s);
         auto kern = G.kp.ndim == 3 ? k_flux_fix<R, 4> : k_flux_fix<R, 2>;
         hipLaunchKernelGGL(kern, dim3(nblk(G.nffix)), dim3(WG), 0, s, G.d_ffix, G.nffix,
-                           (const R *)G.d_flux[0], (const R *)G.d_flux[1],
-                           (const R *)G.d_flux[2], (R *)G.d_flux[0], (R *)G.d_flux[1], (R *)G.d_flux[2],
+                           (const R *)flux[0], (const R *)flux[1],
+                           (const R *)flux[2], (R *)flux[0], (R *)flux[1], (R *)flux[2],
                            G.plan.nface[0], G.plan.nface[1], G.plan.nface[2]);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = update_typed<R, KS>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    if (e == hipSuccess) e = update_typed<R, KS>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
     return e;
 }
 
 template <typename R, int RECON, int FLUX>
 static hipError_t substep_metric(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
-                                 void *Po, double a, double b, hipStream_t s)
+                                 void *Po, double a, double b, hipStream_t s, void *const *flux)
 {
-    if (G.ks) return substep_typed<R, RECON, FLUX, true>(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    return substep_typed<R, RECON, FLUX, false>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    if (G.ks) return substep_typed<R, RECON, FLUX, true>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
+    return substep_typed<R, RECON, FLUX, false>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
 }
 
 template <typename R>
 static hipError_t substep_prec(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
-                               void *Po, double a, double b, hipStream_t s)
+                               void *Po, double a, double b, hipStream_t s, void *const *flux)
 {
     const int r = G.kp.recon, f = G.kp.flux;
     if (r == BHAC_RECON_PPM && f == BHAC_FLUX_HLL)
-        return substep_metric<R, BHAC_RECON_PPM, BHAC_FLUX_HLL>(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    if (r == BHAC_RECON_PPM) return substep_metric<R, BHAC_RECON_PPM, BHAC_FLUX_TVDLF>(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    if (f == BHAC_FLUX_HLL) return substep_metric<R, BHAC_RECON_MC, BHAC_FLUX_HLL>(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    return substep_metric<R, BHAC_RECON_MC, BHAC_FLUX_TVDLF>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+        return substep_metric<R, BHAC_RECON_PPM, BHAC_FLUX_HLL>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
+    if (r == BHAC_RECON_PPM)
+        return substep_metric<R, BHAC_RECON_PPM, BHAC_FLUX_TVDLF>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
+    if (f == BHAC_FLUX_HLL) return substep_metric<R, BHAC_RECON_MC, BHAC_FLUX_HLL>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
+    return substep_metric<R, BHAC_RECON_MC, BHAC_FLUX_TVDLF>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
 }
 
 hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
-                          void *Po, double a, double b, hipStream_t s)
+                          void *Po, double a, double b, hipStream_t s, void *const *flux)
 {
+    if (!flux) flux = G.d_flux;
     hipError_t e = begin_step(G, a == 0.0 ? 1 : 0, s);
     if (e != hipSuccess) return e;
     // block trees: the face ghosts bordering other levels are read from P_stage's
@@ -961,7 +963,8 @@ hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *U
     if (G.nxl_face > 0) e = launch_fill_cross(G, const_cast<void *>(Ps), s, true);
     if (e != hipSuccess) return e;
     if (G.plan.p.fused) e = launch_fused_body(G, Ub, Us, Ps, Uo, Po, a, b, s);
-    else e = G.mixed ? substep_prec<float>(G, Ub, Us, Ps, Uo, Po, a, b, s) : substep_prec<double>(G, Ub, Us, Ps, Uo, Po, a, b, s);
+    else if (G.mixed) e = substep_prec<float>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
+    else e = substep_prec<double>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
     if (e != hipSuccess) return e;
     return end_step(G, s);
 }

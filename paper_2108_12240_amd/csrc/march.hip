@@ -201,7 +201,7 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
 }
 
 template <typename R, int D, int RECON, int FLUX, bool KS>
-hipError_t launch_flux_march_typed(const DeviceGrid &G, const void *Ps, hipStream_t s)
+hipError_t launch_flux_march_typed(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux)
 {
     const std::vector<MarchItem> &w = G.plan.wmarch[D];
     TimedLaunch tl(G.timer, K_FLUX0 + D, s);
@@ -209,38 +209,38 @@ hipError_t launch_flux_march_typed(const DeviceGrid &G, const void *Ps, hipStrea
                              : (G.kp.nvar > NV ? k_flux_march<R, D, RECON, FLUX, KS, false, true>
                                                : k_flux_march<R, D, RECON, FLUX, KS, false, false>);
     hipLaunchKernelGGL(kern, dim3(w.size()), dim3(MWG), 0, s, G.kp, G.gd, G.d_wmarch[D], (const R *)Ps,
-                       (R *)G.d_flux[D], G.plan.nface[D]);
+                       (R *)flux[D], G.plan.nface[D]);
     return hipGetLastError();
 }
 
 template <typename R, int D>
-static hipError_t march_dir(const DeviceGrid &G, const void *Ps, hipStream_t s)
+static hipError_t march_dir(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux)
 {
     const int r = G.kp.recon, f = G.kp.flux;
     if (G.ks) {
         if (r == BHAC_RECON_PPM)
-            return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_HLL, true>(G, Ps, s)
-                                      : launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_TVDLF, true>(G, Ps, s);
-        return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_HLL, true>(G, Ps, s)
-                                  : launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_TVDLF, true>(G, Ps, s);
+            return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_HLL, true>(G, Ps, s, flux)
+                                      : launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_TVDLF, true>(G, Ps, s, flux);
+        return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_HLL, true>(G, Ps, s, flux)
+                                  : launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_TVDLF, true>(G, Ps, s, flux);
     }
     if (r == BHAC_RECON_PPM)
-        return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_HLL, false>(G, Ps, s)
-                                  : launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_TVDLF, false>(G, Ps, s);
-    return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_HLL, false>(G, Ps, s)
-                              : launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_TVDLF, false>(G, Ps, s);
+        return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_HLL, false>(G, Ps, s, flux)
+                                  : launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_TVDLF, false>(G, Ps, s, flux);
+    return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_HLL, false>(G, Ps, s, flux)
+                              : launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_TVDLF, false>(G, Ps, s, flux);
 }
 
-hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStream_t s)
+hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStream_t s, void *const *flux)
 {
     if (G.mixed) {
-        if (D == 0) return march_dir<float, 0>(G, Ps, s);
-        if (D == 1) return march_dir<float, 1>(G, Ps, s);
-        return march_dir<float, 2>(G, Ps, s);
+        if (D == 0) return march_dir<float, 0>(G, Ps, s, flux);
+        if (D == 1) return march_dir<float, 1>(G, Ps, s, flux);
+        return march_dir<float, 2>(G, Ps, s, flux);
     }
-    if (D == 0) return march_dir<double, 0>(G, Ps, s);
-    if (D == 1) return march_dir<double, 1>(G, Ps, s);
-    return march_dir<double, 2>(G, Ps, s);
+    if (D == 0) return march_dir<double, 0>(G, Ps, s, flux);
+    if (D == 1) return march_dir<double, 1>(G, Ps, s, flux);
+    return march_dir<double, 2>(G, Ps, s, flux);
 }
 
 }  // namespace bhac
