@@ -49,7 +49,9 @@ FLOP_KINDS = ("add", "mul", "div", "sqrt", "trans")
 
 
 def build(force: bool = True) -> str:
-    if force or not os.path.exists(LIB):
+    """Compile the op-count build (also when either source is newer than the library)."""
+    stale = not os.path.exists(LIB) or max(os.path.getmtime(SRC), os.path.getmtime(O.SRC)) > os.path.getmtime(LIB)
+    if force or stale:
         tmp = LIB + ".tmp"
         subprocess.check_call(["g++", "-x", "c++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
                                "-fpermissive", "-w", "-fPIC", "-shared", "-I", HERE, "-o", tmp, SRC, "-lm"])

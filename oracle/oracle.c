@@ -56,6 +56,7 @@ typedef struct {
     int amr;                           /* 0 independent same-level patches, 1 2:1 block tree */
     int entropy;                       /* 1: carry the entropy field (P[9] = K, U[9] = U[0] K) */
     int c2p_2d;                        /* 1: a failed inversion tries the two-unknown Newton backup */
+    int ct;                            /* 1: staggered constrained transport instead of GLM cleaning */
 } orc_params;
 
 /* rows of P and U: the nine GRMHD variables, plus the entropy field if carried */
@@ -270,23 +271,12 @@ static void phys_flux(const orc_params *p, const ometric *m, const double *P, in
  * Face flux: exact solve of the (B~^d, psi) GLM subsystem, then HLL or TVDLF on
  * the other variables (reading: Dedner mixed GLM in coordinate space).
  * ------------------------------------------------------------------------------- */
-static double riemann(const orc_params *p, const ometric *mf, int d, const double *PL,
-                      const double *PR, double ch, double *F)
+/* HLL or TVDLF combination of the two face states' fluxes for every variable except
+ * the normal field and psi (their fluxes come from the GLM solve, or vanish under
+ * constrained transport); returns the largest |lambda| of both states. */
+static double hll_combine(const orc_params *p, int d, const double *UL, const double *UR, const double *FL,
+                          const double *FR, double lml, double lpl, double lmr, double lpr, double *F)
 {
-    OC_SCOPE(OC_RIEMANN);
-    const double sg = mf->sqrtg;
-    const double btl = sg * PL[IB1 + d], btr = sg * PR[IB1 + d];
-    const double psl = PL[IPSI], psr = PR[IPSI];
-    const double bstar = 0.5 * (btl + btr) - (psr - psl) / (2.0 * ch);
-    const double psistar = 0.5 * (psl + psr) - 0.5 * ch * (btr - btl);
-    double ql[NV], qr[NV];
-    memcpy(ql, PL, sizeof ql);
-    memcpy(qr, PR, sizeof qr);
-    ql[IB1 + d] = bstar / sg;
-    qr[IB1 + d] = bstar / sg;
-    double UL[NV], UR[NV], FL[NV], FR[NV], lml, lpl, lmr, lpr;
-    phys_flux(p, mf, ql, d, UL, FL, &lml, &lpl);
-    phys_flux(p, mf, qr, d, UR, FR, &lmr, &lpr);
     for (int v = 0; v < NV; v++) {
         if (v == IB1 + d || v == IPSI) continue;
         if (p->flux == 0) {
@@ -305,12 +295,55 @@ static double riemann(const orc_params *p, const ometric *mf, int d, const doubl
             F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * c * (UR[v] - UL[v]);
         }
     }
-    F[IB1 + d] = psistar;
-    F[IPSI] = ch * ch * bstar;
     double lam = fabs(lml);
     if (fabs(lpl) > lam) lam = fabs(lpl);
     if (fabs(lmr) > lam) lam = fabs(lmr);
     if (fabs(lpr) > lam) lam = fabs(lpr);
+    return lam;
+}
+
+static double riemann(const orc_params *p, const ometric *mf, int d, const double *PL,
+                      const double *PR, double ch, double *F)
+{
+    OC_SCOPE(OC_RIEMANN);
+    const double sg = mf->sqrtg;
+    const double btl = sg * PL[IB1 + d], btr = sg * PR[IB1 + d];
+    const double psl = PL[IPSI], psr = PR[IPSI];
+    const double bstar = 0.5 * (btl + btr) - (psr - psl) / (2.0 * ch);
+    const double psistar = 0.5 * (psl + psr) - 0.5 * ch * (btr - btl);
+    double ql[NV], qr[NV];
+    memcpy(ql, PL, sizeof ql);
+    memcpy(qr, PR, sizeof qr);
+    ql[IB1 + d] = bstar / sg;
+    qr[IB1 + d] = bstar / sg;
+    double UL[NV], UR[NV], FL[NV], FR[NV], lml, lpl, lmr, lpr;
+    phys_flux(p, mf, ql, d, UL, FL, &lml, &lpl);
+    phys_flux(p, mf, qr, d, UR, FR, &lmr, &lpr);
+    const double lam = hll_combine(p, d, UL, UR, FL, FR, lml, lpl, lmr, lpr, F);
+    F[IB1 + d] = psistar;
+    F[IPSI] = ch * ch * bstar;
+    return lam;
+}
+
+/* Face flux under constrained transport (reading): the normal field of the face is
+ * the staggered face field phi = sqrt(gamma) B^d there, the same for both states;
+ * no GLM solve: the normal-field and psi fluxes vanish (the face field is advanced by
+ * the edge electric fields instead). */
+static double riemann_ct(const orc_params *p, const ometric *mf, int d, const double *PL, const double *PR,
+                         double phi, double *F)
+{
+    OC_SCOPE(OC_RIEMANN);
+    double ql[NV], qr[NV];
+    memcpy(ql, PL, sizeof ql);
+    memcpy(qr, PR, sizeof qr);
+    ql[IB1 + d] = phi / mf->sqrtg;
+    qr[IB1 + d] = phi / mf->sqrtg;
+    double UL[NV], UR[NV], FL[NV], FR[NV], lml, lpl, lmr, lpr;
+    phys_flux(p, mf, ql, d, UL, FL, &lml, &lpl);
+    phys_flux(p, mf, qr, d, UR, FR, &lmr, &lpr);
+    const double lam = hll_combine(p, d, UL, UR, FL, FR, lml, lpl, lmr, lpr, F);
+    F[IB1 + d] = 0.0;
+    F[IPSI] = 0.0;
     return lam;
 }
 
@@ -753,6 +786,7 @@ typedef struct {
     int gz;               /* ghost layers per axis */
     int gd[3];
     int maxlevel;
+    int64_t *foff[3];     /* staggered face field: first face of each block per direction, nb+1 */
 } orc_grid;
 
 /* Where a block's cells and ghost slots sit in P (data contract shared with the
@@ -809,6 +843,7 @@ void orc_grid_free(orc_grid *G)
     free(G->grp);
     free(G->off);
     free(G->ioff);
+    for (int d = 0; d < 3; d++) free(G->foff[d]);
     free(G->blk);
     free(G);
 }
@@ -898,6 +933,21 @@ orc_grid *orc_grid_new(const orc_params *p, const orc_block *blocks, int64_t nb)
     }
     /* the entropy field: same-level patches only, gamma <= 2 (its inversion needs it) */
     if (p->entropy && (p->entropy != 1 || p->amr || !(p->gamma_ad <= 2.0))) goto bad;
+    /* constrained transport: same-level patches without the entropy field */
+    if (p->ct && (p->ct != 1 || p->amr || p->entropy)) goto bad;
+    /* face layout of the staggered field (every block holds all faces of its cells,
+     * both boundary faces included; blocks one after another, x fastest) */
+    for (int d = 0; d < 3; d++) {
+        G->foff[d] = malloc((nb + 1) * sizeof(int64_t));
+        G->foff[d][0] = 0;
+        for (int64_t b = 0; b < nb; b++) {
+            const orc_block *B = &G->blk[b];
+            const int64_t nf = d < p->ndim ? (int64_t)(B->size[0] + (d == 0)) * (B->size[1] + (d == 1))
+                                                 * (B->size[2] + (d == 2))
+                                           : 0;
+            G->foff[d][b + 1] = G->foff[d][b] + nf;
+        }
+    }
     if (p->amr) {
         /* block tree: one block size, even and at least twice the ghost depth along
          * every axis in use (so every ghost layer lies in a leaf adjacent to the
@@ -1261,9 +1311,22 @@ void orc_set_dt(orc_state *st, double dt)
  * A substep with a == 0 starts a step and latches dt from the previous substep's
  * wave speeds. P_stage ghost slots must be filled. blocks: subset (NULL = all).
  * ------------------------------------------------------------------------------- */
+/* Index of block b's face (i, j, k) of direction d in the staggered field array:
+ * the directions' face arrays one after another, each block's faces x fastest. */
+static int64_t phi_index(const orc_grid *G, int d, int b, int i, int j, int k)
+{
+    int64_t base = 0;
+    for (int e = 0; e < d; e++) base += G->foff[e][G->nb];
+    const orc_block *B = &G->blk[b];
+    const int fs0 = B->size[0] + (d == 0), fs1 = B->size[1] + (d == 1);
+    return base + G->foff[d][b] + ((int64_t)k * fs1 + j) * fs0 + i;
+}
+
 /* Face fluxes of block bk along every direction (F[d]: [9][faces], x fastest);
- * raises lam[d] to the largest |lambda| seen. */
-static void block_fluxes(const orc_grid *G, int bk, const double *Ps, double ch, double *F[3], double *lam)
+ * raises lam[d] to the largest |lambda| seen. Under constrained transport (Phi not
+ * NULL) the normal field of each face is the staggered face field. */
+static void block_fluxes(const orc_grid *G, int bk, const double *Ps, double ch, double *F[3], double *lam,
+                         const double *Phi)
 {
     const orc_params *p = &G->p;
     const int64_t ncp = G->off[G->nb];
@@ -1297,7 +1360,8 @@ static void block_fluxes(const orc_grid *G, int bk, const double *Ps, double ch,
                     ometric mf;
                     metric_at(p, x1, x2, &mf);
                     double Ff[NVE];
-                    const double l = riemann(p, &mf, d, PL, PR, ch, Ff);
+                    const double l = Phi ? riemann_ct(p, &mf, d, PL, PR, Phi[phi_index(G, d, bk, i, j, k)], Ff)
+                                         : riemann(p, &mf, d, PL, PR, ch, Ff);
                     if (l > lam[d]) lam[d] = l;
                     if (p->entropy) {
                         /* entropy field (reading 19): reconstructed like the others and
@@ -1320,7 +1384,7 @@ static void block_fluxes(const orc_grid *G, int bk, const double *Ps, double ch,
 /* Flux divergence, sources, RK combine and inversion of block bk. */
 static void block_update(const orc_grid *G, int bk, double *F[3], const double *Ub, const double *Us,
                          const double *Ps, double *Uo, double *Po, double a, double b, const orc_state *st,
-                         ocount *cnt)
+                         ocount *cnt, const double *Phio)
 {
     const orc_params *p = &G->p;
     const int64_t ncp = G->off[G->nb];
@@ -1353,6 +1417,16 @@ static void block_update(const orc_grid *G, int bk, double *F[3], const double *
                 for (int v = 0; v < nv; v++) {
                     L[v] += Sv[v];
                     Un[v] = a * Ub[v * ncp + c] + b * (Uc[v] + st->dt * L[v]);
+                }
+                if (Phio) {
+                    /* constrained transport: the cell's densitised field is the mean of
+                     * its two updated face fields along each resolved direction */
+                    for (int d = 0; d < p->ndim; d++) {
+                        int hi[3] = { i, j, k };
+                        hi[d] += 1;
+                        Un[IB1 + d] = 0.5 * (Phio[phi_index(G, d, bk, i, j, k)]
+                                             + Phio[phi_index(G, d, bk, hi[0], hi[1], hi[2])]);
+                    }
                 }
                 int nit, fl, bu;
                 const int f = c2p_point(p, &m, Un, Pc, Pn, &nit, &fl, &bu);
@@ -1461,8 +1535,8 @@ int orc_substep(const orc_grid *G, const double *Ub, const double *Us, const dou
                 F[d] = malloc(nvar(p) * nf * sizeof(double));
             }
             ocount cnt = { 0, 0, 0, 0 };
-            block_fluxes(G, bk, Ps, st->ch, F, lam);
-            block_update(G, bk, F, Ub, Us, Ps, Uo, Po, a, b, st, &cnt);
+            block_fluxes(G, bk, Ps, st->ch, F, lam, NULL);
+            block_update(G, bk, F, Ub, Us, Ps, Uo, Po, a, b, st, &cnt, NULL);
 #pragma omp critical(oracle_counts)
             ocount_merge(st, &cnt);
             for (int d = 0; d < p->ndim; d++) free(F[d]);
@@ -1480,14 +1554,14 @@ int orc_substep(const orc_grid *G, const double *Ub, const double *Us, const dou
                 F[bk * 3 + d] = malloc(NV * nf * sizeof(double));
                 Fb[d] = F[bk * 3 + d];
             }
-            block_fluxes(G, (int)bk, Ps, st->ch, Fb, lam);
+            block_fluxes(G, (int)bk, Ps, st->ch, Fb, lam, NULL);
         }
         flux_fix(G, F);
 #pragma omp parallel for schedule(dynamic) num_threads(g_threads)
         for (int64_t q = 0; q < n; q++) {
             const int bk = (int)(blocks ? blocks[q] : q);
             ocount cnt = { 0, 0, 0, 0 };
-            block_update(G, bk, &F[bk * 3], Ub, Us, Ps, Uo, Po, a, b, st, &cnt);
+            block_update(G, bk, &F[bk * 3], Ub, Us, Ps, Uo, Po, a, b, st, &cnt, NULL);
 #pragma omp critical(oracle_counts)
             ocount_merge(st, &cnt);
         }
@@ -1497,6 +1571,209 @@ int orc_substep(const orc_grid *G, const double *Ub, const double *Us, const dou
     for (int d = 0; d < 3; d++) st->lam[d] = lam[d];
     st->dt_next = st->dt_fixed > 0.0 ? st->dt_fixed : dt_from_lam(G, lam);
     return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Staggered-mesh constrained transport (Section 2: the paper's code evolves the
+ * magnetic field by constrained transport on a staggered mesh). Reading:
+ *  - the field is held as phi^d = sqrt(gamma) B^d at the centre of every d-face (a
+ *    block holds all faces of its cells, so a face shared by two blocks has a copy in
+ *    each, kept identical);
+ *  - the face fluxes come from the usual reconstruction and Riemann solve, with the
+ *    face's phi as the normal field of both states and no GLM solve;
+ *  - the induction fluxes give the edge electric fields (i, j, k cyclic)
+ *      E_k = F^j(B~^i) = -F^i(B~^j),
+ *    each edge value the mean of the four face fluxes around the edge (two faces of
+ *    each of the two directions normal to the edge);
+ *  - phi is advanced by Stokes' theorem, d_t phi^i = -(d_j E_k - d_k E_j), in the
+ *    same RK combination as U; the cell's densitised field in U is the mean of its two
+ *    updated face fields along each resolved direction (with ndim = 2 the x3 field
+ *    stays a cell-centred finite-volume variable);
+ *  - a face flux across a block boundary is read from the same-level block beside
+ *    it; where there is none (outflow), from the block's own nearest face.
+ * The discrete divergence sum_d (phi^d(hi) - phi^d(lo)) / dx_d of every cell is then
+ * kept at its initial value to round-off.
+ * ------------------------------------------------------------------------------- */
+/* flux row v of direction d at block bk's face f (f[d] a face index 0..s_d, the
+ * other two cell indices, at most one of them outside the block) */
+static double flux_at(const orc_grid *G, double **F, int bk, int d, int v, const int f[3])
+{
+    const orc_block *B = &G->blk[bk];
+    int b = bk, g[3] = { f[0], f[1], f[2] };
+    for (int e = 0; e < 3; e++) {
+        if (e == d || (f[e] >= 0 && f[e] < B->size[e])) continue;
+        int l[3] = { f[0], f[1], f[2] };
+        if (l[d] > B->size[d] - 1) l[d] = B->size[d] - 1;
+        int sb, src[3];
+        ghost_source(G, bk, l, &sb, src);
+        b = sb;
+        g[e] = src[e];
+    }
+    const orc_block *N = &G->blk[b];
+    int fs[3];
+    for (int e = 0; e < 3; e++) fs[e] = N->size[e] + (e == d);
+    const int64_t nf = (int64_t)fs[0] * fs[1] * fs[2];
+    return F[b * 3 + d][v * nf + ((int64_t)g[2] * fs[1] + g[1]) * fs[0] + g[0]];
+}
+
+/* edge electric field E_k of block bk at the edge whose lower corner is (i, j, k) in
+ * face-index units along the two axes normal to the edge (cell index along k) */
+static double edge_emf(const orc_grid *G, double **F, int bk, int axis, int i, int j, int k)
+{
+    /* (a, b): the two axes normal to the edge, cyclic after the edge's axis */
+    const int a = (axis + 1) % 3, b = (axis + 2) % 3;
+    int fa0[3] = { i, j, k }, fa1[3] = { i, j, k }, fb0[3] = { i, j, k }, fb1[3] = { i, j, k };
+    /* F^b(B~^a) on the two b-faces beside the edge (cells a-1 and a along a) */
+    fb0[a] -= 1;
+    /* F^a(B~^b) on the two a-faces beside the edge (cells b-1 and b along b) */
+    fa0[b] -= 1;
+    const double fb = flux_at(G, F, bk, b, IB1 + a, fb0) + flux_at(G, F, bk, b, IB1 + a, fb1);
+    const double fa = flux_at(G, F, bk, a, IB1 + b, fa0) + flux_at(G, F, bk, a, IB1 + b, fa1);
+    return 0.25 * (fb - fa);
+}
+
+/* new face fields of block bk: phi_out = a phi_base + b (phi_stage + dt L) with
+ * L = -(d_j E_k - d_k E_j) on each face of direction i */
+static void block_ct_update(const orc_grid *G, int bk, double **F, const double *Phib, const double *Phis,
+                            double *Phio, double a, double b, double dt)
+{
+    const orc_params *p = &G->p;
+    const orc_block *B = &G->blk[bk];
+    double dx[3];
+    for (int e = 0; e < 3; e++) dx[e] = level_dx(G, B->level, e);
+    for (int d = 0; d < p->ndim; d++) {
+        int fs[3];
+        for (int e = 0; e < 3; e++) fs[e] = B->size[e] + (e == d);
+        const int dj = (d + 1) % 3, dk = (d + 2) % 3;
+        for (int k = 0; k < fs[2]; k++)
+            for (int j = 0; j < fs[1]; j++)
+                for (int i = 0; i < fs[0]; i++) {
+                    double L = 0.0;
+                    /* -d_j E_k: edges along dk at the low and high side along dj (with
+                     * ndim = 2 only the edges along x3 exist: the other term vanishes) */
+                    if (dj < p->ndim) {
+                        int lo[3] = { i, j, k }, hi[3] = { i, j, k };
+                        hi[dj] += 1;
+                        L -= (edge_emf(G, F, bk, dk, hi[0], hi[1], hi[2]) - edge_emf(G, F, bk, dk, lo[0], lo[1], lo[2]))
+                             / dx[dj];
+                    }
+                    /* +d_k E_j: edges along dj at the low and high side along dk */
+                    if (dk < p->ndim) {
+                        int lo[3] = { i, j, k }, hi[3] = { i, j, k };
+                        hi[dk] += 1;
+                        L += (edge_emf(G, F, bk, dj, hi[0], hi[1], hi[2]) - edge_emf(G, F, bk, dj, lo[0], lo[1], lo[2]))
+                             / dx[dk];
+                    }
+                    const int64_t q = phi_index(G, d, bk, i, j, k);
+                    Phio[q] = a * Phib[q] + b * (Phis[q] + dt * L);
+                }
+    }
+}
+
+/* One RK substep under constrained transport: as orc_substep, plus the face fields
+ * (phi: every block's faces of each resolved direction, the directions one after
+ * another). Every block's fluxes are formed first (the edge fields of a block read
+ * its neighbours' faces), then the face fields and the cells of the selected
+ * blocks. */
+int orc_substep_ct(const orc_grid *G, const double *Ub, const double *Us, const double *Ps, const double *Phib,
+                   const double *Phis, double *Uo, double *Po, double *Phio, double a, double b, orc_state *st,
+                   const int64_t *blocks, int64_t nsel)
+{
+    if (!st->have_dt || !G->p.ct) return -1;
+    const orc_params *p = &G->p;
+    if (a == 0.0) {
+        st->dt = st->dt_fixed > 0.0 ? st->dt_fixed : st->dt_next;
+        double sinv = 0.0, dmin = 1e300;
+        for (int d = 0; d < p->ndim; d++) {
+            const double dx = level_dx(G, G->maxlevel, d);
+            sinv += 1.0 / dx;
+            if (dx < dmin) dmin = dx;
+        }
+        st->ch = p->cfl / (st->dt * sinv);
+        st->kappa = p->glm_alpha * st->ch / dmin;
+    }
+    double lam[3] = { 0.0, 0.0, 0.0 };
+    const int64_t n = blocks ? nsel : G->nb;
+    double **F = calloc(3 * G->nb, sizeof(double *));
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads) reduction(max : lam[:3])
+    for (int64_t bk = 0; bk < G->nb; bk++) {
+        const orc_block *B = &G->blk[bk];
+        double *Fb[3] = { NULL, NULL, NULL };
+        for (int d = 0; d < p->ndim; d++) {
+            const int64_t nf = (int64_t)(B->size[0] + (d == 0)) * (B->size[1] + (d == 1)) * (B->size[2] + (d == 2));
+            F[bk * 3 + d] = malloc(NV * nf * sizeof(double));
+            Fb[d] = F[bk * 3 + d];
+        }
+        block_fluxes(G, (int)bk, Ps, st->ch, Fb, lam, Phis);
+    }
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads)
+    for (int64_t q = 0; q < n; q++) {
+        const int bk = (int)(blocks ? blocks[q] : q);
+        block_ct_update(G, bk, F, Phib, Phis, Phio, a, b, st->dt);
+        ocount cnt = { 0, 0, 0, 0 };
+        block_update(G, bk, &F[bk * 3], Ub, Us, Ps, Uo, Po, a, b, st, &cnt, Phio);
+#pragma omp critical(oracle_counts)
+        ocount_merge(st, &cnt);
+    }
+    for (int64_t t = 0; t < 3 * G->nb; t++) free(F[t]);
+    free(F);
+    for (int d = 0; d < 3; d++) st->lam[d] = lam[d];
+    st->dt_next = st->dt_fixed > 0.0 ? st->dt_fixed : dt_from_lam(G, lam);
+    return 0;
+}
+
+/* Faces per direction (totals over the blocks) of the staggered field. */
+void orc_face_count(const orc_grid *G, int64_t *nface)
+{
+    for (int d = 0; d < 3; d++) nface[d] = G->foff[d][G->nb];
+}
+
+/* Cell-centred field from the face field: P rows B^d (d < ndim) = the mean of the
+ * cell's two face values of phi^d divided by sqrt(gamma) at the cell centre. */
+void orc_ct_center(const orc_grid *G, const double *Phi, double *P)
+{
+    const int64_t ncp = G->off[G->nb];
+    for (int64_t b = 0; b < G->nb; b++) {
+        const orc_block *B = &G->blk[b];
+        for (int k = 0; k < B->size[2]; k++)
+            for (int j = 0; j < B->size[1]; j++)
+                for (int i = 0; i < B->size[0]; i++) {
+                    double x1, x2;
+                    ometric m;
+                    cell_center(G, (int)b, i, j, &x1, &x2);
+                    metric_at(&G->p, x1, x2, &m);
+                    const int64_t c = pad_index(G, (int)b, i, j, k);
+                    for (int d = 0; d < G->p.ndim; d++) {
+                        int hi[3] = { i, j, k };
+                        hi[d] += 1;
+                        const double mean = 0.5 * (Phi[phi_index(G, d, (int)b, i, j, k)]
+                                                   + Phi[phi_index(G, d, (int)b, hi[0], hi[1], hi[2])]);
+                        P[(IB1 + d) * ncp + c] = mean / m.sqrtg;
+                    }
+                }
+    }
+}
+
+/* Discrete divergence of the face field per interior cell (interior-packed order):
+ * sum_d (phi^d(hi) - phi^d(lo)) / dx_d. */
+void orc_ct_divergence(const orc_grid *G, const double *Phi, double *div)
+{
+    for (int64_t b = 0; b < G->nb; b++) {
+        const orc_block *B = &G->blk[b];
+        int64_t c = G->ioff[b];
+        for (int k = 0; k < B->size[2]; k++)
+            for (int j = 0; j < B->size[1]; j++)
+                for (int i = 0; i < B->size[0]; i++, c++) {
+                    double s = 0.0;
+                    for (int d = 0; d < G->p.ndim; d++) {
+                        int hi[3] = { i, j, k };
+                        hi[d] += 1;
+                        s += (Phi[phi_index(G, d, (int)b, hi[0], hi[1], hi[2])] - Phi[phi_index(G, d, (int)b, i, j, k)])
+                             / level_dx(G, B->level, d);
+                    }
+                    div[c] = s;
+                }
+    }
 }
 
 /* ---------------------------------------------------------------------------------

@@ -43,7 +43,8 @@ class Params(C.Structure):
                 ("recon", C.c_int), ("flux", C.c_int),
                 ("cfl", C.c_double), ("rho_floor", C.c_double), ("p_floor", C.c_double),
                 ("w_max", C.c_double), ("glm_alpha", C.c_double), ("c2p_tol", C.c_double),
-                ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int), ("c2p_2d", C.c_int)]
+                ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int), ("c2p_2d", C.c_int),
+                ("ct", C.c_int)]
 
 
 class Block(C.Structure):
@@ -103,6 +104,12 @@ def load(path: str):
     L.orc_c2p_2d_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, _D, _D, C.POINTER(C.c_int)]
     L.orc_c2p_2d_residual.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _D, C.c_double, C.c_double,
                                       _D, _D]
+    L.orc_substep_ct.restype = C.c_int
+    L.orc_substep_ct.argtypes = [C.c_void_p, _D, _D, _D, _D, _D, _D, _D, _D, C.c_double, C.c_double,
+                                 C.POINTER(State), _I64, C.c_int64]
+    L.orc_face_count.argtypes = [C.c_void_p, _I64]
+    L.orc_ct_center.argtypes = [C.c_void_p, _D, _D]
+    L.orc_ct_divergence.argtypes = [C.c_void_p, _D, _D]
     L.orc_set_threads.argtypes = [C.c_int]
     L.orc_get_threads.restype = C.c_int
     return L
@@ -124,6 +131,7 @@ def make_params(d: dict) -> Params:
     p.amr = int(d.get("amr", 0))
     p.entropy = int(d.get("entropy", 0))
     p.c2p_2d = int(d.get("c2p_2d", 0))
+    p.ct = int(d.get("ct", 0))
     for k in ("spin", "gamma_ad", "cfl", "rho_floor", "p_floor", "w_max", "glm_alpha", "c2p_tol"):
         setattr(p, k, float(d[k]))
     for e in range(3):
@@ -233,6 +241,49 @@ class OracleGrid:
                                C.byref(self.state), None if s is None else s.ctypes.data_as(_I64), n)
         if rc != 0:
             raise RuntimeError("oracle substep: dt not initialised")
+
+    # --- staggered face field (constrained transport) -------------------------------
+    def face_count(self):
+        n = np.zeros(3, dtype=np.int64)
+        lib().orc_face_count(self._h, n.ctypes.data_as(_I64))
+        return n
+
+    def substep_ct(self, Ub, Us, Ps, Phib, Phis, Uo, Po, Phio, a, b, blocks=None):
+        s, n = _sel(blocks)
+        rc = lib().orc_substep_ct(self._h, _dp(Ub), _dp(Us), _dp(Ps), _dp(Phib), _dp(Phis), _dp(Uo), _dp(Po),
+                                  _dp(Phio), float(a), float(b), C.byref(self.state),
+                                  None if s is None else s.ctypes.data_as(_I64), n)
+        if rc != 0:
+            raise RuntimeError("oracle CT substep: dt not initialised or constrained transport not enabled")
+
+    def ct_center(self, Phi, P):
+        lib().orc_ct_center(self._h, _dp(Phi), _dp(P))
+
+    def ct_divergence(self, Phi):
+        div = np.zeros(self.nci)
+        lib().orc_ct_divergence(self._h, _dp(Phi), _dp(div))
+        return div
+
+    def init_ct(self, prim_interior, Phi):
+        """Padded P with the cell-centred field from the face field, ghosts filled,
+        U = prim2con(P), dt from the centred reduction."""
+        P = self.pack(np.asarray(prim_interior, dtype=np.float64))
+        self.ct_center(Phi, P)
+        self.fill_ghosts(P)
+        U = self.prim2con(P)
+        self.compute_dt(P)
+        return U, P
+
+    def rk2_step_ct(self, U, P, Phi, U1=None, P1=None, Phi1=None):
+        """One SSP-RK2 step in place on (U, P, Phi)."""
+        U1 = np.zeros_like(U) if U1 is None else U1
+        P1 = np.zeros_like(P) if P1 is None else P1
+        Phi1 = np.zeros_like(Phi) if Phi1 is None else Phi1
+        self.fill_ghosts(P)
+        self.substep_ct(U, U, P, Phi, Phi, U1, P1, Phi1, 0.0, 1.0)
+        self.fill_ghosts(P1)
+        self.substep_ct(U, U1, P1, Phi, Phi1, U, P, Phi, 0.5, 0.5)
+        return U, P, Phi
 
     def stats(self):
         st = self.state

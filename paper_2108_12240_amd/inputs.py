@@ -475,3 +475,64 @@ def uniform_state(n=(16, 16, 16), bs=(16, 16, 16), ndim=3, prim_value=None, bc=B
                          x_lo=[0.0, 0.0, 0.0], x_hi=[1.0, 1.0, 1.0], ncell0=list(n),
                          bc=[[bc] * 2] * 3, recon=recon, flux=flux)
     return Case("uniform", params, blocks, prim, ioff, steps=10)
+
+
+# ----------------------------------------------------------------------------------
+# Staggered face field (constrained transport) from a vector potential.
+# ----------------------------------------------------------------------------------
+def face_counts(params: dict, blocks: np.ndarray):
+    """Faces per direction (totals over the blocks, every block holding all faces of
+    its cells) and each block's first face per direction."""
+    nd = int(params["ndim"])
+    offs, tot = [], []
+    for d in range(3):
+        n = np.array([int((b[1] + (d == 0)) * (b[2] + (d == 1)) * (b[3] + (d == 2))) if d < nd else 0
+                      for b in np.asarray(blocks)], dtype=np.int64)
+        offs.append(np.concatenate([[0], np.cumsum(n)]).astype(np.int64))
+        tot.append(int(offs[-1][-1]))
+    return tot, offs
+
+
+def face_field_from_potential(params: dict, blocks: np.ndarray, A) -> np.ndarray:
+    """The magnetic flux density through every face, phi^d = sqrt(gamma) B^d, as the
+    circulation of an edge-centred vector potential around the face over the face's
+    coordinate area: with (d, j, k) cyclic,
+      phi^d = (A_k(j + 1/2) - A_k(j - 1/2)) / dx_j - (A_j(k + 1/2) - A_j(k - 1/2)) / dx_k,
+    each A_e taken at the centre of an edge along e (the k term only where axis k is
+    resolved). A(e, x1, x2, x3) returns the covariant component along axis e at the
+    given coordinate arrays. Layout: the resolved directions' face arrays one after
+    another, each block's faces x fastest."""
+    nd = int(params["ndim"])
+    x_lo = np.asarray(params["x_lo"], dtype=np.float64)
+    x_hi = np.asarray(params["x_hi"], dtype=np.float64)
+    n0 = np.asarray(params["ncell0"], dtype=np.int64)
+    out = []
+    for d in range(nd):
+        dj, dk = (d + 1) % 3, (d + 2) % 3
+        parts = []
+        for blk in np.asarray(blocks):
+            lev, size, org = int(blk[0]), blk[1:4].astype(np.int64), blk[4:7].astype(np.int64)
+            dx = (x_hi - x_lo) / (n0 * 2 ** lev)
+            fs = size + (np.arange(3) == d)
+            k, j, i = np.meshgrid(np.arange(fs[2]), np.arange(fs[1]), np.arange(fs[0]), indexing="ij")
+            idx = [i.ravel(), j.ravel(), k.ravel()]
+
+            def coord(e, shift):
+                # position along e: face coordinate on axis d, cell centres elsewhere,
+                # moved by `shift` half cells
+                base = org[e] + idx[e] + (0.0 if e == d else 0.5)
+                return x_lo[e] + (base + shift) * dx[e]
+
+            def edge(axis, e_off, off):
+                # A along `axis` at the edge beside the face, offset by off half cells on e_off
+                x = [coord(e, off if e == e_off else 0.0) for e in range(3)]
+                return A(axis, x[0], x[1], x[2])
+
+            phi = np.zeros(idx[0].size)
+            if dj < nd:
+                phi += (edge(dk, dj, 0.5) - edge(dk, dj, -0.5)) / dx[dj]
+            if dk < nd:
+                phi -= (edge(dj, dk, 0.5) - edge(dj, dk, -0.5)) / dx[dk]
+            parts.append(phi)
+        out.append(np.concatenate(parts))
+    return np.concatenate(out)
