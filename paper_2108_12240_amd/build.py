@@ -1,8 +1,9 @@
 """Build the HIP library ``libbhac.so`` in-tree for gfx950.
 
 Every HIP translation unit is compiled with hipcc for gfx950 only; packed FP32
-instructions are disabled (``-packed-fp32-ops``) and FP contraction is left at the
-compiler's default.
+instructions are disabled (``-packed-fp32-ops``) and FP contraction is limited to
+one source expression (``-ffp-contract=on``), so an expression rounds the same way
+in every kernel that inlines it.
 """
 from __future__ import annotations
 
