@@ -114,6 +114,15 @@ enum { BHAC_PREC_FP64 = 0, BHAC_PREC_MIXED = 1 };
  *                       gamma_ad <= 2 (else BHAC_EINVAL), fused = 0 and amr = 0
  *                       (else BHAC_EUNSUPPORTED).
  *  sched                kernel schedule of the unfused substep (see bhac_schedule).
+ *  ct                   0: divergence cleaning (GLM: the normal field of a face from
+ *                       the exact (B~, psi) solve, psi damped). 1: staggered-mesh
+ *                       constrained transport (Section 2: the paper's code evolves the
+ *                       field by constrained transport on a staggered mesh): the field
+ *                       is carried as face fluxes phi^d = sqrt(gamma) B^d and advanced
+ *                       by bhac_substep_ct. Needs fused = 0, amr = 0 and entropy = 0
+ *                       (else BHAC_EUNSUPPORTED); the face fluxes of every direction
+ *                       come from the one-thread-per-face kernel (the schedule's other
+ *                       fields are ignored).
  */
 
 /* Schedule of the unfused substep (fused = 0; the block-tiled path ignores it).
@@ -155,6 +164,7 @@ typedef struct bhac_params {
     int amr;            /* 0 independent patches, 1 block tree */
     int entropy;        /* 0 nine variables, 1 plus the entropy field (inversion backup) */
     bhac_schedule sched;
+    int ct;             /* 0 GLM divergence cleaning, 1 staggered constrained transport */
 } bhac_params;
 
 /* One block: refinement level, interior cells per axis, and origin in level-l
@@ -291,7 +301,7 @@ int bhac_substep(bhac_grid *grid, const double *U_base, const double *U_stage, c
  * Limit: the grid's face fluxes (nvar rows x faces per direction x 4 bytes in mixed
  * precision, 8 in FP64, each direction rounded up to 256 bytes) must fit the 64 MiB
  * (about 80^3 cells in mixed precision, 64^3 in FP64), else BHAC_EINVAL with the
- * sizes in the message; fused = 1 gives BHAC_EUNSUPPORTED; the grid's device must be
+ * sizes in the message; fused = 1 or ct = 1 gives BHAC_EUNSUPPORTED; the grid's device must be
  * the current device (BHAC_EINVAL). Arguments, aliasing rules, time-step handling
  * and other errors as bhac_substep. Every call on one GPU shares that GPU's array and
  * leaves its contents behind; nothing in it has to start at zero (a substep writes
@@ -299,6 +309,44 @@ int bhac_substep(bhac_grid *grid, const double *U_base, const double *U_stage, c
  * streams or host threads) race on the array: serialise them. */
 int bhac_substep_noalloc(bhac_grid *grid, const double *U_base, const double *U_stage, const void *P_stage,
                          double *U_out, void *P_out, double a, double b, void *stream);
+
+/* Staggered face field (constrained transport, params.ct = 1). Layout of a face
+ * field phi (device double): the arrays of directions 0 .. ndim-1 one after another;
+ * direction d holds nface[d] faces, block b's faces from the sum of the earlier
+ * blocks' counts, (size_0 + [d == 0]) x (size_1 + [d == 1]) x (size_2 + [d == 2]) of
+ * them, x fastest. Every block holds all faces of its cells, so a face between two
+ * blocks has one copy in each; the calls keep the copies identical. phi^d is
+ * sqrt(gamma) B^d at the centre of the d-face. bhac_face_count returns nface (host). */
+int bhac_face_count(bhac_grid *grid, int64_t nface[3]);
+
+/* Cell-centred field from a face field: P rows B^d (d < ndim) = the mean of the
+ * cell's two faces of phi^d divided by sqrt(gamma) at the cell centre; the other rows
+ * of prim are untouched (with ndim = 2 the x3 field stays the caller's). phi: device
+ * double; prim: [nvar][ncell_padded] (interior cells written). */
+int bhac_ct_center(bhac_grid *grid, const double *phi, void *prim, void *stream);
+
+/* Discrete divergence of a face field at every interior cell, interior-packed:
+ * div = sum_d (phi^d(high face) - phi^d(low face)) / dx_d. div: device double
+ * [ncell_interior]. */
+int bhac_ct_divergence(bhac_grid *grid, const double *phi, double *div, void *stream);
+
+/* One RK substep under constrained transport (params.ct = 1): as bhac_substep, with
+ * the face field advanced in the same combination,
+ *   phi_out = a phi_base + b (phi_stage - dt curl E),  d_t phi^i = -(d_j E_k - d_k E_j)
+ * ((i, j, k) cyclic), where E_k = F^j(B~^i) = -F^i(B~^j) at each cell edge is the mean
+ * of the four induction fluxes of the faces around the edge (a face beyond the block
+ * taken from the neighbouring block, or from the block's own nearest face where the
+ * halo is zero-gradient). The face fluxes use the face's phi as the normal field of
+ * both states (no GLM solve: normal-field and psi fluxes vanish); the cell's
+ * densitised field in U_out is the mean of its two updated faces along each resolved
+ * direction (with ndim = 2 the x3 field is a cell-centred finite-volume variable). The
+ * discrete divergence (bhac_ct_divergence) is kept at its initial value to round-off.
+ * phi_base, phi_stage, phi_out: device double in the face layout; phi_out may alias
+ * phi_base or phi_stage. Other arguments and errors as bhac_substep; bhac_substep on
+ * a grid with ct = 1 gives BHAC_EINVAL. */
+int bhac_substep_ct(bhac_grid *grid, const double *U_base, const double *U_stage, const void *P_stage,
+                    const double *phi_base, const double *phi_stage, double *U_out, void *P_out, double *phi_out,
+                    double a, double b, void *stream);
 
 /* Standalone wave-speed reduction over cell-centred states of prim (interior
  * cells): sets dt_next = C / sum_d (lambda_d / dx_d), dx on the finest level. */
@@ -334,7 +382,8 @@ int bhac_get_schedule(bhac_grid *grid, bhac_schedule *out);
  * call per step, same results as the two calls made one by one. The time-step
  * state lives on the device, so replays need no host work. Needs an initialised
  * time step (BHAC_EINVAL otherwise); P/P1 aliasing rules as for bhac_substep.
- * Launching before a capture returns BHAC_EINVAL. */
+ * Launching before a capture returns BHAC_EINVAL; a grid with ct = 1 gives
+ * BHAC_EUNSUPPORTED (the graph does not carry the face field). */
 int bhac_capture_rk2_step(bhac_grid *grid, double *U, void *P, double *U1, void *P1);
 int bhac_launch_rk2_step(bhac_grid *grid, void *stream);
 

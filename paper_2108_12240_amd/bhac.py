@@ -39,7 +39,7 @@ class bhac_params(C.Structure):
                 ("precision", C.c_int), ("fused", C.c_int), ("cfl", C.c_double), ("rho_floor", C.c_double),
                 ("p_floor", C.c_double), ("w_max", C.c_double), ("glm_alpha", C.c_double),
                 ("c2p_tol", C.c_double), ("c2p_maxit", C.c_int), ("amr", C.c_int), ("entropy", C.c_int),
-                ("sched", bhac_schedule)]
+                ("sched", bhac_schedule), ("ct", C.c_int)]
 
 
 class bhac_block_desc(C.Structure):
@@ -83,6 +83,10 @@ def lib():
             "bhac_con2prim": [_VP, _VP, _VP, _VP, _VP],
             "bhac_substep": [_VP, _VP, _VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP],
             "bhac_substep_noalloc": [_VP, _VP, _VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP],
+            "bhac_substep_ct": [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP],
+            "bhac_face_count": [_VP, C.POINTER(C.c_int64)],
+            "bhac_ct_center": [_VP, _VP, _VP, _VP],
+            "bhac_ct_divergence": [_VP, _VP, _VP, _VP],
             "bhac_compute_dt": [_VP, _VP, _VP],
             "bhac_set_dt": [_VP, C.c_double, _VP],
             "bhac_get_dt": [_VP, C.POINTER(C.c_double)],
@@ -119,6 +123,7 @@ def make_params(d: dict) -> bhac_params:
     for k in ("ndim", "nghost", "metric", "recon", "flux", "precision", "fused", "c2p_maxit"):
         setattr(p, k, int(d[k]))
     p.amr = int(d.get("amr", 0))
+    p.ct = int(d.get("ct", 0))
     p.entropy = int(d.get("entropy", 0))
     sched = d.get("sched")
     if sched is not None:
@@ -214,6 +219,25 @@ def bhac_substep(h, U_base, U_stage, P_stage, U_out, P_out, a, b, stream=None):
 def bhac_substep_noalloc(h, U_base, U_stage, P_stage, U_out, P_out, a, b, stream=None):
     _check(lib().bhac_substep_noalloc(h, _ptr(U_base), _ptr(U_stage), _ptr(P_stage), _ptr(U_out), _ptr(P_out),
                                       float(a), float(b), _stream(stream)))
+
+
+def bhac_substep_ct(h, U_base, U_stage, P_stage, phi_base, phi_stage, U_out, P_out, phi_out, a, b, stream=None):
+    _check(lib().bhac_substep_ct(h, _ptr(U_base), _ptr(U_stage), _ptr(P_stage), _ptr(phi_base), _ptr(phi_stage),
+                                 _ptr(U_out), _ptr(P_out), _ptr(phi_out), float(a), float(b), _stream(stream)))
+
+
+def bhac_face_count(h):
+    n = (C.c_int64 * 3)()
+    _check(lib().bhac_face_count(h, n))
+    return [int(x) for x in n]
+
+
+def bhac_ct_center(h, phi, prim, stream=None):
+    _check(lib().bhac_ct_center(h, _ptr(phi), _ptr(prim), _stream(stream)))
+
+
+def bhac_ct_divergence(h, phi, div, stream=None):
+    _check(lib().bhac_ct_divergence(h, _ptr(phi), _ptr(div), _stream(stream)))
 
 
 def bhac_compute_dt(h, prim, stream=None):
@@ -353,6 +377,38 @@ class Grid:
 
     def substep_noalloc(self, Ub, Us, Ps, Uo, Po, a, b):
         bhac_substep_noalloc(self.h, Ub, Us, Ps, Uo, Po, a, b)
+
+    # --- staggered face field (constrained transport, params ct = 1) -----------------
+    def face_count(self):
+        return bhac_face_count(self.h)
+
+    def new_faces(self):
+        return self.torch.zeros(sum(self.face_count()), dtype=self.torch.float64, device=self.device)
+
+    def substep_ct(self, Ub, Us, Ps, Phib, Phis, Uo, Po, Phio, a, b):
+        bhac_substep_ct(self.h, Ub, Us, Ps, Phib, Phis, Uo, Po, Phio, a, b)
+
+    def ct_divergence(self, phi):
+        div = self.torch.zeros(self.nci, dtype=self.torch.float64, device=self.device)
+        bhac_ct_divergence(self.h, phi, div)
+        return div
+
+    def init_ct(self, prim_interior, phi_host):
+        """Device P (field rows from the face field, ghosts filled), U = prim2con(P),
+        the face field on the device, and the initial wave-speed reduction."""
+        P = self.pack(prim_interior)
+        phi = self.torch.from_numpy(np.ascontiguousarray(phi_host, dtype=np.float64)).to(self.device)
+        bhac_ct_center(self.h, phi, P)
+        U = self.new_state("U")
+        self.fill_ghosts(P)
+        self.prim2con(P, U)
+        self.compute_dt(P)
+        return U, P, phi
+
+    def rk2_step_ct(self, U, P, phi, U1, P1, phi1):
+        """One SSP-RK2 step in place on (U, P, phi) with scratch (U1, P1, phi1)."""
+        self.substep_ct(U, U, P, phi, phi, U1, P1, phi1, 0.0, 1.0)
+        self.substep_ct(U, U1, P1, phi, phi1, U, P, phi, 0.5, 0.5)
 
     def init(self, prim_interior):
         """Device P (ghosts filled), U = prim2con(P) and the initial wave-speed reduction."""

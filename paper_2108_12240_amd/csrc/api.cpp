@@ -381,9 +381,58 @@ int bhac_substep(bhac_grid *g, const double *U_base, const double *U_stage, cons
                  void *P_out, double a, double b, void *stream)
 {
     if (int rc = check_substep(g, U_base, U_stage, P_stage, U_out, P_out, a, b)) return rc;
+    if (g->dg.plan.p.ct) return fail(BHAC_EINVAL, "the grid uses constrained transport: call bhac_substep_ct");
     g->last_stream = (hipStream_t)stream;
     hipError_t e = bhac::launch_substep(g->dg, U_base, U_stage, P_stage, U_out, P_out, a, b, (hipStream_t)stream);
     return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_substep");
+}
+
+int bhac_substep_ct(bhac_grid *g, const double *U_base, const double *U_stage, const void *P_stage,
+                    const double *phi_base, const double *phi_stage, double *U_out, void *P_out, double *phi_out,
+                    double a, double b, void *stream)
+{
+    if (int rc = check_substep(g, U_base, U_stage, P_stage, U_out, P_out, a, b)) return rc;
+    if (!g->dg.plan.p.ct) return fail(BHAC_EINVAL, "bhac_substep_ct needs a grid with ct = 1");
+    if (!phi_base || !phi_stage || !phi_out) return fail(BHAC_EINVAL, "null face field");
+    const void *u[] = {U_base, U_stage, U_out}, *pr[] = {P_stage, P_out};
+    for (const void *f : {(const void *)phi_base, (const void *)phi_stage, (const void *)phi_out}) {
+        for (const void *x : u)
+            if (x == f) return fail(BHAC_EALIAS, "a face field aliases a conserved array");
+        for (const void *x : pr)
+            if (x == f) return fail(BHAC_EALIAS, "a face field aliases a primitive array");
+    }
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_substep_ct(g->dg, U_base, U_stage, P_stage, phi_base, phi_stage, U_out, P_out, phi_out, a,
+                                           b, (hipStream_t)stream);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_substep_ct");
+}
+
+int bhac_face_count(bhac_grid *g, int64_t nface[3])
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!nface) return fail(BHAC_EINVAL, "null output");
+    for (int d = 0; d < 3; d++) nface[d] = d < g->dg.kp.ndim ? (int64_t)g->dg.plan.nface[d] : 0;
+    return BHAC_OK;
+}
+
+int bhac_ct_center(bhac_grid *g, const double *phi, void *prim, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!phi || !prim) return fail(BHAC_EINVAL, "null array");
+    if ((const void *)phi == prim) return fail(BHAC_EALIAS, "phi aliases prim");
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_ct_center(g->dg, phi, prim, (hipStream_t)stream);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_ct_center");
+}
+
+int bhac_ct_divergence(bhac_grid *g, const double *phi, double *div, void *stream)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!phi || !div) return fail(BHAC_EINVAL, "null array");
+    if (phi == div) return fail(BHAC_EALIAS, "div aliases phi");
+    g->last_stream = (hipStream_t)stream;
+    hipError_t e = bhac::launch_ct_div(g->dg, phi, div, (hipStream_t)stream);
+    return e == hipSuccess ? BHAC_OK : hip_fail(e, "bhac_ct_divergence");
 }
 
 int bhac_substep_noalloc(bhac_grid *g, const double *U_base, const double *U_stage, const void *P_stage,
@@ -392,6 +441,7 @@ int bhac_substep_noalloc(bhac_grid *g, const double *U_base, const double *U_sta
     if (int rc = check_substep(g, U_base, U_stage, P_stage, U_out, P_out, a, b)) return rc;
     const bhac::DeviceGrid &G = g->dg;
     if (G.plan.p.fused) return fail(BHAC_EUNSUPPORTED, "bhac_substep_noalloc runs the unfused substep (fused = 0) only");
+    if (G.plan.p.ct) return fail(BHAC_EUNSUPPORTED, "bhac_substep_noalloc does not run constrained transport");
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != G.device)
         return fail(BHAC_EINVAL, "bhac_substep_noalloc: the grid's device is not the current device");
@@ -500,6 +550,7 @@ int bhac_capture_rk2_step(bhac_grid *g, double *U, void *P, double *U1, void *P1
     if (!U || !P || !U1 || !P1) return fail(BHAC_EINVAL, "null array");
     if (P == P1 || (void *)U == (void *)U1) return fail(BHAC_EALIAS, "stage buffers must differ");
     if (!g->dg.have_dt) return fail(BHAC_EINVAL, "time step not initialised: call bhac_compute_dt or bhac_set_dt");
+    if (g->dg.plan.p.ct) return fail(BHAC_EUNSUPPORTED, "the captured RK2 step does not carry the face field (ct = 1)");
     hipError_t e;
     if (!g->cap_stream) {
         e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);

@@ -48,7 +48,7 @@ struct GridDev {
 
 // Kernel families timed by the optional HIP-event timer.
 enum KernelId { K_FILL, K_FLUX0, K_FLUX1, K_FLUX2, K_UPDATE, K_PRIM2CON, K_CON2PRIM, K_SPEEDS, K_BEGIN, K_END,
-                K_BLOCK_FLUX, K_UPDATE_DIV, K_FILL_XL, K_FLUX_FIX, K_UPDATE_X1, K_COUNT };
+                K_BLOCK_FLUX, K_UPDATE_DIV, K_FILL_XL, K_FLUX_FIX, K_UPDATE_X1, K_CT_FACE, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Optional per-launch timing: a pre-created pool of HIP events recorded on the
@@ -135,5 +135,10 @@ hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStre
 // the state's precision); nullptr = the grid's own (d_flux)
 hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
                           void *Po, double a, double b, hipStream_t s, void *const *flux = nullptr);
+// constrained transport (plan.p.ct): face fields in the face layout (directions one after another)
+hipError_t launch_substep_ct(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, const double *Phb,
+                             const double *Phs, double *Uo, void *Po, double *Pho, double a, double b, hipStream_t s);
+hipError_t launch_ct_center(const DeviceGrid &G, const double *Ph, void *P, hipStream_t s);
+hipError_t launch_ct_div(const DeviceGrid &G, const double *Ph, double *div, hipStream_t s);
 
 }  // namespace bhac

@@ -178,9 +178,12 @@ constexpr int flux_occupancy()
 // ENT (entropy field): the entropy function K (row NV of P) is reconstructed at the
 // face like the other variables, from the same stencil cells, and carried by the
 // face's mass flux from the side that flux comes from (row NV of F).
-template <typename R, int D, int RECON, int FLUX, bool KS, bool XL, bool ENT>
+// CT: constrained transport, the normal field of the face is the face field phi
+// (direction D's array) for both states and there is no GLM solve.
+template <typename R, int D, int RECON, int FLUX, bool KS, bool XL, bool ENT, bool CT = false>
 __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
-                                             const R *__restrict__ P, R *__restrict__ F, long long nftot)
+                                             const R *__restrict__ P, R *__restrict__ F, long long nftot,
+                                             const double *__restrict__ phi)
 {
     __shared__ double red[WG / 64];
     const WorkItem w = work[blockIdx.x];
@@ -253,8 +256,13 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KPara
         }
         const FaceM<R> m = face_metric<R, D, KS>(gd, B, i, j);
         const R ch = (R)gd.st->ch;
+        if constexpr (CT) {
+            const R bn = (R)phi[B.fofs[D] + item] / m.sg;
+            qL[5 + D] = bn;
+            qR[5 + D] = bn;
+        }
         R Ff[NV];
-        lam = (double)face_flux<R, D, FLUX>(qL, qR, m, ch, (R)kp.gam, (R)kp.gfac, Ff);
+        lam = (double)face_flux<R, D, FLUX, CT>(qL, qR, m, ch, (R)kp.gam, (R)kp.gfac, Ff);
         R *out = F + B.fofs[D] + item;
 #pragma unroll
         for (int v = 0; v < NV; v++) out[v * nftot] = Ff[v];
@@ -342,12 +350,17 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(K
 // template parameters so that every load of a cell sits in one basic block and is
 // issued before the first wait (a uniform run-time branch per value would split
 // the loads into serial round trips).
-template <typename R, bool KS, bool ND3, bool BASE, bool ENT>
+// CT: constrained transport; the field rows of U_out along the resolved directions are
+// the means of the cell's two updated faces of the face field (Ph0..Ph2: directions'
+// arrays of phi_out, written earlier in the substep).
+template <typename R, bool KS, bool ND3, bool BASE, bool ENT, bool CT = false>
 __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
                                                const double *Ub, const double *Us, const R *__restrict__ Ps,
                                                double *Uo, R *__restrict__ Po, const R *__restrict__ F0,
                                                const R *__restrict__ F1, const R *__restrict__ F2, long long nf0,
-                                               long long nf1, long long nf2, double a, double b)
+                                               long long nf1, long long nf2, double a, double b,
+                                               const double *__restrict__ Ph0, const double *__restrict__ Ph1,
+                                               const double *__restrict__ Ph2)
 {
     constexpr int NQ = NV + (ENT ? 1 : 0);        // rows: GRMHD variables (+ entropy field)
     __shared__ long long redl[WG / 64];
@@ -363,6 +376,7 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
         const DevLevel &L = gd.levels[B.level];
         // flux divergence, formed per direction in R, summed in double
         double div[3][NQ];
+        double bface[3] = {0.0, 0.0, 0.0};        // CT: mean of the updated face fields
 #pragma unroll
         for (int v = 0; v < NQ; v++) div[2][v] = 0.0;
 #pragma unroll
@@ -375,6 +389,10 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
             const R idx = (R)L.inv_dx[d];
 #pragma unroll
             for (int v = 0; v < NQ; v++) div[d][v] = (double)((Fd[v * nf + hi] - Fd[v * nf + lo]) * idx);
+            if constexpr (CT) {
+                const double *Ph = d == 0 ? Ph0 : (d == 1 ? Ph1 : Ph2);
+                bface[d] = 0.5 * (Ph[lo] + Ph[hi]);
+            }
         }
         double q[NQ], Uc[NQ], S[NQ];
 #pragma unroll
@@ -393,6 +411,10 @@ __global__ __launch_bounds__(WG, 3) void k_update(KParams kp, GridDev gd, const 
             // U_out = a U_base + b (U_stage + dt L) rounded once
             const double Lv = neumaier4(-div[0][v], -div[1][v], -div[2][v], S[v]);
             Un[v] = rk_combine<BASE>(a, BASE ? Ub[v * kp.nci + ci] : 0.0, b, Uc[v], dt, Lv);
+        }
+        if constexpr (CT) {
+#pragma unroll
+            for (int d = 0; d < (ND3 ? 3 : 2); d++) Un[5 + d] = bface[d];
         }
         double Pn[NQ];
         fail = con_to_prim<ENT>(Un, q, m, kp, Pn, nit, floored, backup);
@@ -554,6 +576,139 @@ __global__ __launch_bounds__(WG, 3) void k_update_x1(KParams kp, GridDev gd, con
 // ---------------------------------------------------------------------------------
 // Pointwise kernels.
 // ---------------------------------------------------------------------------------
+// ---------------------------------------------------------------------------------
+// Staggered-mesh constrained transport. The face field phi^d = sqrt(gamma) B^d lives
+// on every face of a block (the layout of the face-flux arrays). Its update needs the
+// edge electric fields E_k = F^j(B~^i) = -F^i(B~^j) ((i, j, k) cyclic), each the mean
+// of the induction fluxes of the four faces around the edge; a face beyond the block
+// is read from the neighbouring block's face array (or, where the halo rule is the
+// zero-gradient clamp, from the block's own nearest face), so the two copies of a
+// face shared by two blocks receive identical updates.
+// ---------------------------------------------------------------------------------
+struct CtFlux {
+    const void *F[3];                // face-flux arrays of the three directions (R)
+    long long nf[3];
+};
+
+// flux row v of direction d at block b's face (f0, f1, f2): f[d] a face index, the
+// others cell indices, at most one of them beyond the block
+template <typename R>
+__device__ __forceinline__ double ct_flux(const GridDev &gd, const DevBlock &B, int b, const CtFlux &cf, int d, int v,
+                                          int f0, int f1, int f2)
+{
+    int f[3] = {f0, f1, f2};
+    int nb = b;
+#pragma unroll
+    for (int e = 0; e < 3; e++) {
+        if (e == d) continue;
+        const int pe = e == 0 ? 1 : (e == 1 ? 3 : 9);
+        if (f[e] < 0) {
+            if ((B.hclamp >> (2 * e)) & 1) f[e] = 0;
+            else { nb = gd.nbr[(long long)b * 27 + 13 - pe]; f[e] += B.s[e]; }
+        } else if (f[e] >= B.s[e]) {
+            if ((B.hclamp >> (2 * e + 1)) & 1) f[e] = B.s[e] - 1;
+            else { nb = gd.nbr[(long long)b * 27 + 13 + pe]; f[e] -= B.s[e]; }
+        }
+    }
+    const long long fofs = nb == b ? B.fofs[d] : gd.blocks[nb].fofs[d];
+    const int fs0 = B.s[0] + (d == 0), fs1 = B.s[1] + (d == 1);
+    const R *F = (const R *)cf.F[d];
+    return (double)F[v * cf.nf[d] + fofs + ((long long)f[2] * fs1 + f[1]) * fs0 + f[0]];
+}
+
+// E along axis AX at the edge whose corner is c in face units along the two axes
+// normal to it (cell index along AX)
+template <typename R, int AX>
+__device__ __forceinline__ double ct_emf(const GridDev &gd, const DevBlock &B, int b, const CtFlux &cf, int c0, int c1,
+                                         int c2)
+{
+    constexpr int A = (AX + 1) % 3, Bx = (AX + 2) % 3;
+    int lo_a[3] = {c0, c1, c2}, lo_b[3] = {c0, c1, c2};
+    lo_a[A] -= 1;           // Bx-faces of the cells on both sides along A
+    lo_b[Bx] -= 1;          // A-faces of the cells on both sides along Bx
+    const double fb = ct_flux<R>(gd, B, b, cf, Bx, 5 + A, lo_a[0], lo_a[1], lo_a[2]) +
+                      ct_flux<R>(gd, B, b, cf, Bx, 5 + A, c0, c1, c2);
+    const double fa = ct_flux<R>(gd, B, b, cf, A, 5 + Bx, lo_b[0], lo_b[1], lo_b[2]) +
+                      ct_flux<R>(gd, B, b, cf, A, 5 + Bx, c0, c1, c2);
+    return 0.25 * (fb - fa);
+}
+
+// phi_out = a phi_base + b (phi_stage + dt L), L = -(d_j E_k - d_k E_j) on the faces of
+// direction D ((D, j, k) cyclic); with ndim = 2 only the edges along x3 exist
+template <typename R, int D, bool ND3, bool BASE>
+__global__ __launch_bounds__(WG) void k_ct_face(KParams kp, GridDev gd, const WorkItem *__restrict__ work, CtFlux cf,
+                                                const double *Phb, const double *Phs, double *Pho, double a, double b)
+{
+    constexpr int DJ = (D + 1) % 3, DK = (D + 2) % 3;
+    const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;
+    const DevBlock B = gd.blocks[w.block];
+    const int fs0 = B.s[0] + (D == 0), fs1 = B.s[1] + (D == 1), fs2 = B.s[2] + (D == 2);
+    const int item = w.start + threadIdx.x;
+    if (item >= fs0 * fs1 * fs2) return;
+    const int i = item % fs0, t = item / fs0, j = t % fs1, k = t / fs1;
+    const DevLevel &L = gd.levels[B.level];
+    double Lv = 0.0;
+    if constexpr (DJ < 2 || ND3) {
+        int h[3] = {i, j, k};
+        h[DJ] += 1;
+        Lv -= (ct_emf<R, DK>(gd, B, w.block, cf, h[0], h[1], h[2]) - ct_emf<R, DK>(gd, B, w.block, cf, i, j, k)) *
+              L.inv_dx[DJ];
+    }
+    if constexpr (DK < 2 || ND3) {
+        int h[3] = {i, j, k};
+        h[DK] += 1;
+        Lv += (ct_emf<R, DJ>(gd, B, w.block, cf, h[0], h[1], h[2]) - ct_emf<R, DJ>(gd, B, w.block, cf, i, j, k)) *
+              L.inv_dx[DK];
+    }
+    const long long q = B.fofs[D] + item;
+    Pho[q] = rk_combine<BASE>(a, BASE ? Phb[q] : 0.0, b, Phs[q], gd.st->dt, Lv);
+}
+
+// cell-centred field from a face field: P rows B^d = mean of the two faces / sqrt(gamma)
+template <typename R, bool KS>
+__global__ __launch_bounds__(WG) void k_ct_center(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+                                                  const double *__restrict__ Ph0, const double *__restrict__ Ph1,
+                                                  const double *__restrict__ Ph2, R *__restrict__ P)
+{
+    const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;
+    const DevBlock B = gd.blocks[w.block];
+    int i, j, k;
+    if (!cell_of(B, w.start + threadIdx.x, i, j, k)) return;
+    const double sg = centre_metric<KS>(gd, B, i, j).sg;
+    const long long c = pad_index(B, kp, i, j, k);
+    for (int d = 0; d < kp.ndim; d++) {
+        const double *Ph = d == 0 ? Ph0 : (d == 1 ? Ph1 : Ph2);
+        const int fs0 = B.s[0] + (d == 0), fs1 = B.s[1] + (d == 1);
+        const long long lo = B.fofs[d] + ((long long)k * fs1 + j) * fs0 + i;
+        const long long hi = lo + (d == 0 ? 1 : (d == 1 ? fs0 : (long long)fs0 * fs1));
+        P[(5 + d) * kp.ncp + c] = (R)(0.5 * (Ph[lo] + Ph[hi]) / sg);
+    }
+}
+
+// discrete divergence of a face field per interior cell (interior-packed)
+__global__ __launch_bounds__(WG) void k_ct_div(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
+                                               const double *__restrict__ Ph0, const double *__restrict__ Ph1,
+                                               const double *__restrict__ Ph2, double *__restrict__ div)
+{
+    const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;
+    const DevBlock B = gd.blocks[w.block];
+    int i, j, k;
+    if (!cell_of(B, w.start + threadIdx.x, i, j, k)) return;
+    const DevLevel &L = gd.levels[B.level];
+    double sdiv = 0.0;
+    for (int d = 0; d < kp.ndim; d++) {
+        const double *Ph = d == 0 ? Ph0 : (d == 1 ? Ph1 : Ph2);
+        const int fs0 = B.s[0] + (d == 0), fs1 = B.s[1] + (d == 1);
+        const long long lo = B.fofs[d] + ((long long)k * fs1 + j) * fs0 + i;
+        const long long hi = lo + (d == 0 ? 1 : (d == 1 ? fs0 : (long long)fs0 * fs1));
+        sdiv += (Ph[hi] - Ph[lo]) * L.inv_dx[d];
+    }
+    div[B.ioff + w.start + threadIdx.x] = sdiv;
+}
+
 template <typename R, bool KS>
 __global__ __launch_bounds__(WG) void k_prim2con(KParams kp, GridDev gd, const WorkItem *__restrict__ work,
                                                  const R *__restrict__ P, double *__restrict__ U)
@@ -694,7 +849,7 @@ inline unsigned nblk(long long n) { return (unsigned)((n + WG - 1) / WG); }
 const char *const kKernelNames[K_COUNT] = {"fill_ghosts", "flux_x1", "flux_x2", "flux_x3", "update",
                                            "prim2con", "con2prim", "cell_speeds", "step_begin", "step_end",
                                            "block_flux", "update_div", "fill_cross_level", "flux_fix",
-                                           "update_x1"};
+                                           "update_x1", "ct_faces"};
 
 hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only)
 {
@@ -837,7 +992,7 @@ static hipError_t flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s, v
     auto kern = xl ? k_flux<R, D, RECON, FLUX, KS, true, false>
                    : (ent ? k_flux<R, D, RECON, FLUX, KS, false, true> : k_flux<R, D, RECON, FLUX, KS, false, false>);
     hipLaunchKernelGGL(kern, dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D], (const R *)Ps,
-                       (R *)flux[D], G.plan.nface[D]);
+                       (R *)flux[D], G.plan.nface[D], (const double *)nullptr);
     return hipGetLastError();
 }
 
@@ -854,7 +1009,8 @@ static hipError_t update_typed(const DeviceGrid &G, const double *Ub, const doub
                    : (base ? k_update<R, KS, false, true, true> : k_update<R, KS, false, false, true>);
     hipLaunchKernelGGL(kern, dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, Ub, Us,
                        (const R *)Ps, Uo, (R *)Po, (const R *)flux[0], (const R *)flux[1],
-                       (const R *)flux[2], G.plan.nface[0], G.plan.nface[1], G.plan.nface[2], a, b);
+                       (const R *)flux[2], G.plan.nface[0], G.plan.nface[1], G.plan.nface[2], a, b,
+                       (const double *)nullptr, (const double *)nullptr, (const double *)nullptr);
     return hipGetLastError();
 }
 
@@ -967,6 +1123,137 @@ hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *U
     else e = substep_prec<double>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
     if (e != hipSuccess) return e;
     return end_step(G, s);
+}
+
+// ---------------------------------------------------------------------------------
+// Constrained-transport substep: face fluxes (one thread per face, normal field from
+// the face field), face-field update per direction, then the cell update.
+// ---------------------------------------------------------------------------------
+struct CtPtrs {
+    const double *b[3], *s[3];
+    double *o[3];
+};
+
+static CtPtrs ct_split(const DeviceGrid &G, const double *Phb, const double *Phs, double *Pho)
+{
+    CtPtrs c{};
+    long long base = 0;
+    for (int d = 0; d < 3; d++) {
+        if (d < G.kp.ndim) {
+            c.b[d] = Phb ? Phb + base : nullptr;
+            c.s[d] = Phs ? Phs + base : nullptr;
+            c.o[d] = Pho ? Pho + base : nullptr;
+            base += G.plan.nface[d];
+        } else {
+            c.b[d] = c.s[d] = nullptr;
+            c.o[d] = nullptr;
+        }
+    }
+    return c;
+}
+
+template <typename R, int D, int RECON, int FLUX, bool KS>
+static hipError_t ct_flux_dir(const DeviceGrid &G, const void *Ps, const double *phs, hipStream_t s)
+{
+    TimedLaunch tl(G.timer, K_FLUX0 + D, s);
+    hipLaunchKernelGGL((k_flux<R, D, RECON, FLUX, KS, false, false, true>), dim3(G.plan.wface[D].size()), dim3(WG), 0,
+                       s, G.kp, G.gd, G.d_wface[D], (const R *)Ps, (R *)G.d_flux[D], G.plan.nface[D], phs);
+    return hipGetLastError();
+}
+
+template <typename R, int D, bool ND3>
+static hipError_t ct_face_dir(const DeviceGrid &G, const CtFlux &cf, const CtPtrs &c, double a, double b, hipStream_t s)
+{
+    TimedLaunch tl(G.timer, K_CT_FACE, s);
+    auto kern = a != 0.0 ? k_ct_face<R, D, ND3, true> : k_ct_face<R, D, ND3, false>;
+    hipLaunchKernelGGL(kern, dim3(G.plan.wface[D].size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D], cf, c.b[D],
+                       c.s[D], c.o[D], a, b);
+    return hipGetLastError();
+}
+
+template <typename R, int RECON, int FLUX, bool KS>
+static hipError_t substep_ct_typed(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps,
+                                   const CtPtrs &c, double *Uo, void *Po, double a, double b, hipStream_t s)
+{
+    const bool nd3 = G.kp.ndim == 3;
+    hipError_t e = ct_flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, c.s[0], s);
+    if (e == hipSuccess) e = ct_flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, c.s[1], s);
+    if (e == hipSuccess && nd3) e = ct_flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, c.s[2], s);
+    const CtFlux cf{{G.d_flux[0], G.d_flux[1], G.d_flux[2]}, {G.plan.nface[0], G.plan.nface[1], G.plan.nface[2]}};
+    if (nd3) {
+        if (e == hipSuccess) e = ct_face_dir<R, 0, true>(G, cf, c, a, b, s);
+        if (e == hipSuccess) e = ct_face_dir<R, 1, true>(G, cf, c, a, b, s);
+        if (e == hipSuccess) e = ct_face_dir<R, 2, true>(G, cf, c, a, b, s);
+    } else {
+        if (e == hipSuccess) e = ct_face_dir<R, 0, false>(G, cf, c, a, b, s);
+        if (e == hipSuccess) e = ct_face_dir<R, 1, false>(G, cf, c, a, b, s);
+    }
+    if (e != hipSuccess) return e;
+    TimedLaunch tl(G.timer, K_UPDATE, s);
+    const bool base = a != 0.0;
+    auto kern = nd3 ? (base ? k_update<R, KS, true, true, false, true> : k_update<R, KS, true, false, false, true>)
+                    : (base ? k_update<R, KS, false, true, false, true> : k_update<R, KS, false, false, false, true>);
+    hipLaunchKernelGGL(kern, dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, Ub, Us, (const R *)Ps,
+                       Uo, (R *)Po, (const R *)G.d_flux[0], (const R *)G.d_flux[1], (const R *)G.d_flux[2],
+                       G.plan.nface[0], G.plan.nface[1], G.plan.nface[2], a, b, (const double *)c.o[0],
+                       (const double *)c.o[1], (const double *)c.o[2]);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t substep_ct_prec(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps,
+                                  const CtPtrs &c, double *Uo, void *Po, double a, double b, hipStream_t s)
+{
+    const int r = G.kp.recon, f = G.kp.flux;
+#define CT_CASE(RC, FL)                                                                                              \
+    return G.ks ? substep_ct_typed<R, RC, FL, true>(G, Ub, Us, Ps, c, Uo, Po, a, b, s)                               \
+                : substep_ct_typed<R, RC, FL, false>(G, Ub, Us, Ps, c, Uo, Po, a, b, s)
+    if (r == BHAC_RECON_PPM && f == BHAC_FLUX_HLL) CT_CASE(BHAC_RECON_PPM, BHAC_FLUX_HLL);
+    if (r == BHAC_RECON_PPM) CT_CASE(BHAC_RECON_PPM, BHAC_FLUX_TVDLF);
+    if (f == BHAC_FLUX_HLL) CT_CASE(BHAC_RECON_MC, BHAC_FLUX_HLL);
+    CT_CASE(BHAC_RECON_MC, BHAC_FLUX_TVDLF);
+#undef CT_CASE
+}
+
+hipError_t launch_substep_ct(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, const double *Phb,
+                             const double *Phs, double *Uo, void *Po, double *Pho, double a, double b, hipStream_t s)
+{
+    hipError_t e = begin_step(G, a == 0.0 ? 1 : 0, s);
+    if (e != hipSuccess) return e;
+    const CtPtrs c = ct_split(G, Phb, Phs, Pho);
+    e = G.mixed ? substep_ct_prec<float>(G, Ub, Us, Ps, c, Uo, Po, a, b, s)
+                : substep_ct_prec<double>(G, Ub, Us, Ps, c, Uo, Po, a, b, s);
+    if (e != hipSuccess) return e;
+    return end_step(G, s);
+}
+
+hipError_t launch_ct_center(const DeviceGrid &G, const double *Ph, void *P, hipStream_t s)
+{
+    const CtPtrs c = ct_split(G, Ph, Ph, nullptr);
+    if (G.mixed) {
+        if (G.ks)
+            hipLaunchKernelGGL((k_ct_center<float, true>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd,
+                               G.d_wcell, c.s[0], c.s[1], c.s[2], (float *)P);
+        else
+            hipLaunchKernelGGL((k_ct_center<float, false>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd,
+                               G.d_wcell, c.s[0], c.s[1], c.s[2], (float *)P);
+    } else {
+        if (G.ks)
+            hipLaunchKernelGGL((k_ct_center<double, true>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd,
+                               G.d_wcell, c.s[0], c.s[1], c.s[2], (double *)P);
+        else
+            hipLaunchKernelGGL((k_ct_center<double, false>), dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd,
+                               G.d_wcell, c.s[0], c.s[1], c.s[2], (double *)P);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ct_div(const DeviceGrid &G, const double *Ph, double *div, hipStream_t s)
+{
+    const CtPtrs c = ct_split(G, Ph, Ph, nullptr);
+    hipLaunchKernelGGL(k_ct_div, dim3(G.plan.wcell.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wcell, c.s[0], c.s[1],
+                       c.s[2], div);
+    return hipGetLastError();
 }
 
 }  // namespace bhac

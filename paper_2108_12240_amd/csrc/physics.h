@@ -356,17 +356,22 @@ __device__ __forceinline__ void recon_face(const R *q, R &qL, R &qR)
 // largest |lambda| of both states. qL/qR are modified (normal field replaced).
 // ---------------------------------------------------------------------------------
 // One pass: both face states fully evaluated once, then combined (more live
-// registers than face_flux_lean, fewer instructions).
-template <typename R, int D, int FLUX>
+// registers than face_flux_lean, fewer instructions). CT: constrained transport, the
+// caller has set both states' normal field from the face field; no GLM solve, the
+// normal-field and psi fluxes vanish.
+template <typename R, int D, int FLUX, bool CT = false>
 __device__ __forceinline__ R face_flux(R *qL, R *qR, const FaceM<R> &m, R ch, R gam, R gfac, R *F)
 {
-    const R sg = m.sg;
-    const R btl = sg * qL[5 + D], btr = sg * qR[5 + D];
-    const R bstar = R(0.5) * (btl + btr) - fdiv(qR[8] - qL[8], R(2) * ch);
-    const R psistar = R(0.5) * (qL[8] + qR[8]) - R(0.5) * ch * (btr - btl);
-    const R bn = fdiv(bstar, sg);
-    qL[5 + D] = bn;
-    qR[5 + D] = bn;
+    R bstar = R(0), psistar = R(0);
+    if constexpr (!CT) {
+        const R sg = m.sg;
+        const R btl = sg * qL[5 + D], btr = sg * qR[5 + D];
+        bstar = R(0.5) * (btl + btr) - fdiv(qR[8] - qL[8], R(2) * ch);
+        psistar = R(0.5) * (qL[8] + qR[8]) - R(0.5) * ch * (btr - btl);
+        const R bn = fdiv(bstar, sg);
+        qL[5 + D] = bn;
+        qR[5 + D] = bn;
+    }
     R UL[NV], FL[NV], UR[NV], FR[NV], lmL, lpL, lmR, lpR;
     face_state<R, D, true, true>(qL, m, gam, gfac, UL, FL, lmL, lpL);
     face_state<R, D, true, true>(qR, m, gam, gfac, UR, FR, lmR, lpR);
@@ -405,7 +410,7 @@ __device__ __forceinline__ R face_flux(R *qL, R *qR, const FaceM<R> &m, R ch, R 
         for (int v = 0; v < 8; v++) F[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * c * (UR[v] - UL[v]);
     }
     F[5 + D] = psistar;
-    F[8] = ch * ch * bstar;
+    F[8] = CT ? R(0) : ch * ch * bstar;
     R lam = fabs(lmL);
     lam = fabs(lpL) > lam ? fabs(lpL) : lam;
     lam = fabs(lmR) > lam ? fabs(lmR) : lam;

@@ -150,6 +150,7 @@ bool check_params(const bhac_params &p, std::string &err)
     if (p.fused != 0 && p.fused != 1) return bad(err, "fused must be 0 or 1");
     if (p.amr != 0 && p.amr != 1) return bad(err, "amr must be 0 or 1");
     if (p.entropy != 0 && p.entropy != 1) return bad(err, "entropy must be 0 or 1");
+    if (p.ct != 0 && p.ct != 1) return bad(err, "ct must be 0 or 1");
     if (p.entropy && !(p.gamma_ad <= 2.0)) return bad(err, "the entropy backup needs gamma_ad <= 2");
     if (p.sched.set != 0 && p.sched.set != 1) return bad(err, "sched.set must be 0 or 1");
     if (p.sched.set) {
@@ -263,6 +264,11 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         auto it = lattice.find(k);
         return it == lattice.end() ? -1 : it->second;
     };
+    if (p.ct && (p.fused || p.amr || p.entropy)) {
+        err = "constrained transport needs the unfused substep (fused = 0) on independent patches (amr = 0) "
+              "without the entropy field";
+        return BHAC_EUNSUPPORTED;
+    }
     if (p.entropy && (p.fused || p.amr)) {
         err = "the entropy field needs the unfused substep (fused = 0) on independent patches (amr = 0)";
         return BHAC_EUNSUPPORTED;
@@ -345,11 +351,12 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     }
     P.march_mask = (p.sched.set ? p.sched.march_mask : p.precision == BHAC_PREC_MIXED ? MARCH_MASK_F32 : MARCH_MASK_F64) &
                    ((1 << p.ndim) - 1);
+    if (p.ct) P.march_mask = 0;           // constrained transport: one thread per face in every direction
     // staged x1 faces when every block's rows fit the LDS tile: a work-group's WG
     // consecutive faces touch at most ceil(WG / (s0 + 1)) + 1 rows of s0 + 6 cells
     {
         const int cap = p.precision == BHAC_PREC_MIXED ? x1s_max_cells<float>() : x1s_max_cells<double>();
-        bool ok = !(P.march_mask & 1) && (!p.sched.set || p.sched.x1_staged);
+        bool ok = !(P.march_mask & 1) && (!p.sched.set || p.sched.x1_staged) && !p.ct;
         for (int64_t b = 0; b < nb && ok; b++) {
             const int s0 = P.dblocks[b].s[0];
             const int rows = (WG + s0) / (s0 + 1) + 1;
@@ -362,7 +369,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     {
         const int cap = p.precision == BHAC_PREC_MIXED ? x1s_max_cells<float>() : x1s_max_cells<double>();
         const int want = p.sched.set ? p.sched.x1_staged : X1_IN_UPDATE_DEFAULT;
-        bool ok = want == 2 && !p.amr && !p.entropy && !p.fused && !(P.march_mask & 1);
+        bool ok = want == 2 && !p.amr && !p.entropy && !p.fused && !p.ct && !(P.march_mask & 1);
         for (int64_t b = 0; b < nb && ok; b++) {
             const int s0 = P.dblocks[b].s[0];
             ok = s0 >= 3 && x1u_rows(s0) >= 1 && x1u_rows(s0) * (s0 + 6) <= cap;

@@ -42,6 +42,10 @@ def wavy_prim(x, y, z):
     q[2] = -0.2 + 0.1 * np.sin(2 * np.pi * x)
     q[3] = 0.1
     q[4] = 1.0 + 0.1 * np.cos(2 * np.pi * (x + y))
+    # out-of-plane field: with ndim = 2 it is the cell-centred variable (a field that
+    # starts from zero would be measured against its own small size); with ndim = 3
+    # the face field replaces it
+    q[7] = 0.08 + 0.03 * np.cos(2 * np.pi * (x - y))
     return q
 
 
