@@ -88,3 +88,30 @@ def test_zero_weight_base_is_not_read(harness):
     r = _run(harness, x)
     assert r[0, 0] == float(Fr(2.0) + Fr(1e-2) * Fr(3.0))
     assert r[1, 0] == float(Fr(-1.0) + Fr(1e-3) * Fr(0.5))
+
+
+def _rk2(exe, u0, dt, rates):
+    inp = np.concatenate([[u0, dt], np.asarray(rates, dtype=np.float64).ravel()]).tobytes()
+    out = subprocess.run([exe, "rk2"], input=inp, capture_output=True, check=True).stdout
+    return np.frombuffer(out, dtype=np.float64)
+
+
+def test_many_steps_follow_the_once_rounded_recurrence(harness):
+    """Over 1500 SSP-RK2 steps the compensated state is exactly the recurrence that
+    rounds each stored stage value once (to nearest double) from the exact stage
+    combination; the plain expression departs from it. This is what the in-register
+    compensation buys: no rounding inside a substep. It carries nothing across
+    substeps, so the once-per-substep rounding itself still accumulates (a steady
+    rate rounds the same way every step)."""
+    rng = np.random.default_rng(2108)
+    for _ in range(4):
+        n = 1500
+        u0, dt = float(rng.uniform(0.5, 2.0)), float(rng.uniform(1e-4, 1e-2))
+        rates = rng.normal(0.0, 1.0, (n, 2)) * 10.0 ** float(rng.integers(-9, -3))
+        comp, plain = _rk2(harness, u0, dt, rates)
+        u, h = Fr(u0), Fr(dt)
+        for l1, l2 in rates:
+            u1 = Fr(float(u + h * Fr(l1)))
+            u = Fr(float(Fr(1, 2) * u + Fr(1, 2) * (u1 + h * Fr(l2))))
+        assert comp == float(u)
+        assert plain != float(u)
