@@ -103,32 +103,39 @@ WORKLOADS = {
 # on; with any other sources the field is reported as null.
 TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
-    ("ks_torus_128_fp64_plain", "update"): (1165887115, "bf50faf62767a30b"),
-    ("ks_torus_128_mixed_plain", "update"): (773995659, "bf50faf62767a30b"),
-    ("ks_torus_128_mixed_auto", "update"): (773995659, "bf50faf62767a30b"),
+    # profiles/update_ks_turb_384_hbm_traffic.md, update_ks_torus_192_mixed_128_fp64_hbm_traffic.md
+    ("ks_turb_384_mixed_plain", "update"): (20828320500, "ba3485b0bb0a6c6e"),
+    ("ks_turb_384_fp64_plain", "update"): (31409802815, "ba3485b0bb0a6c6e"),
+    ("ks_torus_192_mixed_plain", "update"): (2607502410, "ba3485b0bb0a6c6e"),
+    ("ks_torus_128_fp64_plain", "update"): (1165977893, "ba3485b0bb0a6c6e"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
-# launches of two RK2 steps) of the compute-bound kernels, with the digest of the
-# sources they were counted on. With the HIP-event duration of the same kernel
-# they give its VALU issue rate against the chip's 256 CUs x 4 SIMDs x 16 lanes x
-# 2.4 GHz = 39.3e12 lane-instructions/s (one wave64 instruction takes 4 cycles of
-# a 16-lane SIMD; FP64 and unpacked FP32 issue at the same rate).
+# launches of two RK2 steps), with the digest of the sources they were counted on.
+# With the HIP-event duration of the same kernel they give its VALU issue rate
+# against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s (one
+# wave64 instruction takes 4 cycles of a 16-lane SIMD; FP64 and unpacked FP32 issue
+# at the same rate). The counter includes transcendental instructions, which issue
+# on a unit of their own, so float kernels heavy in reciprocals and square roots can
+# read slightly above 1.
+# profiles/ks_turb_384_valu_counters.md, ks_torus_192_mixed_128_fp64_valu_counters.md
 VALU = {
-    ("ks_torus_128_fp64_x1u", "flux_x2"): (27163123, "bf50faf62767a30b"),
-    ("ks_torus_128_fp64_x1u", "flux_x3"): (24566791, "bf50faf62767a30b"),
-    ("ks_torus_128_fp64_x1u", "update_x1"): (94183020, "bf50faf62767a30b"),
-    ("ks_torus_128_mixed_x1u", "flux_x2"): (23059687, "bf50faf62767a30b"),
-    ("ks_torus_128_mixed_x1u", "flux_x3"): (20330794, "bf50faf62767a30b"),
-    ("ks_torus_128_mixed_x1u", "update_x1"): (85035948, "bf50faf62767a30b"),
-    ("ks_torus_128_fp64_plain", "flux_x1"): (49046930, "bf50faf62767a30b"),
-    ("ks_torus_128_fp64_plain", "flux_x2"): (27163084, "bf50faf62767a30b"),
-    ("ks_torus_128_fp64_plain", "flux_x3"): (24566778, "bf50faf62767a30b"),
-    ("ks_torus_128_fp64_plain", "update"): (43153478, "bf50faf62767a30b"),
-    ("ks_torus_128_mixed_plain", "flux_x1"): (38379255, "bf50faf62767a30b"),
-    ("ks_torus_128_mixed_plain", "flux_x2"): (23059859, "bf50faf62767a30b"),
-    ("ks_torus_128_mixed_plain", "flux_x3"): (20330799, "bf50faf62767a30b"),
-    ("ks_torus_128_mixed_plain", "update"): (44726327, "bf50faf62767a30b"),
+    ("ks_turb_384_mixed_plain", "flux_x1"): (1033853013, "ba3485b0bb0a6c6e"),
+    ("ks_turb_384_mixed_plain", "flux_x2"): (618230341, "ba3485b0bb0a6c6e"),
+    ("ks_turb_384_mixed_plain", "flux_x3"): (546281541, "ba3485b0bb0a6c6e"),
+    ("ks_turb_384_mixed_plain", "update"): (1255450967, "ba3485b0bb0a6c6e"),
+    ("ks_turb_384_fp64_plain", "flux_x1"): (1321782205, "ba3485b0bb0a6c6e"),
+    ("ks_turb_384_fp64_plain", "flux_x2"): (734164721, "ba3485b0bb0a6c6e"),
+    ("ks_turb_384_fp64_plain", "flux_x3"): (659868595, "ba3485b0bb0a6c6e"),
+    ("ks_turb_384_fp64_plain", "update"): (1212983642, "ba3485b0bb0a6c6e"),
+    ("ks_torus_192_mixed_plain", "flux_x1"): (129382650, "ba3485b0bb0a6c6e"),
+    ("ks_torus_192_mixed_plain", "flux_x2"): (77645665, "ba3485b0bb0a6c6e"),
+    ("ks_torus_192_mixed_plain", "flux_x3"): (68428713, "ba3485b0bb0a6c6e"),
+    ("ks_torus_192_mixed_plain", "update"): (158204750, "ba3485b0bb0a6c6e"),
+    ("ks_torus_128_fp64_plain", "flux_x1"): (49047017, "ba3485b0bb0a6c6e"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27163190, "ba3485b0bb0a6c6e"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24566756, "ba3485b0bb0a6c6e"),
+    ("ks_torus_128_fp64_plain", "update"): (45512725, "ba3485b0bb0a6c6e"),
 }
 VALU_PEAK = 39.3e12      # lane-instructions/s
 
