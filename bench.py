@@ -37,6 +37,9 @@ METRIC = "zone-updates/s per RK substep (FP64 vs mixed, 1 GPU) + % HBM roofline"
 # hydrodynamic primitives stored (stage 1 reads U and P and writes them; stage 2 also
 # reads U_base): 260 B with P in double, 220 B with P in float.
 STATE_BYTES = {8: 260.0, 4: 220.0}
+# Under constrained transport the state also holds the face field (three FP64 faces
+# per cell): read at the stage, read at the base in half the stages, written.
+CT_FACE_BYTES = 3 * 8 * 2.5
 
 # Algorithmic flops per zone-substep (additions, multiplications, divisions, square
 # roots, transcendental calls) of the method on each workload: the oracle's op
@@ -89,6 +92,10 @@ WORKLOADS = {
     "ks_torus_128_mixed_entropy": dict(cfg=2, n=128, precision=1, fused=0, entropy=1),
     "amr_tree_96_mixed_auto": dict(cfg="tree", n0=96, bs=16, levels=3, precision=1, fused="auto"),
     "amr_tree_96_fp64_auto": dict(cfg="tree", n0=96, bs=16, levels=3, precision=0, fused="auto"),
+    # the same grid under staggered constrained transport (face field from the torus's
+    # azimuthal potential), FP64 and mixed
+    "ks_torus_128_fp64_ct": dict(cfg=2, n=128, precision=0, fused=0, ct=1),
+    "ks_torus_128_mixed_ct": dict(cfg=2, n=128, precision=1, fused=0, ct=1),
     "ks_torus_128_fp64_x1u": dict(cfg=2, n=128, precision=0, fused=0,
                                   sched=dict(march_mask=6, march_faces=17, x1_staged=2)),
     "ks_torus_128_mixed_x1u": dict(cfg=2, n=128, precision=1, fused=0,
@@ -197,21 +204,30 @@ def grid_info(case, G):
     return dict(ghost_slots=int(dst.size), nface=nface, ncell=int(G.nci), nvar=int(G.nvar))
 
 
-def run_gpu(case, steps, warmup, repeats=1, graph=True, timing_steps=None):
+def run_gpu(case, steps, warmup, repeats=1, graph=True, timing_steps=None, phi=None):
     """One continuous CFL-stepped run: `warmup` untimed RK2 steps, then `repeats`
     timed segments of `steps` steps each (HIP events on the launch stream around each
     segment). With graph=True the timed loop replays the captured step graph; the
     per-kernel durations then come from an eager pass of `timing_steps` further steps
-    with HIP events around every launch (same kernels, same stream)."""
+    with HIP events around every launch (same kernels, same stream). phi: the face
+    field of a constrained-transport grid (host), carried through every step."""
     import torch
     from paper_2108_12240_amd import bhac as B
 
     G = B.Grid(case.params, case.blocks, device="cuda:0")
-    U, P = G.init(case.prim)
     U1, P1 = G.new_state("U"), G.new_state("P")
-    if graph:
-        G.capture_rk2_step(U, P, U1, P1)
-    step = G.launch_rk2_step if graph else (lambda: G.rk2_step(U, P, U1, P1))
+    if phi is None:
+        U, P = G.init(case.prim)
+        if graph:
+            G.capture_rk2_step(U, P, U1, P1)
+        eager = lambda: G.rk2_step(U, P, U1, P1)
+    else:
+        U, P, ph = G.init_ct(case.prim, phi)
+        ph1 = G.new_faces()
+        if graph:
+            G.capture_rk2_step_ct(U, P, U1, P1, ph, ph1)
+        eager = lambda: G.rk2_step_ct(U, P, ph, U1, P1, ph1)
+    step = G.launch_rk2_step if graph else eager
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -232,7 +248,7 @@ def run_gpu(case, steps, warmup, repeats=1, graph=True, timing_steps=None):
     if graph:
         B.bhac_set_timing(G.h, True)
         for _ in range(timing_steps or steps):
-            G.rk2_step(U, P, U1, P1)
+            eager()
         torch.cuda.synchronize()
     B.bhac_set_timing(G.h, False)
     ktimes = B.bhac_get_timing(G.h)
@@ -281,7 +297,11 @@ def autotune_summary(rep):
 UPDATE_FAMILIES = ("update", "update_x1", "update_div")
 
 
-def roofline(res, rsz, workload):
+def state_bytes(rsz, ct=False):
+    return STATE_BYTES[rsz] + (CT_FACE_BYTES if ct else 0.0)
+
+
+def roofline(res, rsz, workload, ct=False):
     """Roofline of the dominant kernel (largest share of the timed kernels).
 
     The per-cell update is the kernel that moves the method's state (U_stage, U_base,
@@ -297,7 +317,7 @@ def roofline(res, rsz, workload):
     launches, total_ms = kt[dom]
     avg_s = total_ms / launches / 1e3
     own = bytes_per_unit(dom, rsz, res["info"]["nvar"]) * units_per_launch(dom, res["info"])
-    alg = STATE_BYTES[rsz] * res["info"]["ncell"] if dom in UPDATE_FAMILIES else own
+    alg = state_bytes(rsz, ct) * res["info"]["ncell"] if dom in UPDATE_FAMILIES else own
     achieved = alg / avg_s / 1e9
     dig = source_digest()
     measured = TRAFFIC.get((workload, dom))
@@ -318,15 +338,16 @@ def roofline(res, rsz, workload):
     return out
 
 
-def substep_roofline(res, rsz, workload):
+def substep_roofline(res, rsz, workload, ct=False):
     """The whole substep against both ceilings: the state bytes at 8 TB/s and the
     method's algorithmic flops (oracle op counter) at the vector peak."""
     zones = res["info"]["ncell"]
     t = res["ms_per_step"] / 2 / 1e3
-    hbm = STATE_BYTES[rsz] * zones / t
-    out = dict(ms=round(t * 1e3, 4), state_bytes_per_zone=STATE_BYTES[rsz],
+    sb = state_bytes(rsz, ct)
+    hbm = sb * zones / t
+    out = dict(ms=round(t * 1e3, 4), state_bytes_per_zone=sb,
                hbm_achieved_GBs=round(hbm / 1e9, 1), hbm_frac=round(hbm / (HBM_PEAK_GBS * 1e9), 4),
-               hbm_floor_ms=round(STATE_BYTES[rsz] * zones / (HBM_PEAK_GBS * 1e9) * 1e3, 4))
+               hbm_floor_ms=round(sb * zones / (HBM_PEAK_GBS * 1e9) * 1e3, 4))
     ops = OPCOUNT.get(WORKLOAD_OPS.get(workload, ""))
     if ops:
         fl = ops["algorithmic"] * zones
@@ -420,7 +441,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="ks_turb_384_mixed_plain", choices=sorted(WORKLOADS))
     ap.add_argument("--compare", default="ks_turb_384_fp64_plain",
                     help="second path on the same grid reported beside the headline ('' to skip)")
-    ap.add_argument("--extra", default="ks_torus_128_fp64_plain,ks_torus_192_mixed_plain",
+    ap.add_argument("--extra", default="ks_torus_128_fp64_plain,ks_torus_192_mixed_plain,ks_torus_128_fp64_ct",
                     help="further workloads timed with --extra-steps per segment ('' to skip)")
     ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of each oracle sample")
@@ -460,17 +481,20 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     torch.cuda.set_device(0)
-    cases = {}
+    cases, faces = {}, {}
 
     def make(name):
         w = dict(WORKLOADS[name])
         kw = {k: w[k] for k in ("n", "n0", "bs", "levels") if k in w}
-        key = (str(w["cfg"]), str(kw), bool(w.get("entropy")))
+        key = (str(w["cfg"]), str(kw), bool(w.get("entropy")), bool(w.get("ct")))
         if key not in cases:
             log(f"inputs of {name}")
             c0 = I.make_case(w["cfg"], **kw)
+            if w.get("ct"):
+                c0, faces[key] = I.torus_with_face_field(c0)
             cases[key] = I.with_entropy(c0) if w.get("entropy") else c0
         c0 = cases[key]
+        w["phi"] = faces.get(key)
         c = I.Case(c0.name, dict(c0.params), c0.blocks, c0.prim, c0.ioff, c0.steps)
         if w["fused"] == "auto":
             from paper_2108_12240_amd import autotune
@@ -487,13 +511,13 @@ def main(argv=None):
         c, w = make(name)
         log(f"timing {name}: {args.warmup} warmup + {args.repeats} x {steps} RK2 steps")
         r = run_gpu(c, steps, args.warmup, repeats=args.repeats, graph=not args.eager,
-                    timing_steps=min(steps, 4))
+                    timing_steps=min(steps, 4), phi=w.get("phi"))
         rsz = 4 if w["precision"] == 1 else 8
         summary = dict(workload=name, value=round(r["value"], 1), value_best=round(r["value_best"], 1),
                        ms_per_step=round(r["ms_per_step"], 4), ms_per_step_best=round(r["ms_per_step_best"], 4),
                        segments_ms=r["segments_ms"], steps_per_segment=steps, dtype="f64" if rsz == 8 else "f32+f64",
-                       zones=r["info"]["ncell"], roofline=roofline(r, rsz, name),
-                       substep=substep_roofline(r, rsz, name),
+                       zones=r["info"]["ncell"], roofline=roofline(r, rsz, name, bool(w.get("ct"))),
+                       substep=substep_roofline(r, rsz, name, bool(w.get("ct"))),
                        kernel_ms={k: round(v[1] / max(v[0], 1), 4) for k, v in r["ktimes"].items()},
                        valu=valu_rates(r, name), c2p=r["stats"], finite=r["finite"], dt_last=r["dt"])
         if "autotune" in w:

@@ -120,9 +120,9 @@ enum { BHAC_PREC_FP64 = 0, BHAC_PREC_MIXED = 1 };
  *                       field by constrained transport on a staggered mesh): the field
  *                       is carried as face fluxes phi^d = sqrt(gamma) B^d and advanced
  *                       by bhac_substep_ct. Needs fused = 0, amr = 0 and entropy = 0
- *                       (else BHAC_EUNSUPPORTED); the face fluxes of every direction
- *                       come from the one-thread-per-face kernel (the schedule's other
- *                       fields are ignored).
+ *                       (else BHAC_EUNSUPPORTED). The face fluxes follow the schedule
+ *                       as in the GLM substep (the x1 faces are never computed inside
+ *                       the update under constrained transport).
  */
 
 /* Schedule of the unfused substep (fused = 0; the block-tiled path ignores it).
@@ -383,9 +383,18 @@ int bhac_get_schedule(bhac_grid *grid, bhac_schedule *out);
  * state lives on the device, so replays need no host work. Needs an initialised
  * time step (BHAC_EINVAL otherwise); P/P1 aliasing rules as for bhac_substep.
  * Launching before a capture returns BHAC_EINVAL; a grid with ct = 1 gives
- * BHAC_EUNSUPPORTED (the graph does not carry the face field). */
+ * BHAC_EUNSUPPORTED (use bhac_capture_rk2_step_ct). */
 int bhac_capture_rk2_step(bhac_grid *grid, double *U, void *P, double *U1, void *P1);
 int bhac_launch_rk2_step(bhac_grid *grid, void *stream);
+
+/* The same under constrained transport (params.ct = 1; otherwise BHAC_EINVAL): the
+ * graph of
+ *   substep_ct(U, U, P, phi, phi -> U1, P1, phi1, 0, 1)
+ *   -> substep_ct(U, U1, P1, phi, phi1 -> U, P, phi, 1/2, 1/2)
+ * for these exact buffers (phi, phi1: device double in the face layout, distinct
+ * from each other and from the state arrays, BHAC_EALIAS otherwise), replayed by
+ * bhac_launch_rk2_step. */
+int bhac_capture_rk2_step_ct(bhac_grid *grid, double *U, void *P, double *U1, void *P1, double *phi, double *phi1);
 
 /* Optional kernel timing (the measurement behind the roofline figures). While
  * enabled, every kernel the grid launches is bracketed by a pair of HIP events

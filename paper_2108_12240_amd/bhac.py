@@ -97,6 +97,7 @@ def lib():
             "bhac_get_schedule": [_VP, C.POINTER(bhac_schedule)],
             "bhac_set_timing": [_VP, C.c_int],
             "bhac_capture_rk2_step": [_VP, _VP, _VP, _VP, _VP],
+            "bhac_capture_rk2_step_ct": [_VP, _VP, _VP, _VP, _VP, _VP, _VP],
             "bhac_launch_rk2_step": [_VP, _VP],
             "bhac_get_timing": [_VP, C.POINTER(bhac_kernel_time), C.c_int, C.POINTER(C.c_int)],
             "bhac_plan_ghosts": [C.POINTER(bhac_params), C.POINTER(bhac_block_desc), C.c_int64,
@@ -280,6 +281,10 @@ def bhac_capture_rk2_step(h, U, P, U1, P1):
     _check(lib().bhac_capture_rk2_step(h, _ptr(U), _ptr(P), _ptr(U1), _ptr(P1)))
 
 
+def bhac_capture_rk2_step_ct(h, U, P, U1, P1, phi, phi1):
+    _check(lib().bhac_capture_rk2_step_ct(h, _ptr(U), _ptr(P), _ptr(U1), _ptr(P1), _ptr(phi), _ptr(phi1)))
+
+
 def bhac_launch_rk2_step(h, stream=None):
     _check(lib().bhac_launch_rk2_step(h, _stream(stream)))
 
@@ -427,6 +432,9 @@ class Grid:
 
     def capture_rk2_step(self, U, P, U1, P1):
         bhac_capture_rk2_step(self.h, U, P, U1, P1)
+
+    def capture_rk2_step_ct(self, U, P, U1, P1, phi, phi1):
+        bhac_capture_rk2_step_ct(self.h, U, P, U1, P1, phi, phi1)
 
     def launch_rk2_step(self):
         bhac_launch_rk2_step(self.h)

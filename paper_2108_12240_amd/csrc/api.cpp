@@ -544,13 +544,13 @@ int bhac_get_schedule(bhac_grid *g, bhac_schedule *out)
     return BHAC_OK;
 }
 
-int bhac_capture_rk2_step(bhac_grid *g, double *U, void *P, double *U1, void *P1)
+// Records the two substeps that `record` launches on a stream the grid owns into the
+// grid's step graph (replacing any previous one) and instantiates it.
+extern "C++" {
+template <typename Rec>
+static int capture_step(bhac_grid *g, Rec record, const char *what)
 {
-    if (int rc = check_grid(g)) return rc;
-    if (!U || !P || !U1 || !P1) return fail(BHAC_EINVAL, "null array");
-    if (P == P1 || (void *)U == (void *)U1) return fail(BHAC_EALIAS, "stage buffers must differ");
     if (!g->dg.have_dt) return fail(BHAC_EINVAL, "time step not initialised: call bhac_compute_dt or bhac_set_dt");
-    if (g->dg.plan.p.ct) return fail(BHAC_EUNSUPPORTED, "the captured RK2 step does not carry the face field (ct = 1)");
     hipError_t e;
     if (!g->cap_stream) {
         e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
@@ -558,7 +558,7 @@ int bhac_capture_rk2_step(bhac_grid *g, double *U, void *P, double *U1, void *P1
     }
     // work queued earlier on other streams must not race the capture's own launches
     e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(e, "bhac_capture_rk2_step");
+    if (e != hipSuccess) return hip_fail(e, what);
     release_graph(g);
     const bool timing = g->dg.timer.on;
     g->dg.timer.on = false;                 // no event records inside the graph
@@ -570,8 +570,7 @@ int bhac_capture_rk2_step(bhac_grid *g, double *U, void *P, double *U1, void *P1
     }
     // every substep reads its halo cells from the neighbouring blocks' interiors,
     // so the step needs no ghost fill
-    hipError_t le = bhac::launch_substep(g->dg, U, U, P, U1, P1, 0.0, 1.0, s);
-    if (le == hipSuccess) le = bhac::launch_substep(g->dg, U, U1, P1, U, P, 0.5, 0.5, s);
+    hipError_t le = record(s);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     g->dg.timer.on = timing;
@@ -587,6 +586,43 @@ int bhac_capture_rk2_step(bhac_grid *g, double *U, void *P, double *U1, void *P1
         return hip_fail(e, "hipGraphInstantiate");
     }
     return BHAC_OK;
+}
+}  // extern "C++"
+
+int bhac_capture_rk2_step(bhac_grid *g, double *U, void *P, double *U1, void *P1)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!U || !P || !U1 || !P1) return fail(BHAC_EINVAL, "null array");
+    if (P == P1 || (void *)U == (void *)U1) return fail(BHAC_EALIAS, "stage buffers must differ");
+    if (g->dg.plan.p.ct) return fail(BHAC_EUNSUPPORTED, "constrained transport: use bhac_capture_rk2_step_ct");
+    return capture_step(
+        g,
+        [&](hipStream_t s) {
+            hipError_t le = bhac::launch_substep(g->dg, U, U, P, U1, P1, 0.0, 1.0, s);
+            if (le == hipSuccess) le = bhac::launch_substep(g->dg, U, U1, P1, U, P, 0.5, 0.5, s);
+            return le;
+        },
+        "bhac_capture_rk2_step");
+}
+
+int bhac_capture_rk2_step_ct(bhac_grid *g, double *U, void *P, double *U1, void *P1, double *phi, double *phi1)
+{
+    if (int rc = check_grid(g)) return rc;
+    if (!g->dg.plan.p.ct) return fail(BHAC_EINVAL, "bhac_capture_rk2_step_ct needs a grid with ct = 1");
+    if (!U || !P || !U1 || !P1 || !phi || !phi1) return fail(BHAC_EINVAL, "null array");
+    if (P == P1 || (void *)U == (void *)U1 || phi == phi1) return fail(BHAC_EALIAS, "stage buffers must differ");
+    const void *st[] = {U, P, U1, P1};
+    for (const void *f : {(const void *)phi, (const void *)phi1})
+        for (const void *x : st)
+            if (x == f) return fail(BHAC_EALIAS, "a face field aliases a state array");
+    return capture_step(
+        g,
+        [&](hipStream_t s) {
+            hipError_t le = bhac::launch_substep_ct(g->dg, U, U, P, phi, phi, U1, P1, phi1, 0.0, 1.0, s);
+            if (le == hipSuccess) le = bhac::launch_substep_ct(g->dg, U, U1, P1, phi, phi1, U, P, phi, 0.5, 0.5, s);
+            return le;
+        },
+        "bhac_capture_rk2_step_ct");
 }
 
 int bhac_launch_rk2_step(bhac_grid *g, void *stream)

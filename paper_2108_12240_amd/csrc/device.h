@@ -130,7 +130,9 @@ hipError_t launch_set_dt(const DeviceGrid &G, double dt, hipStream_t s);
 hipError_t launch_reset_stats(const DeviceGrid &G, hipStream_t s);
 hipError_t launch_fused_body(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,
                              void *Po, double a, double b, hipStream_t s);
-hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStream_t s, void *const *flux);
+// phi: the face field of direction D under constrained transport (else nullptr)
+hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStream_t s, void *const *flux,
+                             const double *phi = nullptr);
 // flux: the three face-flux arrays of the unfused path (nvar rows x nface[d] faces in
 // the state's precision); nullptr = the grid's own (d_flux)
 hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,

@@ -279,11 +279,13 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux(KPara
 // Along x1 a face's stencil lies in one padded row, so without staging every
 // load instruction of a wave touches several rows and the neighbours' halo lines.
 // ---------------------------------------------------------------------------------
-template <typename R, int RECON, int FLUX, bool KS, bool XL, bool ENT>
+// CT: constrained transport, as in the face kernel (phi: the x1 face field).
+template <typename R, int RECON, int FLUX, bool KS, bool XL, bool ENT, bool CT = false>
 __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(KParams kp, GridDev gd,
                                                                             const WorkItem *__restrict__ work,
                                                                             const R *__restrict__ P,
-                                                                            R *__restrict__ F, long long nftot)
+                                                                            R *__restrict__ F, long long nftot,
+                                                                            const double *__restrict__ phi)
 {
     constexpr int NS = NV + (ENT ? 1 : 0);        // staged rows of P (the entropy function last)
     __shared__ R tile[NS][x1s_max_cells<R>()];
@@ -332,8 +334,13 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(K
             recon_face<R, RECON>(q, KL, KR);
         }
         const FaceM<R> m = face_metric<R, 0, KS>(gd, B, i, row % B.s[1]);
+        if constexpr (CT) {
+            const R bn = (R)phi[B.fofs[0] + item] / m.sg;
+            qL[5] = bn;
+            qR[5] = bn;
+        }
         R Ff[NV];
-        lam = (double)face_flux<R, 0, FLUX>(qL, qR, m, (R)gd.st->ch, (R)kp.gam, (R)kp.gfac, Ff);
+        lam = (double)face_flux<R, 0, FLUX, CT>(qL, qR, m, (R)gd.st->ch, (R)kp.gam, (R)kp.gfac, Ff);
         R *out = F + B.fofs[0] + item;
 #pragma unroll
         for (int v = 0; v < NV; v++) out[v * nftot] = Ff[v];
@@ -986,7 +993,7 @@ static hipError_t flux_dir(const DeviceGrid &G, const void *Ps, hipStream_t s, v
         auto kern = xl ? k_flux_x1s<R, RECON, FLUX, KS, true, false>
                        : (ent ? k_flux_x1s<R, RECON, FLUX, KS, false, true> : k_flux_x1s<R, RECON, FLUX, KS, false, false>);
         hipLaunchKernelGGL(kern, dim3(w.size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[0], (const R *)Ps,
-                           (R *)flux[0], G.plan.nface[0]);
+                           (R *)flux[0], G.plan.nface[0], (const double *)nullptr);
         return hipGetLastError();
     }
     auto kern = xl ? k_flux<R, D, RECON, FLUX, KS, true, false>
@@ -1152,10 +1159,19 @@ static CtPtrs ct_split(const DeviceGrid &G, const double *Phb, const double *Phs
     return c;
 }
 
+// face fluxes of direction D under constrained transport, by the form the plan gives
+// that direction (line march, LDS-staged x1 faces or one thread per face)
 template <typename R, int D, int RECON, int FLUX, bool KS>
 static hipError_t ct_flux_dir(const DeviceGrid &G, const void *Ps, const double *phs, hipStream_t s)
 {
+    void *const *flux = G.d_flux;
+    if (G.plan.march_mask >> D & 1) return launch_flux_march(G, D, Ps, s, flux, phs);
     TimedLaunch tl(G.timer, K_FLUX0 + D, s);
+    if (D == 0 && G.plan.x1_staged) {
+        hipLaunchKernelGGL((k_flux_x1s<R, RECON, FLUX, KS, false, false, true>), dim3(G.plan.wface[0].size()), dim3(WG),
+                           0, s, G.kp, G.gd, G.d_wface[0], (const R *)Ps, (R *)G.d_flux[0], G.plan.nface[0], phs);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_flux<R, D, RECON, FLUX, KS, false, false, true>), dim3(G.plan.wface[D].size()), dim3(WG), 0,
                        s, G.kp, G.gd, G.d_wface[D], (const R *)Ps, (R *)G.d_flux[D], G.plan.nface[D], phs);
     return hipGetLastError();
@@ -1176,9 +1192,21 @@ static hipError_t substep_ct_typed(const DeviceGrid &G, const double *Ub, const 
                                    const CtPtrs &c, double *Uo, void *Po, double a, double b, hipStream_t s)
 {
     const bool nd3 = G.kp.ndim == 3;
-    hipError_t e = ct_flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, c.s[0], s);
-    if (e == hipSuccess) e = ct_flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, c.s[1], s);
-    if (e == hipSuccess && nd3) e = ct_flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, c.s[2], s);
+    hipError_t e = hipSuccess;
+    if (nd3 && G.side[0] && G.side[1] && !G.timer.on) {
+        // x2 and x3 on the grid's side streams, concurrently with x1 (as in the GLM substep)
+        e = hipEventRecord(G.ev_fork, s);
+        for (int q = 0; q < 2 && e == hipSuccess; q++) e = hipStreamWaitEvent(G.side[q], G.ev_fork, 0);
+        if (e == hipSuccess) e = ct_flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, c.s[1], G.side[0]);
+        if (e == hipSuccess) e = ct_flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, c.s[2], G.side[1]);
+        if (e == hipSuccess) e = ct_flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, c.s[0], s);
+        for (int q = 0; q < 2 && e == hipSuccess; q++) e = hipEventRecord(G.ev_join[q], G.side[q]);
+        for (int q = 0; q < 2 && e == hipSuccess; q++) e = hipStreamWaitEvent(s, G.ev_join[q], 0);
+    } else {
+        e = ct_flux_dir<R, 0, RECON, FLUX, KS>(G, Ps, c.s[0], s);
+        if (e == hipSuccess) e = ct_flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, c.s[1], s);
+        if (e == hipSuccess && nd3) e = ct_flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, c.s[2], s);
+    }
     const CtFlux cf{{G.d_flux[0], G.d_flux[1], G.d_flux[2]}, {G.plan.nface[0], G.plan.nface[1], G.plan.nface[2]}};
     if (nd3) {
         if (e == hipSuccess) e = ct_face_dir<R, 0, true>(G, cf, c, a, b, s);

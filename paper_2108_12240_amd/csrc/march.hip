@@ -23,9 +23,13 @@ namespace bhac {
 // ENT (entropy field): the entropy function K (row NV of P) marches with the other
 // variables and is carried by each face's mass flux from the side that flux comes
 // from (row NV of F).
-template <typename R, int D, int RECON, int FLUX, bool KS, bool XL, bool ENT>
+// CT (constrained transport): the normal field of both states of a face is the face
+// field phi there (direction D's array, the layout of F) over sqrt(gamma), and there
+// is no GLM solve, as in the face kernel.
+template <typename R, int D, int RECON, int FLUX, bool KS, bool XL, bool ENT, bool CT = false>
 __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KParams kp, GridDev gd, const MarchItem *__restrict__ work,
-                                                    const R *__restrict__ P, R *__restrict__ F, long long nftot)
+                                                    const R *__restrict__ P, R *__restrict__ F, long long nftot,
+                                                    const double *__restrict__ phi)
 {
     __shared__ double red[MWG / 64];
     constexpr int NM = NV + (ENT ? 1 : 0);        // marched variables
@@ -95,8 +99,13 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
                 m = mnext;
                 if (f + 1 < w.f1) mnext = metric(f + 1);
             }
+            if constexpr (CT) {
+                const R bn = (R)phi[face0 + f * fA] / m.sg;
+                qL[5 + D] = bn;
+                qR[5 + D] = bn;
+            }
             R Ff[NV];
-            const R l = face_flux<R, D, FLUX>(qL, qR, m, ch, gam, gfac, Ff);
+            const R l = face_flux<R, D, FLUX, CT>(qL, qR, m, ch, gam, gfac, Ff);
             lmax = l > lmax ? l : lmax;
             R *out = F + face0 + f * fA;
 #pragma unroll
@@ -201,46 +210,53 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
 }
 
 template <typename R, int D, int RECON, int FLUX, bool KS>
-hipError_t launch_flux_march_typed(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux)
+hipError_t launch_flux_march_typed(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux,
+                                   const double *phi)
 {
     const std::vector<MarchItem> &w = G.plan.wmarch[D];
     TimedLaunch tl(G.timer, K_FLUX0 + D, s);
     auto kern = G.plan.p.amr ? k_flux_march<R, D, RECON, FLUX, KS, true, false>
                              : (G.kp.nvar > NV ? k_flux_march<R, D, RECON, FLUX, KS, false, true>
                                                : k_flux_march<R, D, RECON, FLUX, KS, false, false>);
+    if (phi) kern = k_flux_march<R, D, RECON, FLUX, KS, false, false, true>;
     hipLaunchKernelGGL(kern, dim3(w.size()), dim3(MWG), 0, s, G.kp, G.gd, G.d_wmarch[D], (const R *)Ps,
-                       (R *)flux[D], G.plan.nface[D]);
+                       (R *)flux[D], G.plan.nface[D], phi);
     return hipGetLastError();
 }
 
 template <typename R, int D>
-static hipError_t march_dir(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux)
+static hipError_t march_dir(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux, const double *phi)
 {
     const int r = G.kp.recon, f = G.kp.flux;
+#define MARCH_CASE(RC, FL, KSV) return launch_flux_march_typed<R, D, RC, FL, KSV>(G, Ps, s, flux, phi)
     if (G.ks) {
-        if (r == BHAC_RECON_PPM)
-            return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_HLL, true>(G, Ps, s, flux)
-                                      : launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_TVDLF, true>(G, Ps, s, flux);
-        return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_HLL, true>(G, Ps, s, flux)
-                                  : launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_TVDLF, true>(G, Ps, s, flux);
+        if (r == BHAC_RECON_PPM) {
+            if (f == BHAC_FLUX_HLL) MARCH_CASE(BHAC_RECON_PPM, BHAC_FLUX_HLL, true);
+            MARCH_CASE(BHAC_RECON_PPM, BHAC_FLUX_TVDLF, true);
+        }
+        if (f == BHAC_FLUX_HLL) MARCH_CASE(BHAC_RECON_MC, BHAC_FLUX_HLL, true);
+        MARCH_CASE(BHAC_RECON_MC, BHAC_FLUX_TVDLF, true);
     }
-    if (r == BHAC_RECON_PPM)
-        return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_HLL, false>(G, Ps, s, flux)
-                                  : launch_flux_march_typed<R, D, BHAC_RECON_PPM, BHAC_FLUX_TVDLF, false>(G, Ps, s, flux);
-    return f == BHAC_FLUX_HLL ? launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_HLL, false>(G, Ps, s, flux)
-                              : launch_flux_march_typed<R, D, BHAC_RECON_MC, BHAC_FLUX_TVDLF, false>(G, Ps, s, flux);
+    if (r == BHAC_RECON_PPM) {
+        if (f == BHAC_FLUX_HLL) MARCH_CASE(BHAC_RECON_PPM, BHAC_FLUX_HLL, false);
+        MARCH_CASE(BHAC_RECON_PPM, BHAC_FLUX_TVDLF, false);
+    }
+    if (f == BHAC_FLUX_HLL) MARCH_CASE(BHAC_RECON_MC, BHAC_FLUX_HLL, false);
+    MARCH_CASE(BHAC_RECON_MC, BHAC_FLUX_TVDLF, false);
+#undef MARCH_CASE
 }
 
-hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStream_t s, void *const *flux)
+hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStream_t s, void *const *flux,
+                             const double *phi)
 {
     if (G.mixed) {
-        if (D == 0) return march_dir<float, 0>(G, Ps, s, flux);
-        if (D == 1) return march_dir<float, 1>(G, Ps, s, flux);
-        return march_dir<float, 2>(G, Ps, s, flux);
+        if (D == 0) return march_dir<float, 0>(G, Ps, s, flux, phi);
+        if (D == 1) return march_dir<float, 1>(G, Ps, s, flux, phi);
+        return march_dir<float, 2>(G, Ps, s, flux, phi);
     }
-    if (D == 0) return march_dir<double, 0>(G, Ps, s, flux);
-    if (D == 1) return march_dir<double, 1>(G, Ps, s, flux);
-    return march_dir<double, 2>(G, Ps, s, flux);
+    if (D == 0) return march_dir<double, 0>(G, Ps, s, flux, phi);
+    if (D == 1) return march_dir<double, 1>(G, Ps, s, flux, phi);
+    return march_dir<double, 2>(G, Ps, s, flux, phi);
 }
 
 }  // namespace bhac

@@ -351,12 +351,11 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     }
     P.march_mask = (p.sched.set ? p.sched.march_mask : p.precision == BHAC_PREC_MIXED ? MARCH_MASK_F32 : MARCH_MASK_F64) &
                    ((1 << p.ndim) - 1);
-    if (p.ct) P.march_mask = 0;           // constrained transport: one thread per face in every direction
     // staged x1 faces when every block's rows fit the LDS tile: a work-group's WG
     // consecutive faces touch at most ceil(WG / (s0 + 1)) + 1 rows of s0 + 6 cells
     {
         const int cap = p.precision == BHAC_PREC_MIXED ? x1s_max_cells<float>() : x1s_max_cells<double>();
-        bool ok = !(P.march_mask & 1) && (!p.sched.set || p.sched.x1_staged) && !p.ct;
+        bool ok = !(P.march_mask & 1) && (!p.sched.set || p.sched.x1_staged);
         for (int64_t b = 0; b < nb && ok; b++) {
             const int s0 = P.dblocks[b].s[0];
             const int rows = (WG + s0) / (s0 + 1) + 1;

@@ -204,14 +204,17 @@ def _uniform_blocks(n, bs):
     return np.array(out, dtype=np.int32)
 
 
-def _finish_torus(prim, r):
+def _field_scale(prim, r):
     # field normalisation: max p / max(|B|^2/2) = 100 with the flat spatial metric
     bsq = (r * prim[B1]) ** 2 + (r * prim[B2]) ** 2
     bmax = float(bsq.max())
-    if bmax > 0.0:
-        scale = math.sqrt(float(prim[PRS].max()) / (100.0 * 0.5 * bmax))
-        prim[B1] *= scale
-        prim[B2] *= scale
+    return math.sqrt(float(prim[PRS].max()) / (100.0 * 0.5 * bmax)) if bmax > 0.0 else 1.0
+
+
+def _finish_torus(prim, r):
+    scale = _field_scale(prim, r)
+    prim[B1] *= scale
+    prim[B2] *= scale
     return prim
 
 
@@ -239,6 +242,27 @@ def case_torus(cfg: int, n=128, bs: int = 16, precision=None, fused=None, phi_sl
         _add_turbulence(params, prim, r, th, g, n, rng)
     steps = 100 if cfg == 5 else 10
     return Case(f"case{cfg}_ks_torus_{n[0]}x{n[1]}x{n[2]}", params, blocks, prim, ioff, steps)
+
+
+def torus_with_face_field(case: Case):
+    """A uniform-grid torus case (case_torus, case_torus_2d) for constrained
+    transport: params with ct = 1 and the face field phi^d = sqrt(gamma) B^d as the
+    discrete curl of the azimuthal potential A_phi = max(rho_t - 0.2, 0) that gives
+    the cell-centred field, with the same normalisation (so phi^1 = dA/dtheta and
+    phi^2 = -dA/dx1 on the faces, and the cell field follows from them)."""
+    params = dict(case.params, ct=1)
+    g = [np.concatenate(v) for v in zip(*(_block_cells(b) for b in case.blocks))]
+    raw, r, _ = _torus_cells(case.params, 0, g[0], g[1], g[2], np.full(g[0].size, 0.5))
+    raw[PRS] = case.prim[PRS]
+    scale = _field_scale(raw, r)
+
+    def potential(e, x1, x2, x3):
+        if e != 2:
+            return np.zeros_like(x1)
+        return scale * np.maximum(_torus_density(np.exp(x1), x2) - 0.2, 0.0)
+
+    phi = face_field_from_potential(params, case.blocks, potential)
+    return Case(case.name + "_ct", params, case.blocks, case.prim, case.ioff, case.steps), phi
 
 
 def case_torus_2d(n=(64, 64), bs: int = 16, precision=PREC_FP64, seed: int = 12250) -> Case:

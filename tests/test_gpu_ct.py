@@ -2,7 +2,9 @@
 oracle through the C ABI: the state U, P and the face field phi after 10 SSP-RK2
 steps with the CFL time step (FP64 within 1e-11, mixed within 1e-5 relative L1 per
 field and per field direction), the discrete divergence kept at round-off over 100
-steps, the two copies of every shared face identical, and the entry points' errors."""
+steps, the two copies of every shared face identical, every kernel schedule giving the
+same bits, the captured RK2 step equal to the eager steps, and the entry points'
+errors."""
 import math
 
 import numpy as np
@@ -151,6 +153,65 @@ def test_shared_face_copies_stay_identical(torch):
     assert np.array_equal(a[:, -1, :], c[:, 0, :])
 
 
+SCHEDULES = {"faces": dict(march_mask=0, march_faces=17, x1_staged=0),
+             "staged_x1": dict(march_mask=0, march_faces=17, x1_staged=1),
+             "lines": dict(march_mask=7, march_faces=9, x1_staged=0)}
+
+
+def run_ct(torch, params, blocks, prim, phi0, steps):
+    G = B.Grid(params, blocks)
+    U, P, phi = G.init_ct(prim, phi0)
+    U1, P1, phi1 = G.new_state("U"), G.new_state("P"), G.new_faces()
+    for _ in range(steps):
+        G.rk2_step_ct(U, P, phi, U1, P1, phi1)
+    torch.cuda.synchronize()
+    out = (U.cpu().numpy(), P.cpu().numpy(), phi.cpu().numpy(), G.schedule())
+    G.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
+@pytest.mark.parametrize("name,make", [("flat_3d_32", flat3d), ("ks_3d_48x32x32", ks3d)])
+def test_every_schedule_gives_identical_results(torch, name, make, prec):
+    """The face fluxes come from the line-march, staged-x1 or one-thread-per-face
+    kernels as the schedule says; all give the same bits (5 steps)."""
+    params, blocks, prim, phi0 = make()
+    params = dict(params, precision=prec, fused=0)
+    banner(f"schedules {name} prec={prec}")
+    ref = run_ct(torch, params, blocks, prim, phi0, 5)
+    assert ref[3]["march_mask"] == 6 and ref[3]["x1_staged"] == 1, ref[3]
+    for key, sc in SCHEDULES.items():
+        got = run_ct(torch, dict(params, sched=sc), blocks, prim, phi0, 5)
+        for a, b in zip(got[:3], ref[:3]):
+            assert np.array_equal(a, b), key
+
+
+@pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
+def test_captured_step_matches_eager_steps(torch, prec):
+    """The RK2 step captured as a HIP graph (bhac_capture_rk2_step_ct) replayed three
+    times, with eager work and synchronisations between the replays, equals the eager
+    steps of a second grid bit for bit after every replay."""
+    params, blocks, prim, phi0 = ks3d()
+    params = dict(params, precision=prec, fused=0)
+    banner(f"captured ct step prec={prec}")
+    Ge, Gg = B.Grid(params, blocks), B.Grid(params, blocks)
+    Ue, Pe, fe = Ge.init_ct(prim, phi0)
+    Ug, Pg, fg = Gg.init_ct(prim, phi0)
+    Ue1, Pe1, fe1 = Ge.new_state("U"), Ge.new_state("P"), Ge.new_faces()
+    Ug1, Pg1, fg1 = Gg.new_state("U"), Gg.new_state("P"), Gg.new_faces()
+    Gg.capture_rk2_step_ct(Ug, Pg, Ug1, Pg1, fg, fg1)
+    for rep in range(3):
+        Ge.rk2_step_ct(Ue, Pe, fe, Ue1, Pe1, fe1)
+        Gg.launch_rk2_step()
+        torch.cuda.synchronize()
+        scratch = torch.zeros_like(Ug1).sum().item()       # eager work between replays
+        assert scratch == 0.0
+        assert torch.equal(Ue, Ug) and torch.equal(Pe, Pg) and torch.equal(fe, fg), rep
+    assert Ge.timestep()["dt"] == Gg.timestep()["dt"]
+    Ge.close()
+    Gg.close()
+
+
 def test_entry_point_errors(torch):
     params, blocks, prim, phi0 = flat3d()
     params = dict(params, precision=I.PREC_FP64, fused=0)
@@ -164,6 +225,9 @@ def test_entry_point_errors(torch):
         G.capture_rk2_step(U, P, U1, P1)
     assert ei.value.code == B.BHAC_EUNSUPPORTED
     with pytest.raises(B.BhacError) as ei:
+        G.capture_rk2_step_ct(U, P, U1, P1, phi, phi)
+    assert ei.value.code == B.BHAC_EALIAS
+    with pytest.raises(B.BhacError) as ei:
         G.substep_ct(U, U, P, phi, phi, U1, P1, U1, 0.0, 1.0)
     assert ei.value.code == B.BHAC_EALIAS
     G.close()
@@ -176,4 +240,7 @@ def test_entry_point_errors(torch):
     with pytest.raises(B.BhacError) as ei:
         G2.substep_ct(U, U, P, U, U, G2.new_state("U"), G2.new_state("P"), G2.new_faces(), 0.0, 1.0)
     assert ei.value.code in (B.BHAC_EINVAL, B.BHAC_EALIAS)
+    with pytest.raises(B.BhacError) as ei:
+        G2.capture_rk2_step_ct(U, P, G2.new_state("U"), G2.new_state("P"), G2.new_faces(), G2.new_faces())
+    assert ei.value.code == B.BHAC_EINVAL
     G2.close()
