@@ -61,7 +61,8 @@ void release(bhac::DeviceGrid &G)
     release_timer(G);
     void *ptrs[] = {G.d_blocks, G.d_levels, G.d_ctab, G.d_f0tab, G.d_f1tab, G.d_ctab32, G.d_f0tab32, G.d_f1tab32,
                     G.d_state, G.d_wcell,
-                    G.d_wface[0], G.d_wface[1], G.d_wface[2], G.d_wupd1, G.d_wmarch[0], G.d_wmarch[1], G.d_wmarch[2],
+                    G.d_wface[0], G.d_wface[1], G.d_wface[2], G.d_wupd1, G.d_wedge[0], G.d_wedge[1],
+                    G.d_wedge[2], G.d_eofs, G.d_edge[0], G.d_edge[1], G.d_edge[2], G.d_wmarch[0], G.d_wmarch[1], G.d_wmarch[2],
                     G.d_gdst, G.d_gsrc, G.d_xoff, G.d_xdat, G.d_ffix, G.d_nbr, G.d_halo,
                     G.d_flux[0], G.d_flux[1], G.d_flux[2], G.d_div};
     for (void *p : ptrs)
@@ -246,6 +247,8 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
     UP(G.d_wcell, P.wcell);
     for (int d = 0; d < 3; d++) UP(G.d_wface[d], P.wface[d]);
     UP(G.d_wupd1, P.wupd1);
+    for (int K = 0; K < 3; K++) UP(G.d_wedge[K], P.wedge[K]);
+    UP(G.d_eofs, P.eofs);
     for (int d = 0; d < 3; d++) UP(G.d_wmarch[d], P.wmarch[d]);
     UP(G.d_gdst, P.gdst);
     UP(G.d_gsrc, P.gsrc);
@@ -266,6 +269,11 @@ int bhac_alloc_blocks(const bhac_params *params, const bhac_block_desc *blocks, 
             e = hipMalloc(&G.d_flux[d], (size_t)G.kp.nvar * P.nface[d] * rsz);
             if (e != hipSuccess) goto hip_error;
         }
+        for (int K = 0; K < 3; K++)
+            if (P.nedge[K] > 0) {
+                e = hipMalloc((void **)&G.d_edge[K], (size_t)P.nedge[K] * sizeof(double));
+                if (e != hipSuccess) goto hip_error;
+            }
         if (p.fused) {
             e = hipMalloc(&G.d_div, (size_t)bhac::NV * P.ncell_interior * sizeof(float));
             if (e != hipSuccess) goto hip_error;

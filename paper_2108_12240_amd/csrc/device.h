@@ -48,7 +48,7 @@ struct GridDev {
 
 // Kernel families timed by the optional HIP-event timer.
 enum KernelId { K_FILL, K_FLUX0, K_FLUX1, K_FLUX2, K_UPDATE, K_PRIM2CON, K_CON2PRIM, K_SPEEDS, K_BEGIN, K_END,
-                K_BLOCK_FLUX, K_UPDATE_DIV, K_FILL_XL, K_FLUX_FIX, K_UPDATE_X1, K_CT_FACE, K_COUNT };
+                K_BLOCK_FLUX, K_UPDATE_DIV, K_FILL_XL, K_FLUX_FIX, K_UPDATE_X1, K_CT_FACE, K_CT_EDGE, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Optional per-launch timing: a pre-created pool of HIP events recorded on the
@@ -101,6 +101,9 @@ struct DeviceGrid {
     DevState *d_state = nullptr;
     WorkItem *d_wcell = nullptr, *d_wface[3] = {nullptr, nullptr, nullptr}, *d_wupd1 = nullptr;
     MarchItem *d_wmarch[3] = {nullptr, nullptr, nullptr};
+    WorkItem *d_wedge[3] = {nullptr, nullptr, nullptr};
+    long long *d_eofs = nullptr;                     // constrained transport: edge offsets per block
+    double *d_edge[3] = {nullptr, nullptr, nullptr}; // constrained transport: edge fields per direction
     int32_t *d_gdst = nullptr, *d_gsrc = nullptr;
     int32_t *d_xoff = nullptr, *d_xdat = nullptr;    // cross-level recipes (block trees)
     long long nxl = 0, nxl_face = 0;

@@ -108,6 +108,11 @@ struct Plan {
     // work lists (one entry per work-group of WG items inside one block)
     std::vector<WorkItem> wcell, wface[3];
     std::vector<MarchItem> wmarch[3];
+    // constrained transport: edge fields along each direction K, per block
+    // (size_d + [d != K]) edges along d, x fastest; eofs[3 b + K] is block b's first edge
+    std::vector<long long> eofs;
+    std::vector<WorkItem> wedge[3];
+    long long nedge[3] = {0, 0, 0};
     int march_mask = 0;                  // bit D: direction D uses the line kernel
     bool x1_staged = false;              // x1 faces by the LDS-staged face kernel
     bool x1_in_update = false;           // x1 faces computed inside the update kernel

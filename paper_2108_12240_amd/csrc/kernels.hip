@@ -640,10 +640,40 @@ __device__ __forceinline__ double ct_emf(const GridDev &gd, const DevBlock &B, i
     return 0.25 * (fb - fa);
 }
 
+// Edge fields stored per direction K: block b's edges along K start at eofs[3 b + K],
+// (size_d + [d != K]) of them along each axis d, x fastest.
+struct CtEdge {
+    double *E[3];
+    const long long *eofs;
+};
+
+template <int K>
+__device__ __forceinline__ long long edge_index(const DevBlock &B, const CtEdge &ce, int b, int c0, int c1, int c2)
+{
+    const int e0 = B.s[0] + (K != 0), e1 = B.s[1] + (K != 1);
+    return ce.eofs[(long long)b * 3 + K] + ((long long)c2 * e1 + c1) * e0 + c0;
+}
+
+// every edge along K of a block, once: E_K from the four induction fluxes around it
+template <typename R, int K>
+__global__ __launch_bounds__(WG) void k_ct_edge(KParams kp, GridDev gd, const WorkItem *__restrict__ work, CtFlux cf,
+                                                CtEdge ce)
+{
+    const WorkItem w = work[blockIdx.x];
+    if (w.block < 0) return;
+    const DevBlock B = gd.blocks[w.block];
+    const int e0 = B.s[0] + (K != 0), e1 = B.s[1] + (K != 1), e2 = B.s[2] + (K != 2);
+    const int item = w.start + threadIdx.x;
+    if (item >= e0 * e1 * e2) return;
+    const int c0 = item % e0, t = item / e0, c1 = t % e1, c2 = t / e1;
+    ce.E[K][edge_index<K>(B, ce, w.block, c0, c1, c2)] = ct_emf<R, K>(gd, B, w.block, cf, c0, c1, c2);
+}
+
 // phi_out = a phi_base + b (phi_stage + dt L), L = -(d_j E_k - d_k E_j) on the faces of
-// direction D ((D, j, k) cyclic); with ndim = 2 only the edges along x3 exist
-template <typename R, int D, bool ND3, bool BASE>
-__global__ __launch_bounds__(WG) void k_ct_face(KParams kp, GridDev gd, const WorkItem *__restrict__ work, CtFlux cf,
+// direction D ((D, j, k) cyclic), from the block's stored edge fields; with ndim = 2
+// only the edges along x3 exist
+template <int D, bool ND3, bool BASE>
+__global__ __launch_bounds__(WG) void k_ct_face(KParams kp, GridDev gd, const WorkItem *__restrict__ work, CtEdge ce,
                                                 const double *Phb, const double *Phs, double *Pho, double a, double b)
 {
     constexpr int DJ = (D + 1) % 3, DK = (D + 2) % 3;
@@ -659,14 +689,16 @@ __global__ __launch_bounds__(WG) void k_ct_face(KParams kp, GridDev gd, const Wo
     if constexpr (DJ < 2 || ND3) {
         int h[3] = {i, j, k};
         h[DJ] += 1;
-        Lv -= (ct_emf<R, DK>(gd, B, w.block, cf, h[0], h[1], h[2]) - ct_emf<R, DK>(gd, B, w.block, cf, i, j, k)) *
-              L.inv_dx[DJ];
+        const double eh = ce.E[DK][edge_index<DK>(B, ce, w.block, h[0], h[1], h[2])];
+        const double el = ce.E[DK][edge_index<DK>(B, ce, w.block, i, j, k)];
+        Lv -= (eh - el) * L.inv_dx[DJ];
     }
     if constexpr (DK < 2 || ND3) {
         int h[3] = {i, j, k};
         h[DK] += 1;
-        Lv += (ct_emf<R, DJ>(gd, B, w.block, cf, h[0], h[1], h[2]) - ct_emf<R, DJ>(gd, B, w.block, cf, i, j, k)) *
-              L.inv_dx[DK];
+        const double eh = ce.E[DJ][edge_index<DJ>(B, ce, w.block, h[0], h[1], h[2])];
+        const double el = ce.E[DJ][edge_index<DJ>(B, ce, w.block, i, j, k)];
+        Lv += (eh - el) * L.inv_dx[DK];
     }
     const long long q = B.fofs[D] + item;
     Pho[q] = rk_combine<BASE>(a, BASE ? Phb[q] : 0.0, b, Phs[q], gd.st->dt, Lv);
@@ -856,7 +888,7 @@ inline unsigned nblk(long long n) { return (unsigned)((n + WG - 1) / WG); }
 const char *const kKernelNames[K_COUNT] = {"fill_ghosts", "flux_x1", "flux_x2", "flux_x3", "update",
                                            "prim2con", "con2prim", "cell_speeds", "step_begin", "step_end",
                                            "block_flux", "update_div", "fill_cross_level", "flux_fix",
-                                           "update_x1", "ct_faces"};
+                                           "update_x1", "ct_faces", "ct_edges"};
 
 hipError_t launch_fill(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only)
 {
@@ -1177,12 +1209,21 @@ static hipError_t ct_flux_dir(const DeviceGrid &G, const void *Ps, const double 
     return hipGetLastError();
 }
 
-template <typename R, int D, bool ND3>
-static hipError_t ct_face_dir(const DeviceGrid &G, const CtFlux &cf, const CtPtrs &c, double a, double b, hipStream_t s)
+template <typename R, int K>
+static hipError_t ct_edge_dir(const DeviceGrid &G, const CtFlux &cf, const CtEdge &ce, hipStream_t s)
+{
+    TimedLaunch tl(G.timer, K_CT_EDGE, s);
+    hipLaunchKernelGGL((k_ct_edge<R, K>), dim3(G.plan.wedge[K].size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wedge[K], cf,
+                       ce);
+    return hipGetLastError();
+}
+
+template <int D, bool ND3>
+static hipError_t ct_face_dir(const DeviceGrid &G, const CtEdge &ce, const CtPtrs &c, double a, double b, hipStream_t s)
 {
     TimedLaunch tl(G.timer, K_CT_FACE, s);
-    auto kern = a != 0.0 ? k_ct_face<R, D, ND3, true> : k_ct_face<R, D, ND3, false>;
-    hipLaunchKernelGGL(kern, dim3(G.plan.wface[D].size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D], cf, c.b[D],
+    auto kern = a != 0.0 ? k_ct_face<D, ND3, true> : k_ct_face<D, ND3, false>;
+    hipLaunchKernelGGL(kern, dim3(G.plan.wface[D].size()), dim3(WG), 0, s, G.kp, G.gd, G.d_wface[D], ce, c.b[D],
                        c.s[D], c.o[D], a, b);
     return hipGetLastError();
 }
@@ -1207,14 +1248,21 @@ static hipError_t substep_ct_typed(const DeviceGrid &G, const double *Ub, const 
         if (e == hipSuccess) e = ct_flux_dir<R, 1, RECON, FLUX, KS>(G, Ps, c.s[1], s);
         if (e == hipSuccess && nd3) e = ct_flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, c.s[2], s);
     }
+    // edge fields once per edge, then every face's Stokes update from its four edges
     const CtFlux cf{{G.d_flux[0], G.d_flux[1], G.d_flux[2]}, {G.plan.nface[0], G.plan.nface[1], G.plan.nface[2]}};
+    const CtEdge ce{{G.d_edge[0], G.d_edge[1], G.d_edge[2]}, G.d_eofs};
     if (nd3) {
-        if (e == hipSuccess) e = ct_face_dir<R, 0, true>(G, cf, c, a, b, s);
-        if (e == hipSuccess) e = ct_face_dir<R, 1, true>(G, cf, c, a, b, s);
-        if (e == hipSuccess) e = ct_face_dir<R, 2, true>(G, cf, c, a, b, s);
+        if (e == hipSuccess) e = ct_edge_dir<R, 0>(G, cf, ce, s);
+        if (e == hipSuccess) e = ct_edge_dir<R, 1>(G, cf, ce, s);
+    }
+    if (e == hipSuccess) e = ct_edge_dir<R, 2>(G, cf, ce, s);
+    if (nd3) {
+        if (e == hipSuccess) e = ct_face_dir<0, true>(G, ce, c, a, b, s);
+        if (e == hipSuccess) e = ct_face_dir<1, true>(G, ce, c, a, b, s);
+        if (e == hipSuccess) e = ct_face_dir<2, true>(G, ce, c, a, b, s);
     } else {
-        if (e == hipSuccess) e = ct_face_dir<R, 0, false>(G, cf, c, a, b, s);
-        if (e == hipSuccess) e = ct_face_dir<R, 1, false>(G, cf, c, a, b, s);
+        if (e == hipSuccess) e = ct_face_dir<0, false>(G, ce, c, a, b, s);
+        if (e == hipSuccess) e = ct_face_dir<1, false>(G, ce, c, a, b, s);
     }
     if (e != hipSuccess) return e;
     TimedLaunch tl(G.timer, K_UPDATE, s);

@@ -385,6 +385,22 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         }
     }
 
+    // constrained transport: edges along K (every direction in 3-D, x3 only in 2-D)
+    P.eofs.assign(p.ct ? (size_t)nb * 3 : 0, 0);
+    for (int K = 0; K < 3; K++) {
+        P.wedge[K].clear();
+        P.nedge[K] = 0;
+    }
+    if (p.ct)
+        for (int64_t b = 0; b < nb; b++)
+            for (int K = p.ndim == 3 ? 0 : 2; K < 3; K++) {
+                const DevBlock &D = P.dblocks[b];
+                const long long ne = (long long)(D.s[0] + (K != 0)) * (D.s[1] + (K != 1)) * (D.s[2] + (K != 2));
+                P.eofs[(size_t)b * 3 + K] = P.nedge[K];
+                P.nedge[K] += ne;
+                for (long long st = 0; st < ne; st += WG) P.wedge[K].push_back({(int)b, (int)st});
+            }
+
     // XCD-aware order: work-group p runs on XCD p % NXCD, so item q is placed at
     // p = (q % per) * NXCD + q / per. Each XCD then walks a contiguous range of items
     // (neighbouring planes and blocks share its L2). Padding entries have block -1.
@@ -396,6 +412,7 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     };
     xcd_order(P.wcell, WorkItem{-1, 0});
     xcd_order(P.wupd1, WorkItem{-1, 0});
+    for (int K = 0; K < 3; K++) xcd_order(P.wedge[K], WorkItem{-1, 0});
     for (int d = 0; d < p.ndim; d++) {
         xcd_order(P.wface[d], WorkItem{-1, 0});
         xcd_order(P.wmarch[d], MarchItem{-1, 0, 0, 0});
