@@ -140,7 +140,11 @@ enum { BHAC_PREC_FP64 = 0, BHAC_PREC_MIXED = 1 };
  *               with their halo in LDS where every block's rows fit; 2: the update
  *               kernel stages the rows and computes the x1 faces itself, so no x1
  *               flux array is written or read (independent patches without the
- *               entropy field, rows fitting the LDS tile; otherwise as 1).
+ *               entropy field, rows fitting the LDS tile, no constrained transport;
+ *               otherwise as 1).
+ * Defaults (set = 0): x2 and x3 marched (march_mask 6), segments of 33 faces in mixed
+ * precision and 17 in FP64, x1 faces staged in LDS (1) in mixed precision and inside
+ * the update (2) in FP64.
  * Out-of-range values give BHAC_EINVAL. */
 typedef struct bhac_schedule {
     int set;

@@ -67,10 +67,12 @@ constexpr int x1s_max_cells() { return sizeof(R) == 4 ? 600 : 400; }
 constexpr int x1u_rows(int s0) { return WG / (s0 + 1); }
 constexpr int MARCH_MASK_F32 = 6;
 constexpr int MARCH_MASK_F64 = 6;
-// the x1 faces are computed inside the update kernel (sched.x1_staged = 2) only when
-// a schedule asks for it: it pays at 128^3 in FP64 (-4 % per step) but costs 8 % on
-// the 384^3 grid in mixed precision, so it is left to the autotuner
-constexpr int X1_IN_UPDATE_DEFAULT = 0;
+// the x1 faces are computed inside the update kernel (sched.x1_staged = 2) by default
+// in FP64, where the exhaustive search finds it fastest on the torus grids (-4 % per
+// step at 128^3, -3 % at 384^3); in mixed precision it costs 8 % at 384^3, so there
+// the staged face kernel is the default
+constexpr int X1_IN_UPDATE_DEFAULT_F64 = 2;
+constexpr int X1_IN_UPDATE_DEFAULT_F32 = 0;
 // default longest march segment, per precision (exhaustive search: 33 is never
 // slower in float and 5 % faster on the block tree; 17 is 1 % faster there in FP64)
 constexpr int MARCH_FACES_F32 = 33;

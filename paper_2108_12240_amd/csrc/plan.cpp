@@ -367,7 +367,8 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
     // x1 not marched, every block's rows fit the LDS tile
     {
         const int cap = p.precision == BHAC_PREC_MIXED ? x1s_max_cells<float>() : x1s_max_cells<double>();
-        const int want = p.sched.set ? p.sched.x1_staged : X1_IN_UPDATE_DEFAULT;
+        const int want = p.sched.set ? p.sched.x1_staged
+                                     : (p.precision == BHAC_PREC_MIXED ? X1_IN_UPDATE_DEFAULT_F32 : X1_IN_UPDATE_DEFAULT_F64);
         bool ok = want == 2 && !p.amr && !p.entropy && !p.fused && !p.ct && !(P.march_mask & 1);
         for (int64_t b = 0; b < nb && ok; b++) {
             const int s0 = P.dblocks[b].s[0];
