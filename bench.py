@@ -110,11 +110,14 @@ WORKLOADS = {
 # on; with any other sources the field is reported as null.
 TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
-    # profiles/update_ks_turb_384_hbm_traffic.md, update_ks_torus_192_mixed_128_fp64_hbm_traffic.md
-    ("ks_turb_384_mixed_plain", "update"): (20828320500, "ba3485b0bb0a6c6e"),
-    ("ks_turb_384_fp64_plain", "update"): (31409802815, "ba3485b0bb0a6c6e"),
-    ("ks_torus_192_mixed_plain", "update"): (2607502410, "ba3485b0bb0a6c6e"),
-    ("ks_torus_128_fp64_plain", "update"): (1165977893, "ba3485b0bb0a6c6e"),
+    # profiles/update_ks_turb_384_hbm_traffic.md, update_ks_torus_192_mixed_128_fp64_hbm_traffic.md,
+    # update_ks_torus_128_ct_hbm_traffic.md
+    ("ks_turb_384_mixed_plain", "update"): (20828285209, "ea33815275bb2c6c"),
+    ("ks_turb_384_fp64_plain", "update_x1"): (36357667395, "ea33815275bb2c6c"),
+    ("ks_torus_192_mixed_plain", "update"): (2607506257, "ea33815275bb2c6c"),
+    ("ks_torus_128_fp64_plain", "update_x1"): (1325984199, "ea33815275bb2c6c"),
+    ("ks_torus_128_mixed_ct", "update"): (671363052, "ea33815275bb2c6c"),
+    ("ks_torus_128_fp64_ct", "update"): (983088782, "ea33815275bb2c6c"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
@@ -125,24 +128,33 @@ TRAFFIC = {
 # at the same rate). The counter includes transcendental instructions, which issue
 # on a unit of their own, so float kernels heavy in reciprocals and square roots can
 # read slightly above 1.
-# profiles/ks_turb_384_valu_counters.md, ks_torus_192_mixed_128_fp64_valu_counters.md
 VALU = {
-    ("ks_turb_384_mixed_plain", "flux_x1"): (1033853013, "ba3485b0bb0a6c6e"),
-    ("ks_turb_384_mixed_plain", "flux_x2"): (618230341, "ba3485b0bb0a6c6e"),
-    ("ks_turb_384_mixed_plain", "flux_x3"): (546281541, "ba3485b0bb0a6c6e"),
-    ("ks_turb_384_mixed_plain", "update"): (1255450967, "ba3485b0bb0a6c6e"),
-    ("ks_turb_384_fp64_plain", "flux_x1"): (1321782205, "ba3485b0bb0a6c6e"),
-    ("ks_turb_384_fp64_plain", "flux_x2"): (734164721, "ba3485b0bb0a6c6e"),
-    ("ks_turb_384_fp64_plain", "flux_x3"): (659868595, "ba3485b0bb0a6c6e"),
-    ("ks_turb_384_fp64_plain", "update"): (1212983642, "ba3485b0bb0a6c6e"),
-    ("ks_torus_192_mixed_plain", "flux_x1"): (129382650, "ba3485b0bb0a6c6e"),
-    ("ks_torus_192_mixed_plain", "flux_x2"): (77645665, "ba3485b0bb0a6c6e"),
-    ("ks_torus_192_mixed_plain", "flux_x3"): (68428713, "ba3485b0bb0a6c6e"),
-    ("ks_torus_192_mixed_plain", "update"): (158204750, "ba3485b0bb0a6c6e"),
-    ("ks_torus_128_fp64_plain", "flux_x1"): (49047017, "ba3485b0bb0a6c6e"),
-    ("ks_torus_128_fp64_plain", "flux_x2"): (27163190, "ba3485b0bb0a6c6e"),
-    ("ks_torus_128_fp64_plain", "flux_x3"): (24566756, "ba3485b0bb0a6c6e"),
-    ("ks_torus_128_fp64_plain", "update"): (45512725, "ba3485b0bb0a6c6e"),
+    # profiles/ks_turb_384_valu_counters.md, ks_torus_192_mixed_128_fp64_valu_counters.md,
+    # ks_torus_128_ct_valu_counters.md
+    ("ks_turb_384_mixed_plain", "flux_x1"): (1033853143, "ea33815275bb2c6c"),
+    ("ks_turb_384_mixed_plain", "flux_x2"): (618230357, "ea33815275bb2c6c"),
+    ("ks_turb_384_mixed_plain", "flux_x3"): (546281603, "ea33815275bb2c6c"),
+    ("ks_turb_384_mixed_plain", "update"): (1255450950, "ea33815275bb2c6c"),
+    ("ks_turb_384_fp64_plain", "flux_x2"): (734164749, "ea33815275bb2c6c"),
+    ("ks_turb_384_fp64_plain", "flux_x3"): (659868586, "ea33815275bb2c6c"),
+    ("ks_turb_384_fp64_plain", "update_x1"): (2591882998, "ea33815275bb2c6c"),
+    ("ks_torus_192_mixed_plain", "flux_x1"): (129382381, "ea33815275bb2c6c"),
+    ("ks_torus_192_mixed_plain", "flux_x2"): (77645635, "ea33815275bb2c6c"),
+    ("ks_torus_192_mixed_plain", "flux_x3"): (68428752, "ea33815275bb2c6c"),
+    ("ks_torus_192_mixed_plain", "update"): (158204650, "ea33815275bb2c6c"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27163230, "ea33815275bb2c6c"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24566753, "ea33815275bb2c6c"),
+    ("ks_torus_128_fp64_plain", "update_x1"): (96708918, "ea33815275bb2c6c"),
+    ("ks_torus_128_fp64_ct", "flux_x1"): (43390281, "ea33815275bb2c6c"),
+    ("ks_torus_128_fp64_ct", "flux_x2"): (26786612, "ea33815275bb2c6c"),
+    ("ks_torus_128_fp64_ct", "flux_x3"): (24352524, "ea33815275bb2c6c"),
+    ("ks_torus_128_fp64_ct", "update"): (39467067, "ea33815275bb2c6c"),
+    ("ks_torus_128_fp64_ct", "ct_edges"): (6303829, "ea33815275bb2c6c"),
+    ("ks_torus_128_mixed_ct", "flux_x1"): (34745233, "ea33815275bb2c6c"),
+    ("ks_torus_128_mixed_ct", "flux_x2"): (21133398, "ea33815275bb2c6c"),
+    ("ks_torus_128_mixed_ct", "flux_x3"): (18436869, "ea33815275bb2c6c"),
+    ("ks_torus_128_mixed_ct", "update"): (40745000, "ea33815275bb2c6c"),
+    ("ks_torus_128_mixed_ct", "ct_edges"): (6453333, "ea33815275bb2c6c"),
 }
 VALU_PEAK = 39.3e12      # lane-instructions/s
 
