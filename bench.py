@@ -444,6 +444,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, repeats: int = 10) -> float:
+    """Read-plus-write GB/s of a plain device-to-device copy of nbytes (the
+    achievable streaming ceiling of this GPU, measured beside the HBM peak)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(repeats):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * repeats / (a.elapsed_time(b) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -466,21 +488,8 @@ def main(argv=None):
     if args.copy_probe:
         import torch
         torch.cuda.set_device(0)
-        n = 1 << 28
-        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(10):
-            dst.copy_(src)
-        b.record()
-        torch.cuda.synchronize()
-        gbs = 2 * n * 4 * 10 / (a.elapsed_time(b) / 1e3) / 1e9
-        print(json.dumps(dict(copy_probe_bytes=n * 4, repeats=13, read_plus_write_GBps=round(gbs, 1))), flush=True)
+        print(json.dumps(dict(copy_probe_bytes=1 << 30, repeats=13, read_plus_write_GBps=round(copy_bandwidth(), 1))),
+              flush=True)
         return 0
 
     if args.gpus != 1:
@@ -537,6 +546,11 @@ def main(argv=None):
         return c, w, r, summary
 
     case, w, res, head = measure(args.workload, args.steps)
+    copy_gbs = copy_bandwidth()
+    head["roofline"]["copy_ceiling_GBs"] = round(copy_gbs, 1)
+    if head["roofline"]["unit"] == "GB/s":
+        head["roofline"]["frac_of_copy"] = round(head["roofline"]["achieved"] / copy_gbs, 4)
+    head["substep"]["frac_of_copy"] = round(head["substep"]["hbm_achieved_GBs"] / copy_gbs, 4)
     rsz = 4 if w["precision"] == 1 else 8
     out = dict(metric=METRIC, value=head["value"], unit="zone-updates/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=head["ms_per_step"], higher_is_better=True,
