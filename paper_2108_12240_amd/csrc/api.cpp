@@ -497,7 +497,9 @@ int bhac_set_dt(bhac_grid *g, double dt, void *stream)
 
 static int read_state(bhac_grid *g, bhac::DevState &st)
 {
-    hipError_t e = hipStreamSynchronize(g->last_stream);
+    hipError_t e = bhac::launch_finish_step(g->dg, g->last_stream);
+    if (e != hipSuccess) return hip_fail(e, "finish step");
+    e = hipStreamSynchronize(g->last_stream);
     if (e != hipSuccess) return hip_fail(e, "stream synchronise");
     e = hipMemcpy(&st, g->dg.d_state, sizeof st, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "state copy");

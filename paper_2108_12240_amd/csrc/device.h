@@ -29,7 +29,7 @@ struct DevState {
     unsigned long long lam_acc[3];   // bit patterns of non-negative doubles (atomicMax)
     unsigned long long c2p_fail, floor_hits;
     int max_iter;
-    int pad;
+    int lam_pending;                 // lam_acc holds a finished substep's maxima not yet turned into dt_next
     unsigned long long c2p_backup;   // cells inverted by the entropy backup
 };
 
@@ -128,6 +128,8 @@ hipError_t launch_fill_cross(const DeviceGrid &G, void *P, hipStream_t s, bool f
 hipError_t launch_fill_copies(const DeviceGrid &G, void *P, hipStream_t s, bool faces_only);
 hipError_t launch_prim2con(const DeviceGrid &G, const void *P, double *U, hipStream_t s);
 hipError_t launch_con2prim(const DeviceGrid &G, const double *U, void *P, int8_t *fail, hipStream_t s);
+// turns pending wave-speed maxima into dt_next (before a host read of the state)
+hipError_t launch_finish_step(const DeviceGrid &G, hipStream_t s);
 hipError_t launch_compute_dt(const DeviceGrid &G, const void *P, hipStream_t s);
 hipError_t launch_set_dt(const DeviceGrid &G, double dt, hipStream_t s);
 hipError_t launch_reset_stats(const DeviceGrid &G, hipStream_t s);

@@ -312,11 +312,16 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(K
 #pragma unroll
         for (int v = 0; v < NS; v++) tile[v][t] = P[v * kp.ncp + c];
     }
-    __syncthreads();
+    // the face's metric record is requested before the barrier, so its latency
+    // overlaps the staging
     const int item = w.start + threadIdx.x;
+    const int iface = item % fs0, rface = item / fs0;
+    FaceM<R> m;
+    if (item < nface) m = face_metric<R, 0, KS>(gd, B, iface, rface % B.s[1]);
+    __syncthreads();
     double lam = 0.0;
     if (item < nface) {
-        const int i = item % fs0, row = item / fs0;
+        const int i = iface, row = rface;
         const int t0 = (row - r0) * rowlen + i;   // tile slot of cell i - 3
         R qL[NV], qR[NV];
 #pragma unroll
@@ -333,7 +338,6 @@ __global__ __launch_bounds__(WG, (flux_occupancy<R, RECON>())) void k_flux_x1s(K
             for (int s = 0; s < 6; s++) q[s] = tile[NV][t0 + s];
             recon_face<R, RECON>(q, KL, KR);
         }
-        const FaceM<R> m = face_metric<R, 0, KS>(gd, B, i, row % B.s[1]);
         if constexpr (CT) {
             const R bn = (R)phi[B.fofs[0] + item] / m.sg;
             qL[5] = bn;
@@ -490,11 +494,15 @@ __global__ __launch_bounds__(WG, 3) void k_update_x1(KParams kp, GridDev gd, con
 #pragma unroll
         for (int v = 0; v < NV; v++) tile[v][t] = Ps[v * kp.ncp + c];
     }
+    // the face's metric record is requested before the barrier (its latency
+    // overlaps the staging)
+    const int frow = threadIdx.x / fs0, fi = threadIdx.x % fs0;
+    FaceM<R> mf;
+    if (threadIdx.x < nr * fs0) mf = face_metric<R, 0, KS>(gd, B, fi, (r0 + frow) % B.s[1]);
     __syncthreads();
     // x1 face t of the item (faces 0 .. s0 of each row, row-major)
     double lam = 0.0;
     if (threadIdx.x < nr * fs0) {
-        const int frow = threadIdx.x / fs0, fi = threadIdx.x % fs0;
         const int t0 = frow * rowlen + fi;        // tile slot of cell fi - 3
         R qL[NV], qR[NV];
 #pragma unroll
@@ -504,9 +512,8 @@ __global__ __launch_bounds__(WG, 3) void k_update_x1(KParams kp, GridDev gd, con
             for (int s = 0; s < 6; s++) q[s] = tile[v][t0 + s];
             recon_face<R, RECON>(q, qL[v], qR[v]);
         }
-        const FaceM<R> m = face_metric<R, 0, KS>(gd, B, fi, (r0 + frow) % B.s[1]);
         R Ff[NV];
-        lam = (double)face_flux<R, 0, FLUX>(qL, qR, m, (R)gd.st->ch, (R)kp.gam, (R)kp.gfac, Ff);
+        lam = (double)face_flux<R, 0, FLUX>(qL, qR, mf, (R)gd.st->ch, (R)kp.gam, (R)kp.gfac, Ff);
 #pragma unroll
         for (int v = 0; v < NV; v++) fx[v][threadIdx.x] = Ff[v];
     }
@@ -843,17 +850,8 @@ __global__ __launch_bounds__(WG) void k_cell_speeds(KParams kp, GridDev gd, cons
 // ---------------------------------------------------------------------------------
 // Time-step bookkeeping (single thread).
 // ---------------------------------------------------------------------------------
-__global__ void k_begin(KParams kp, DevState *st, int latch)
-{
-    if (latch) {
-        st->dt = st->dt_fixed > 0.0 ? st->dt_fixed : st->dt_next;
-        st->ch = kp.cfl / (st->dt * kp.sinv_fine);
-        st->kappa = kp.glm_alpha * st->ch / kp.dmin_fine;
-    }
-    st->lam_acc[0] = st->lam_acc[1] = st->lam_acc[2] = 0ull;
-}
-
-__global__ void k_end(KParams kp, DevState *st)
+// dt_next from the wave-speed maxima of the substep that last filled lam_acc
+__device__ __forceinline__ void finish_step(const KParams &kp, DevState *st)
 {
     double s = 0.0;
     for (int d = 0; d < kp.ndim; d++) {
@@ -862,10 +860,34 @@ __global__ void k_end(KParams kp, DevState *st)
         s += l * kp.inv_dx_fine[d];
     }
     st->dt_next = st->dt_fixed > 0.0 ? st->dt_fixed : kp.cfl / s;
+    st->lam_pending = 0;
 }
 
-__global__ void k_set_dt(DevState *st, double dt)
+// Start of a substep: first the previous substep's maxima become dt_next (a substep
+// ends without a kernel of its own, so the step graph has one node fewer per
+// substep; host reads finish it through k_end), then the latch, then the reset.
+__global__ void k_begin(KParams kp, DevState *st, int latch)
 {
+    if (st->lam_pending) finish_step(kp, st);
+    if (latch) {
+        st->dt = st->dt_fixed > 0.0 ? st->dt_fixed : st->dt_next;
+        st->ch = kp.cfl / (st->dt * kp.sinv_fine);
+        st->kappa = kp.glm_alpha * st->ch / kp.dmin_fine;
+    }
+    st->lam_acc[0] = st->lam_acc[1] = st->lam_acc[2] = 0ull;
+    st->lam_pending = 1;
+}
+
+// the pending maxima, if any, become dt_next (before a host read, and after the
+// standalone reduction)
+__global__ void k_end(KParams kp, DevState *st)
+{
+    if (st->lam_pending) finish_step(kp, st);
+}
+
+__global__ void k_set_dt(KParams kp, DevState *st, double dt)
+{
+    if (st->lam_pending) finish_step(kp, st);      // the last substep's dt_next, under the old setting
     st->dt_fixed = dt;
     if (dt > 0.0) st->dt_next = dt;
 }
@@ -1003,7 +1025,7 @@ hipError_t launch_compute_dt(const DeviceGrid &G, const void *P, hipStream_t s)
 
 hipError_t launch_set_dt(const DeviceGrid &G, double dt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, s, G.d_state, dt);
+    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, s, G.kp, G.d_state, dt);
     return hipGetLastError();
 }
 
@@ -1160,7 +1182,11 @@ hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *U
     if (G.plan.p.fused) e = launch_fused_body(G, Ub, Us, Ps, Uo, Po, a, b, s);
     else if (G.mixed) e = substep_prec<float>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
     else e = substep_prec<double>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
-    if (e != hipSuccess) return e;
+    return e;      // dt_next follows at the next substep's start (or on a host read)
+}
+
+hipError_t launch_finish_step(const DeviceGrid &G, hipStream_t s)
+{
     return end_step(G, s);
 }
 
@@ -1299,8 +1325,7 @@ hipError_t launch_substep_ct(const DeviceGrid &G, const double *Ub, const double
     const CtPtrs c = ct_split(G, Phb, Phs, Pho);
     e = G.mixed ? substep_ct_prec<float>(G, Ub, Us, Ps, c, Uo, Po, a, b, s)
                 : substep_ct_prec<double>(G, Ub, Us, Ps, c, Uo, Po, a, b, s);
-    if (e != hipSuccess) return e;
-    return end_step(G, s);
+    return e;      // dt_next follows at the next substep's start (or on a host read)
 }
 
 hipError_t launch_ct_center(const DeviceGrid &G, const double *Ph, void *P, hipStream_t s)

@@ -88,11 +88,25 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
         FaceM<R> mnext;
         if constexpr (D == 2 || !LST) mnext = metric(w.f0);
         R lmax = R(0);
+        // double along x1/x2 (nine variables, independent patches): the face's metric
+        // record is loaded at the top of the iteration that solves it, so its latency
+        // overlaps that cell's reconstruction (a record fetched one face ahead would
+        // not fit the register budget; with the entropy field or tree halos this one
+        // would not either, and those variants load it at the solve)
+        constexpr bool PRE = LST && D != 2 && !ENT && !XL;
+        FaceM<R> mcur;
+        auto fetch = [&](int f) {
+            if constexpr (PRE) {
+                if (f >= w.f0 && f < w.f1) mcur = metric(f);
+            }
+        };
 
         auto solve = [&](int f, R *qL, R *qR) {
             FaceM<R> m;
             if constexpr (D == 2) {
                 m = mnext;
+            } else if constexpr (PRE) {
+                m = mcur;
             } else if constexpr (LST) {
                 m = metric(f);
             } else {
@@ -147,10 +161,12 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
             }
             for (int c = w.f0 - 1; c < w.f1; c++) {
                 // float: q_{c+3} is fetched one cell ahead; double loads q_{c+2} here
-                // (no room for a second set; the other wave on the SIMD hides it)
+                // (no room for a second set, neither in registers nor, beside the march
+                // state, in LDS without spilling; the other wave on the SIMD hides it)
                 R q3[LST ? 1 : NM];
                 if constexpr (LST) load(c + 2, q2);
                 else if (c + 1 < w.f1) load(c + 3, q3);
+                fetch(c);
                 R qm[NM], qL[NM];
 #pragma unroll
                 for (int v = 0; v < NM; v++) {
@@ -186,6 +202,7 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
             for (int c = w.f0; c < w.f1; c++) {
                 R q2[NM];
                 if (c + 1 < w.f1) load(c + 2, q2);
+                fetch(c);
                 R qL[NM], qR[NM];
 #pragma unroll
                 for (int v = 0; v < NM; v++) {
