@@ -112,12 +112,12 @@ TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
     # profiles/update_ks_turb_384_hbm_traffic.md, update_ks_torus_192_mixed_128_fp64_hbm_traffic.md,
     # update_ks_torus_128_ct_hbm_traffic.md
-    ("ks_turb_384_mixed_plain", "update"): (20828285209, "ea33815275bb2c6c"),
-    ("ks_turb_384_fp64_plain", "update_x1"): (36357667395, "ea33815275bb2c6c"),
-    ("ks_torus_192_mixed_plain", "update"): (2607506257, "ea33815275bb2c6c"),
-    ("ks_torus_128_fp64_plain", "update_x1"): (1325984199, "ea33815275bb2c6c"),
-    ("ks_torus_128_mixed_ct", "update"): (671363052, "ea33815275bb2c6c"),
-    ("ks_torus_128_fp64_ct", "update"): (983088782, "ea33815275bb2c6c"),
+    ("ks_turb_384_mixed_plain", "update"): (20828525394, "81a6ac547773c6a0"),
+    ("ks_turb_384_fp64_plain", "update_x1"): (36373470977, "81a6ac547773c6a0"),
+    ("ks_torus_192_mixed_plain", "update"): (2607459599, "81a6ac547773c6a0"),
+    ("ks_torus_128_fp64_plain", "update_x1"): (1327009594, "81a6ac547773c6a0"),
+    ("ks_torus_128_mixed_ct", "update"): (671374492, "81a6ac547773c6a0"),
+    ("ks_torus_128_fp64_ct", "update"): (983128734, "81a6ac547773c6a0"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
@@ -131,30 +131,30 @@ TRAFFIC = {
 VALU = {
     # profiles/ks_turb_384_valu_counters.md, ks_torus_192_mixed_128_fp64_valu_counters.md,
     # ks_torus_128_ct_valu_counters.md
-    ("ks_turb_384_mixed_plain", "flux_x1"): (1033853143, "ea33815275bb2c6c"),
-    ("ks_turb_384_mixed_plain", "flux_x2"): (618230357, "ea33815275bb2c6c"),
-    ("ks_turb_384_mixed_plain", "flux_x3"): (546281603, "ea33815275bb2c6c"),
-    ("ks_turb_384_mixed_plain", "update"): (1255450950, "ea33815275bb2c6c"),
-    ("ks_turb_384_fp64_plain", "flux_x2"): (734164749, "ea33815275bb2c6c"),
-    ("ks_turb_384_fp64_plain", "flux_x3"): (659868586, "ea33815275bb2c6c"),
-    ("ks_turb_384_fp64_plain", "update_x1"): (2591882998, "ea33815275bb2c6c"),
-    ("ks_torus_192_mixed_plain", "flux_x1"): (129382381, "ea33815275bb2c6c"),
-    ("ks_torus_192_mixed_plain", "flux_x2"): (77645635, "ea33815275bb2c6c"),
-    ("ks_torus_192_mixed_plain", "flux_x3"): (68428752, "ea33815275bb2c6c"),
-    ("ks_torus_192_mixed_plain", "update"): (158204650, "ea33815275bb2c6c"),
-    ("ks_torus_128_fp64_plain", "flux_x2"): (27163230, "ea33815275bb2c6c"),
-    ("ks_torus_128_fp64_plain", "flux_x3"): (24566753, "ea33815275bb2c6c"),
-    ("ks_torus_128_fp64_plain", "update_x1"): (96708918, "ea33815275bb2c6c"),
-    ("ks_torus_128_fp64_ct", "flux_x1"): (43390281, "ea33815275bb2c6c"),
-    ("ks_torus_128_fp64_ct", "flux_x2"): (26786612, "ea33815275bb2c6c"),
-    ("ks_torus_128_fp64_ct", "flux_x3"): (24352524, "ea33815275bb2c6c"),
-    ("ks_torus_128_fp64_ct", "update"): (39467067, "ea33815275bb2c6c"),
-    ("ks_torus_128_fp64_ct", "ct_edges"): (6303829, "ea33815275bb2c6c"),
-    ("ks_torus_128_mixed_ct", "flux_x1"): (34745233, "ea33815275bb2c6c"),
-    ("ks_torus_128_mixed_ct", "flux_x2"): (21133398, "ea33815275bb2c6c"),
-    ("ks_torus_128_mixed_ct", "flux_x3"): (18436869, "ea33815275bb2c6c"),
-    ("ks_torus_128_mixed_ct", "update"): (40745000, "ea33815275bb2c6c"),
-    ("ks_torus_128_mixed_ct", "ct_edges"): (6453333, "ea33815275bb2c6c"),
+    ("ks_turb_384_fp64_plain", "flux_x2"): (734164576, "81a6ac547773c6a0"),
+    ("ks_turb_384_fp64_plain", "flux_x3"): (659868626, "81a6ac547773c6a0"),
+    ("ks_turb_384_mixed_plain", "flux_x2"): (618230367, "81a6ac547773c6a0"),
+    ("ks_turb_384_mixed_plain", "flux_x3"): (546281563, "81a6ac547773c6a0"),
+    ("ks_turb_384_mixed_plain", "flux_x1"): (1033852724, "81a6ac547773c6a0"),
+    ("ks_turb_384_mixed_plain", "update"): (1255451055, "81a6ac547773c6a0"),
+    ("ks_turb_384_fp64_plain", "update_x1"): (2592712184, "81a6ac547773c6a0"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27163095, "81a6ac547773c6a0"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24566754, "81a6ac547773c6a0"),
+    ("ks_torus_192_mixed_plain", "flux_x2"): (77645691, "81a6ac547773c6a0"),
+    ("ks_torus_192_mixed_plain", "flux_x3"): (68428719, "81a6ac547773c6a0"),
+    ("ks_torus_192_mixed_plain", "flux_x1"): (129381733, "81a6ac547773c6a0"),
+    ("ks_torus_192_mixed_plain", "update"): (158204663, "81a6ac547773c6a0"),
+    ("ks_torus_128_fp64_plain", "update_x1"): (96739644, "81a6ac547773c6a0"),
+    ("ks_torus_128_fp64_ct", "ct_edges"): (6303829, "81a6ac547773c6a0"),
+    ("ks_torus_128_mixed_ct", "ct_edges"): (6453333, "81a6ac547773c6a0"),
+    ("ks_torus_128_fp64_ct", "flux_x2"): (26786526, "81a6ac547773c6a0"),
+    ("ks_torus_128_fp64_ct", "flux_x3"): (24352543, "81a6ac547773c6a0"),
+    ("ks_torus_128_mixed_ct", "flux_x2"): (21133475, "81a6ac547773c6a0"),
+    ("ks_torus_128_mixed_ct", "flux_x3"): (18436843, "81a6ac547773c6a0"),
+    ("ks_torus_128_fp64_ct", "flux_x1"): (43390243, "81a6ac547773c6a0"),
+    ("ks_torus_128_mixed_ct", "flux_x1"): (34745008, "81a6ac547773c6a0"),
+    ("ks_torus_128_fp64_ct", "update"): (39467095, "81a6ac547773c6a0"),
+    ("ks_torus_128_mixed_ct", "update"): (40744995, "81a6ac547773c6a0"),
 }
 VALU_PEAK = 39.3e12      # lane-instructions/s
 
