@@ -475,7 +475,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="ks_turb_384_mixed_plain", choices=sorted(WORKLOADS))
     ap.add_argument("--compare", default="ks_turb_384_fp64_plain",
                     help="second path on the same grid reported beside the headline ('' to skip)")
-    ap.add_argument("--extra", default="ks_torus_128_fp64_plain,ks_torus_192_mixed_plain,ks_torus_128_fp64_ct",
+    ap.add_argument("--extra", default="ks_torus_128_fp64_plain,ks_torus_192_mixed_plain,amr_like_4096_mixed_plain,"
+                                       "ks_torus_128_fp64_ct",
                     help="further workloads timed with --extra-steps per segment ('' to skip)")
     ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of each oracle sample")
