@@ -33,7 +33,7 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
 {
     __shared__ double red[MWG / 64];
     constexpr int NM = NV + (ENT ? 1 : 0);        // marched variables
-    constexpr bool LST = sizeof(R) == 8;          // march state in LDS (double)
+    constexpr bool LST = sizeof(R) == 8;          // march state declared in LDS (double)
     __shared__ R lst[LST ? 3 : 1][NM][LST ? MWG : 1];
     const MarchItem w = work[blockIdx.x];
     if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
@@ -130,9 +130,9 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
         if constexpr (RECON == BHAC_RECON_PPM) {
             // state before cell c: q_c, q_{c+1}, q_{c+2} (registers), and per
             // variable the MC slope s_c, the interface value a_{c-1/2} and the
-            // limited upper value qp_{c-1} of cell c-1 (registers in float; in
-            // double they live in this lane's LDS slots, which keeps the kernel
-            // within the register budget of two waves per SIMD)
+            // limited upper value qp_{c-1} of cell c-1 (registers in float; double
+            // declares them in LDS slots, kept in registers in the loop by the
+            // compiler: fits two waves/SIMD unspilled, as arrays spills 64-224 B/lane)
             R qc[NM], qn[NM], q2[NM];
             R sreg[LST ? 1 : 3][NM];
             auto get = [&](int a, int v) -> R {
