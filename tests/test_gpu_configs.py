@@ -12,6 +12,10 @@
 * the same grid, 100 steps with the CFL time step in the captured step graph, as the
   benchmark runs it (no oracle: 1.1e10 zone-updates); the state stays finite and
   physical.
+* the AMR-like list (4096 independent patches of 8^3, 12^3 and 16^3 cells on three
+  levels, about 6.5 M zones), 10 steps with the CFL time step: mixed precision on
+  the default schedule (the benchmark's path) at 1e-5 and FP64 at 1e-11, whole grid,
+  per field.
 
 The oracle runs its block loops on the host's cores (bit-identical to one thread).
 Error measure (per field): own-sum relative L1 sum|a-b| / sum|b|; the relative L1
@@ -115,6 +119,23 @@ def test_case3_192_mixed_full_grid_ten_steps():
     assert (eU <= 1e-5).all(), eU
     assert (eP <= 1e-5).all(), eP
     assert ts["dt_next"] == pytest.approx(ost["dt_next"], rel=1e-5)
+
+
+@pytest.mark.parametrize("prec,tol", [(I.PREC_MIXED, 1e-5), (I.PREC_FP64, 1e-11)])
+def test_case4_amr_like_full_grid_ten_steps(prec, tol):
+    c = I.case4()
+    c.params = dict(c.params, precision=prec, fused=0)
+    print(f"\n[config] {c.name}: {len(c.blocks)} blocks of 8^3/12^3/16^3 on three levels, prec={prec}, "
+          f"default schedule, whole grid, 10 RK2 steps, CFL dt", flush=True)
+    Ug, Pg, Uo, Po, st, ts, ost = full_grid(c, 10)
+    eU = report("U", U_NAMES, Ug, Uo)
+    eP = report("P", P_NAMES, Pg, Po)
+    assert (eU <= tol).all(), eU
+    assert (eP <= tol).all(), eP
+    assert ts["dt_next"] == pytest.approx(ost["dt_next"], rel=tol)
+    if prec == I.PREC_FP64:
+        assert st["c2p_fail"] == ost["c2p_fail"]
+        assert st["floor_hits"] == ost["floor_hits"]
 
 
 def test_case5_384_mixed_full_grid_ten_steps():
