@@ -16,6 +16,9 @@
   levels, about 6.5 M zones), 10 steps with the CFL time step: mixed precision on
   the default schedule (the benchmark's path) at 1e-5 and FP64 at 1e-11, whole grid,
   per field.
+* the 96^3-base three-level block tree (972 blocks of 16^3, 4.0 M zones, cross-level
+  ghost fill and flux correction every substep), 10 steps with the CFL time step,
+  same bars.
 
 The oracle runs its block loops on the host's cores (bit-identical to one thread).
 Error measure (per field): own-sum relative L1 sum|a-b| / sum|b|; the relative L1
@@ -127,6 +130,23 @@ def test_case4_amr_like_full_grid_ten_steps(prec, tol):
     c.params = dict(c.params, precision=prec, fused=0)
     print(f"\n[config] {c.name}: {len(c.blocks)} blocks of 8^3/12^3/16^3 on three levels, prec={prec}, "
           f"default schedule, whole grid, 10 RK2 steps, CFL dt", flush=True)
+    Ug, Pg, Uo, Po, st, ts, ost = full_grid(c, 10)
+    eU = report("U", U_NAMES, Ug, Uo)
+    eP = report("P", P_NAMES, Pg, Po)
+    assert (eU <= tol).all(), eU
+    assert (eP <= tol).all(), eP
+    assert ts["dt_next"] == pytest.approx(ost["dt_next"], rel=tol)
+    if prec == I.PREC_FP64:
+        assert st["c2p_fail"] == ost["c2p_fail"]
+        assert st["floor_hits"] == ost["floor_hits"]
+
+
+@pytest.mark.parametrize("prec,tol", [(I.PREC_MIXED, 1e-5), (I.PREC_FP64, 1e-11)])
+def test_block_tree_96_full_grid_ten_steps(prec, tol):
+    c = I.case_tree(n0=96, bs=16, levels=3, precision=prec)
+    c.params = dict(c.params, precision=prec, fused=0)
+    print(f"\n[config] {c.name}: {len(c.blocks)} blocks of 16^3 on three levels, prec={prec}, default "
+          f"schedule, whole grid, 10 RK2 steps, CFL dt", flush=True)
     Ug, Pg, Uo, Po, st, ts, ost = full_grid(c, 10)
     eU = report("U", U_NAMES, Ug, Uo)
     eP = report("P", P_NAMES, Pg, Po)
