@@ -110,6 +110,52 @@ def test_ten_steps_match_oracle(torch, name, make, prec, tol):
     assert np.abs(Ug[8]).max() == 0.0
 
 
+@pytest.mark.parametrize("prec,tol", [(I.PREC_FP64, 1e-11), (I.PREC_MIXED, 1e-5)])
+def test_benchmark_grid_128_ten_steps(torch, prec, tol):
+    """The benchmark's constrained-transport workload at its size: the 128^3 torus
+    (512 blocks of 16^3) with the face field of its azimuthal potential, 10 RK2
+    steps with the CFL time step, the whole grid and every face against the oracle
+    (run on the host's cores), and the discrete divergence at the end."""
+    import os
+    c, phi0 = I.torus_with_face_field(I.case_torus(2, n=128))
+    params = dict(c.params, precision=prec, fused=0)
+    banner(f"128^3 torus, constrained transport, prec={prec}, 10 steps")
+    G = B.Grid(params, c.blocks)
+    U, P, phi = G.init_ct(c.prim, phi0)
+    U1, P1, phi1 = G.new_state("U"), G.new_state("P"), G.new_faces()
+    for _ in range(10):
+        G.rk2_step_ct(U, P, phi, U1, P1, phi1)
+    torch.cuda.synchronize()
+    dx = min((params["x_hi"][e] - params["x_lo"][e]) / params["ncell0"][e] for e in range(3))
+    div = (G.ct_divergence(phi).abs().max() * dx / phi.abs().max()).item()
+    Ug, Pg, phig = G.unpack(U), G.unpack(P), phi.cpu().numpy()
+    nface = G.face_count()
+    st, ts = G.stats(), G.timestep()
+    G.close()
+    n = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    O.set_threads(max(1, min(16, n if n > 0 else (os.cpu_count() or 1))))
+    try:
+        Og = O.OracleGrid(params, c.blocks)
+        phio = phi0.copy()
+        Uo, Po = Og.init_ct(c.prim, phio)
+        for _ in range(10):
+            Og.rk2_step_ct(Uo, Po, phio)
+    finally:
+        O.set_threads(1)
+    idx = Og.interior_index()
+    eU = rel_l1(Ug, Uo[:, idx])
+    eP = rel_l1(Pg, Po[:, idx])
+    ef = face_rel_l1(phig, phio, nface)
+    print(f"  rel-L1 U {eU}\n  rel-L1 P {eP}\n  rel-L1 phi per direction {ef}\n  max |div| dx / max |phi| {div:.3e}\n"
+          f"  gpu {st} dt {ts['dt_next']!r}\n  oracle {Og.stats()}", flush=True)
+    assert (eU[:8] <= tol).all(), eU
+    assert (eP[:8] <= tol).all(), eP
+    assert (ef <= tol).all(), ef
+    assert ts["dt_next"] == pytest.approx(Og.stats()["dt_next"], rel=1e-9 if prec == I.PREC_FP64 else 1e-5)
+    assert np.abs(Ug[8]).max() == 0.0
+    assert div < 1e-12
+
+
 @pytest.mark.parametrize("prec", [I.PREC_FP64, I.PREC_MIXED])
 @pytest.mark.parametrize("name,make", [("flat_3d_32", flat3d), ("ks_2d_64", ks2d)])
 def test_divergence_stays_at_roundoff(torch, name, make, prec):
