@@ -6,9 +6,9 @@
 * 192^3 torus (1728 blocks), mixed precision on the library's default schedule (the
   path the benchmark times), 10 steps with the CFL time step: whole grid, per field,
   at 1e-5 relative L1.
-* 384^3 turbulent torus (13824 blocks), mixed precision on the default schedule, 10
-  steps with the CFL time step: whole grid, per field, at 1e-5 relative L1 (the
-  oracle takes about two minutes on 16 host cores).
+* 384^3 turbulent torus (13824 blocks), mixed precision and FP64 each on its
+  default schedule, 10 steps with the CFL time step: whole grid, per field, at 1e-5
+  and 1e-11 relative L1 against one oracle run (about two minutes on 16 host cores).
 * the same grid, 100 steps with the CFL time step in the captured step graph, as the
   benchmark runs it (no oracle: 1.1e10 zone-updates); the state stays finite and
   physical.
@@ -66,7 +66,7 @@ def report(tag, names, got, ref):
     return bar
 
 
-def full_grid(c, steps):
+def gpu_run(c, steps):
     import torch
     t0 = time.perf_counter()
     G = B.Grid(c.params, c.blocks)
@@ -77,6 +77,11 @@ def full_grid(c, steps):
     G.close()
     del U, P
     torch.cuda.empty_cache()
+    print(f"  gpu {time.perf_counter() - t0:.1f} s, stats {st}", flush=True)
+    return Ug, Pg, st, ts
+
+
+def oracle_run(c, steps):
     t1 = time.perf_counter()
     O.set_threads(host_threads())
     try:
@@ -90,12 +95,15 @@ def full_grid(c, steps):
     finally:
         O.set_threads(1)
     idx = Og.interior_index()
-    Uo, Po = Uo[:, idx], Po[:, idx]
-    t2 = time.perf_counter()
-    print(f"  gpu {t1 - t0:.1f} s, oracle {t2 - t1:.1f} s on {host_threads()} threads\n"
-          f"  gpu stats {st}\n  oracle stats {Og.stats()}\n  dt gpu {ts['dt_next']!r} oracle {Og.state.dt_next!r}",
-          flush=True)
-    return Ug, Pg, Uo, Po, st, ts, Og.stats()
+    print(f"  oracle {time.perf_counter() - t1:.1f} s on {host_threads()} threads, stats {Og.stats()}", flush=True)
+    return Uo[:, idx], Po[:, idx], Og.stats()
+
+
+def full_grid(c, steps):
+    Ug, Pg, st, ts = gpu_run(c, steps)
+    Uo, Po, ost = oracle_run(c, steps)
+    print(f"  dt gpu {ts['dt_next']!r} oracle {ost['dt_next']!r}", flush=True)
+    return Ug, Pg, Uo, Po, st, ts, ost
 
 
 def test_case2_128_fp64_full_grid_ten_steps():
@@ -158,20 +166,31 @@ def test_block_tree_96_full_grid_ten_steps(prec, tol):
         assert st["floor_hits"] == ost["floor_hits"]
 
 
-def test_case5_384_mixed_full_grid_ten_steps():
-    """The headline grid: 384^3 turbulent torus (13824 blocks), mixed precision on the
-    default schedule, 10 RK2 steps with the CFL time step, the whole grid against the
-    oracle's whole grid (1.1e9 zone-updates on the host's cores), per field at 1e-5."""
+def test_case5_384_full_grid_ten_steps_both_precisions():
+    """The headline grid: 384^3 turbulent torus (13824 blocks), mixed precision (the
+    headline path) and FP64 (the benchmark's comparison path), each on its default
+    schedule, 10 RK2 steps with the CFL time step, the whole grid against one run of
+    the oracle's whole grid (1.1e9 zone-updates on the host's cores): per field at
+    1e-5 (mixed) and 1e-11 (FP64)."""
     print("\n[config] 384^3 turbulent torus: inputs", flush=True)
     c = I.case_torus(5, n=384)
-    c.params = dict(c.params, precision=I.PREC_MIXED, fused=0)
-    print(f"[config] {c.name}: 384^3 mixed, default schedule, whole grid, 10 RK2 steps, CFL dt", flush=True)
-    Ug, Pg, Uo, Po, st, ts, ost = full_grid(c, 10)
-    eU = report("U", U_NAMES, Ug, Uo)
-    eP = report("P", P_NAMES, Pg, Po)
-    assert (eU <= 1e-5).all(), eU
-    assert (eP <= 1e-5).all(), eP
-    assert ts["dt_next"] == pytest.approx(ost["dt_next"], rel=1e-5)
+    runs = {}
+    for prec in (I.PREC_MIXED, I.PREC_FP64):
+        cp = I.Case(c.name, dict(c.params, precision=prec, fused=0), c.blocks, c.prim, c.ioff, c.steps)
+        print(f"[config] {c.name}: 384^3 prec={prec}, default schedule, whole grid, 10 RK2 steps, CFL dt", flush=True)
+        runs[prec] = gpu_run(cp, 10)
+    Uo, Po, ost = oracle_run(c, 10)
+    for prec, tol in ((I.PREC_MIXED, 1e-5), (I.PREC_FP64, 1e-11)):
+        Ug, Pg, st, ts = runs[prec]
+        print(f"[config] prec={prec}: dt gpu {ts['dt_next']!r} oracle {ost['dt_next']!r}", flush=True)
+        eU = report("U", U_NAMES, Ug, Uo)
+        eP = report("P", P_NAMES, Pg, Po)
+        assert (eU <= tol).all(), (prec, eU)
+        assert (eP <= tol).all(), (prec, eP)
+        assert ts["dt_next"] == pytest.approx(ost["dt_next"], rel=tol)
+        if prec == I.PREC_FP64:
+            assert st["c2p_fail"] == ost["c2p_fail"]
+            assert st["floor_hits"] == ost["floor_hits"]
 
 
 def test_case5_384_mixed_hundred_steps_with_cfl():
