@@ -471,7 +471,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="SSP-RK2 steps (2 substeps each) per timed segment")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--repeats", type=int, default=5, help="timed segments of one continuous run")
+    ap.add_argument("--repeats", type=int, default=15, help="timed segments of one continuous run (median and best reported)")
     ap.add_argument("--workload", default="ks_turb_384_mixed_plain", choices=sorted(WORKLOADS))
     ap.add_argument("--compare", default="ks_turb_384_fp64_plain",
                     help="second path on the same grid reported beside the headline ('' to skip)")
