@@ -378,10 +378,21 @@ int make_plan(const bhac_params *pp, const bhac_block_desc *blocks, int64_t nb, 
         P.wupd1.clear();
         if (ok) {
             P.x1_staged = false;
-            for (int64_t b = 0; b < nb; b++) {
+            // blocks in rows along x1 (as the x1 face work): a work item's x1 halo
+            // pieces are the end cells of its x1 neighbours' rows, which their own
+            // work items read at about the same time on the same XCD (one L2)
+            std::vector<int> ord(nb);
+            for (int64_t b = 0; b < nb; b++) ord[b] = (int)b;
+            auto key = [&](int b) {
+                const bhac_block_desc &B = blocks[b];
+                return std::make_tuple(B.level, B.size[0], B.size[1], B.size[2], B.origin[2] / B.size[2],
+                                       B.origin[1] / B.size[1], B.origin[0] / B.size[0]);
+            };
+            std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) < key(b); });
+            for (int b : ord) {
                 const DevBlock &D = P.dblocks[b];
                 const int rpw = x1u_rows(D.s[0]), nrow = D.s[1] * D.s[2];
-                for (int r = 0; r < nrow; r += rpw) P.wupd1.push_back({(int)b, r});
+                for (int r = 0; r < nrow; r += rpw) P.wupd1.push_back({b, r});
             }
         }
     }
