@@ -112,12 +112,12 @@ TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
     # profiles/update_ks_turb_384_hbm_traffic.md, update_ks_torus_192_mixed_128_fp64_hbm_traffic.md,
     # update_ks_torus_128_ct_hbm_traffic.md
-    ("ks_turb_384_mixed_plain", "update"): (20828525394, "81a6ac547773c6a0"),
-    ("ks_turb_384_fp64_plain", "update_x1"): (36373470977, "81a6ac547773c6a0"),
-    ("ks_torus_192_mixed_plain", "update"): (2607459599, "81a6ac547773c6a0"),
-    ("ks_torus_128_fp64_plain", "update_x1"): (1327009594, "81a6ac547773c6a0"),
-    ("ks_torus_128_mixed_ct", "update"): (671374492, "81a6ac547773c6a0"),
-    ("ks_torus_128_fp64_ct", "update"): (983128734, "81a6ac547773c6a0"),
+    ("ks_turb_384_mixed_plain", "update"): (20828500374, "567e16efe17f985d"),
+    ("ks_turb_384_fp64_plain", "update_x1"): (30605902354, "567e16efe17f985d"),
+    ("ks_torus_192_mixed_plain", "update"): (2607484839, "567e16efe17f985d"),
+    ("ks_torus_128_fp64_plain", "update_x1"): (1133665255, "567e16efe17f985d"),
+    ("ks_torus_128_mixed_ct", "update"): (671371798, "567e16efe17f985d"),
+    ("ks_torus_128_fp64_ct", "update"): (983061331, "567e16efe17f985d"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
@@ -131,30 +131,30 @@ TRAFFIC = {
 VALU = {
     # profiles/ks_turb_384_valu_counters.md, ks_torus_192_mixed_128_fp64_valu_counters.md,
     # ks_torus_128_ct_valu_counters.md
-    ("ks_turb_384_fp64_plain", "flux_x2"): (734164576, "81a6ac547773c6a0"),
-    ("ks_turb_384_fp64_plain", "flux_x3"): (659868626, "81a6ac547773c6a0"),
-    ("ks_turb_384_mixed_plain", "flux_x2"): (618230367, "81a6ac547773c6a0"),
-    ("ks_turb_384_mixed_plain", "flux_x3"): (546281563, "81a6ac547773c6a0"),
-    ("ks_turb_384_mixed_plain", "flux_x1"): (1033852724, "81a6ac547773c6a0"),
-    ("ks_turb_384_mixed_plain", "update"): (1255451055, "81a6ac547773c6a0"),
-    ("ks_turb_384_fp64_plain", "update_x1"): (2592712184, "81a6ac547773c6a0"),
-    ("ks_torus_128_fp64_plain", "flux_x2"): (27163095, "81a6ac547773c6a0"),
-    ("ks_torus_128_fp64_plain", "flux_x3"): (24566754, "81a6ac547773c6a0"),
-    ("ks_torus_192_mixed_plain", "flux_x2"): (77645691, "81a6ac547773c6a0"),
-    ("ks_torus_192_mixed_plain", "flux_x3"): (68428719, "81a6ac547773c6a0"),
-    ("ks_torus_192_mixed_plain", "flux_x1"): (129381733, "81a6ac547773c6a0"),
-    ("ks_torus_192_mixed_plain", "update"): (158204663, "81a6ac547773c6a0"),
-    ("ks_torus_128_fp64_plain", "update_x1"): (96739644, "81a6ac547773c6a0"),
-    ("ks_torus_128_fp64_ct", "ct_edges"): (6303829, "81a6ac547773c6a0"),
-    ("ks_torus_128_mixed_ct", "ct_edges"): (6453333, "81a6ac547773c6a0"),
-    ("ks_torus_128_fp64_ct", "flux_x2"): (26786526, "81a6ac547773c6a0"),
-    ("ks_torus_128_fp64_ct", "flux_x3"): (24352543, "81a6ac547773c6a0"),
-    ("ks_torus_128_mixed_ct", "flux_x2"): (21133475, "81a6ac547773c6a0"),
-    ("ks_torus_128_mixed_ct", "flux_x3"): (18436843, "81a6ac547773c6a0"),
-    ("ks_torus_128_fp64_ct", "flux_x1"): (43390243, "81a6ac547773c6a0"),
-    ("ks_torus_128_mixed_ct", "flux_x1"): (34745008, "81a6ac547773c6a0"),
-    ("ks_torus_128_fp64_ct", "update"): (39467095, "81a6ac547773c6a0"),
-    ("ks_torus_128_mixed_ct", "update"): (40744995, "81a6ac547773c6a0"),
+    ("ks_turb_384_fp64_plain", "flux_x2"): (734164638, "567e16efe17f985d"),
+    ("ks_turb_384_fp64_plain", "flux_x3"): (659868762, "567e16efe17f985d"),
+    ("ks_turb_384_mixed_plain", "flux_x2"): (618230358, "567e16efe17f985d"),
+    ("ks_turb_384_mixed_plain", "flux_x3"): (546281593, "567e16efe17f985d"),
+    ("ks_turb_384_mixed_plain", "flux_x1"): (1033852605, "567e16efe17f985d"),
+    ("ks_turb_384_mixed_plain", "update"): (1255451031, "567e16efe17f985d"),
+    ("ks_turb_384_fp64_plain", "update_x1"): (2592712443, "567e16efe17f985d"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27163141, "567e16efe17f985d"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24566805, "567e16efe17f985d"),
+    ("ks_torus_192_mixed_plain", "flux_x2"): (77645655, "567e16efe17f985d"),
+    ("ks_torus_192_mixed_plain", "flux_x3"): (68428761, "567e16efe17f985d"),
+    ("ks_torus_192_mixed_plain", "flux_x1"): (129381829, "567e16efe17f985d"),
+    ("ks_torus_192_mixed_plain", "update"): (158204622, "567e16efe17f985d"),
+    ("ks_torus_128_fp64_plain", "update_x1"): (96739698, "567e16efe17f985d"),
+    ("ks_torus_128_fp64_ct", "ct_edges"): (6303829, "567e16efe17f985d"),
+    ("ks_torus_128_mixed_ct", "ct_edges"): (6453333, "567e16efe17f985d"),
+    ("ks_torus_128_fp64_ct", "flux_x2"): (26786547, "567e16efe17f985d"),
+    ("ks_torus_128_fp64_ct", "flux_x3"): (24352510, "567e16efe17f985d"),
+    ("ks_torus_128_mixed_ct", "flux_x2"): (21133434, "567e16efe17f985d"),
+    ("ks_torus_128_mixed_ct", "flux_x3"): (18436861, "567e16efe17f985d"),
+    ("ks_torus_128_fp64_ct", "flux_x1"): (43390073, "567e16efe17f985d"),
+    ("ks_torus_128_mixed_ct", "flux_x1"): (34744922, "567e16efe17f985d"),
+    ("ks_torus_128_fp64_ct", "update"): (39467127, "567e16efe17f985d"),
+    ("ks_torus_128_mixed_ct", "update"): (40745008, "567e16efe17f985d"),
 }
 VALU_PEAK = 39.3e12      # lane-instructions/s
 
