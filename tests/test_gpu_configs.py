@@ -42,6 +42,27 @@ U_NAMES = ("D", "S1", "S2", "S3", "tau", "B1", "B2", "B3", "psi")
 P_NAMES = ("rho", "u1", "u2", "u3", "p", "B1", "B2", "B3", "psi")
 
 
+_capman = None
+
+
+@pytest.fixture(autouse=True)
+def _live_output(request):
+    global _capman
+    _capman = request.config.pluginmanager.getplugin("capturemanager")
+    yield
+    _capman = None
+
+
+def live(msg):
+    """A progress line of a long test, written past pytest's output capture (a run
+    that prints nothing for minutes is taken to be hung)."""
+    if _capman is not None:
+        with _capman.global_and_fixture_disabled():
+            print(msg, flush=True)
+    else:
+        print(msg, flush=True)
+
+
 def host_threads():
     n = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
     return max(1, min(16, n if n > 0 else (os.cpu_count() or 1)))
@@ -77,7 +98,7 @@ def gpu_run(c, steps):
     G.close()
     del U, P
     torch.cuda.empty_cache()
-    print(f"  gpu {time.perf_counter() - t0:.1f} s, stats {st}", flush=True)
+    live(f"  gpu {time.perf_counter() - t0:.1f} s, stats {st}")
     return Ug, Pg, st, ts
 
 
@@ -90,7 +111,7 @@ def oracle_run(c, steps):
         U1o, P1o = np.zeros_like(Uo), np.zeros_like(Po)
         for s in range(steps):
             Og.rk2_step(Uo, Po, U1o, P1o)
-            print(f"  oracle step {s + 1} ({time.perf_counter() - t1:.0f} s)", flush=True)
+            live(f"  oracle step {s + 1} ({time.perf_counter() - t1:.0f} s)")
         del U1o, P1o
     finally:
         O.set_threads(1)
@@ -172,7 +193,7 @@ def test_case5_384_full_grid_ten_steps_both_precisions():
     schedule, 10 RK2 steps with the CFL time step, the whole grid against one run of
     the oracle's whole grid (1.1e9 zone-updates on the host's cores): per field at
     1e-5 (mixed) and 1e-11 (FP64)."""
-    print("\n[config] 384^3 turbulent torus: inputs", flush=True)
+    live("\n[config] 384^3 turbulent torus: inputs")
     c = I.case_torus(5, n=384)
     runs = {}
     for prec in (I.PREC_MIXED, I.PREC_FP64):
@@ -208,7 +229,7 @@ def test_case5_384_mixed_hundred_steps_with_cfl():
         G.launch_rk2_step()
         if s % 25 == 24:
             torch.cuda.synchronize()
-            print(f"  step {s + 1}: dt {G.timestep()['dt']!r}", flush=True)
+            live(f"  step {s + 1}: dt {G.timestep()['dt']!r}")
     torch.cuda.synchronize()
     ts, st = G.timestep(), G.stats()
     finite = bool(torch.isfinite(P[:9]).all().item()) and bool(torch.isfinite(U).all().item())
