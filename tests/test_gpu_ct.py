@@ -6,6 +6,7 @@ steps, the two copies of every shared face identical, every kernel schedule givi
 same bits, the captured RK2 step equal to the eager steps, and the entry points'
 errors."""
 import math
+import os
 
 import numpy as np
 import pytest
