@@ -138,6 +138,9 @@ hipError_t launch_fused_body(const DeviceGrid &G, const double *Ub, const double
 // phi: the face field of direction D under constrained transport (else nullptr)
 hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStream_t s, void *const *flux,
                              const double *phi = nullptr);
+// the x2 and x3 line marches as one launch (both directions marched; independent
+// patches without the entropy field, GLM)
+hipError_t launch_flux_march_x23(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux);
 // flux: the three face-flux arrays of the unfused path (nvar rows x nface[d] faces in
 // the state's precision); nullptr = the grid's own (d_flux)
 hipError_t launch_substep(const DeviceGrid &G, const double *Ub, const double *Us, const void *Ps, double *Uo,

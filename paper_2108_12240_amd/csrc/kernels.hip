@@ -1105,10 +1105,15 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
         return flux_dir<R, 2, RECON, FLUX, KS>(G, Ps, st, flux);
     };
     hipError_t e = hipSuccess;
+    // both x2 and x3 marched on independent patches (GLM, no entropy field): one
+    // launch runs both directions' line marches
+    const bool x23 = G.kp.ndim == 3 && !G.timer.on && (mm & 6) == 6 && !G.plan.p.amr && G.kp.nvar == NV;
     if (G.plan.x1_in_update) {
         // x2 (and x3 on a side stream, concurrently) by face kernels, then the update,
         // which computes the x1 faces itself
-        if (G.kp.ndim == 3 && !G.timer.on) {
+        if (x23) {
+            e = launch_flux_march_x23(G, Ps, s, flux);
+        } else if (G.kp.ndim == 3 && !G.timer.on) {
             e = hipEventRecord(G.ev_fork, s);
             if (e == hipSuccess) e = hipStreamWaitEvent(G.side[0], G.ev_fork, 0);
             if (e == hipSuccess) e = dir(2, G.side[0]);
@@ -1122,7 +1127,15 @@ static hipError_t substep_typed(const DeviceGrid &G, const double *Ub, const dou
         if (e == hipSuccess) e = update_x1_typed<R, RECON, FLUX, KS>(G, Ub, Us, Ps, Uo, Po, a, b, s, flux);
         return e;
     }
-    if (G.kp.ndim == 3 && G.side[0] && G.side[1] && !G.timer.on) {
+    if (x23 && G.side[0]) {
+        // x1 on the caller's stream, x2 and x3 in one launch on a side stream
+        e = hipEventRecord(G.ev_fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(G.side[0], G.ev_fork, 0);
+        if (e == hipSuccess) e = launch_flux_march_x23(G, Ps, G.side[0], flux);
+        if (e == hipSuccess) e = dir(0, s);
+        if (e == hipSuccess) e = hipEventRecord(G.ev_join[0], G.side[0]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, G.ev_join[0], 0);
+    } else if (G.kp.ndim == 3 && G.side[0] && G.side[1] && !G.timer.on) {
         e = hipEventRecord(G.ev_fork, s);
         for (int q = 0; q < 2 && e == hipSuccess; q++) e = hipStreamWaitEvent(G.side[q], G.ev_fork, 0);
         if (e == hipSuccess) e = dir(1, G.side[0]);

@@ -26,17 +26,24 @@ namespace bhac {
 // CT (constrained transport): the normal field of both states of a face is the face
 // field phi there (direction D's array, the layout of F) over sqrt(gamma), and there
 // is no GLM solve, as in the face kernel.
-template <typename R, int D, int RECON, int FLUX, bool KS, bool XL, bool ENT, bool CT = false>
-__global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KParams kp, GridDev gd, const MarchItem *__restrict__ work,
-                                                    const R *__restrict__ P, R *__restrict__ F, long long nftot,
-                                                    const double *__restrict__ phi)
+template <typename R, bool ENT>
+struct MarchLds {
+    static constexpr int NM = NV + (ENT ? 1 : 0); // marched variables
+    static constexpr bool LST = sizeof(R) == 8;   // march state declared in LDS (double)
+    double red[MWG / 64];
+    R lst[LST ? 3 : 1][NM][LST ? MWG : 1];
+};
+
+// one work item: the faces [f0, f1) of MWG lines of one block (the work-group's
+// LDS passed in, so that a kernel running items of two directions declares it once)
+template <typename R, int D, int RECON, int FLUX, bool KS, bool XL, bool ENT, bool CT>
+__device__ __forceinline__ void march_item(const KParams &kp, const GridDev &gd, const MarchItem &w,
+                                           const R *__restrict__ P, R *__restrict__ F, long long nftot,
+                                           const double *__restrict__ phi, MarchLds<R, ENT> &sm)
 {
-    __shared__ double red[MWG / 64];
-    constexpr int NM = NV + (ENT ? 1 : 0);        // marched variables
-    constexpr bool LST = sizeof(R) == 8;          // march state declared in LDS (double)
-    __shared__ R lst[LST ? 3 : 1][NM][LST ? MWG : 1];
-    const MarchItem w = work[blockIdx.x];
-    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
+    constexpr int NM = MarchLds<R, ENT>::NM;
+    constexpr bool LST = MarchLds<R, ENT>::LST;
+    auto &lst = sm.lst;
     const DevBlock B = gd.blocks[w.block];
     constexpr int A = D == 0 ? 1 : 0;             // fastest axis across the lines
     constexpr int C = D == 2 ? 1 : 2;
@@ -222,8 +229,42 @@ __global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KPar
         }
         lam = (double)lmax;
     }
-    const double mx = wg_max<MWG>(lam, red);
+    const double mx = wg_max<MWG>(lam, sm.red);
     if (threadIdx.x == 0) raise_max(&gd.st->lam_acc[D], mx);
+}
+
+template <typename R, int D, int RECON, int FLUX, bool KS, bool XL, bool ENT, bool CT = false>
+__global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march(KParams kp, GridDev gd, const MarchItem *__restrict__ work,
+                                                    const R *__restrict__ P, R *__restrict__ F, long long nftot,
+                                                    const double *__restrict__ phi)
+{
+    __shared__ MarchLds<R, ENT> sm;
+    const MarchItem w = work[blockIdx.x];
+    if (w.block < 0) return;                      // padding of the XCD order (whole work-group)
+    march_item<R, D, RECON, FLUX, KS, XL, ENT, CT>(kp, gd, w, P, F, nftot, phi, sm);
+}
+
+// The x2 and x3 line marches of a substep as one launch: work-groups [0, n2) take
+// the x2 work list, the rest the x3 list (n2 is a multiple of the XCD count, so both
+// keep their XCD order). One graph node instead of two kernels on two streams and
+// the join between them (independent patches, no entropy field, GLM).
+template <typename R, int RECON, int FLUX, bool KS>
+__global__ __launch_bounds__(MWG, sizeof(R) == 8 ? 2 : 1) void k_flux_march_x23(KParams kp, GridDev gd,
+                                                        const MarchItem *__restrict__ work2, long long n2,
+                                                        const MarchItem *__restrict__ work3, const R *__restrict__ P,
+                                                        R *__restrict__ F2, long long nf2, R *__restrict__ F3,
+                                                        long long nf3)
+{
+    __shared__ MarchLds<R, false> sm;
+    if (blockIdx.x < n2) {
+        const MarchItem w = work2[blockIdx.x];
+        if (w.block < 0) return;
+        march_item<R, 1, RECON, FLUX, KS, false, false, false>(kp, gd, w, P, F2, nf2, nullptr, sm);
+    } else {
+        const MarchItem w = work3[blockIdx.x - n2];
+        if (w.block < 0) return;
+        march_item<R, 2, RECON, FLUX, KS, false, false, false>(kp, gd, w, P, F3, nf3, nullptr, sm);
+    }
 }
 
 template <typename R, int D, int RECON, int FLUX, bool KS>
@@ -261,6 +302,43 @@ static hipError_t march_dir(const DeviceGrid &G, const void *Ps, hipStream_t s, 
     if (f == BHAC_FLUX_HLL) MARCH_CASE(BHAC_RECON_MC, BHAC_FLUX_HLL, false);
     MARCH_CASE(BHAC_RECON_MC, BHAC_FLUX_TVDLF, false);
 #undef MARCH_CASE
+}
+
+template <typename R, int RECON, int FLUX, bool KS>
+static hipError_t launch_x23_typed(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux)
+{
+    const size_t n2 = G.plan.wmarch[1].size(), n3 = G.plan.wmarch[2].size();
+    hipLaunchKernelGGL((k_flux_march_x23<R, RECON, FLUX, KS>), dim3(n2 + n3), dim3(MWG), 0, s, G.kp, G.gd,
+                       G.d_wmarch[1], (long long)n2, G.d_wmarch[2], (const R *)Ps, (R *)flux[1], G.plan.nface[1],
+                       (R *)flux[2], G.plan.nface[2]);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t x23_dir(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux)
+{
+    const int r = G.kp.recon, f = G.kp.flux;
+#define X23_CASE(RC, FL, KSV) return launch_x23_typed<R, RC, FL, KSV>(G, Ps, s, flux)
+    if (G.ks) {
+        if (r == BHAC_RECON_PPM) {
+            if (f == BHAC_FLUX_HLL) X23_CASE(BHAC_RECON_PPM, BHAC_FLUX_HLL, true);
+            X23_CASE(BHAC_RECON_PPM, BHAC_FLUX_TVDLF, true);
+        }
+        if (f == BHAC_FLUX_HLL) X23_CASE(BHAC_RECON_MC, BHAC_FLUX_HLL, true);
+        X23_CASE(BHAC_RECON_MC, BHAC_FLUX_TVDLF, true);
+    }
+    if (r == BHAC_RECON_PPM) {
+        if (f == BHAC_FLUX_HLL) X23_CASE(BHAC_RECON_PPM, BHAC_FLUX_HLL, false);
+        X23_CASE(BHAC_RECON_PPM, BHAC_FLUX_TVDLF, false);
+    }
+    if (f == BHAC_FLUX_HLL) X23_CASE(BHAC_RECON_MC, BHAC_FLUX_HLL, false);
+    X23_CASE(BHAC_RECON_MC, BHAC_FLUX_TVDLF, false);
+#undef X23_CASE
+}
+
+hipError_t launch_flux_march_x23(const DeviceGrid &G, const void *Ps, hipStream_t s, void *const *flux)
+{
+    return G.mixed ? x23_dir<float>(G, Ps, s, flux) : x23_dir<double>(G, Ps, s, flux);
 }
 
 hipError_t launch_flux_march(const DeviceGrid &G, int D, const void *Ps, hipStream_t s, void *const *flux,
