@@ -112,12 +112,12 @@ TRAFFIC = {
     # (workload, kernel family): (bytes per launch, source digest)
     # profiles/update_ks_turb_384_hbm_traffic.md, update_ks_torus_192_mixed_128_fp64_hbm_traffic.md,
     # update_ks_torus_128_ct_hbm_traffic.md
-    ("ks_turb_384_mixed_plain", "update"): (20828500374, "567e16efe17f985d"),
-    ("ks_turb_384_fp64_plain", "update_x1"): (30605902354, "567e16efe17f985d"),
-    ("ks_torus_192_mixed_plain", "update"): (2607484839, "567e16efe17f985d"),
-    ("ks_torus_128_fp64_plain", "update_x1"): (1133665255, "567e16efe17f985d"),
-    ("ks_torus_128_mixed_ct", "update"): (671371798, "567e16efe17f985d"),
-    ("ks_torus_128_fp64_ct", "update"): (983061331, "567e16efe17f985d"),
+    ("ks_turb_384_mixed_plain", "update"): (20828609478, "469e3e1370c9e273"),
+    ("ks_turb_384_fp64_plain", "update_x1"): (30566730643, "469e3e1370c9e273"),
+    ("ks_torus_192_mixed_plain", "update"): (2607481265, "469e3e1370c9e273"),
+    ("ks_torus_128_fp64_plain", "update_x1"): (1133698907, "469e3e1370c9e273"),
+    ("ks_torus_128_mixed_ct", "update"): (671370394, "469e3e1370c9e273"),
+    ("ks_torus_128_fp64_ct", "update"): (983060125, "469e3e1370c9e273"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
@@ -131,30 +131,30 @@ TRAFFIC = {
 VALU = {
     # profiles/ks_turb_384_valu_counters.md, ks_torus_192_mixed_128_fp64_valu_counters.md,
     # ks_torus_128_ct_valu_counters.md
-    ("ks_turb_384_fp64_plain", "flux_x2"): (734164638, "567e16efe17f985d"),
-    ("ks_turb_384_fp64_plain", "flux_x3"): (659868762, "567e16efe17f985d"),
-    ("ks_turb_384_mixed_plain", "flux_x2"): (618230358, "567e16efe17f985d"),
-    ("ks_turb_384_mixed_plain", "flux_x3"): (546281593, "567e16efe17f985d"),
-    ("ks_turb_384_mixed_plain", "flux_x1"): (1033852605, "567e16efe17f985d"),
-    ("ks_turb_384_mixed_plain", "update"): (1255451031, "567e16efe17f985d"),
-    ("ks_turb_384_fp64_plain", "update_x1"): (2592712443, "567e16efe17f985d"),
-    ("ks_torus_128_fp64_plain", "flux_x2"): (27163141, "567e16efe17f985d"),
-    ("ks_torus_128_fp64_plain", "flux_x3"): (24566805, "567e16efe17f985d"),
-    ("ks_torus_192_mixed_plain", "flux_x2"): (77645655, "567e16efe17f985d"),
-    ("ks_torus_192_mixed_plain", "flux_x3"): (68428761, "567e16efe17f985d"),
-    ("ks_torus_192_mixed_plain", "flux_x1"): (129381829, "567e16efe17f985d"),
-    ("ks_torus_192_mixed_plain", "update"): (158204622, "567e16efe17f985d"),
-    ("ks_torus_128_fp64_plain", "update_x1"): (96739698, "567e16efe17f985d"),
-    ("ks_torus_128_fp64_ct", "ct_edges"): (6303829, "567e16efe17f985d"),
-    ("ks_torus_128_mixed_ct", "ct_edges"): (6453333, "567e16efe17f985d"),
-    ("ks_torus_128_fp64_ct", "flux_x2"): (26786547, "567e16efe17f985d"),
-    ("ks_torus_128_fp64_ct", "flux_x3"): (24352510, "567e16efe17f985d"),
-    ("ks_torus_128_mixed_ct", "flux_x2"): (21133434, "567e16efe17f985d"),
-    ("ks_torus_128_mixed_ct", "flux_x3"): (18436861, "567e16efe17f985d"),
-    ("ks_torus_128_fp64_ct", "flux_x1"): (43390073, "567e16efe17f985d"),
-    ("ks_torus_128_mixed_ct", "flux_x1"): (34744922, "567e16efe17f985d"),
-    ("ks_torus_128_fp64_ct", "update"): (39467127, "567e16efe17f985d"),
-    ("ks_torus_128_mixed_ct", "update"): (40745008, "567e16efe17f985d"),
+    ("ks_turb_384_fp64_plain", "flux_x2"): (750792543, "469e3e1370c9e273"),
+    ("ks_turb_384_fp64_plain", "flux_x3"): (664407997, "469e3e1370c9e273"),
+    ("ks_turb_384_mixed_plain", "flux_x2"): (632278966, "469e3e1370c9e273"),
+    ("ks_turb_384_mixed_plain", "flux_x3"): (568482207, "469e3e1370c9e273"),
+    ("ks_turb_384_mixed_plain", "flux_x1"): (1033852654, "469e3e1370c9e273"),
+    ("ks_turb_384_mixed_plain", "update"): (1255450966, "469e3e1370c9e273"),
+    ("ks_turb_384_fp64_plain", "update_x1"): (2592712348, "469e3e1370c9e273"),
+    ("ks_torus_128_fp64_plain", "flux_x2"): (27779563, "469e3e1370c9e273"),
+    ("ks_torus_128_fp64_plain", "flux_x3"): (24798987, "469e3e1370c9e273"),
+    ("ks_torus_192_mixed_plain", "flux_x2"): (79490969, "469e3e1370c9e273"),
+    ("ks_torus_192_mixed_plain", "flux_x3"): (71312299, "469e3e1370c9e273"),
+    ("ks_torus_192_mixed_plain", "flux_x1"): (129381759, "469e3e1370c9e273"),
+    ("ks_torus_192_mixed_plain", "update"): (158204683, "469e3e1370c9e273"),
+    ("ks_torus_128_fp64_plain", "update_x1"): (96739932, "469e3e1370c9e273"),
+    ("ks_torus_128_fp64_ct", "ct_edges"): (6303829, "469e3e1370c9e273"),
+    ("ks_torus_128_mixed_ct", "ct_edges"): (6453333, "469e3e1370c9e273"),
+    ("ks_torus_128_fp64_ct", "flux_x2"): (26931940, "469e3e1370c9e273"),
+    ("ks_torus_128_fp64_ct", "flux_x3"): (24497943, "469e3e1370c9e273"),
+    ("ks_torus_128_mixed_ct", "flux_x2"): (21784795, "469e3e1370c9e273"),
+    ("ks_torus_128_mixed_ct", "flux_x3"): (19088117, "469e3e1370c9e273"),
+    ("ks_torus_128_fp64_ct", "flux_x1"): (43389954, "469e3e1370c9e273"),
+    ("ks_torus_128_mixed_ct", "flux_x1"): (34744871, "469e3e1370c9e273"),
+    ("ks_torus_128_fp64_ct", "update"): (39467065, "469e3e1370c9e273"),
+    ("ks_torus_128_mixed_ct", "update"): (40744997, "469e3e1370c9e273"),
 }
 VALU_PEAK = 39.3e12      # lane-instructions/s
 
