@@ -118,6 +118,8 @@ TRAFFIC = {
     ("ks_torus_128_fp64_plain", "update_x1"): (1133698907, "469e3e1370c9e273"),
     ("ks_torus_128_mixed_ct", "update"): (671370394, "469e3e1370c9e273"),
     ("ks_torus_128_fp64_ct", "update"): (983060125, "469e3e1370c9e273"),
+    # profiles/update_amr_like_4096_hbm_traffic.md
+    ("amr_like_4096_mixed_plain", "update"): (2569056062, "469e3e1370c9e273"),
 }
 
 # Measured VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, mean over the
