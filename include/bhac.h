@@ -409,7 +409,8 @@ int bhac_capture_rk2_step_ct(bhac_grid *grid, double *U, void *P, double *U1, vo
  * *n_entries, and restarts the accumulation. Launches beyond the pool are not
  * timed (their count is returned as a family named "untimed"). While timing is
  * enabled the face kernels of a 3-D substep run one after another on the
- * caller's stream instead of concurrently on the grid's side streams, so each
+ * caller's stream (the x2 and x3 line marches as two launches) instead of
+ * concurrently on the grid's side streams or as one x2+x3 launch, so each
  * measured duration is the kernel's own (results are the same either way). */
 typedef struct bhac_kernel_time {
     const char *name;
