@@ -55,3 +55,36 @@ def test_launch_without_capture_is_an_error():
         G.launch_rk2_step()
     assert e.value.code == B.BHAC_EINVAL
     G.close()
+
+
+@pytest.mark.parametrize("prec,x1", [(I.PREC_FP64, 2), (I.PREC_MIXED, 1), (I.PREC_MIXED, 2)])
+def test_combined_x2_x3_launch_matches_separate_launches(prec, x1):
+    """With x2 and x3 both marched, a substep runs both directions' line marches as
+    one launch; under kernel timing it runs them as two launches on the caller's
+    stream. Both give the same bits, eagerly and in a captured graph."""
+    import torch
+    c = I.case_torus(2, n=(48, 32, 32))
+    c.params = dict(c.params, precision=prec, fused=0, sched=dict(march_mask=6, march_faces=17, x1_staged=x1))
+    print(f"\n[graph] x2+x3 launch prec={prec} x1_staged={x1}", flush=True)
+    out = []
+    for timing, graph in ((True, False), (False, False), (False, True)):
+        G = B.Grid(c.params, c.blocks)
+        assert G.schedule()["march_mask"] == 6
+        U, P = G.init(c.prim)
+        U1, P1 = G.new_state("U"), G.new_state("P")
+        B.bhac_set_timing(G.h, timing)
+        if graph:
+            G.capture_rk2_step(U, P, U1, P1)
+        for _ in range(4):
+            if graph:
+                G.launch_rk2_step()
+            else:
+                G.rk2_step(U, P, U1, P1)
+        torch.cuda.synchronize()
+        B.bhac_set_timing(G.h, False)
+        out.append((G.unpack(U), G.unpack(P), G.timestep()["dt_next"]))
+        G.close()
+    for got in out[1:]:
+        assert np.array_equal(out[0][0], got[0])
+        assert np.array_equal(out[0][1], got[1])
+        assert out[0][2] == got[2]
